@@ -1,0 +1,212 @@
+"""Pins for the oracle's targets, per-kernel quantities and forward pass.
+
+Each test checks the oracle against something other than itself: a closed
+form, a hand-derived worked example, brute force, or an invariant."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# --- eq. 3-10 -------------------------------------------------------------
+
+def test_targets_golden_dyadic_values():
+    for m, S, t in _read_golden("eq3_10_targets.txt"):
+        got = O.targets_from_sdf(np.array([float(S)]), float(m))[0]
+        assert got == pytest.approx(float(t), rel=1e-15, abs=1e-300)
+
+
+def test_targets_monotone_and_range():
+    S = np.linspace(-0.3, 2.0, 1001)
+    t = O.targets_from_sdf(S, -0.3)
+    assert np.all(np.diff(t) < 0)
+    assert t[0] == pytest.approx(2.0) and np.all(t > 0) and np.all(t <= 2.0)
+    # inside (S < 0) maps to (1, 2], outside to (0, 1)
+    assert np.all(t[S < 0] > 1.0) and np.all(t[S > 0] < 1.0)
+
+
+def test_targets_need_negative_min():
+    with pytest.raises(ValueError):
+        O.targets_from_sdf(np.array([0.1, 0.2]), 0.1)
+
+
+# --- rotation and per-kernel quantities ----------------------------------
+
+def test_rotation_orthonormal_and_identity():
+    rng = np.random.default_rng(0)
+    q = synth.random_unit_quaternions(200, rng) * rng.uniform(0.5, 3.0, size=(200, 1))
+    K = O.make_kernels(np.ones(200), np.zeros((200, 3)), np.zeros((200, 3)), q, 3.0)
+    I = np.eye(3)
+    assert np.abs(np.einsum("mki,mkj->mij", K.R, K.R) - I).max() < 1e-14
+    assert np.abs(np.linalg.det(K.R) - 1.0).max() < 1e-14
+    K1 = O.make_kernels([1.0], [[0, 0, 0]], [[0, 0, 0]], [[2.5, 0, 0, 0]], 3.0)
+    assert np.abs(K1.R[0] - I).max() == 0.0
+
+
+def test_rotation_worked_examples():
+    axes = {"x": (1, 0, 0), "y": (0, 1, 0), "z": (0, 0, 1)}
+    for ax, ang, ox, oy, oz, d1, d2, d3, ex in _read_golden("rotation_worked_examples.txt"):
+        half = math.radians(float(ang)) / 2
+        q = [math.cos(half)] + [math.sin(half) * v for v in axes[ax]]
+        d = np.array([float(d1), float(d2), float(d3)])
+        c = np.array([0.1, -0.2, 0.3])
+        K = O.make_kernels([1.0], [c], [np.log(d)], [q], 100.0)
+        x = c + np.array([float(ox), float(oy), float(oz)])
+        got = O.forward_at_points(x[None], K, culled=False)[0]
+        assert got == pytest.approx(math.exp(-float(ex)), rel=1e-13)
+
+
+def test_amplitude_and_radius():
+    K = O.make_kernels([-0.3, 0.2], [[0, 0, 0]] * 2, [[0.0, 1.0, 2.0], [1.0, 1.0, 1.0]],
+                       [[1, 0, 0, 0]] * 2, 3.0)
+    assert K.a[0] == pytest.approx(-0.09) and K.a[1] == pytest.approx(0.04)
+    assert K.dadw[0] == pytest.approx(0.6)
+    assert K.r2[0] == pytest.approx(9.0)             # min d = e^0 = 1
+    assert K.r2[1] == pytest.approx(9.0 / math.e ** 2)
+    KL = O.make_kernels([-0.3], [[0, 0, 0]], [[0, 0, 0]], [[1, 0, 0, 0]], 3.0, weight_map=1)
+    assert KL.a[0] == pytest.approx(-0.3) and KL.dadw[0] == 1.0
+
+
+# --- forward --------------------------------------------------------------
+
+def _tiny_level(n=16, seed=0):
+    ax = synth.axis_coords(n)
+    return O.make_level(n, ax)
+
+
+def test_single_isotropic_kernel_closed_form():
+    lv = _tiny_level(16)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        q = synth.random_unit_quaternions(1, rng)
+        c = rng.uniform(-0.5, 0.5, size=3)
+        dv = 3.0
+        w = 0.7
+        K = O.make_kernels([w], [c], [[math.log(dv)] * 3], q, 3.0)
+        f = O.forward([lv], K, culled=False)[0]
+        pts = O.level_points(lv)
+        ref = w * abs(w) * np.exp(-dv * dv * np.sum((pts - c) ** 2, axis=1))
+        assert np.abs(f - ref).max() < 1e-14
+
+
+def test_identity_quaternion_separable_product():
+    lv = _tiny_level(12)
+    d = np.array([2.0, 3.5, 5.0])
+    c = np.array([0.05, -0.1, 0.2])
+    K = O.make_kernels([-0.5], [c], [np.log(d)], [[1, 0, 0, 0]], 3.0)
+    f = O.forward([lv], K, culled=False)[0]
+    pts = O.level_points(lv)
+    ref = -0.25 * np.prod(np.exp(-(d ** 2) * (pts - c) ** 2), axis=1)
+    assert np.abs(f - ref).max() < 1e-15
+
+
+def _rand_problem(seed, n=16, m=12, lo=1.5, hi=2.5, cull=3.0):
+    p = synth.make_custom(seed, [n], m, (lo, hi), kinds=("ellipsoid", "torus"))
+    K = O.kernels_from_packed(p.params, p.m, p.cap, cull)
+    lv = O.make_level(n, p.levels[0].axis, S=p.levels[0].S)
+    return lv, K, p
+
+
+def test_culled_vs_all_pairs_within_truncation_bound():
+    lv, K, _ = _rand_problem(3)
+    fa = O.forward([lv], K, culled=False)[0]
+    fc = O.forward([lv], K, culled=True)[0]
+    bound = O.truncation_bound([lv], K)[0]
+    diff = np.abs(fa - fc)
+    assert np.all(diff <= bound * (1 + 1e-12) + 1e-300)
+    # the bound is not vacuous: something was culled
+    assert bound.max() > 0 and diff.max() > 0
+    # global form of the bound: e^{-k^2} sum |a_j|
+    assert diff.max() <= math.exp(-9.0) * np.abs(K.a).sum()
+
+
+def test_cull_predicate_brute_force_counts():
+    lv, K, _ = _rand_problem(4)
+    pts = O.level_points(lv)
+    brute = 0
+    for j in range(K.m):
+        brute += int(np.sum(np.sum((pts - K.c[j]) ** 2, axis=1) < K.r2[j]))
+    pf, _ = O.pair_counts([lv], K)
+    assert pf == brute
+
+
+def test_forward_at_points_matches_grid_forward():
+    lv, K, _ = _rand_problem(5)
+    f = O.forward([lv], K)[0]
+    pts = O.level_points(lv)
+    idx = np.random.default_rng(0).choice(pts.shape[0], 64, replace=False)
+    g = O.forward_at_points(pts[idx], K)
+    assert np.abs(g - f[idx]).max() < 1e-14
+
+
+def _perturbed(K, **kw):
+    fields = dict(w=K.w, c=K.c, s=K.s, q=K.q)
+    fields.update(kw)
+    return O.make_kernels(fields["w"], fields["c"], fields["s"], fields["q"],
+                          3.0, K.weight_map)
+
+
+def test_invariances_permutation_sign_scale_translation():
+    lv, K, _ = _rand_problem(6)
+    f0 = O.forward([lv], K)[0]
+    perm = np.random.default_rng(0).permutation(K.m)
+    Kp = O.make_kernels(K.w[perm], K.c[perm], K.s[perm], K.q[perm], 3.0)
+    assert np.abs(O.forward([lv], Kp)[0] - f0).max() < 1e-13
+    assert np.abs(O.forward([lv], _perturbed(K, q=-K.q))[0] - f0).max() < 1e-13
+    assert np.abs(O.forward([lv], _perturbed(K, q=3.7 * K.q))[0] - f0).max() < 1e-13
+    # dyadic translation of every point and centre by 2 grid spacings
+    shift = 2 * (lv.axis[1] - lv.axis[0])
+    lv2 = O.make_level(lv.n, lv.axis + shift)
+    Kt = _perturbed(K, c=K.c + shift)
+    assert np.abs(O.forward([lv2], Kt)[0] - f0).max() < 1e-13
+
+
+def test_isotropic_kernels_ignore_orientation():
+    lv, K, _ = _rand_problem(7)
+    iso = np.repeat(K.s[:, :1], 3, axis=1)
+    Ki = _perturbed(K, s=iso)
+    q2 = synth.random_unit_quaternions(K.m, np.random.default_rng(9))
+    f1 = O.forward([lv], Ki)[0]
+    f2 = O.forward([lv], _perturbed(Ki, q=q2))[0]
+    assert np.abs(f1 - f2).max() < 1e-13
+
+
+def test_multi_level_and_active_mask():
+    p = synth.make_custom(8, [8, 16], 10, (1.5, 2.5), bands=[None, 0.2])
+    K = O.kernels_from_packed(p.params, p.m, p.cap, 3.0)
+    lvs = [O.make_level(l.n, l.axis, active=l.active_mask(), S=l.S) for l in p.levels]
+    f = O.forward(lvs, K)
+    # level-by-level evaluation equals the joint evaluation
+    assert np.array_equal(O.forward([lvs[0]], K)[0], f[0])
+    act = lvs[1].active
+    assert np.all(f[1][~act] == 0.0)
+    full = O.forward([O.make_level(16, p.levels[1].axis)], K)[0]
+    assert np.abs(f[1][act] - full[act]).max() == 0.0
+
+
+def test_boundary_allowance_counts_only_near_shell():
+    lv, K, _ = _rand_problem(10)
+    al, cnt = O.boundary_allowance([lv], K, rel=1e-2)
+    pts = O.level_points(lv)
+    brute = 0
+    for j in range(K.m):
+        d2 = np.sum((pts - K.c[j]) ** 2, axis=1)
+        brute += int(np.sum(np.abs(d2 - K.r2[j]) <= 1e-2 * K.r2[j]))
+    assert cnt == brute
