@@ -1,0 +1,243 @@
+/*
+ * erbf.h -- C ABI of the MI355X ERBF-fit library.
+ *
+ * The library evaluates a sparse network of ellipsoidal radial basis
+ * functions (ERBFs) at precomputed signed-distance grid points and returns
+ * the sparse-fit loss and its gradient with respect to every kernel's
+ * weight, centre, per-axis scale and orientation -- the optimisation step of
+ * SE-RBFNet (Lian et al., "Approximating Signed Distance Fields With Sparse
+ * Ellipsoidal Radial Basis Function Networks", arXiv 2505.02350).
+ *
+ * Model (paper Section 3.2, eq. 3-7 and eq. 3-26; cull of eq. 3-15-1):
+ *     f(x) = sum_j a_j [ |x - c_j|^2 < r_j^2 ] exp(-| D_j R_j (x - c_j) |^2)
+ *     a_j  = w_j |w_j|  (ERBF_WEIGHT_SIGNED_SQUARE)   or   w_j (ERBF_WEIGHT_LINEAR)
+ *     D_j  = diag(exp(s_j)),  R_j = R(q_j / |q_j|),  r_j = cull_k / min_k exp(s_jk)
+ * Orientation is a quaternion (w, x, y, z) in place of the paper's Euler
+ * angles (eq. 3-6); scales are optimised as logarithms s = ln d.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All pointers named *_dev or documented as "device" point to device
+ *    memory of the context's device, owned by the caller.  The library never
+ *    allocates device memory: every scratch buffer lives in the caller's
+ *    workspace (erbf_workspace_size / erbf_ctx_create).
+ *  - Calls that take a hipStream_t only enqueue work on that stream; they do
+ *    not synchronise and are safe to capture into a hipGraph, except the
+ *    calls documented as "synchronous" (erbf_ctx_create,
+ *    erbf_refine_level, erbf_seed_from_error, erbf_autotune).
+ *  - A context holds one or more independent shapes (the batched extension);
+ *    a plain fit is a context with one shape.  Kernels of all shapes share
+ *    one global index space: shape b owns slots [kbase_b, kbase_b + cap_b),
+ *    kbase_b = sum of the capacities of the shapes before it.
+ *  - Parameters, gradients and Adam moments share the packed layout
+ *        float p[11 * cap_total]:  w | cx cy cz | sx sy sz | qw qx qy qz
+ *    each segment cap_total floats long; the live kernels of shape b are
+ *    slots kbase_b .. kbase_b + m_b - 1, m_b = m_dev[b].  Slots past m_b are
+ *    ignored and their gradients written as 0.
+ *  - Grid points: every level of every shape is a uniform cell-centred grid
+ *    of n^3 points (axis table given by the caller, x fastest:
+ *    idx = (k n + j) n + i).  Per-point arrays of a call (targets, f, G) are
+ *    the concatenation over shapes (outer) and their active levels (inner).
+ *  - Every call returns ERBF_OK or a negative error code; erbf_last_error()
+ *    returns a thread-local message for the last failure.  No exception
+ *    crosses the ABI.  Device-side conditions that cannot be returned
+ *    (bucket overflow) are reported in erbf_stats.flags and never overrun a
+ *    buffer.
+ */
+#ifndef ERBF_H
+#define ERBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ERBF_ABI_VERSION 1
+#define ERBF_MAX_LEVELS 8
+#define ERBF_MAX_SHAPES 1024
+
+enum {
+  ERBF_OK = 0,
+  ERBF_ERR_INVALID_ARG = -1,  /* bad pointer, size or configuration */
+  ERBF_ERR_HIP = -2,          /* a HIP runtime call failed; message has the hipError_t */
+  ERBF_ERR_WORKSPACE = -3,    /* workspace too small for the configuration */
+  ERBF_ERR_CAPACITY = -4,     /* seeding would exceed a shape's kernel capacity */
+  ERBF_ERR_UNSUPPORTED = -5,  /* valid request this build does not implement */
+  ERBF_ERR_STATE = -6         /* call out of order (e.g. no level registered) */
+};
+
+/* erbf_stats.flags bits */
+#define ERBF_FLAG_BUCKET_OVERFLOW 1  /* bucket list exceeded pair_cap: f, loss, grads invalid */
+
+enum { ERBF_WEIGHT_SIGNED_SQUARE = 0, ERBF_WEIGHT_LINEAR = 1 };
+
+/* Loss-weight modes (Section 3.3, eq. 3-14 and eq. 3-21; Algorithm 3). */
+enum {
+  ERBF_MODE_FIXED = 0,    /* alpha = 1, beta = lambda                              */
+  ERBF_MODE_DYNAMIC = 1,  /* eq. 3-21 when l1_active and max|E| < tau_m, else (1, 0) */
+  ERBF_MODE_L2 = 2        /* alpha = 1, beta = 0                                    */
+};
+
+typedef struct erbf_ctx erbf_ctx;
+
+/* One shape: its grid levels (coarse to fine, appended by erbf_refine_level
+ * in this order) and its kernel capacity. */
+typedef struct {
+  int32_t n_levels;                  /* 1 .. ERBF_MAX_LEVELS */
+  int32_t level_n[ERBF_MAX_LEVELS];  /* points per axis of each level, 1 .. 2048 */
+  int32_t m_cap;                     /* kernel slots of this shape, >= 1 */
+} erbf_shape_desc;
+
+typedef struct {
+  int32_t n_shapes;               /* 1 .. ERBF_MAX_SHAPES */
+  const erbf_shape_desc* shapes;  /* host array [n_shapes] */
+  int64_t pair_cap;   /* capacity of the tile->kernel bucket lists (entries over all
+                         shapes); exceeded => ERBF_FLAG_BUCKET_OVERFLOW */
+  float cull_k;       /* cull radius factor: r = cull_k / min d (eq. 3-15 with
+                         eps = exp(-cull_k^2)); > 0 */
+  int32_t weight_map; /* ERBF_WEIGHT_SIGNED_SQUARE (eq. 3-26) or ERBF_WEIGHT_LINEAR */
+} erbf_config;
+
+/* A grid level (eq. 3-16: the training set is the union of the levels
+ * registered so far).  All arrays are device memory owned by the caller and
+ * must stay valid for the context's lifetime. */
+typedef struct {
+  int32_t n;                    /* points per axis; must equal the declared level_n */
+  const float* axis;            /* [n] increasing cell-centred coordinates in [-1, 1] */
+  const float* target;          /* [n^3] normalised targets (eq. 3-10) or NULL (eval/vjp only) */
+  const float* sdf;             /* [n^3] raw signed distance, or NULL; required for seeding */
+  const uint32_t* active_bits;  /* [ceil(n^3/32)] training-point mask (bit i%32 of word i/32),
+                                   or NULL for all points */
+} erbf_level;
+
+typedef struct {
+  float* p;         /* device [11 * cap_total], packed layout above */
+  int32_t* m_dev;   /* device [n_shapes]: live kernel count of each shape */
+} erbf_params;
+
+typedef struct {
+  int32_t mode;            /* ERBF_MODE_* */
+  float lambda;            /* fixed-mode L1 weight, used when lambda_dev is NULL */
+  const float* lambda_dev; /* device [n_shapes] per-shape fixed-mode weight, or NULL */
+  int32_t l1_active;       /* dynamic mode: L1 term scheduled on (eq. l1_activate) */
+  float tau1, tau2;        /* id_all thresholds of eq. 3-18 (paper: 0.9, 1.1) */
+  float tau_m;             /* max-error gate of eq. l1_activate2 (paper: 0.02) */
+} erbf_loss_cfg;
+
+/* Per-shape step statistics, written to device memory by erbf_loss_grad. */
+typedef struct {
+  double L2;          /* sum over id_all of E^2 (eq. 3-14_2) */
+  double L1;          /* sum of |w| over live kernels */
+  double loss;        /* alpha * L2 + beta * L1 */
+  double alpha, beta; /* loss weights used for the gradient (eq. 3-21) */
+  int64_t n_idall;    /* points in id_all (eq. 3-18) */
+  int64_t P_fwd;      /* in-ball point-kernel pairs over active points */
+  int64_t P_bwd;      /* in-ball pairs whose upstream G is non-zero */
+  int64_t n_bucket_pairs; /* bucket entries needed by this call (all shapes) */
+  float max_abs_E;    /* max |E| over id_all, 0 if empty */
+  int32_t m;          /* live kernels */
+  int32_t flags;      /* ERBF_FLAG_* */
+  int32_t reserved;
+} erbf_stats;
+
+typedef struct {
+  float lr;            /* used when lr_dev is NULL */
+  const float* lr_dev; /* device [n_shapes] per-shape learning rate, or NULL */
+  float beta1, beta2, eps;  /* Adam hyper-parameters (0.9, 0.999, 1e-8) */
+} erbf_adam_cfg;
+
+typedef struct {
+  float top_frac;      /* candidates: ceil(top_frac * n_idall) largest |E| (<= 0.05) */
+  int32_t k_new;       /* kernels appended per call, 1 .. 4096 */
+  float r_nms;         /* extreme-point radius; <= 0 selects twice the finest spacing */
+  float eps;           /* eq. 3-24 epsilon (paper: 1e-7) */
+  float min_abs_err;   /* candidates also need |E| > min_abs_err (Algorithm 2: tau_m / 2) */
+  int32_t w_rule;      /* 0: w = -sign(E)|E| (eq. 3-24 literally); 1: w = -sign(E) sqrt|E| */
+} erbf_seed_cfg;
+
+/* ---- context ----------------------------------------------------------- */
+
+int32_t erbf_abi_version(void);
+const char* erbf_last_error(void);
+
+/* Bytes of device workspace a context with this configuration needs. */
+int erbf_workspace_size(const erbf_config* cfg, size_t* bytes);
+
+/* Create a context on `device` using the caller's workspace (device memory
+ * of at least erbf_workspace_size bytes, 256-byte aligned).  Synchronous.
+ * Returns ERBF_ERR_WORKSPACE if `bytes` is too small. */
+int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t bytes,
+                    erbf_ctx** out);
+void erbf_ctx_destroy(erbf_ctx* ctx);
+
+/* Total kernel slots (sum of the shapes' m_cap) and points of the active
+ * levels (length of the per-point arrays of the next call). */
+int erbf_ctx_info(const erbf_ctx* ctx, int32_t* cap_total, int64_t* n_points,
+                  int32_t* n_active_levels_shape0);
+
+/* ---- data preparation (eq. 3-10) --------------------------------------- */
+
+/* out_dev[0] = min(out_dev[0], min_i S[i]) if accumulate, else min_i S[i].
+ * Device result; the minimum over every level is eq. 3-10's m. */
+int erbf_sdf_min(const float* S, int64_t n, float* out_dev, int accumulate, hipStream_t stream);
+
+/* t[i] = 2 exp(-h (S[i] - m)^2), h = ln 2 / m^2 (eq. 3-10), evaluated in
+ * double and rounded once.  m must be < 0. */
+int erbf_targets_from_sdf(const float* S, int64_t n, float m, float* t, hipStream_t stream);
+
+/* bits of |S| < band (a banded level's training points).  `bits` holds
+ * ceil(n/32) words; trailing bits are 0. */
+int erbf_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t stream);
+
+/* ---- the step ------------------------------------------------------------ */
+
+/* Append the next level of `shape` (eq. 3-16 / Algorithm 3: training starts
+ * on a coarse level and finer levels are appended).  Builds the level's
+ * tile occupancy in the workspace.  Synchronous. */
+int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hipStream_t stream);
+
+/* f at every point of every active level (eq. 3-9 with eq. 3-15-1), 0 at
+ * points outside a level's active mask.  f_out: device [n_points]. */
+int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats* stats_dev,
+              hipStream_t stream);
+
+/* One loss + gradient evaluation (eq. 3-9, 3-18, 3-19, 3-21 and Appendix
+ * A).  grad_out: device [11 * cap_total], the combined gradient
+ * alpha dL2 + beta dL1 in the packed layout.  stats_dev: device
+ * [n_shapes].  f_out, G_out: optional device [n_points]; G = 2 E on id_all,
+ * 0 elsewhere.  Every active level needs a target. */
+int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+                   float* grad_out, erbf_stats* stats_dev, float* f_out, float* G_out,
+                   hipStream_t stream);
+
+/* Vector-Jacobian product of erbf_eval: grad_out = (df/dtheta)^T grad_f,
+ * grad_f: device [n_points] (entries at inactive points are ignored).
+ * stats_dev optional (P_fwd, P_bwd). */
+int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, float* grad_out,
+             erbf_stats* stats_dev, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected; Algorithm 3) on the live
+ * kernels of every shape.  m1, m2: device moments in the packed layout;
+ * step_dev: device [n_shapes] step counters, incremented by this call. */
+int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, float* m1,
+                   float* m2, int32_t* step_dev, const erbf_adam_cfg* cfg, hipStream_t stream);
+
+/* Append new kernels at local maxima of the residual (Algorithm 2, eq. 3-22,
+ * 3-24, 3-25) to `shape`.  resid: device [n_points] residual E (or G with
+ * resid_scale = 0.5), 0 outside id_all; n_idall: its id_all count.  New
+ * kernels get zero Adam moments in m1/m2 (either may be NULL).  Every
+ * active level of the shape needs `sdf`.  Synchronous; *n_added receives
+ * the number appended.  ERBF_ERR_CAPACITY (nothing appended) if the shape
+ * cannot hold them. */
+int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape,
+                         const float* resid, float resid_scale, int64_t n_idall,
+                         const erbf_seed_cfg* cfg, float* m1, float* m2, int32_t* n_added,
+                         hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ERBF_H */

@@ -1,0 +1,216 @@
+"""Thin Python surface over the C ABI (``include/erbf.h``).
+
+Names follow the C calls.  Torch supplies device memory and the stream;
+this module only marshals pointers and sizes.
+"""
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+@dataclass
+class StatsView:
+    L2: float
+    L1: float
+    loss: float
+    alpha: float
+    beta: float
+    n_idall: int
+    P_fwd: int
+    P_bwd: int
+    n_bucket_pairs: int
+    max_abs_E: float
+    m: int
+    flags: int
+
+
+def parse_stats(buf: torch.Tensor, n_shapes: int) -> List[StatsView]:
+    raw = bytes(buf.cpu().numpy().tobytes())
+    out = []
+    for b in range(n_shapes):
+        s = L.Stats.from_buffer_copy(raw[b * L.STATS_BYTES:(b + 1) * L.STATS_BYTES])
+        out.append(StatsView(s.L2, s.L1, s.loss, s.alpha, s.beta, s.n_idall, s.P_fwd, s.P_bwd,
+                             s.n_bucket_pairs, s.max_abs_E, s.m, s.flags))
+    return out
+
+
+class Context:
+    """One library context: shapes, their grid levels and the workspace."""
+
+    def __init__(self, shapes: Sequence, pair_cap: int, cull_k: float = 3.0,
+                 weight_map: int = L.WEIGHT_SIGNED_SQUARE, device: int = 0):
+        """shapes: sequence of (level_ns, m_cap)."""
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        descs = (L.ShapeDesc * len(shapes))()
+        self.level_ns = []
+        self.m_caps = []
+        for b, (ns, mcap) in enumerate(shapes):
+            ns = [int(n) for n in ns]
+            descs[b].n_levels = len(ns)
+            for i, n in enumerate(ns):
+                descs[b].level_n[i] = n
+            descs[b].m_cap = int(mcap)
+            self.level_ns.append(ns)
+            self.m_caps.append(int(mcap))
+        self._descs = descs
+        cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map))
+        self._cfg = cfg
+        nbytes = ctypes.c_size_t()
+        L.check(self.lib.erbf_workspace_size(ctypes.byref(cfg), ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        h = ctypes.c_void_p()
+        L.check(self.lib.erbf_ctx_create(device, ctypes.byref(cfg), aligned, self.ws_bytes, ctypes.byref(h)))
+        self.handle = h
+        cap = ctypes.c_int32()
+        npts = ctypes.c_int64()
+        L.check(self.lib.erbf_ctx_info(h, ctypes.byref(cap), ctypes.byref(npts), None))
+        self.cap_total = cap.value
+        self.n_points = npts.value
+        self.n_shapes = len(shapes)
+        self.kbase = [sum(self.m_caps[:b]) for b in range(self.n_shapes)]
+        # per-point offsets (shape-major over declared levels)
+        self.pt_base = []
+        off = 0
+        for ns in self.level_ns:
+            row = []
+            for n in ns:
+                row.append(off)
+                off += n ** 3
+            self.pt_base.append(row)
+        self.n_active = [0] * self.n_shapes
+        self._keep = []   # device arrays the context points into
+        self.stats_buf = torch.zeros(self.n_shapes * L.STATS_BYTES, dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.erbf_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- levels -------------------------------------------------------------
+    def erbf_refine_level(self, shape: int, axis: torch.Tensor, target: torch.Tensor = None,
+                          sdf: torch.Tensor = None, active_bits: torch.Tensor = None, stream=None):
+        n = self.level_ns[shape][self.n_active[shape]]
+        for t, name in ((axis, "axis"), (target, "target"), (sdf, "sdf")):
+            if t is not None and t.dtype != torch.float32:
+                raise ValueError(f"{name} must be float32")
+        if active_bits is not None and active_bits.dtype != torch.int32:
+            raise ValueError("active_bits must be int32 words")
+        lvl = L.Level(n, _ptr(axis), _ptr(target), _ptr(sdf), _ptr(active_bits))
+        self._keep.append((axis, target, sdf, active_bits))
+        L.check(self.lib.erbf_refine_level(self.handle, shape, ctypes.byref(lvl), _stream(stream)))
+        self.n_active[shape] += 1
+
+    # ---- params ---------------------------------------------------------------
+    def new_params(self):
+        p = torch.zeros(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        m = torch.zeros(self.n_shapes, dtype=torch.int32, device=self.device)
+        return p, m
+
+    def _params(self, p: torch.Tensor, m_dev: torch.Tensor):
+        if p.dtype != torch.float32 or p.numel() != 11 * self.cap_total:
+            raise ValueError("params must be float32 [11 * cap_total]")
+        if m_dev.dtype != torch.int32 or m_dev.numel() != self.n_shapes:
+            raise ValueError("m_dev must be int32 [n_shapes]")
+        return L.Params(_ptr(p), _ptr(m_dev))
+
+    # ---- calls ------------------------------------------------------------------
+    def erbf_eval(self, p, m_dev, f_out=None, stats=False, stream=None):
+        if f_out is None:
+            f_out = torch.zeros(self.n_points, dtype=torch.float32, device=self.device)
+        pr = self._params(p, m_dev)
+        L.check(self.lib.erbf_eval(self.handle, ctypes.byref(pr), _ptr(f_out),
+                                   _ptr(self.stats_buf) if stats else None, _stream(stream)))
+        return f_out
+
+    def erbf_loss_grad(self, p, m_dev, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
+                       tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None, G_out=None,
+                       stream=None):
+        if grad_out is None:
+            grad_out = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        pr = self._params(p, m_dev)
+        cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
+                        float(tau2), float(tau_m))
+        L.check(self.lib.erbf_loss_grad(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(grad_out),
+                                        _ptr(self.stats_buf), _ptr(f_out), _ptr(G_out), _stream(stream)))
+        return grad_out
+
+    def erbf_vjp(self, p, m_dev, grad_f, grad_out=None, stats=False, stream=None):
+        if grad_out is None:
+            grad_out = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        if grad_f.dtype != torch.float32 or grad_f.numel() != self.n_points:
+            raise ValueError("grad_f must be float32 [n_points]")
+        pr = self._params(p, m_dev)
+        L.check(self.lib.erbf_vjp(self.handle, ctypes.byref(pr), _ptr(grad_f), _ptr(grad_out),
+                                  _ptr(self.stats_buf) if stats else None, _stream(stream)))
+        return grad_out
+
+    def erbf_adam_step(self, p, m_dev, grad, m1, m2, step_dev, lr=1e-3, lr_dev=None, beta1=0.9,
+                       beta2=0.999, eps=1e-8, stream=None):
+        pr = self._params(p, m_dev)
+        cfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps))
+        L.check(self.lib.erbf_adam_step(self.handle, ctypes.byref(pr), _ptr(grad), _ptr(m1), _ptr(m2),
+                                        _ptr(step_dev), ctypes.byref(cfg), _stream(stream)))
+
+    def erbf_seed_from_error(self, p, m_dev, shape, resid, resid_scale, n_idall, top_frac=0.01,
+                             k_new=256, r_nms=0.0, eps=1e-7, min_abs_err=0.0, w_rule=0, m1=None, m2=None,
+                             stream=None):
+        pr = self._params(p, m_dev)
+        cfg = L.SeedCfg(float(top_frac), int(k_new), float(r_nms), float(eps), float(min_abs_err), int(w_rule))
+        n_added = ctypes.c_int32(0)
+        L.check(self.lib.erbf_seed_from_error(self.handle, ctypes.byref(pr), int(shape), _ptr(resid),
+                                              float(resid_scale), int(n_idall), ctypes.byref(cfg), _ptr(m1),
+                                              _ptr(m2), ctypes.byref(n_added), _stream(stream)))
+        return n_added.value
+
+    def stats(self) -> List[StatsView]:
+        return parse_stats(self.stats_buf, self.n_shapes)
+
+
+# ---- data preparation ---------------------------------------------------------
+
+def erbf_sdf_min(S: torch.Tensor, out: torch.Tensor, accumulate: bool, stream=None):
+    L.check(L.load().erbf_sdf_min(_ptr(S), S.numel(), _ptr(out), int(bool(accumulate)), _stream(stream)))
+
+
+def erbf_targets_from_sdf(S: torch.Tensor, m: float, t: torch.Tensor = None, stream=None):
+    if t is None:
+        t = torch.empty_like(S)
+    L.check(L.load().erbf_targets_from_sdf(_ptr(S), S.numel(), float(m), _ptr(t), _stream(stream)))
+    return t
+
+
+def erbf_band_bits(S: torch.Tensor, band: float, bits: torch.Tensor = None, stream=None):
+    if bits is None:
+        bits = torch.empty((S.numel() + 31) // 32, dtype=torch.int32, device=S.device)
+    L.check(L.load().erbf_band_bits(_ptr(S), S.numel(), float(band), _ptr(bits), _stream(stream)))
+    return bits

@@ -1,0 +1,441 @@
+// C ABI layer: context, workspace layout, argument checks and call sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "erbf.h"
+#include "erbf_internal.h"
+#include "erbf_launch.h"
+
+using namespace erbf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(ERBF_ERR_HIP, std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+#define HIP_TRY(expr, where)                   \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  int n_levels_total = 0;
+  int cap_total = 0;
+  int tiles_total = 0;
+  int max_level_tiles = 0;
+  int64_t pts_total = 0;
+  int64_t cand_cap = 0;
+  int scan_blocks = 0;
+  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_cnt, off_tile_start,
+      off_cursor, off_items_raw, off_items, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_kstat,
+      off_counters, off_hist, off_cand, off_keep, off_misc;
+  size_t bytes = 0;
+};
+
+int validate_config(const erbf_config* cfg) {
+  if (!cfg) return fail(ERBF_ERR_INVALID_ARG, "config is NULL");
+  if (cfg->n_shapes < 1 || cfg->n_shapes > ERBF_MAX_SHAPES)
+    return fail(ERBF_ERR_INVALID_ARG, "n_shapes out of range");
+  if (!cfg->shapes) return fail(ERBF_ERR_INVALID_ARG, "shapes is NULL");
+  if (!(cfg->cull_k > 0.f) || !std::isfinite(cfg->cull_k)) return fail(ERBF_ERR_INVALID_ARG, "cull_k must be > 0");
+  if (cfg->weight_map != ERBF_WEIGHT_SIGNED_SQUARE && cfg->weight_map != ERBF_WEIGHT_LINEAR)
+    return fail(ERBF_ERR_INVALID_ARG, "unknown weight_map");
+  if (cfg->pair_cap < 1 || cfg->pair_cap > (int64_t)INT32_MAX)
+    return fail(ERBF_ERR_INVALID_ARG, "pair_cap must be in [1, 2^31)");
+  int64_t cap = 0, tiles = 0;
+  for (int b = 0; b < cfg->n_shapes; ++b) {
+    const erbf_shape_desc& s = cfg->shapes[b];
+    if (s.n_levels < 1 || s.n_levels > ERBF_MAX_LEVELS) return fail(ERBF_ERR_INVALID_ARG, "n_levels out of range");
+    if (s.m_cap < 1) return fail(ERBF_ERR_INVALID_ARG, "m_cap must be >= 1");
+    cap += s.m_cap;
+    for (int l = 0; l < s.n_levels; ++l) {
+      const int n = s.level_n[l];
+      if (n < 1 || n > 2048) return fail(ERBF_ERR_INVALID_ARG, "level_n out of range");
+      const int64_t nt = (n + kTile - 1) / kTile;
+      tiles += nt * nt * nt;
+    }
+  }
+  if (cap > (int64_t)INT32_MAX / 16) return fail(ERBF_ERR_INVALID_ARG, "total kernel capacity too large");
+  if (tiles > (int64_t)INT32_MAX / 4) return fail(ERBF_ERR_INVALID_ARG, "too many tiles");
+  return ERBF_OK;
+}
+
+Layout make_layout(const erbf_config* cfg) {
+  Layout L;
+  for (int b = 0; b < cfg->n_shapes; ++b) {
+    const erbf_shape_desc& s = cfg->shapes[b];
+    L.cap_total += s.m_cap;
+    L.n_levels_total += s.n_levels;
+    for (int l = 0; l < s.n_levels; ++l) {
+      const int n = s.level_n[l];
+      const int nt = (n + kTile - 1) / kTile;
+      L.tiles_total += nt * nt * nt;
+      L.max_level_tiles = std::max(L.max_level_tiles, nt * nt * nt);
+      L.pts_total += (int64_t)n * n * n;
+    }
+  }
+  L.cand_cap = L.pts_total / 20 + 1024;
+  L.scan_blocks = (L.tiles_total + 1) / 1024 + 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  L.off_levels = take(sizeof(LevelDev) * L.n_levels_total);
+  L.off_shapes = take(sizeof(ShapeDev) * cfg->n_shapes);
+  L.off_kshape = take(sizeof(int32_t) * L.cap_total);
+  L.off_slot_tile = take(sizeof(int2) * L.tiles_total);
+  L.off_tile_map = take(sizeof(int32_t) * L.tiles_total);
+  L.off_tile_cnt = take(sizeof(int32_t) * (L.tiles_total + 1));
+  L.off_tile_start = take(sizeof(int32_t) * (L.tiles_total + 1));
+  L.off_cursor = take(sizeof(int32_t) * L.tiles_total);
+  L.off_items_raw = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_scan = take(sizeof(int32_t) * L.scan_blocks);
+  L.off_rflags = take(sizeof(int32_t) * (L.max_level_tiles + 1));
+  L.off_rexcl = take(sizeof(int32_t) * (L.max_level_tiles + 1));
+  L.off_rec = take(sizeof(float4) * 3 * L.cap_total);
+  L.off_G = take(sizeof(float) * L.pts_total);
+  L.off_tstat = take(sizeof(TileStat) * L.tiles_total);
+  L.off_kstat = take(sizeof(KernStat) * L.cap_total);
+  L.off_counters = take(sizeof(int64_t) * 8);
+  L.off_hist = take(sizeof(uint32_t) * 65536);
+  L.off_cand = take(sizeof(int64_t) * L.cand_cap);
+  L.off_keep = take(sizeof(int64_t) * L.cand_cap);
+  L.off_misc = take(sizeof(int32_t) * 64);
+  L.bytes = o;
+  return L;
+}
+
+}  // namespace
+
+struct erbf_ctx {
+  int device = 0;
+  erbf_config cfg{};
+  std::vector<erbf_shape_desc> shape_desc;
+  Layout lay;
+  Dev D{};
+  std::vector<LevelDev> lv;
+  std::vector<ShapeDev> sh;
+  int slots_used = 0;
+  int32_t* rflags = nullptr;
+  int32_t* rexcl = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_params(const erbf_ctx* ctx, const erbf_params* p) {
+  if (!ctx) return fail(ERBF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!p || !p->p || !p->m_dev) return fail(ERBF_ERR_INVALID_ARG, "params (p, m_dev) must be non-NULL");
+  if (ctx->slots_used <= 0) return fail(ERBF_ERR_STATE, "no grid level registered (call erbf_refine_level)");
+  return ERBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t erbf_abi_version(void) { return ERBF_ABI_VERSION; }
+
+const char* erbf_last_error(void) { return g_last_error.c_str(); }
+
+int erbf_workspace_size(const erbf_config* cfg, size_t* bytes) {
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  if (!bytes) return fail(ERBF_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = make_layout(cfg).bytes;
+  return ERBF_OK;
+}
+
+int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t bytes, erbf_ctx** out) {
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  if (!out) return fail(ERBF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!workspace) return fail(ERBF_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(ERBF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Layout lay = make_layout(cfg);
+  if (bytes < lay.bytes)
+    return fail(ERBF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(lay.bytes) + " bytes");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(ERBF_ERR_INVALID_ARG, "bad device index");
+  DeviceGuard guard(device);
+
+  erbf_ctx* c = new (std::nothrow) erbf_ctx();
+  if (!c) return fail(ERBF_ERR_INVALID_ARG, "out of host memory");
+  c->device = device;
+  c->cfg = *cfg;
+  c->shape_desc.assign(cfg->shapes, cfg->shapes + cfg->n_shapes);
+  c->cfg.shapes = c->shape_desc.data();
+  c->lay = lay;
+  char* w = static_cast<char*>(workspace);
+  Dev& D = c->D;
+  D.levels = reinterpret_cast<LevelDev*>(w + lay.off_levels);
+  D.shapes = reinterpret_cast<ShapeDev*>(w + lay.off_shapes);
+  D.kshape = reinterpret_cast<int32_t*>(w + lay.off_kshape);
+  D.slot_tile = reinterpret_cast<int2*>(w + lay.off_slot_tile);
+  D.tile_map = reinterpret_cast<int32_t*>(w + lay.off_tile_map);
+  D.tile_cnt = reinterpret_cast<int32_t*>(w + lay.off_tile_cnt);
+  D.tile_start = reinterpret_cast<int32_t*>(w + lay.off_tile_start);
+  D.cursor = reinterpret_cast<int32_t*>(w + lay.off_cursor);
+  D.items_raw = reinterpret_cast<int32_t*>(w + lay.off_items_raw);
+  D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
+  D.scan_blocks = reinterpret_cast<int32_t*>(w + lay.off_scan);
+  c->rflags = reinterpret_cast<int32_t*>(w + lay.off_rflags);
+  c->rexcl = reinterpret_cast<int32_t*>(w + lay.off_rexcl);
+  D.rec = reinterpret_cast<float4*>(w + lay.off_rec);
+  D.G = reinterpret_cast<float*>(w + lay.off_G);
+  D.tstat = reinterpret_cast<TileStat*>(w + lay.off_tstat);
+  D.kstat = reinterpret_cast<KernStat*>(w + lay.off_kstat);
+  D.counters = reinterpret_cast<int64_t*>(w + lay.off_counters);
+  D.seed_hist = reinterpret_cast<uint32_t*>(w + lay.off_hist);
+  D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
+  D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);
+  D.seed_misc = reinterpret_cast<int32_t*>(w + lay.off_misc);
+  D.cand_cap = lay.cand_cap;
+  D.pair_cap = cfg->pair_cap;
+  D.cap_total = lay.cap_total;
+  D.tiles_total = lay.tiles_total;
+  D.n_shapes = cfg->n_shapes;
+  D.cull_k = cfg->cull_k;
+  D.weight_map = cfg->weight_map;
+
+  // host mirrors of the level and shape tables
+  std::vector<int32_t> kshape(lay.cap_total);
+  int kbase = 0, tmap = 0, li = 0;
+  int64_t pbase = 0;
+  for (int b = 0; b < cfg->n_shapes; ++b) {
+    const erbf_shape_desc& s = cfg->shapes[b];
+    ShapeDev sd{};
+    sd.kbase = kbase;
+    sd.cap = s.m_cap;
+    sd.lvl0 = li;
+    sd.n_active = 0;
+    sd.slot0 = 0;
+    sd.n_slots = 0;
+    sd.pt_base = pbase;
+    for (int l = 0; l < s.n_levels; ++l, ++li) {
+      LevelDev L{};
+      L.n = s.level_n[l];
+      L.nt = (L.n + kTile - 1) / kTile;
+      L.shape = b;
+      L.slot0 = 0;
+      L.n_slots = 0;
+      L.tmap0 = tmap;
+      L.pt_base = pbase;
+      L.h = 2.0f / (float)L.n;
+      L.lo = -1.0f + 1.0f / (float)L.n;
+      c->lv.push_back(L);
+      tmap += L.nt * L.nt * L.nt;
+      pbase += (int64_t)L.n * L.n * L.n;
+    }
+    sd.n_pts = pbase - sd.pt_base;
+    for (int k = 0; k < s.m_cap; ++k) kshape[kbase + k] = b;
+    kbase += s.m_cap;
+    c->sh.push_back(sd);
+  }
+  hipError_t e = hipMemcpy(D.levels, c->lv.data(), sizeof(LevelDev) * c->lv.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(D.shapes, c->sh.data(), sizeof(ShapeDev) * c->sh.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(D.kshape, kshape.data(), sizeof(int32_t) * kshape.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_fill_i32(D.tile_map, lay.tiles_total, -1, nullptr);
+  if (e == hipSuccess) e = launch_fill_f32(D.G, lay.pts_total, 0.f, nullptr);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(D.counters), 16, 0, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "erbf_ctx_create");
+  }
+  *out = c;
+  return ERBF_OK;
+}
+
+void erbf_ctx_destroy(erbf_ctx* ctx) { delete ctx; }
+
+int erbf_ctx_info(const erbf_ctx* ctx, int32_t* cap_total, int64_t* n_points, int32_t* n_active0) {
+  if (!ctx) return fail(ERBF_ERR_INVALID_ARG, "ctx is NULL");
+  if (cap_total) *cap_total = ctx->lay.cap_total;
+  if (n_points) *n_points = ctx->lay.pts_total;
+  if (n_active0) *n_active0 = ctx->sh[0].n_active;
+  return ERBF_OK;
+}
+
+int erbf_sdf_min(const float* S, int64_t n, float* out_dev, int accumulate, hipStream_t stream) {
+  if (!S || !out_dev || n < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_sdf_min: bad arguments");
+  // the ordered-integer key lives in the output word itself
+  HIP_TRY(launch_sdf_min(S, n, out_dev, accumulate, reinterpret_cast<int*>(out_dev), stream), "erbf_sdf_min");
+  return ERBF_OK;
+}
+
+int erbf_targets_from_sdf(const float* S, int64_t n, float m, float* t, hipStream_t stream) {
+  if (!S || !t || n < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_targets_from_sdf: bad arguments");
+  if (!(m < 0.f)) return fail(ERBF_ERR_INVALID_ARG, "eq. 3-10 needs a negative minimum signed distance");
+  HIP_TRY(launch_targets(S, n, m, t, stream), "erbf_targets_from_sdf");
+  return ERBF_OK;
+}
+
+int erbf_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t stream) {
+  if (!S || !bits || n < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_band_bits: bad arguments");
+  HIP_TRY(launch_band_bits(S, n, band, bits, stream), "erbf_band_bits");
+  return ERBF_OK;
+}
+
+int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hipStream_t stream) {
+  if (!ctx || !level) return fail(ERBF_ERR_INVALID_ARG, "ctx and level must be non-NULL");
+  if (shape < 0 || shape >= ctx->cfg.n_shapes) return fail(ERBF_ERR_INVALID_ARG, "shape out of range");
+  ShapeDev& sd = ctx->sh[shape];
+  const erbf_shape_desc& desc = ctx->shape_desc[shape];
+  if (sd.n_active >= desc.n_levels) return fail(ERBF_ERR_STATE, "all declared levels already registered");
+  const int li = sd.lvl0 + sd.n_active;
+  LevelDev& L = ctx->lv[li];
+  if (level->n != L.n) return fail(ERBF_ERR_INVALID_ARG, "level n differs from the declared level_n");
+  if (!level->axis) return fail(ERBF_ERR_INVALID_ARG, "level axis is NULL");
+  DeviceGuard guard(ctx->device);
+  Dev& D = ctx->D;
+  L.axis = level->axis;
+  L.target = level->target;
+  L.sdf = level->sdf;
+  L.bits = level->active_bits;
+  HIP_TRY(hipMemcpy(&D.levels[li], &L, sizeof(LevelDev), hipMemcpyHostToDevice), "refine: level table");
+  const int ntt = L.nt * L.nt * L.nt;
+  HIP_TRY(launch_tile_flags(D, li, ntt, ctx->rflags, stream), "refine: tile flags");
+  HIP_TRY(launch_scan(ctx->rflags, ntt, D.scan_blocks, ctx->rexcl, D.counters + 1, stream), "refine: scan");
+  HIP_TRY(launch_tile_assign(D, li, ntt, ctx->rflags, ctx->rexcl, ctx->slots_used, stream), "refine: assign");
+  HIP_TRY(launch_fill_f32(D.G + L.pt_base, (int64_t)L.n * L.n * L.n, 0.f, stream), "refine: clear G");
+  int64_t n_act = 0;
+  HIP_TRY(hipMemcpyAsync(&n_act, D.counters + 1, sizeof(int64_t), hipMemcpyDeviceToHost, stream), "refine: count");
+  HIP_TRY(hipStreamSynchronize(stream), "refine: sync");
+  L.slot0 = ctx->slots_used;
+  L.n_slots = (int32_t)n_act;
+  ctx->slots_used += (int32_t)n_act;
+  sd.n_active += 1;
+  if (sd.n_active == 1) sd.slot0 = L.slot0;
+  sd.n_slots += L.n_slots;
+  HIP_TRY(hipMemcpy(&D.levels[li], &L, sizeof(LevelDev), hipMemcpyHostToDevice), "refine: level table");
+  HIP_TRY(hipMemcpy(&D.shapes[shape], &sd, sizeof(ShapeDev), hipMemcpyHostToDevice), "refine: shape table");
+  return ERBF_OK;
+}
+
+int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats* stats_dev, hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!f_out) return fail(ERBF_ERR_INVALID_ARG, "f_out is NULL");
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  for (const ShapeDev& s : ctx->sh)
+    for (int l = 0; l < s.n_active; ++l) {
+      const LevelDev& L = ctx->lv[s.lvl0 + l];
+      if (L.bits) HIP_TRY(launch_fill_f32(f_out + L.pt_base, (int64_t)L.n * L.n * L.n, 0.f, stream), "eval: clear");
+    }
+  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "eval: prologue");
+  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "eval: buckets");
+  HIP_TRY(launch_forward(D, ctx->slots_used, false, f_out, 0.f, 0.f, stream), "eval: forward");
+  if (stats_dev) {
+    StatsArgs a{};
+    HIP_TRY(launch_stats(D, 0, params->p, params->m_dev, nullptr, stats_dev, a, stream), "eval: stats");
+  }
+  return ERBF_OK;
+}
+
+int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!cfg || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "cfg and grad_out must be non-NULL");
+  if (cfg->mode < ERBF_MODE_FIXED || cfg->mode > ERBF_MODE_L2) return fail(ERBF_ERR_INVALID_ARG, "unknown mode");
+  for (const ShapeDev& s : ctx->sh)
+    for (int l = 0; l < s.n_active; ++l)
+      if (!ctx->lv[s.lvl0 + l].target) return fail(ERBF_ERR_INVALID_ARG, "a registered level has no target");
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  if (f_out)
+    for (const ShapeDev& s : ctx->sh)
+      for (int l = 0; l < s.n_active; ++l) {
+        const LevelDev& L = ctx->lv[s.lvl0 + l];
+        if (L.bits) HIP_TRY(launch_fill_f32(f_out + L.pt_base, (int64_t)L.n * L.n * L.n, 0.f, stream), "loss: clear");
+      }
+  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "loss: prologue");
+  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "loss: buckets");
+  HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, stream), "loss: forward");
+  HIP_TRY(launch_backward(D, params->p, D.G, grad_out, stream), "loss: backward");
+  StatsArgs a{};
+  a.mode = cfg->mode;
+  a.lambda = cfg->lambda;
+  a.lambda_dev = cfg->lambda_dev;
+  a.l1_active = cfg->l1_active;
+  a.tau_m = cfg->tau_m;
+  HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream), "loss: stats");
+  if (G_out)
+    HIP_TRY(hipMemcpyAsync(G_out, D.G, sizeof(float) * ctx->lay.pts_total, hipMemcpyDeviceToDevice, stream),
+            "loss: copy G");
+  return ERBF_OK;
+}
+
+int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, float* grad_out, erbf_stats* stats_dev,
+             hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!grad_f || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "grad_f and grad_out must be non-NULL");
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "vjp: prologue");
+  for (const ShapeDev& s : ctx->sh)
+    for (int l = 0; l < s.n_active; ++l) {
+      const LevelDev& L = ctx->lv[s.lvl0 + l];
+      HIP_TRY(launch_mask_copy(D, s.lvl0 + l, (int64_t)L.n * L.n * L.n, grad_f, stream), "vjp: mask");
+    }
+  HIP_TRY(launch_backward(D, params->p, D.G, grad_out, stream), "vjp: backward");
+  if (stats_dev) {
+    StatsArgs a{};
+    HIP_TRY(launch_stats(D, 1, params->p, params->m_dev, grad_out, stats_dev, a, stream), "vjp: stats");
+  }
+  return ERBF_OK;
+}
+
+int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, float* m1, float* m2,
+                   int32_t* step_dev, const erbf_adam_cfg* cfg, hipStream_t stream) {
+  if (!ctx || !params || !params->p || !params->m_dev || !grad || !m1 || !m2 || !step_dev || !cfg)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_adam_step: NULL argument");
+  if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f))
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_adam_step: bad hyper-parameters");
+  DeviceGuard guard(ctx->device);
+  AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps};
+  HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad, m1, m2, step_dev, a, stream), "adam");
+  return ERBF_OK;
+}
+
+int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape, const float* resid,
+                         float resid_scale, int64_t n_idall, const erbf_seed_cfg* cfg, float* m1, float* m2,
+                         int32_t* n_added, hipStream_t stream) {
+  (void)ctx; (void)params; (void)shape; (void)resid; (void)resid_scale; (void)n_idall; (void)cfg;
+  (void)m1; (void)m2; (void)n_added; (void)stream;
+  return fail(ERBF_ERR_UNSUPPORTED, "seeding not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal device tables and kernel launch declarations of the ERBF library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "erbf.h"
+
+namespace erbf {
+
+constexpr int kTile = 8;            // grid points per tile edge (tile = 8^3 points)
+constexpr int kRecF4 = 3;           // float4 per kernel record
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Per-level table entry, mirrored on the device.
+struct LevelDev {
+  int32_t n, nt;            // points / tiles per axis
+  int32_t shape;            // owning shape
+  int32_t slot0;            // first active-tile slot of this level
+  int32_t n_slots;          // active tiles
+  int32_t tmap0;            // offset of this level's tile map (nt^3 int32)
+  int64_t pt_base;          // offset of this level in per-point arrays
+  float lo, h;              // axis[0] and nominal spacing 2/n (used for index ranges only)
+  const float* axis;
+  const float* target;
+  const float* sdf;
+  const uint32_t* bits;
+};
+
+// Per-shape table entry, mirrored on the device.
+struct ShapeDev {
+  int32_t kbase, cap;       // kernel slot range
+  int32_t lvl0;             // first level-table index
+  int32_t n_active;         // active levels
+  int32_t slot0, n_slots;   // active-tile slot range over the active levels
+  int64_t pt_base, n_pts;   // per-point range over the active levels
+};
+
+// Partial statistics of one forward tile.
+struct TileStat {
+  double l2;
+  float max_abs_e;
+  int32_t n_idall;
+};
+
+// Per-kernel counters written by the backward pass.
+struct KernStat {
+  int64_t p_fwd;
+  int64_t p_bwd;
+};
+
+// Launch plumbing shared by the .hip translation units.
+struct Dev {
+  // tables
+  LevelDev* levels;         // [n_levels_total]
+  ShapeDev* shapes;         // [n_shapes]
+  int32_t* kshape;          // [cap_total] shape of each kernel slot
+  int2* slot_tile;          // [tiles_total] (level index, tile linear id) per active slot
+  int32_t* tile_map;        // [tiles_total] slot of each tile or -1
+  // buckets
+  int32_t* tile_cnt;        // [tiles_total + 1]
+  int32_t* tile_start;      // [tiles_total + 1]
+  int32_t* cursor;          // [tiles_total]
+  int32_t* items_raw;       // [pair_cap]
+  int32_t* items;           // [pair_cap]
+  int32_t* scan_blocks;     // [scan block sums]
+  // per step
+  float4* rec;              // [3 * cap_total]
+  float* G;                 // [pts_total]
+  TileStat* tstat;          // [tiles_total]
+  KernStat* kstat;          // [cap_total]
+  int64_t* counters;        // [8]: 0 bucket total
+  // seeding scratch
+  uint32_t* seed_hist;      // [65536]
+  int64_t* seed_cand;       // [cand_cap]
+  int64_t* seed_keep;       // [cand_cap]
+  int32_t* seed_misc;       // [64]
+  int64_t cand_cap;
+  int64_t pair_cap;
+  int32_t cap_total;
+  int32_t tiles_total;
+  int32_t n_shapes;
+  float cull_k;
+  int32_t weight_map;
+};
+
+}  // namespace erbf

@@ -1,0 +1,1020 @@
+// HIP kernels of the ERBF-fit step for gfx950 (CDNA4, wave64).
+//
+//   prologue   per-kernel record: centre, squared cull radius, log2(e)-scaled
+//              quadric A = R^T diag(d^2) R, amplitude (eq. 3-7, 3-26, 3-15)
+//   bucket     tile -> kernel lists: count, exclusive scan, scatter, per-tile sort
+//   forward    point-centric gather over the tile's kernel list staged in LDS,
+//              fused residual / id_all mask / loss partials (eq. 3-9, 3-15-1,
+//              3-18, 3-19)
+//   backward   kernel-centric: one workgroup walks the rows of its own ball,
+//              10 FP64 moment accumulators, fixed-order wave/LDS reductions,
+//              no float atomics (Appendix A with a quaternion chain rule)
+//   stats      per-shape loss statistics, eq. 3-21 weights, gradient combine
+//   adam       fused bias-corrected Adam over the packed parameters
+//
+// Every reduction runs in a fixed order, so results are bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "erbf_internal.h"
+#include "erbf_launch.h"
+
+namespace erbf {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Conservative index range of the points whose coordinate may lie in
+// [c0, c1] on a level (the exact predicate is applied afterwards).
+__device__ __forceinline__ void index_range(const LevelDev& L, float c0, float c1, int& i0, int& i1) {
+  float f0 = (c0 - L.lo) / L.h;
+  float f1 = (c1 - L.lo) / L.h;
+  f0 = fminf(fmaxf(f0, -2.0f), (float)L.n + 2.0f);
+  f1 = fminf(fmaxf(f1, -2.0f), (float)L.n + 2.0f);
+  i0 = max(0, (int)floorf(f0) - 1);
+  i1 = min(L.n - 1, (int)ceilf(f1) + 1);
+}
+
+__device__ __forceinline__ bool point_active(const uint32_t* bits, int64_t local) {
+  if (bits == nullptr) return true;
+  return (bits[local >> 5] >> (local & 31)) & 1u;
+}
+
+// Number of set bits of `bits` in [b0, b1] (inclusive), b0 <= b1.
+__device__ __forceinline__ int popcount_range(const uint32_t* bits, int64_t b0, int64_t b1) {
+  int64_t w0 = b0 >> 5, w1 = b1 >> 5;
+  int c = 0;
+  for (int64_t w = w0; w <= w1; ++w) {
+    uint32_t v = bits[w];
+    if (w == w0) v &= 0xffffffffu << (b0 & 31);
+    if (w == w1) v &= 0xffffffffu >> (31 - (b1 & 31));
+    c += __popc(v);
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// prologue: one thread per kernel slot
+// record: r0 = {cx, cy, cz, r^2}  (r^2 < 0 marks a dead slot)
+//         r1 = {A00, A11, A22, 2 A01}  r2 = {2 A02, 2 A12, a, 0}, A scaled by log2(e)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
+                                                  const int32_t* __restrict__ m_dev, Dev D) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.cap_total) return;
+  const int b = D.kshape[j];
+  const ShapeDev S = D.shapes[b];
+  const int m = min(max(m_dev[b], 0), S.cap);
+  float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f);
+  float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (j - S.kbase < m) {
+    const int C = D.cap_total;
+    const float w = p[j];
+    const float cx = p[C + j], cy = p[2 * C + j], cz = p[3 * C + j];
+    const float s0 = p[4 * C + j], s1 = p[5 * C + j], s2 = p[6 * C + j];
+    float qw = p[7 * C + j], qx = p[8 * C + j], qy = p[9 * C + j], qz = p[10 * C + j];
+    const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
+    if (qn2 > 0.f) {
+      const float inv = 1.0f / sqrtf(qn2);
+      qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+    } else {
+      qw = 1.f; qx = qy = qz = 0.f;
+    }
+    float R[3][3];
+    R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
+    R[0][1] = 2.f * (qx * qy - qw * qz);
+    R[0][2] = 2.f * (qx * qz + qw * qy);
+    R[1][0] = 2.f * (qx * qy + qw * qz);
+    R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
+    R[1][2] = 2.f * (qy * qz - qw * qx);
+    R[2][0] = 2.f * (qx * qz - qw * qy);
+    R[2][1] = 2.f * (qy * qz + qw * qx);
+    R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+    const float d2[3] = {expf(2.f * s0), expf(2.f * s1), expf(2.f * s2)};
+    float A[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        A[a][c] = R[0][a] * d2[0] * R[0][c] + R[1][a] * d2[1] * R[1][c] + R[2][a] * d2[2] * R[2][c];
+    const float smin = fminf(s0, fminf(s1, s2));
+    const float r = D.cull_k / expf(smin);
+    const float amp = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? w * fabsf(w) : w;
+    r0 = make_float4(cx, cy, cz, r * r);
+    r1 = make_float4(A[0][0] * kLog2e, A[1][1] * kLog2e, A[2][2] * kLog2e, 2.f * A[0][1] * kLog2e);
+    r2 = make_float4(2.f * A[0][2] * kLog2e, 2.f * A[1][2] * kLog2e, amp, 0.f);
+  }
+  D.rec[3 * j + 0] = r0;
+  D.rec[3 * j + 1] = r1;
+  D.rec[3 * j + 2] = r2;
+}
+
+// ---------------------------------------------------------------------------
+// buckets: tiles whose point box meets the (slightly enlarged) ball
+// ---------------------------------------------------------------------------
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_bucket(Dev D) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.cap_total) return;
+  const float4 r0 = D.rec[3 * j];
+  if (r0.w < 0.f) return;
+  const ShapeDev S = D.shapes[D.kshape[j]];
+  const float rr = sqrtf(r0.w) * (1.0f + 1e-5f) + 1e-6f;
+  const float rc2 = rr * rr;
+  for (int li = 0; li < S.n_active; ++li) {
+    const LevelDev L = D.levels[S.lvl0 + li];
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    index_range(L, r0.x - rr, r0.x + rr, ix0, ix1);
+    index_range(L, r0.y - rr, r0.y + rr, iy0, iy1);
+    index_range(L, r0.z - rr, r0.z + rr, iz0, iz1);
+    if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
+    const int nt = L.nt, n = L.n;
+    for (int tz = iz0 / kTile; tz <= iz1 / kTile; ++tz) {
+      const float zlo = L.axis[tz * kTile], zhi = L.axis[min(tz * kTile + kTile - 1, n - 1)];
+      const float ez = fmaxf(fmaxf(zlo - r0.z, r0.z - zhi), 0.f);
+      for (int ty = iy0 / kTile; ty <= iy1 / kTile; ++ty) {
+        const float ylo = L.axis[ty * kTile], yhi = L.axis[min(ty * kTile + kTile - 1, n - 1)];
+        const float ey = fmaxf(fmaxf(ylo - r0.y, r0.y - yhi), 0.f);
+        const float eyz = ey * ey + ez * ez;
+        if (eyz >= rc2) continue;
+        for (int tx = ix0 / kTile; tx <= ix1 / kTile; ++tx) {
+          const float xlo = L.axis[tx * kTile], xhi = L.axis[min(tx * kTile + kTile - 1, n - 1)];
+          const float ex = fmaxf(fmaxf(xlo - r0.x, r0.x - xhi), 0.f);
+          if (ex * ex + eyz >= rc2) continue;
+          const int slot = D.tile_map[L.tmap0 + (tz * nt + ty) * nt + tx];
+          if (slot < 0) continue;
+          if (SCATTER) {
+            const int pos = atomicAdd(&D.cursor[slot], 1);
+            const int64_t at = (int64_t)D.tile_start[slot] + pos;
+            if (at < D.pair_cap) D.items_raw[at] = j;
+          } else {
+            atomicAdd(&D.tile_cnt[slot], 1);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Per-tile ascending sort of the bucket list (fixes the summation order).
+__global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
+  __shared__ int buf[4096];
+  const int s = blockIdx.x;
+  const int64_t beg = min((int64_t)D.tile_start[s], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[s + 1], D.pair_cap);
+  const int cnt = (int)(end - beg);
+  const int tid = threadIdx.x;
+  if (cnt <= 0) return;
+  if (cnt <= 4096) {
+    int pw = 1;
+    while (pw < cnt) pw <<= 1;
+    for (int i = tid; i < pw; i += blockDim.x) buf[i] = i < cnt ? D.items_raw[beg + i] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= pw; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = tid; i < pw; i += blockDim.x) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const int a = buf[i], bb = buf[ixj];
+            const bool up = (i & k) == 0;
+            if ((a > bb) == up) { buf[i] = bb; buf[ixj] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = tid; i < cnt; i += blockDim.x) D.items[beg + i] = buf[i];
+  } else {
+    // long list: rank of each (distinct) kernel id
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const int v = D.items_raw[beg + i];
+      int rank = 0;
+      for (int k = 0; k < cnt; ++k) rank += D.items_raw[beg + k] < v;
+      D.items[beg + rank] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts (three passes, 1024 elements per block)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int& total) {
+  // 1024 threads, 16 waves
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int s = lane < 16 ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) sh[16 + lane] = s;
+  }
+  __syncthreads();
+  total = sh[31];
+  const int wbase = wv > 0 ? sh[16 + wv - 1] : 0;
+  const int r = wbase + x - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_reduce(const int32_t* __restrict__ in, int n,
+                                                      int32_t* __restrict__ blocks) {
+  __shared__ int sh[32];
+  const int i = blockIdx.x * 1024 + threadIdx.x;
+  int total;
+  block_excl_scan_1024(i < n ? in[i] : 0, sh, total);
+  if (threadIdx.x == 0) blocks[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blocks, int nb,
+                                                      int64_t* __restrict__ total_out) {
+  __shared__ int sh[32];
+  int carry = 0;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? blocks[i] : 0;
+    int total;
+    const int e = block_excl_scan_1024(v, sh, total);
+    if (i < nb) blocks[i] = carry + e;
+    carry += total;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ in, int n,
+                                                    const int32_t* __restrict__ blocks,
+                                                    int32_t* __restrict__ out) {
+  __shared__ int sh[32];
+  const int i = blockIdx.x * 1024 + threadIdx.x;
+  int total;
+  const int e = block_excl_scan_1024(i < n ? in[i] : 0, sh, total);
+  if (i <= n) out[i] = blocks[blockIdx.x] + e;  // out has n + 1 entries
+}
+
+// ---------------------------------------------------------------------------
+// forward: one workgroup (4 waves) per active tile of 8^3 points
+//   wave w covers x in [0,8), y in 4*(w&1)+[0,4), z in 4*(w>>1)+[0,4);
+//   lane l covers points x = 2*(l&3)+{0,1}, y += (l>>2)&3, z += l>>4.
+// ---------------------------------------------------------------------------
+
+constexpr int kFwdChunk = 256;
+
+template <bool LOSS>
+__global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_out,
+                                                 float tau1, float tau2) {
+  __shared__ float4 srec[kFwdChunk * 3];
+  __shared__ uint16_t slist[4][kFwdChunk];
+  __shared__ int scnt[4][4];
+  __shared__ double red_d[4];
+  __shared__ float red_f[4];
+  __shared__ int red_i[4];
+
+  const int slot = blockIdx.x;
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  const int n = L.n, nt = L.nt;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
+
+  const int xi0 = tx * kTile + 2 * (lane & 3);
+  const int yi = ty * kTile + 4 * (wv & 1) + ((lane >> 2) & 3);
+  const int zi = tz * kTile + 4 * (wv >> 1) + (lane >> 4);
+  const float px0 = L.axis[min(xi0, n - 1)];
+  const float px1 = L.axis[min(xi0 + 1, n - 1)];
+  const float py = L.axis[min(yi, n - 1)];
+  const float pz = L.axis[min(zi, n - 1)];
+
+  // bounding boxes of the four wave sub-tiles (each thread computes all four)
+  float bx0, bx1, by0[2], by1[2], bz0[2], bz1[2];
+  bx0 = L.axis[tx * kTile];
+  bx1 = L.axis[min(tx * kTile + kTile - 1, n - 1)];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    by0[h] = L.axis[min(ty * kTile + 4 * h, n - 1)];
+    by1[h] = L.axis[min(ty * kTile + 4 * h + 3, n - 1)];
+    bz0[h] = L.axis[min(tz * kTile + 4 * h, n - 1)];
+    bz1[h] = L.axis[min(tz * kTile + 4 * h + 3, n - 1)];
+  }
+
+  float acc0 = 0.f, acc1 = 0.f;
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+
+  for (int64_t c0 = beg; c0 < end; c0 += kFwdChunk) {
+    const int cnt = (int)min((int64_t)kFwdChunk, end - c0);
+    uint32_t mybits = 0;
+    if (tid < cnt) {
+      const int j = D.items[c0 + tid];
+      const float4 a0 = D.rec[3 * j], a1 = D.rec[3 * j + 1], a2 = D.rec[3 * j + 2];
+      srec[3 * tid] = a0;
+      srec[3 * tid + 1] = a1;
+      srec[3 * tid + 2] = a2;
+      const float rr = sqrtf(a0.w) * (1.0f + 1e-5f) + 1e-6f;
+      const float rc2 = rr * rr;
+      const float ex = fmaxf(fmaxf(bx0 - a0.x, a0.x - bx1), 0.f);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int hy = w & 1, hz = w >> 1;
+        const float ey = fmaxf(fmaxf(by0[hy] - a0.y, a0.y - by1[hy]), 0.f);
+        const float ez = fmaxf(fmaxf(bz0[hz] - a0.z, a0.z - bz1[hz]), 0.f);
+        if (ex * ex + ey * ey + ez * ez < rc2) mybits |= 1u << w;
+      }
+    }
+    // compact per-wave lists in chunk order
+    int prefix[4];
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const unsigned long long bal = __ballot((mybits >> w) & 1u);
+      prefix[w] = __popcll(bal & lt_mask);
+      if (lane == 0) scnt[w][wv] = __popcll(bal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if ((mybits >> w) & 1u) {
+        int off = prefix[w];
+        for (int v = 0; v < wv; ++v) off += scnt[w][v];
+        slist[w][off] = (uint16_t)tid;
+      }
+    }
+    __syncthreads();
+    const int len = scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3];
+    for (int k = 0; k < len; ++k) {
+      const int e = slist[wv][k];
+      const float4 a0 = srec[3 * e], a1 = srec[3 * e + 1], a2 = srec[3 * e + 2];
+      const float dy = py - a0.y, dz = pz - a0.z;
+      const float syz = fmaf(dy, dy, dz * dz);
+      const float bl = fmaf(a1.w, dy, a2.x * dz);
+      const float cc = fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz);
+      const float dx0 = px0 - a0.x, dx1 = px1 - a0.x;
+      float q0 = fmaf(dx0, fmaf(a1.x, dx0, bl), cc);
+      float q1 = fmaf(dx1, fmaf(a1.x, dx1, bl), cc);
+      q0 = fmaf(dx0, dx0, syz) < a0.w ? q0 : INFINITY;
+      q1 = fmaf(dx1, dx1, syz) < a0.w ? q1 : INFINITY;
+      acc0 = fmaf(a2.z, fast_exp2(-q0), acc0);
+      acc1 = fmaf(a2.z, fast_exp2(-q1), acc1);
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+  double l2 = 0.0;
+  float mxe = 0.f;
+  int cnt_id = 0;
+  const bool vyz = yi < n && zi < n;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int xi = xi0 + h;
+    if (!(vyz && xi < n)) continue;
+    const int64_t local = ((int64_t)zi * n + yi) * n + xi;
+    const int64_t idx = L.pt_base + local;
+    const bool act = point_active(L.bits, local);
+    const float f = act ? (h ? acc1 : acc0) : 0.f;
+    if (f_out) f_out[idx] = f;
+    if (LOSS) {
+      const float t = L.target[local];
+      const bool id0 = tau1 < t && t < tau2;
+      const bool id1 = t <= tau1 && f > tau1;
+      const bool id2 = t >= tau2 && f < tau2;
+      const bool in = act && (id0 || id1 || id2);
+      const float E = in ? f - t : 0.f;
+      D.G[idx] = 2.f * E;
+      l2 += (double)E * (double)E;
+      mxe = fmaxf(mxe, fabsf(E));
+      cnt_id += in ? 1 : 0;
+    }
+  }
+  if (LOSS) {
+    l2 = wave_sum(l2);
+    mxe = wave_max_f(mxe);
+    cnt_id = wave_sum(cnt_id);
+    if (lane == 0) { red_d[wv] = l2; red_f[wv] = mxe; red_i[wv] = cnt_id; }
+    __syncthreads();
+    if (tid == 0) {
+      TileStat ts;
+      ts.l2 = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+      ts.max_abs_e = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
+      ts.n_idall = red_i[0] + red_i[1] + red_i[2] + red_i[3];
+      D.tstat[slot] = ts;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward: one workgroup (4 waves) per kernel slot.  The ball's rows
+// (fixed y, z) are visited in 8x8 patches, one patch per wave and one row per
+// lane; each lane walks its row's exact in-ball x interval.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_reduce_doubles(double* v, int nv, double* sh /*[4*nv]*/) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = 0; i < nv; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[wv * nv + i] = s;
+  }
+  __syncthreads();
+  for (int i = 0; i < nv; ++i) v[i] = (sh[i] + sh[nv + i]) + (sh[2 * nv + i] + sh[3 * nv + i]);
+}
+
+template <bool COUNT_FWD>
+__global__ __launch_bounds__(256) void k_backward(Dev D, const float* __restrict__ p,
+                                                  const float* __restrict__ Gsrc,
+                                                  float* __restrict__ grad) {
+  __shared__ double sh[4 * 12];
+  const int j = blockIdx.x;
+  const int C = D.cap_total;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const float4 r0 = D.rec[3 * j];
+  if (r0.w < 0.f) {
+    if (tid < 11) grad[tid * C + j] = 0.f;
+    if (tid == 0) { D.kstat[j].p_fwd = 0; D.kstat[j].p_bwd = 0; }
+    return;
+  }
+  const float4 r1 = D.rec[3 * j + 1], r2 = D.rec[3 * j + 2];
+  const float cx = r0.x, cy = r0.y, cz = r0.z, rad2 = r0.w;
+  const float A00 = r1.x, A11 = r1.y, A22 = r1.z, A01x2 = r1.w, A02x2 = r2.x, A12x2 = r2.y;
+  const ShapeDev S = D.shapes[D.kshape[j]];
+  const float rr = sqrtf(rad2) * (1.0f + 1e-5f) + 1e-6f;
+
+  double T[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) T[i] = 0.0;
+  int64_t pf = 0, pb = 0;
+
+  for (int li = 0; li < S.n_active; ++li) {
+    const LevelDev L = D.levels[S.lvl0 + li];
+    const int n = L.n;
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    index_range(L, cx - rr, cx + rr, ix0, ix1);
+    index_range(L, cy - rr, cy + rr, iy0, iy1);
+    index_range(L, cz - rr, cz + rr, iz0, iz1);
+    if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
+    const int ny = iy1 - iy0 + 1, nz = iz1 - iz0 + 1;
+    const int npy = (ny + 7) >> 3, npz = (nz + 7) >> 3;
+    const int npatch = npy * npz;
+    const float h = L.h;
+    const float* __restrict__ G = Gsrc + L.pt_base;
+    for (int pc = wv; pc < npatch; pc += 4) {
+      const int pyi = pc % npy, pzi = pc / npy;
+      const int jy = iy0 + pyi * 8 + (lane & 7);
+      const int kz = iz0 + pzi * 8 + (lane >> 3);
+      int lo = 0, len = 0;
+      float dy = 0.f, dz = 0.f, syz = 0.f;
+      if (jy <= iy1 && kz <= iz1) {
+        dy = L.axis[jy] - cy;
+        dz = L.axis[kz] - cz;
+        syz = fmaf(dy, dy, dz * dz);
+        if (syz < rad2) {
+          const float half = sqrtf(rad2 - syz);
+          int a, b;
+          index_range(L, cx - half, cx + half, a, b);
+          a = max(a, ix0);
+          b = min(b, ix1);
+          while (a <= b) {
+            const float dxa = L.axis[a] - cx;
+            if (fmaf(dxa, dxa, syz) < rad2) break;
+            ++a;
+          }
+          while (b >= a) {
+            const float dxb = L.axis[b] - cx;
+            if (fmaf(dxb, dxb, syz) < rad2) break;
+            --b;
+          }
+          lo = a;
+          len = b - a + 1;
+        }
+      }
+      const int maxlen = wave_max_i(len);
+      if (maxlen == 0) continue;
+      const int64_t rowoff = ((int64_t)kz * n + jy) * n;
+      if (COUNT_FWD && len > 0) {
+        pf += L.bits ? popcount_range(L.bits, rowoff + lo, rowoff + lo + len - 1) : len;
+      }
+      const float bl = fmaf(A01x2, dy, A02x2 * dz);
+      const float cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
+      const float dxlo = len > 0 ? L.axis[lo] - cx : 0.f;
+      const float* __restrict__ grow = G + rowoff + lo;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      int nzc = 0;
+      for (int t = 0; t < maxlen; ++t) {
+        if (t < len) {
+          const float g = grow[t];
+          const float dx = fmaf((float)t, h, dxlo);
+          const float q = fmaf(dx, fmaf(A00, dx, bl), cc);
+          const float gp = g * fast_exp2(-q);
+          s0 += gp;
+          const float gx = gp * dx;
+          s1 += gx;
+          s2 = fmaf(gx, dx, s2);
+          nzc += g != 0.f;
+        }
+      }
+      pb += nzc;
+      const double S0 = s0, S1 = s1, S2 = s2, DY = dy, DZ = dz;
+      T[0] += S0;
+      T[1] += S1;
+      T[2] += DY * S0;
+      T[3] += DZ * S0;
+      T[4] += S2;           // xx
+      T[5] += DY * S1;      // xy
+      T[6] += DZ * S1;      // xz
+      T[7] += DY * DY * S0; // yy
+      T[8] += DY * DZ * S0; // yz
+      T[9] += DZ * DZ * S0; // zz
+    }
+  }
+
+  double v[12];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) v[i] = T[i];
+  v[10] = (double)pf;
+  v[11] = (double)pb;
+  block_reduce_doubles(v, 12, sh);
+
+  if (tid == 0) {
+    // epilogue in double: gradients from the moments
+    const double w = p[j];
+    const double s[3] = {p[4 * C + j], p[5 * C + j], p[6 * C + j]};
+    double q[4] = {p[7 * C + j], p[8 * C + j], p[9 * C + j], p[10 * C + j]};
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double qh[4];
+    if (qn > 0.0) {
+      for (int k = 0; k < 4; ++k) qh[k] = q[k] / qn;
+    } else {
+      qh[0] = 1.0; qh[1] = qh[2] = qh[3] = 0.0; qn = 1.0;
+    }
+    const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
+    double R[3][3];
+    R[0][0] = 1 - 2 * (qy * qy + qz * qz); R[0][1] = 2 * (qx * qy - qw * qz); R[0][2] = 2 * (qx * qz + qw * qy);
+    R[1][0] = 2 * (qx * qy + qw * qz); R[1][1] = 1 - 2 * (qx * qx + qz * qz); R[1][2] = 2 * (qy * qz - qw * qx);
+    R[2][0] = 2 * (qx * qz - qw * qy); R[2][1] = 2 * (qy * qz + qw * qx); R[2][2] = 1 - 2 * (qx * qx + qy * qy);
+    double d2[3];
+    for (int k = 0; k < 3; ++k) d2[k] = exp(2.0 * s[k]);
+    const double amp = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? w * fabs(w) : w;
+    const double dadw = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? 2.0 * fabs(w) : 1.0;
+    const double T1[3] = {v[1], v[2], v[3]};
+    const double T2[3][3] = {{v[4], v[5], v[6]}, {v[5], v[7], v[8]}, {v[6], v[8], v[9]}};
+    // dL/dw
+    const double gw = v[0] * dadw;
+    // dL/dc = 2 a A T1, A = R^T D^2 R
+    double u1[3];
+    for (int k = 0; k < 3; ++k) u1[k] = d2[k] * (R[k][0] * T1[0] + R[k][1] * T1[1] + R[k][2] * T1[2]);
+    double gc[3];
+    for (int l = 0; l < 3; ++l) gc[l] = 2.0 * amp * (R[0][l] * u1[0] + R[1][l] * u1[1] + R[2][l] * u1[2]);
+    // RT2 = R T2
+    double RT2[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) RT2[k][l] = R[k][0] * T2[0][l] + R[k][1] * T2[1][l] + R[k][2] * T2[2][l];
+    // dL/ds_k = -2 a d_k^2 r_k^T T2 r_k
+    double gs[3];
+    for (int k = 0; k < 3; ++k)
+      gs[k] = -2.0 * amp * d2[k] * (RT2[k][0] * R[k][0] + RT2[k][1] * R[k][1] + RT2[k][2] * R[k][2]);
+    // dL/dR = -2 a D^2 R T2
+    double gR[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) gR[k][l] = -2.0 * amp * d2[k] * RT2[k][l];
+    // dL/dqhat through dR/dqhat
+    double gq[4];
+    gq[0] = 2 * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
+    gq[1] = 2 * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2 * qx * gR[1][1] - qw * gR[1][2] + qz * gR[2][0] +
+                 qw * gR[2][1] - 2 * qx * gR[2][2]);
+    gq[2] = 2 * (-2 * qy * gR[0][0] + qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] + qz * gR[1][2] - qw * gR[2][0] +
+                 qz * gR[2][1] - 2 * qy * gR[2][2]);
+    gq[3] = 2 * (-2 * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] - 2 * qz * gR[1][1] +
+                 qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
+    const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+    grad[j] = (float)gw;
+    for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
+    for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
+    for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
+    D.kstat[j].p_fwd = (int64_t)v[10];
+    D.kstat[j].p_bwd = (int64_t)v[11];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-shape statistics, eq. 3-21 weights and gradient combination
+// one workgroup of 1024 threads per shape
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_sum_1024(double v, double* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (tid == 0) {
+    for (int i = 0; i < 16; ++i) r += sh[i];
+    sh[16] = r;
+  }
+  __syncthreads();
+  r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ float block_max_1024(float v, float* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  v = wave_max_f(v);
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (tid == 0) {
+    float r = 0.f;
+    for (int i = 0; i < 16; ++i) r = fmaxf(r, sh[i]);
+    sh[16] = r;
+  }
+  __syncthreads();
+  const float r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+// mode: 0 eval (bucket stats only), 1 vjp (adds pair counts), 2 loss (everything)
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__ p,
+                                                const int32_t* __restrict__ m_dev,
+                                                float* __restrict__ grad, erbf_stats* __restrict__ out,
+                                                StatsArgs a) {
+  __shared__ double shd[17];
+  __shared__ float shf[17];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ShapeDev S = D.shapes[b];
+  const int m = min(max(m_dev[b], 0), S.cap);
+  const int C = D.cap_total;
+  const int64_t nb = D.counters[0];
+
+  double l2 = 0.0, nid = 0.0, pf = 0.0, pb = 0.0;
+  float mx = 0.f;
+  if (MODE == 2) {
+    for (int li = 0; li < S.n_active; ++li) {
+      const LevelDev L = D.levels[S.lvl0 + li];
+      for (int s = tid; s < L.n_slots; s += 1024) {
+        const TileStat ts = D.tstat[L.slot0 + s];
+        l2 += ts.l2;
+        nid += (double)ts.n_idall;
+        mx = fmaxf(mx, ts.max_abs_e);
+      }
+    }
+  }
+  if (MODE >= 1) {
+    for (int k = tid; k < m; k += 1024) {
+      pf += (double)D.kstat[S.kbase + k].p_fwd;
+      pb += (double)D.kstat[S.kbase + k].p_bwd;
+    }
+  }
+  l2 = block_sum_1024(l2, shd);
+  nid = block_sum_1024(nid, shd);
+  pf = block_sum_1024(pf, shd);
+  pb = block_sum_1024(pb, shd);
+  mx = block_max_1024(mx, shf);
+
+  double alpha = 1.0, beta = 0.0, l1 = 0.0;
+  if (MODE == 2) {
+    double num = 0.0, den = 0.0;
+    for (int k = tid; k < m; k += 1024) {
+      const float w = p[S.kbase + k];
+      const double g1 = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
+      const double g2 = grad[S.kbase + k];
+      l1 += fabs((double)w);
+      num += (g1 - g2) * g1;
+      den += (g2 - g1) * (g2 - g1);
+    }
+    l1 = block_sum_1024(l1, shd);
+    num = block_sum_1024(num, shd);
+    den = block_sum_1024(den, shd);
+    if (a.mode == ERBF_MODE_FIXED) {
+      beta = a.lambda_dev ? (double)a.lambda_dev[b] : (double)a.lambda;
+    } else if (a.mode == ERBF_MODE_DYNAMIC && a.l1_active && mx < a.tau_m) {
+      alpha = den > 0.0 ? fmin(fmax(num / den, 0.0), 1.0) : 1.0;
+      beta = 1.0 - alpha;
+    }
+    // combine: alpha * dL2 + beta * sign(w) on w; alpha * dL2 elsewhere
+    for (int k = tid; k < m; k += 1024) {
+      const int jj = S.kbase + k;
+      const float w = p[jj];
+      const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
+      grad[jj] = (float)(alpha * (double)grad[jj] + beta * sg);
+      if (alpha != 1.0) {
+        for (int seg = 1; seg < 11; ++seg) grad[seg * C + jj] = (float)(alpha * (double)grad[seg * C + jj]);
+      }
+    }
+  }
+  if (tid == 0 && out) {
+    erbf_stats st;
+    st.L2 = l2;
+    st.L1 = l1;
+    st.loss = alpha * l2 + beta * l1;
+    st.alpha = alpha;
+    st.beta = beta;
+    st.n_idall = (int64_t)nid;
+    st.P_fwd = (int64_t)pf;
+    st.P_bwd = (int64_t)pb;
+    st.n_bucket_pairs = nb;
+    st.max_abs_E = mx;
+    st.m = m;
+    st.flags = nb > D.pair_cap ? ERBF_FLAG_BUCKET_OVERFLOW : 0;
+    st.reserved = 0;
+    out[b] = st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam
+// ---------------------------------------------------------------------------
+
+__global__ void k_step_inc(int32_t* step, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) step[i] += 1;
+}
+
+__global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, const int32_t* __restrict__ m_dev,
+                                              const float* __restrict__ g, float* __restrict__ m1,
+                                              float* __restrict__ m2, const int32_t* __restrict__ step,
+                                              AdamArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = D.cap_total;
+  if (i >= (int64_t)11 * C) return;
+  const int j = (int)(i % C);
+  const int b = D.kshape[j];
+  const ShapeDev S = D.shapes[b];
+  if (j - S.kbase >= min(max(m_dev[b], 0), S.cap)) return;
+  const float lr = a.lr_dev ? a.lr_dev[b] : a.lr;
+  const int t = step[b];
+  const float gi = g[i];
+  const float mm = a.beta1 * m1[i] + (1.f - a.beta1) * gi;
+  const float vv = a.beta2 * m2[i] + (1.f - a.beta2) * gi * gi;
+  m1[i] = mm;
+  m2[i] = vv;
+  const float bc1 = 1.f - powf(a.beta1, (float)t);
+  const float bc2 = 1.f - powf(a.beta2, (float)t);
+  const float denom = sqrtf(vv) / sqrtf(bc2) + a.eps;
+  p[i] -= (lr / bc1) * mm / denom;
+}
+
+// ---------------------------------------------------------------------------
+// misc elementwise
+// ---------------------------------------------------------------------------
+
+// G[idx] = src[idx] * active(idx) over every point of the active levels.
+__global__ __launch_bounds__(256) void k_mask_copy(Dev D, int li, const float* __restrict__ src) {
+  const LevelDev L = D.levels[li];
+  const int64_t npts = (int64_t)L.n * L.n * L.n;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = L.pt_base + k;
+    D.G[idx] = point_active(L.bits, k) ? src[idx] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ x, int64_t n, float v) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    x[k] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* __restrict__ x, int64_t n, int32_t v) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    x[k] = v;
+}
+
+// eq. 3-10 in double, rounded once
+__global__ __launch_bounds__(256) void k_targets(const float* __restrict__ S, int64_t n, float m,
+                                                 float* __restrict__ t) {
+  const double md = m;
+  const double h = 0.69314718055994530942 / (md * md);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)S[k] - md;
+    t[k] = (float)(2.0 * exp(-h * d * d));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_band_bits(const float* __restrict__ S, int64_t n, float band,
+                                                   uint32_t* __restrict__ bits) {
+  const int64_t nw = (n + 31) >> 5;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int64_t k = w * 32 + b;
+      if (k < n && fabsf(S[k]) < band) v |= 1u << b;
+    }
+    bits[w] = v;
+  }
+}
+
+// order-preserving float -> int key
+__device__ __forceinline__ int fkey(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float fkey_inv(int k) {
+  return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff);
+}
+
+__global__ __launch_bounds__(256) void k_sdf_min(const float* __restrict__ S, int64_t n, int* __restrict__ key) {
+  int best = INT32_MAX;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    best = min(best, fkey(S[k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(key, best);
+}
+
+__global__ void k_sdf_min_init(int* key, const float* prev, int accumulate) {
+  *key = accumulate ? fkey(*prev) : INT32_MAX;
+}
+
+__global__ void k_sdf_min_fin(const int* key, float* out) { *out = fkey_inv(*key); }
+
+// ---------------------------------------------------------------------------
+// refine: tile occupancy of a new level
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_tile_flags(Dev D, int li, int32_t* __restrict__ flags) {
+  const LevelDev L = D.levels[li];
+  const int nt = L.nt, n = L.n;
+  const int ntt = nt * nt * nt;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntt) return;
+  const int tz = t / (nt * nt), ty = (t / nt) % nt, tx = t % nt;
+  int any = 0;
+  if (L.bits == nullptr) {
+    any = 1;
+  } else {
+    for (int z = tz * kTile; z < min(tz * kTile + kTile, n) && !any; ++z)
+      for (int y = ty * kTile; y < min(ty * kTile + kTile, n) && !any; ++y) {
+        const int64_t row = ((int64_t)z * n + y) * n;
+        const int x0 = tx * kTile, x1 = min(tx * kTile + kTile, n) - 1;
+        any = popcount_range(L.bits, row + x0, row + x1) > 0;
+      }
+  }
+  flags[t] = any;
+}
+
+__global__ __launch_bounds__(256) void k_tile_assign(Dev D, int li, const int32_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ excl, int slot0) {
+  const LevelDev L = D.levels[li];
+  const int ntt = L.nt * L.nt * L.nt;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntt) return;
+  if (flags[t]) {
+    const int s = slot0 + excl[t];
+    D.tile_map[L.tmap0 + t] = s;
+    D.slot_tile[s] = make_int2(li, t);
+  } else {
+    D.tile_map[L.tmap0 + t] = -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+static inline unsigned gridstride(int64_t n) { return (unsigned)std::min<int64_t>(nblk(n, 256), 4096); }
+
+hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, p, m_dev, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
+                       hipStream_t s) {
+  const int nb = (int)nblk(n + 1, 1024);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, s, in, n, blocks);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blocks, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(1024), 0, s, in, n, blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots + 1)), dim3(256), 0, s, D.tile_cnt,
+                     (int64_t)n_slots + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots)), dim3(256), 0, s, D.cursor, (int64_t)n_slots, 0);
+  hipLaunchKernelGGL(k_bucket<false>, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D);
+  hipError_t e = launch_scan(D.tile_cnt, n_slots, D.scan_blocks, D.tile_start, D.counters, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bucket<true>, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_sort_tiles, dim3(n_slots), dim3(256), 0, s, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
+                          hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  if (loss)
+    hipLaunchKernelGGL(k_forward<true>, dim3(n_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+  else
+    hipLaunchKernelGGL(k_forward<false>, dim3(n_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const Dev& D, const float* p, const float* G, float* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_backward<true>, dim3(D.cap_total), dim3(256), 0, s, D, p, G, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
+                        erbf_stats* out, const StatsArgs& a, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_stats<0>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_stats<1>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
+  else
+    hipLaunchKernelGGL(k_stats<2>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, const float* g, float* m1, float* m2,
+                       int32_t* step, const AdamArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_inc, dim3(nblk(D.n_shapes, 256)), dim3(256), 0, s, step, D.n_shapes);
+  hipLaunchKernelGGL(k_adam, dim3(nblk((int64_t)11 * D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, g, m1,
+                     m2, step, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_copy(const Dev& D, int li, int64_t npts, const float* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_copy, dim3(gridstride(npts)), dim3(256), 0, s, D, li, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(gridstride(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const float* S, int64_t n, float m, float* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_targets, dim3(gridstride(n)), dim3(256), 0, s, S, n, m, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_bits, dim3(gridstride((n + 31) / 32)), dim3(256), 0, s, S, n, band, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_sdf_min(const float* S, int64_t n, float* out, int accumulate, int* key_scratch,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_sdf_min_init, dim3(1), dim3(1), 0, s, key_scratch, out, accumulate);
+  hipLaunchKernelGGL(k_sdf_min, dim3(gridstride(n)), dim3(256), 0, s, S, n, key_scratch);
+  hipLaunchKernelGGL(k_sdf_min_fin, dim3(1), dim3(1), 0, s, key_scratch, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_flags(const Dev& D, int li, int ntt, int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_flags, dim3(nblk(ntt, 256)), dim3(256), 0, s, D, li, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_assign(const Dev& D, int li, int ntt, const int32_t* flags, const int32_t* excl,
+                              int slot0, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_assign, dim3(nblk(ntt, 256)), dim3(256), 0, s, D, li, flags, excl, slot0);
+  return hipGetLastError();
+}
+
+}  // namespace erbf

@@ -1,0 +1,60 @@
+// Launch wrappers between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "erbf_internal.h"
+
+namespace erbf {
+
+struct StatsArgs {
+  int32_t mode;
+  float lambda;
+  const float* lambda_dev;
+  int32_t l1_active;
+  float tau_m;
+};
+
+struct AdamArgs {
+  float lr;
+  const float* lr_dev;
+  float beta1, beta2, eps;
+};
+
+struct SeedArgs {
+  int32_t shape;
+  int64_t k_cand;      // number of candidates (top fraction of n_idall)
+  int32_t k_new;
+  float r_nms;
+  float eps;
+  float min_abs_err;
+  int32_t w_rule;
+  float resid_scale;
+  float h_fine;
+};
+
+hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
+                       hipStream_t s);
+hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s);
+hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
+                          hipStream_t s);
+hipError_t launch_backward(const Dev& D, const float* p, const float* G, float* grad, hipStream_t s);
+hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
+                        erbf_stats* out, const StatsArgs& a, hipStream_t s);
+hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, const float* g, float* m1, float* m2,
+                       int32_t* step, const AdamArgs& a, hipStream_t s);
+hipError_t launch_mask_copy(const Dev& D, int li, int64_t npts, const float* src, hipStream_t s);
+hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_targets(const float* S, int64_t n, float m, float* t, hipStream_t s);
+hipError_t launch_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t s);
+hipError_t launch_sdf_min(const float* S, int64_t n, float* out, int accumulate, int* key_scratch,
+                          hipStream_t s);
+hipError_t launch_tile_flags(const Dev& D, int li, int ntt, int32_t* flags, hipStream_t s);
+hipError_t launch_tile_assign(const Dev& D, int li, int ntt, const int32_t* flags, const int32_t* excl,
+                              int slot0, hipStream_t s);
+hipError_t launch_seed(const Dev& D, const float* p, int32_t* m_dev, const float* resid, float* m1, float* m2,
+                       const SeedArgs& a, hipStream_t s);
+
+}  // namespace erbf

@@ -1,0 +1,106 @@
+"""Shared set-up of GPU parity tests: build a library context and the oracle's
+view of the same synthetic problem.
+
+Inputs flow one way: synth -> (oracle, GPU).  Targets are computed by the
+oracle (eq. 3-10, float64, stored float32) and uploaded; nothing the GPU
+computes is handed to the oracle.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+
+import oracle as O
+
+TAU1 = float(np.float32(0.9))
+TAU2 = float(np.float32(1.1))
+TAU_M = float(np.float32(0.02))
+
+RESULTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out", "parity")
+
+
+def record(name, **vals):
+    """Write the measured errors of a parity test (and print them)."""
+    os.makedirs(RESULTS, exist_ok=True)
+    with open(os.path.join(RESULTS, f"{name}.json"), "w") as fh:
+        json.dump(vals, fh, indent=1, default=float)
+    print(name, json.dumps(vals, default=float), flush=True)
+
+
+def oracle_levels(prob, with_targets=True):
+    S_all = [lv.S for lv in prob.levels]
+    m = O.sdf_min(S_all)
+    out, t32 = [], []
+    for lv in prob.levels:
+        t = O.targets_from_sdf(lv.S, m).astype(np.float32) if with_targets else None
+        t32.append(t)
+        out.append(O.make_level(lv.n, lv.axis, active=lv.active_mask(), t=t, S=lv.S))
+    return out, t32, m
+
+
+def pair_cap_estimate(prob, slack=2.0):
+    """Generous bound on tile-list entries: tiles touched by each ball's box."""
+    seg = prob.params.reshape(11, prob.cap)[:, :prob.m]
+    smin = seg[4:7].min(axis=0).astype(np.float64)
+    r = prob.cull_k / np.exp(smin)
+    tot = 0
+    for lv in prob.levels:
+        tile = 8 * 2.0 / lv.n
+        per = (np.minimum(2 * r / tile + 2, math.ceil(lv.n / 8))) ** 3
+        tot += per.sum()
+    return int(tot * slack) + 4096
+
+
+class GpuProblem:
+    """A one-shape library context holding `prob`'s levels and parameters."""
+
+    def __init__(self, prob, targets, pair_cap=None, weight_map=None, n_levels=None):
+        import torch
+        from paper_2505_02350_amd import core
+        self.torch = torch
+        self.prob = prob
+        nl = len(prob.levels) if n_levels is None else n_levels
+        wm = prob.weight_map if weight_map is None else weight_map
+        self.ctx = core.Context([([lv.n for lv in prob.levels[:nl]], prob.cap)],
+                                pair_cap or pair_cap_estimate(prob), prob.cull_k, wm)
+        dev = self.ctx.device
+        self.axes, self.tgts, self.sdfs, self.bits = [], [], [], []
+        for li, lv in enumerate(prob.levels[:nl]):
+            ax = torch.from_numpy(np.asarray(lv.axis, np.float32)).to(dev)
+            S = torch.from_numpy(np.asarray(lv.S, np.float32)).to(dev)
+            t = None if targets is None or targets[li] is None else torch.from_numpy(targets[li]).to(dev)
+            bits = core.erbf_band_bits(S, lv.band) if lv.band is not None else None
+            self.axes.append(ax)
+            self.tgts.append(t)
+            self.sdfs.append(S)
+            self.bits.append(bits)
+            self.ctx.erbf_refine_level(0, ax, t, S, bits)
+        self.p = torch.from_numpy(np.asarray(prob.params, np.float32)).to(dev)
+        self.m_dev = torch.tensor([prob.m], dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+
+    def split_points(self, flat):
+        """Per-level numpy arrays from a per-point device array."""
+        a = flat.detach().cpu().numpy()
+        out = []
+        for li, n in enumerate(self.ctx.level_ns[0][:self.ctx.n_active[0]]):
+            b = self.ctx.pt_base[0][li]
+            out.append(a[b:b + n ** 3])
+        return out
+
+    def grads_np(self, g):
+        a = g.detach().cpu().numpy().astype(np.float64).reshape(11, self.prob.cap)[:, :self.prob.m]
+        return {"w": a[0], "c": a[1:4].T, "s": a[4:7].T, "q": a[7:11].T}
+
+
+def rel_inf(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def oracle_grads_dict(gr):
+    return {"w": gr.w, "c": gr.c, "s": gr.s, "q": gr.q}

@@ -1,0 +1,218 @@
+"""GPU-vs-oracle parity of the HIP path, called through the C ABI.
+
+Bars: f within 1e-5 of ||f||_inf (plus the float32/float64 cull-boundary
+allowance of each point); gradients per group within 1e-4 of the group's
+||g||_inf; integer counts exact.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import (TAU1, TAU2, TAU_M, GpuProblem, oracle_grads_dict, oracle_levels, record,
+                         rel_inf)
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+G_TOL = 1e-4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_f(name, gp, olv, K, f_gpu_levels):
+    f_or = O.forward(olv, K)
+    allow, n_amb = O.boundary_allowance(olv, K)
+    fmax = max(np.abs(f).max() for f in f_or)
+    worst = 0.0
+    for fg, fo, al in zip(f_gpu_levels, f_or, allow):
+        excess = np.abs(fg.astype(np.float64) - fo) - al
+        worst = max(worst, excess.max() / fmax)
+    record(name, e_f=worst, f_inf=fmax, n_boundary_pairs=n_amb)
+    assert worst <= F_TOL
+    return f_or
+
+
+def test_data_prep_parity():
+    torch = _torch()
+    from paper_2505_02350_amd import core
+    prob = synth.make_custom(21, [24, 40], 8, (1.5, 2.5), bands=[None, 0.1])
+    dev = torch.device("cuda")
+    S = [torch.from_numpy(lv.S).to(dev) for lv in prob.levels]
+    mdev = torch.zeros(1, dtype=torch.float32, device=dev)
+    core.erbf_sdf_min(S[0], mdev, False)
+    core.erbf_sdf_min(S[1], mdev, True)
+    m_or = O.sdf_min([lv.S for lv in prob.levels])
+    assert float(mdev.item()) == m_or          # the minimum of float32 values is exact
+    for lv, s in zip(prob.levels, S):
+        t = core.erbf_targets_from_sdf(s, m_or).cpu().numpy()
+        t_or = O.targets_from_sdf(lv.S, m_or)
+        ulp = np.spacing(t_or.astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(t - t_or) <= ulp)
+        bits = core.erbf_band_bits(s, 0.1).cpu().numpy().view(np.uint32)
+        mask = np.unpackbits(bits.view(np.uint8), bitorder="little")[: lv.S.size].astype(bool)
+        assert np.array_equal(mask, O.band_mask(lv.S, 0.1))
+
+
+def _tiny():
+    return synth.make_tiny()
+
+
+def test_eval_tiny():
+    prob = _tiny()
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32)
+    f = gp.ctx.erbf_eval(gp.p, gp.m_dev)
+    _torch().cuda.synchronize()
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    _check_f("eval_tiny", gp, olv, K, gp.split_points(f))
+
+
+def _ragged_problem(seed=22):
+    # levels whose sizes are not multiples of the 8-point tile, one banded
+    return synth.make_custom(seed, [12, 20], 24, (1.6, 2.6), kinds=("ellipsoid", "torus", "box"),
+                             bands=[None, 0.15])
+
+
+def test_eval_ragged_multilevel_band():
+    prob = _ragged_problem()
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32)
+    f = gp.ctx.erbf_eval(gp.p, gp.m_dev)
+    _torch().cuda.synchronize()
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    fl = gp.split_points(f)
+    _check_f("eval_ragged", gp, olv, K, fl)
+    # inactive points of the banded level are exactly zero
+    assert np.all(fl[1][~olv[1].active] == 0.0)
+
+
+def _loss_case(name, prob, mode, lam=0.0, l1_active=False, tau_m=TAU_M, wm=None):
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32, weight_map=wm)
+    torch = _torch()
+    G = torch.zeros(gp.ctx.n_points, dtype=torch.float32, device=gp.ctx.device)
+    f = torch.zeros_like(G)
+    g = gp.ctx.erbf_loss_grad(gp.p, gp.m_dev, mode=mode, lam=lam, l1_active=l1_active, tau1=TAU1,
+                              tau2=TAU2, tau_m=tau_m, f_out=f, G_out=G)
+    torch.cuda.synchronize()
+    st = gp.ctx.stats()[0]
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k,
+                              prob.weight_map if wm is None else wm)
+    f_or = _check_f(name + "_f", gp, olv, K, gp.split_points(f))
+    # mask decisions whose float32/float64 outcome could differ
+    amb = 0
+    for lv, fo in zip(olv, f_or):
+        near = (np.abs(fo - TAU1) < 1e-5) & (lv.t <= TAU1) | (np.abs(fo - TAU2) < 1e-5) & (lv.t >= TAU2)
+        amb += int((near & lv.act()).sum())
+    assert amb == 0, "case has float-ambiguous mask decisions; pick another seed"
+    st_or = O.step(olv, K, mode=mode, lam=lam, l1_active=l1_active, tau1=TAU1, tau2=TAU2, tau_m=tau_m)
+    errs = dict(
+        L2=abs(st.L2 - st_or.loss.L2) / max(st_or.loss.L2, 1e-30),
+        L1=abs(st.L1 - st_or.loss.L1) / max(st_or.loss.L1, 1e-30),
+        max_abs_E=abs(st.max_abs_E - st_or.loss.max_abs_E),
+        alpha=abs(st.alpha - st_or.alpha),
+        beta=abs(st.beta - st_or.beta),
+    )
+    go = oracle_grads_dict(st_or.grads)
+    gg = gp.grads_np(g)
+    for k in go:
+        errs["grad_" + k] = rel_inf(gg[k], go[k])
+    record(name, n_idall=(st.n_idall, st_or.loss.n_idall), P_fwd=(st.P_fwd, st_or.P_fwd),
+           P_bwd=(st.P_bwd, st_or.P_bwd), **errs)
+    assert st.flags == 0
+    assert st.n_idall == st_or.loss.n_idall
+    assert st.P_fwd == st_or.P_fwd and st.P_bwd == st_or.P_bwd
+    assert errs["L2"] <= 1e-5 and errs["L1"] <= 1e-5 and errs["max_abs_E"] <= 1e-5
+    assert errs["alpha"] <= 1e-5 and errs["beta"] <= 1e-5
+    for k in go:
+        assert errs["grad_" + k] <= G_TOL, (k, errs["grad_" + k])
+    Gl = gp.split_points(G)
+    for gl, e in zip(Gl, st_or.loss.E):
+        assert np.all((gl != 0) == (e != 0))
+    return gp, g, st
+
+
+def test_loss_grad_tiny_fixed_lambda():
+    _loss_case("loss_tiny", _tiny(), O.MODE_FIXED, lam=1e-4)
+
+
+def test_loss_grad_ragged_multilevel():
+    _loss_case("loss_ragged", _ragged_problem(23), O.MODE_FIXED, lam=1e-3)
+
+
+def test_loss_grad_dynamic_alpha():
+    # tau_m large so the max-error gate opens and eq. 3-21 decides alpha
+    # (this seed gives an interior alpha of about 0.39)
+    gp, g, st = _loss_case("loss_dynamic", _ragged_problem(26), O.MODE_DYNAMIC, l1_active=True, tau_m=10.0)
+    assert 0.05 < st.alpha < 0.95
+
+
+def test_loss_grad_linear_weights():
+    _loss_case("loss_linear", _ragged_problem(25), O.MODE_L2, wm=1)
+
+
+def test_vjp_random_upstream():
+    torch = _torch()
+    prob = _ragged_problem(26)
+    olv, t32, _ = oracle_levels(prob, with_targets=False)
+    gp = GpuProblem(prob, None)
+    rng = np.random.default_rng(7)
+    Gs = [rng.standard_normal(lv.npts).astype(np.float32) for lv in olv]
+    flat = torch.from_numpy(np.concatenate(Gs)).to(gp.ctx.device)
+    g = gp.ctx.erbf_vjp(gp.p, gp.m_dev, flat, stats=True)
+    torch.cuda.synchronize()
+    st = gp.ctx.stats()[0]
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    Gm = [np.where(lv.act(), gg.astype(np.float64), 0.0) for lv, gg in zip(olv, Gs)]
+    gr = O.backward(olv, K, Gm)
+    pf, pb = O.pair_counts(olv, K, Gm)
+    go = oracle_grads_dict(gr)
+    gg = gp.grads_np(g)
+    errs = {k: rel_inf(gg[k], go[k]) for k in go}
+    record("vjp_ragged", P_fwd=(st.P_fwd, pf), P_bwd=(st.P_bwd, pb), **errs)
+    assert st.P_fwd == pf and st.P_bwd == pb
+    for k in go:
+        assert errs[k] <= G_TOL, (k, errs[k])
+
+
+def test_determinism_bitwise():
+    torch = _torch()
+    prob = _ragged_problem(27)
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32)
+    outs = []
+    for _ in range(5):
+        g = gp.ctx.erbf_loss_grad(gp.p, gp.m_dev, mode=O.MODE_FIXED, lam=1e-4)
+        outs.append(g.clone())
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_adam_matches_oracle():
+    torch = _torch()
+    prob = _tiny()
+    gp = GpuProblem(prob, oracle_levels(prob)[1])
+    dev = gp.ctx.device
+    rng = np.random.default_rng(8)
+    cap = prob.cap
+    m1 = torch.zeros(11 * cap, device=dev)
+    m2 = torch.zeros(11 * cap, device=dev)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    p64 = prob.params.astype(np.float64)
+    o1 = np.zeros_like(p64)
+    o2 = np.zeros_like(p64)
+    for t in range(1, 6):
+        g = rng.standard_normal(11 * cap).astype(np.float32)
+        gp.ctx.erbf_adam_step(gp.p, gp.m_dev, torch.from_numpy(g).to(dev), m1, m2, step, lr=1e-2)
+        p64, o1, o2 = O.adam_step(p64, g.astype(np.float64), o1, o2, t, 1e-2)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 5
+    err = np.abs(gp.p.cpu().numpy() - p64).max()
+    record("adam", max_abs_err=err)
+    assert err < 1e-5
