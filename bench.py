@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of one SE-RBFNet optimisation step on the MI355X.
+
+Workload (timing snapshot of the large hierarchy): smooth union of 12 boxes,
+6 capsules and 4 tori sampled on 64^3 + 128^3 + 256^3 grid levels (the finest
+restricted to |S| < 0.1), 16384 ERBFs drawn with the kernel init rule.  One
+step = prologue, tile buckets, forward + masked loss, backward, eq. 3-21
+weights and Adam, all on the device; inputs are resident in HBM before the
+timed region.
+
+Prints one JSON line.  `value` is whole-step pair throughput,
+(P_fwd + P_bwd) per step divided by the wall time of a step.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FWD_FLOP_PER_PAIR = 25.0   # delta 3, ball test 5, quadric 14, exp2 1, accumulate 2
+BWD_FLOP_PER_PAIR = 43.0   # + g 1, T0 1, g*delta 3, T1 3, T2 12
+FP32_VECTOR_PEAK = 157.3e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, budget_s=15.0, seed=0):
+    """The FP64 oracle's culled forward + loss + backward on a sample of the
+    workload's kernels (all three levels, every point), timed on the host."""
+    import oracle as O
+    S_all = [lv.S for lv in prob.levels]
+    m = O.sdf_min(S_all)
+    olv = [O.make_level(lv.n, lv.axis, active=(O.band_mask(lv.S, lv.band) if lv.band else None),
+                        t=O.targets_from_sdf(lv.S, m).astype(np.float32), S=lv.S) for lv in prob.levels]
+    Kall = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    order = np.random.default_rng(seed).permutation(prob.m)
+
+    def sub(idx):
+        return O.make_kernels(Kall.w[idx], Kall.c[idx], Kall.s[idx], Kall.q[idx], prob.cull_k)
+
+    def run(idx):
+        K = sub(idx)
+        t0 = time.perf_counter()
+        f = O.forward(olv, K)
+        lo = O.loss(olv, f, K, tau1=float(np.float32(0.9)), tau2=float(np.float32(1.1)))
+        G = [2.0 * e for e in lo.E]
+        O.backward(olv, K, G)
+        dt = time.perf_counter() - t0
+        pf, pb = O.pair_counts(olv, K, G)
+        return dt, pf, pb
+
+    # calibrate a fixed + per-kernel cost model, then size the sample to the budget
+    d1, _, _ = run(order[:16])
+    d2, _, _ = run(order[:64])
+    per = max((d2 - d1) / 48.0, 1e-4)
+    fixed = max(d1 - 16 * per, 0.0)
+    n = int(min(prob.m, max(64, (budget_s - fixed) / per)))
+    dt, pf, pb = run(order[:n])
+    return {"value": (pf + pb) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} of {prob.m} kernels (seeded random), all 3 levels, one culled "
+                      f"fwd+loss+bwd in float64 numpy, {dt:.1f} s, {pf + pb} pairs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--graph", action="store_true", help="also time HIP-graph replays of the step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+
+    t_setup = time.perf_counter()
+    prob = synth.make_large_snapshot()
+    log(f"workload generated in {time.perf_counter() - t_setup:.1f} s")
+    shape = ShapeInput.from_problem(prob)
+    t0 = time.perf_counter()
+    fit = Fitter([shape], cull_k=prob.cull_k, all_levels=False)
+    refine_ms = []
+    for _ in prob.levels:
+        r0 = time.perf_counter()
+        fit.refine(0)
+        refine_ms.append(1e3 * (time.perf_counter() - r0))
+    torch.cuda.synchronize()
+    log(f"device set-up {time.perf_counter() - t0:.1f} s; refine ms {refine_ms}")
+
+    kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
+    for _ in range(args.warmup):
+        fit.step(**kw)
+    torch.cuda.synchronize()
+    st = fit.stats()[0]
+    if st.flags:
+        raise SystemExit(f"bucket overflow: need {st.n_bucket_pairs} entries")
+    log(f"warm-up done: P_fwd={st.P_fwd} P_bwd={st.P_bwd} n_idall={st.n_idall} L2={st.L2:.4g}")
+
+    fit.ctx.reset_stats()
+    fit.ctx.erbf_timing_enable(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fit.step(**kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms, bt_ms, br_ms, ncalls = fit.ctx.erbf_timing_read()
+    st = fit.stats()[0]
+    K = args.steps
+    assert ncalls == K and st.calls == K and st.flags == 0
+    P_fwd, P_bwd = st.P_fwd_total, st.P_bwd_total
+    ms_per_step = 1e3 * wall / K
+    pairs_per_step = (P_fwd + P_bwd) / K
+    value = (P_fwd + P_bwd) / wall
+    fwd_avg, bt_avg, br_avg = fwd_ms / K, bt_ms / K, br_ms / K
+    fwd_rate = FWD_FLOP_PER_PAIR * P_fwd / K / (fwd_avg * 1e-3)
+    # the backward's per-pair arithmetic runs in the tile kernel; the reduce
+    # kernel only sums per-tile moments
+    bwd_rate = BWD_FLOP_PER_PAIR * P_bwd / K / (bt_avg * 1e-3)
+    if bt_avg >= fwd_avg:
+        dom, ach, t_dom = "k_bwd_tiles (backward moments)", bwd_rate, bt_avg
+    else:
+        dom, ach, t_dom = "k_forward (forward + loss)", fwd_rate, fwd_avg
+    log(f"timed {K} steps: {ms_per_step:.3f} ms/step; forward {fwd_avg:.3f} ms, backward tiles "
+        f"{bt_avg:.3f} ms, reduce {br_avg:.3f} ms")
+
+    graph_ms = None
+    if args.graph:
+        fit.capture(**kw)
+        for _ in range(3):
+            fit.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            fit.replay()
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t0) / K
+
+    out = {
+        "metric": "fwd+bwd ERBF point-kernel pairs/s",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "large_snapshot: smooth union of 12 boxes + 6 capsules + 4 tori on 64^3 + 128^3 + "
+                        "256^3 (|S|<0.1) grid levels, 16384 ERBFs, cull 3/min-scale, seed 2",
+            "points": int(sum(lv.n ** 3 for lv in prob.levels[:2]) + int(np.count_nonzero(np.abs(prob.levels[2].S) < 0.1))),
+            "kernels": prob.m,
+            "pairs_per_step": pairs_per_step,
+            "P_fwd_per_step": P_fwd / K,
+            "P_bwd_per_step": P_bwd / K,
+            "mode": "dynamic (eq. 3-21), Adam lr 1e-2",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "kernel_ms": t_dom,
+            "achieved": ach / 1e12,
+            "peak": FP32_VECTOR_PEAK / 1e12,
+            "unit": "TFLOP/s",
+            "frac": ach / FP32_VECTOR_PEAK,
+            "traffic": None,
+        },
+        "kernels_ms": {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
+                       "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12},
+        "fwd_bwd_pairs_per_s": (P_fwd + P_bwd) / ((fwd_ms + bt_ms + br_ms) * 1e-3),
+        "bucket_entries": st.n_bucket_pairs,
+        "graph_ms_per_step": graph_ms,
+        "per_level_refine_ms": refine_ms,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

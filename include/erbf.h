@@ -141,6 +141,9 @@ typedef struct {
   int32_t m;          /* live kernels */
   int32_t flags;      /* ERBF_FLAG_* */
   int32_t reserved;
+  /* running totals: each call adds its P_fwd, P_bwd and 1 to the values
+   * already in stats_dev (zero the buffer to reset them) */
+  int64_t P_fwd_total, P_bwd_total, calls;
 } erbf_stats;
 
 typedef struct {
@@ -236,6 +239,20 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
                          const float* resid, float resid_scale, int64_t n_idall,
                          const erbf_seed_cfg* cfg, float* m1, float* m2, int32_t* n_added,
                          hipStream_t stream);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* Time the hot kernels of the next `max_calls` erbf_loss_grad / erbf_vjp
+ * calls (0 disables): the forward kernel and the two backward kernels are
+ * launched with start/stop events taken at the kernels' own start and end
+ * (hipExtLaunchKernel), on the call's stream.  Not for use while a stream
+ * is being captured. */
+int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls);
+
+/* Synchronise on the recorded events; ms[0..2] receive the summed times
+ * (milliseconds) of the forward, backward-tile and backward-reduce kernels
+ * and *n_calls the number of calls recorded.  Clears the records. */
+int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls);
 
 #ifdef __cplusplus
 }

@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("n_idall", ctypes.c_int64),
                 ("P_fwd", ctypes.c_int64), ("P_bwd", ctypes.c_int64), ("n_bucket_pairs", ctypes.c_int64),
                 ("max_abs_E", ctypes.c_float), ("m", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("P_fwd_total", ctypes.c_int64), ("P_bwd_total", ctypes.c_int64),
+                ("calls", ctypes.c_int64)]
 
 
 class AdamCfg(ctypes.Structure):
@@ -98,6 +99,8 @@ _SIGS = [
     ("erbf_loss_grad", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, _V, _V, _V, _V]),
     ("erbf_vjp", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V]),
     ("erbf_adam_step", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V, ctypes.POINTER(AdamCfg), _V]),
+    ("erbf_timing_enable", ctypes.c_int, [_V, ctypes.c_int32]),
+    ("erbf_timing_read", ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     ("erbf_seed_from_error", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, _V, ctypes.c_float,
                                             ctypes.c_int64, ctypes.POINTER(SeedCfg), _V, _V,
                                             ctypes.POINTER(ctypes.c_int32), _V]),

@@ -42,6 +42,9 @@ class StatsView:
     max_abs_E: float
     m: int
     flags: int
+    P_fwd_total: int
+    P_bwd_total: int
+    calls: int
 
 
 def parse_stats(buf: torch.Tensor, n_shapes: int) -> List[StatsView]:
@@ -50,7 +53,8 @@ def parse_stats(buf: torch.Tensor, n_shapes: int) -> List[StatsView]:
     for b in range(n_shapes):
         s = L.Stats.from_buffer_copy(raw[b * L.STATS_BYTES:(b + 1) * L.STATS_BYTES])
         out.append(StatsView(s.L2, s.L1, s.loss, s.alpha, s.beta, s.n_idall, s.P_fwd, s.P_bwd,
-                             s.n_bucket_pairs, s.max_abs_E, s.m, s.flags))
+                             s.n_bucket_pairs, s.max_abs_E, s.m, s.flags, s.P_fwd_total, s.P_bwd_total,
+                             s.calls))
     return out
 
 
@@ -191,6 +195,19 @@ class Context:
                                               float(resid_scale), int(n_idall), ctypes.byref(cfg), _ptr(m1),
                                               _ptr(m2), ctypes.byref(n_added), _stream(stream)))
         return n_added.value
+
+    def erbf_timing_enable(self, max_calls: int):
+        L.check(self.lib.erbf_timing_enable(self.handle, int(max_calls)))
+
+    def erbf_timing_read(self):
+        """(forward_ms, backward_tiles_ms, backward_reduce_ms, n_calls), summed."""
+        ms = (ctypes.c_double * 3)()
+        n = ctypes.c_int32()
+        L.check(self.lib.erbf_timing_read(self.handle, ms, ctypes.byref(n)))
+        return ms[0], ms[1], ms[2], n.value
+
+    def reset_stats(self):
+        self.stats_buf.zero_()
 
     def stats(self) -> List[StatsView]:
         return parse_stats(self.stats_buf, self.n_shapes)

@@ -45,7 +45,8 @@ struct Layout {
   int64_t cand_cap = 0;
   int scan_blocks = 0;
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_cnt, off_tile_start,
-      off_cursor, off_items_raw, off_items, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_kstat,
+      off_cursor, off_items_raw, off_visit_raw, off_items, off_kcnt, off_kstart, off_kmap, off_partials,
+      off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_kstat,
       off_counters, off_hist, off_cand, off_keep, off_misc;
   size_t bytes = 0;
 };
@@ -93,7 +94,7 @@ Layout make_layout(const erbf_config* cfg) {
     }
   }
   L.cand_cap = L.pts_total / 20 + 1024;
-  L.scan_blocks = (L.tiles_total + 1) / 1024 + 2;
+  L.scan_blocks = (std::max(L.tiles_total, L.cap_total) + 1) / 1024 + 2;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   L.off_levels = take(sizeof(LevelDev) * L.n_levels_total);
@@ -105,7 +106,13 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_tile_start = take(sizeof(int32_t) * (L.tiles_total + 1));
   L.off_cursor = take(sizeof(int32_t) * L.tiles_total);
   L.off_items_raw = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_visit_raw = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
+  L.off_kstart = take(sizeof(int32_t) * (L.cap_total + 1));
+  L.off_kmap = take(sizeof(int2) * cfg->pair_cap);
+  L.off_partials = take(sizeof(float4) * 3 * cfg->pair_cap);
+  L.off_tile_nz = take(sizeof(int32_t) * L.tiles_total);
   L.off_scan = take(sizeof(int32_t) * L.scan_blocks);
   L.off_rflags = take(sizeof(int32_t) * (L.max_level_tiles + 1));
   L.off_rexcl = take(sizeof(int32_t) * (L.max_level_tiles + 1));
@@ -135,6 +142,13 @@ struct erbf_ctx {
   int slots_used = 0;
   int32_t* rflags = nullptr;
   int32_t* rexcl = nullptr;
+  // optional kernel timing: six events per recorded call (start/stop of the
+  // forward, backward-tiles and backward-reduce kernels)
+  std::vector<hipEvent_t> tev;
+  int t_max = 0, t_used = 0;
+  ~erbf_ctx() {
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -149,6 +163,14 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+constexpr int kEvPerCall = 6;
+
+// events of the current timed call (nullptr when not timing)
+const hipEvent_t* tev_call(erbf_ctx* c) {
+  if (c->t_used >= c->t_max) return nullptr;
+  return &c->tev[kEvPerCall * c->t_used];
+}
 
 int check_params(const erbf_ctx* ctx, const erbf_params* p) {
   if (!ctx) return fail(ERBF_ERR_INVALID_ARG, "ctx is NULL");
@@ -206,7 +228,13 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.tile_start = reinterpret_cast<int32_t*>(w + lay.off_tile_start);
   D.cursor = reinterpret_cast<int32_t*>(w + lay.off_cursor);
   D.items_raw = reinterpret_cast<int32_t*>(w + lay.off_items_raw);
+  D.visit_raw = reinterpret_cast<int32_t*>(w + lay.off_visit_raw);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
+  D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
+  D.kstart = reinterpret_cast<int32_t*>(w + lay.off_kstart);
+  D.kmap = reinterpret_cast<int2*>(w + lay.off_kmap);
+  D.partials = reinterpret_cast<float4*>(w + lay.off_partials);
+  D.tile_nz = reinterpret_cast<int32_t*>(w + lay.off_tile_nz);
   D.scan_blocks = reinterpret_cast<int32_t*>(w + lay.off_scan);
   c->rflags = reinterpret_cast<int32_t*>(w + lay.off_rflags);
   c->rexcl = reinterpret_cast<int32_t*>(w + lay.off_rexcl);
@@ -355,7 +383,7 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
     }
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "eval: prologue");
   HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "eval: buckets");
-  HIP_TRY(launch_forward(D, ctx->slots_used, false, f_out, 0.f, 0.f, stream), "eval: forward");
+  HIP_TRY(launch_forward(D, ctx->slots_used, false, f_out, 0.f, 0.f, nullptr, stream), "eval: forward");
   if (stats_dev) {
     StatsArgs a{};
     HIP_TRY(launch_stats(D, 0, params->p, params->m_dev, nullptr, stats_dev, a, stream), "eval: stats");
@@ -382,8 +410,11 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
       }
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "loss: prologue");
   HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "loss: buckets");
-  HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, stream), "loss: forward");
-  HIP_TRY(launch_backward(D, params->p, D.G, grad_out, stream), "loss: backward");
+  const hipEvent_t* ev = tev_call(ctx);
+  HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, ev, stream), "loss: forward");
+  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
+          "loss: backward");
+  if (ev) ctx->t_used += 1;
   StatsArgs a{};
   a.mode = cfg->mode;
   a.lambda = cfg->lambda;
@@ -405,12 +436,21 @@ int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, floa
   DeviceGuard guard(ctx->device);
   const Dev& D = ctx->D;
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "vjp: prologue");
+  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "vjp: buckets");
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l) {
       const LevelDev& L = ctx->lv[s.lvl0 + l];
       HIP_TRY(launch_mask_copy(D, s.lvl0 + l, (int64_t)L.n * L.n * L.n, grad_f, stream), "vjp: mask");
     }
-  HIP_TRY(launch_backward(D, params->p, D.G, grad_out, stream), "vjp: backward");
+  const hipEvent_t* ev = tev_call(ctx);
+  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
+          "vjp: backward");
+  if (ev) {
+    // no forward in a VJP: give its pair of events a zero-length interval
+    HIP_TRY(hipEventRecord(ev[0], stream), "vjp: event");
+    HIP_TRY(hipEventRecord(ev[1], stream), "vjp: event");
+    ctx->t_used += 1;
+  }
   if (stats_dev) {
     StatsArgs a{};
     HIP_TRY(launch_stats(D, 1, params->p, params->m_dev, grad_out, stats_dev, a, stream), "vjp: stats");
@@ -427,6 +467,39 @@ int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, 
   DeviceGuard guard(ctx->device);
   AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps};
   HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad, m1, m2, step_dev, a, stream), "adam");
+  return ERBF_OK;
+}
+
+int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls) {
+  if (!ctx || max_calls < 0) return fail(ERBF_ERR_INVALID_ARG, "erbf_timing_enable: bad arguments");
+  DeviceGuard guard(ctx->device);
+  const size_t need = kEvPerCall * (size_t)max_calls;
+  while (ctx->tev.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    ctx->tev.push_back(e);
+  }
+  ctx->t_max = max_calls;
+  ctx->t_used = 0;
+  return ERBF_OK;
+}
+
+int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls) {
+  if (!ctx || !ms) return fail(ERBF_ERR_INVALID_ARG, "erbf_timing_read: NULL argument");
+  DeviceGuard guard(ctx->device);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < ctx->t_used; ++k) {
+    const hipEvent_t* e = &ctx->tev[kEvPerCall * k];
+    HIP_TRY(hipEventSynchronize(e[5]), "timing: sync");
+    for (int i = 0; i < 3; ++i) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, e[2 * i], e[2 * i + 1]), "timing: elapsed");
+      acc[i] += t;
+    }
+  }
+  for (int i = 0; i < 3; ++i) ms[i] = acc[i];
+  if (n_calls) *n_calls = ctx->t_used;
+  ctx->t_used = 0;
   return ERBF_OK;
 }
 

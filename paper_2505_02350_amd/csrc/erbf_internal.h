@@ -41,6 +41,7 @@ struct TileStat {
   double l2;
   float max_abs_e;
   int32_t n_idall;
+  int64_t p_fwd;           // in-ball pairs at active points of the tile
 };
 
 // Per-kernel counters written by the backward pass.
@@ -61,8 +62,14 @@ struct Dev {
   int32_t* tile_cnt;        // [tiles_total + 1]
   int32_t* tile_start;      // [tiles_total + 1]
   int32_t* cursor;          // [tiles_total]
-  int32_t* items_raw;       // [pair_cap]
-  int32_t* items;           // [pair_cap]
+  int32_t* items_raw;       // [pair_cap] kernel ids in arrival order
+  int32_t* visit_raw;       // [pair_cap] per-kernel visit index of each raw entry
+  int32_t* items;           // [pair_cap] kernel ids, ascending within each tile
+  int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
+  int32_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
+  int2* kmap;               // [pair_cap] (entry, tile slot) of each kernel's entries, visit order
+  float4* partials;         // [3 * pair_cap] backward moments of each (tile, kernel) entry
+  int32_t* tile_nz;         // [tiles_total] tile has a non-zero upstream gradient
   int32_t* scan_blocks;     // [scan block sums]
   // per step
   float4* rec;              // [3 * cap_total]

@@ -6,14 +6,17 @@
 //   forward    point-centric gather over the tile's kernel list staged in LDS,
 //              fused residual / id_all mask / loss partials (eq. 3-9, 3-15-1,
 //              3-18, 3-19)
-//   backward   kernel-centric: one workgroup walks the rows of its own ball,
-//              10 FP64 moment accumulators, fixed-order wave/LDS reductions,
-//              no float atomics (Appendix A with a quaternion chain rule)
+//   backward   tile-centric moments: lanes own the tile's kernels and walk the
+//              tile's points with non-zero upstream gradient; a second pass
+//              sums each kernel's per-tile moments in a fixed order in FP64
+//              and forms the gradients (Appendix A, quaternion chain rule);
+//              no float atomics
 //   stats      per-shape loss statistics, eq. 3-21 weights, gradient combine
 //   adam       fused bias-corrected Adam over the packed parameters
 //
 // Every reduction runs in a fixed order, so results are bitwise reproducible.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -136,18 +139,28 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
-// buckets: tiles whose point box meets the (slightly enlarged) ball
+// buckets: tiles whose point box meets the (slightly enlarged) ball.
+// One wave per kernel slot; lanes test the tiles of the ball's tile box.  A
+// kernel's tiles are numbered in a fixed order (level, z, y, x): that visit
+// index lets the backward reduce a kernel's per-tile partials in a fixed
+// order.
 // ---------------------------------------------------------------------------
 
 template <bool SCATTER>
 __global__ __launch_bounds__(256) void k_bucket(Dev D) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= D.cap_total) return;
   const float4 r0 = D.rec[3 * j];
-  if (r0.w < 0.f) return;
+  if (r0.w < 0.f) {
+    if (!SCATTER && lane == 0) D.kcnt[j] = 0;
+    return;
+  }
   const ShapeDev S = D.shapes[D.kshape[j]];
   const float rr = sqrtf(r0.w) * (1.0f + 1e-5f) + 1e-6f;
   const float rc2 = rr * rr;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  int vbase = 0;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
     int ix0, ix1, iy0, iy1, iz0, iz1;
@@ -156,36 +169,50 @@ __global__ __launch_bounds__(256) void k_bucket(Dev D) {
     index_range(L, r0.z - rr, r0.z + rr, iz0, iz1);
     if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
     const int nt = L.nt, n = L.n;
-    for (int tz = iz0 / kTile; tz <= iz1 / kTile; ++tz) {
-      const float zlo = L.axis[tz * kTile], zhi = L.axis[min(tz * kTile + kTile - 1, n - 1)];
-      const float ez = fmaxf(fmaxf(zlo - r0.z, r0.z - zhi), 0.f);
-      for (int ty = iy0 / kTile; ty <= iy1 / kTile; ++ty) {
+    const int tx0 = ix0 / kTile, ty0 = iy0 / kTile, tz0 = iz0 / kTile;
+    const int ntx = ix1 / kTile - tx0 + 1, nty = iy1 / kTile - ty0 + 1, ntz = iz1 / kTile - tz0 + 1;
+    const int total = ntx * nty * ntz;
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      bool hit = false;
+      int slot = -1;
+      if (idx < total) {
+        const int tx = tx0 + idx % ntx, ty = ty0 + (idx / ntx) % nty, tz = tz0 + idx / (ntx * nty);
+        const float xlo = L.axis[tx * kTile], xhi = L.axis[min(tx * kTile + kTile - 1, n - 1)];
         const float ylo = L.axis[ty * kTile], yhi = L.axis[min(ty * kTile + kTile - 1, n - 1)];
+        const float zlo = L.axis[tz * kTile], zhi = L.axis[min(tz * kTile + kTile - 1, n - 1)];
+        const float ex = fmaxf(fmaxf(xlo - r0.x, r0.x - xhi), 0.f);
         const float ey = fmaxf(fmaxf(ylo - r0.y, r0.y - yhi), 0.f);
-        const float eyz = ey * ey + ez * ez;
-        if (eyz >= rc2) continue;
-        for (int tx = ix0 / kTile; tx <= ix1 / kTile; ++tx) {
-          const float xlo = L.axis[tx * kTile], xhi = L.axis[min(tx * kTile + kTile - 1, n - 1)];
-          const float ex = fmaxf(fmaxf(xlo - r0.x, r0.x - xhi), 0.f);
-          if (ex * ex + eyz >= rc2) continue;
-          const int slot = D.tile_map[L.tmap0 + (tz * nt + ty) * nt + tx];
-          if (slot < 0) continue;
-          if (SCATTER) {
-            const int pos = atomicAdd(&D.cursor[slot], 1);
-            const int64_t at = (int64_t)D.tile_start[slot] + pos;
-            if (at < D.pair_cap) D.items_raw[at] = j;
-          } else {
-            atomicAdd(&D.tile_cnt[slot], 1);
-          }
+        const float ez = fmaxf(fmaxf(zlo - r0.z, r0.z - zhi), 0.f);
+        if (ex * ex + ey * ey + ez * ez < rc2) {
+          slot = D.tile_map[L.tmap0 + (tz * nt + ty) * nt + tx];
+          hit = slot >= 0;
         }
       }
+      const unsigned long long bal = __ballot(hit);
+      if (hit) {
+        if (SCATTER) {
+          const int v = vbase + __popcll(bal & lt_mask);
+          const int pos = atomicAdd(&D.cursor[slot], 1);
+          const int64_t at = (int64_t)D.tile_start[slot] + pos;
+          if (at < D.pair_cap) {
+            D.items_raw[at] = j;
+            D.visit_raw[at] = v;
+          }
+        } else {
+          atomicAdd(&D.tile_cnt[slot], 1);
+        }
+      }
+      vbase += __popcll(bal);
     }
   }
+  if (!SCATTER && lane == 0) D.kcnt[j] = vbase;
 }
 
-// Per-tile ascending sort of the bucket list (fixes the summation order).
+// Per-tile ascending sort of the bucket list (fixes the forward's summation
+// order) and the kernel-major map of entries used by the backward reduction.
 __global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
-  __shared__ int buf[4096];
+  __shared__ int2 buf[4096];
   const int s = blockIdx.x;
   const int64_t beg = min((int64_t)D.tile_start[s], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[s + 1], D.pair_cap);
@@ -195,22 +222,28 @@ __global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
   if (cnt <= 4096) {
     int pw = 1;
     while (pw < cnt) pw <<= 1;
-    for (int i = tid; i < pw; i += blockDim.x) buf[i] = i < cnt ? D.items_raw[beg + i] : INT32_MAX;
+    for (int i = tid; i < pw; i += blockDim.x)
+      buf[i] = i < cnt ? make_int2(D.items_raw[beg + i], D.visit_raw[beg + i]) : make_int2(INT32_MAX, 0);
     __syncthreads();
     for (int k = 2; k <= pw; k <<= 1) {
       for (int jj = k >> 1; jj > 0; jj >>= 1) {
         for (int i = tid; i < pw; i += blockDim.x) {
           const int ixj = i ^ jj;
           if (ixj > i) {
-            const int a = buf[i], bb = buf[ixj];
+            const int2 a = buf[i], bb = buf[ixj];
             const bool up = (i & k) == 0;
-            if ((a > bb) == up) { buf[i] = bb; buf[ixj] = a; }
+            if ((a.x > bb.x) == up) { buf[i] = bb; buf[ixj] = a; }
           }
         }
         __syncthreads();
       }
     }
-    for (int i = tid; i < cnt; i += blockDim.x) D.items[beg + i] = buf[i];
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const int2 e = buf[i];
+      D.items[beg + i] = e.x;
+      const int64_t km = (int64_t)D.kstart[e.x] + e.y;
+      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + i), s);
+    }
   } else {
     // long list: rank of each (distinct) kernel id
     for (int i = tid; i < cnt; i += blockDim.x) {
@@ -218,6 +251,8 @@ __global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
       int rank = 0;
       for (int k = 0; k < cnt; ++k) rank += D.items_raw[beg + k] < v;
       D.items[beg + rank] = v;
+      const int64_t km = (int64_t)D.kstart[v] + D.visit_raw[beg + i];
+      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + rank), s);
     }
   }
 }
@@ -305,6 +340,7 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
   __shared__ double red_d[4];
   __shared__ float red_f[4];
   __shared__ int red_i[4];
+  __shared__ int64_t red_p[4];
 
   const int slot = blockIdx.x;
   const int2 lt = D.slot_tile[slot];
@@ -332,6 +368,14 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
     bz0[h] = L.axis[min(tz * kTile + 4 * h, n - 1)];
     bz1[h] = L.axis[min(tz * kTile + 4 * h + 3, n - 1)];
   }
+
+  // training points of this lane (inside the grid and the level's mask)
+  const bool vyz = yi < n && zi < n;
+  const int64_t local0 = ((int64_t)min(zi, n - 1) * n + min(yi, n - 1)) * n + min(xi0, n - 1);
+  const bool act0 = vyz && xi0 < n && point_active(L.bits, local0);
+  const bool act1 = vyz && xi0 + 1 < n && point_active(L.bits, local0 + 1);
+  const unsigned long long act_mask0 = __ballot(act0), act_mask1 = __ballot(act1);
+  int64_t pfw = 0;   // in-ball pairs at this wave's training points (wave-uniform)
 
   float acc0 = 0.f, acc1 = 0.f;
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
@@ -387,10 +431,13 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
       const float dx0 = px0 - a0.x, dx1 = px1 - a0.x;
       float q0 = fmaf(dx0, fmaf(a1.x, dx0, bl), cc);
       float q1 = fmaf(dx1, fmaf(a1.x, dx1, bl), cc);
-      q0 = fmaf(dx0, dx0, syz) < a0.w ? q0 : INFINITY;
-      q1 = fmaf(dx1, dx1, syz) < a0.w ? q1 : INFINITY;
+      const bool in0 = fmaf(dx0, dx0, syz) < a0.w;
+      const bool in1 = fmaf(dx1, dx1, syz) < a0.w;
+      q0 = in0 ? q0 : INFINITY;
+      q1 = in1 ? q1 : INFINITY;
       acc0 = fmaf(a2.z, fast_exp2(-q0), acc0);
       acc1 = fmaf(a2.z, fast_exp2(-q1), acc1);
+      pfw += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
     }
     __syncthreads();
   }
@@ -399,7 +446,6 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
   double l2 = 0.0;
   float mxe = 0.f;
   int cnt_id = 0;
-  const bool vyz = yi < n && zi < n;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int xi = xi0 + h;
@@ -426,208 +472,239 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
     l2 = wave_sum(l2);
     mxe = wave_max_f(mxe);
     cnt_id = wave_sum(cnt_id);
-    if (lane == 0) { red_d[wv] = l2; red_f[wv] = mxe; red_i[wv] = cnt_id; }
-    __syncthreads();
-    if (tid == 0) {
-      TileStat ts;
-      ts.l2 = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
-      ts.max_abs_e = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
-      ts.n_idall = red_i[0] + red_i[1] + red_i[2] + red_i[3];
-      D.tstat[slot] = ts;
-    }
+  }
+  if (lane == 0) { red_d[wv] = l2; red_f[wv] = mxe; red_i[wv] = cnt_id; red_p[wv] = pfw; }
+  __syncthreads();
+  if (tid == 0) {
+    TileStat ts;
+    ts.l2 = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+    ts.max_abs_e = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
+    ts.n_idall = red_i[0] + red_i[1] + red_i[2] + red_i[3];
+    ts.p_fwd = (red_p[0] + red_p[1]) + (red_p[2] + red_p[3]);
+    D.tstat[slot] = ts;
   }
 }
 
 // ---------------------------------------------------------------------------
-// backward: one workgroup (4 waves) per kernel slot.  The ball's rows
-// (fixed y, z) are visited in 8x8 patches, one patch per wave and one row per
-// lane; each lane walks its row's exact in-ball x interval.
+// backward, stage 1: one workgroup per active tile.  The tile's points with a
+// non-zero upstream gradient are staged in LDS in (z, y, x) order; each lane
+// owns one kernel of the tile's list and walks those points, so every branch
+// of the walk (row changes, empty tiles) is uniform across the wave.  Per
+// row the lane keeps three sums over x (sum g, sum g dx, sum g dx^2) and folds
+// them into the ten moments with the row's dy, dz:
+//   T0 = sum g, T1 = sum g D, T2 = sum g D D^T,  g = G exp(-D^T A D)
+// The moments of each (tile, kernel) entry go to `partials`.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void block_reduce_doubles(double* v, int nv, double* sh /*[4*nv]*/) {
+__global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
+  __shared__ float4 spt[kTile * kTile * kTile];
+  __shared__ int srow[kTile * kTile * kTile];
+  __shared__ int swc[2][4];
+
+  const int slot = blockIdx.x;
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  const int n = L.n, nt = L.nt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = 0; i < nv; ++i) {
-    const double s = wave_sum(v[i]);
-    if (lane == 0) sh[wv * nv + i] = s;
+  const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
+  const float* __restrict__ G = Gsrc + L.pt_base;
+
+  // stage the non-zero points in local-index order (p = t + 256 h)
+  float4 pt[2];
+  int prow[2];
+  bool nz[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = tid + 256 * h;
+    const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
+    float g = 0.f;
+    if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
+    nz[h] = g != 0.f;
+    prow[h] = p >> 3;
+    pt[h] = nz[h] ? make_float4(L.axis[xi], L.axis[yi], L.axis[zi], g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  unsigned long long bal[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    bal[h] = __ballot(nz[h]);
+    if (lane == 0) swc[h][wv] = __popcll(bal[h]);
   }
   __syncthreads();
-  for (int i = 0; i < nv; ++i) v[i] = (sh[i] + sh[nv + i]) + (sh[2 * nv + i] + sh[3 * nv + i]);
+  int off0 = 0, tot0 = 0, tot1 = 0;
+  for (int v = 0; v < 4; ++v) {
+    if (v < wv) off0 += swc[0][v];
+    tot0 += swc[0][v];
+    tot1 += swc[1][v];
+  }
+  int off1 = tot0;
+  for (int v = 0; v < wv; ++v) off1 += swc[1][v];
+  if (nz[0]) {
+    const int k = off0 + __popcll(bal[0] & lt_mask);
+    spt[k] = pt[0];
+    srow[k] = prow[0];
+  }
+  if (nz[1]) {
+    const int k = off1 + __popcll(bal[1] & lt_mask);
+    spt[k] = pt[1];
+    srow[k] = prow[1];
+  }
+  const int Z = tot0 + tot1;
+  if (tid == 0) D.tile_nz[slot] = Z > 0;
+  if (Z == 0) return;
+  __syncthreads();
+
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  for (int64_t c0 = beg; c0 < end; c0 += 256) {
+    const bool have = c0 + tid < end;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
+           r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (have) {
+      const int j = D.items[c0 + tid];
+      r0 = D.rec[3 * j];
+      r1 = D.rec[3 * j + 1];
+      r2 = D.rec[3 * j + 2];
+    }
+    const float cx = r0.x, cy = r0.y, cz = r0.z, rad2 = r0.w;
+    const float A00 = r1.x, A11 = r1.y, A22 = r1.z, A01x2 = r1.w, A02x2 = r2.x, A12x2 = r2.y;
+    float T[10];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) T[i] = 0.f;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, cnt = 0.f;
+    float dy = 0.f, dz = 0.f, syz = 0.f, bl = 0.f, cc = 0.f;
+    int cur = -1;
+    for (int k = 0; k < Z; ++k) {
+      const float4 P = spt[k];
+      const int row = srow[k];
+      if (row != cur) {
+        T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
+        T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
+        T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
+        s0 = s1 = s2 = 0.f;
+        dy = P.y - cy;
+        dz = P.z - cz;
+        syz = fmaf(dy, dy, dz * dz);
+        bl = fmaf(A01x2, dy, A02x2 * dz);
+        cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
+        cur = row;
+      }
+      const float dx = P.x - cx;
+      const bool in = fmaf(dx, dx, syz) < rad2;
+      float q = fmaf(dx, fmaf(A00, dx, bl), cc);
+      q = in ? q : INFINITY;
+      const float g = P.w * fast_exp2(-q);
+      s0 += g;
+      const float gx = g * dx;
+      s1 += gx;
+      s2 = fmaf(gx, dx, s2);
+      cnt += in ? 1.f : 0.f;
+    }
+    T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
+    T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
+    T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
+    if (have) {
+      float4* o = D.partials + 3 * (c0 + tid);
+      o[0] = make_float4(T[0], T[1], T[2], T[3]);
+      o[1] = make_float4(T[4], T[5], T[6], T[7]);
+      o[2] = make_float4(T[8], T[9], cnt, 0.f);
+    }
+  }
 }
 
-template <bool COUNT_FWD>
-__global__ __launch_bounds__(256) void k_backward(Dev D, const float* __restrict__ p,
-                                                  const float* __restrict__ Gsrc,
-                                                  float* __restrict__ grad) {
-  __shared__ double sh[4 * 12];
+// ---------------------------------------------------------------------------
+// backward, stage 2: one wave per kernel slot.  Sums the kernel's per-tile
+// moments in its fixed visit order (lane-strided, then a fixed butterfly) in
+// float64 and turns them into gradients (Appendix A; quaternion chain rule).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restrict__ p,
+                                                   float* __restrict__ grad) {
   const int j = blockIdx.x;
   const int C = D.cap_total;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lane = threadIdx.x;
   const float4 r0 = D.rec[3 * j];
   if (r0.w < 0.f) {
-    if (tid < 11) grad[tid * C + j] = 0.f;
-    if (tid == 0) { D.kstat[j].p_fwd = 0; D.kstat[j].p_bwd = 0; }
+    if (lane < 11) grad[lane * C + j] = 0.f;
+    if (lane == 0) { D.kstat[j].p_fwd = 0; D.kstat[j].p_bwd = 0; }
     return;
   }
-  const float4 r1 = D.rec[3 * j + 1], r2 = D.rec[3 * j + 2];
-  const float cx = r0.x, cy = r0.y, cz = r0.z, rad2 = r0.w;
-  const float A00 = r1.x, A11 = r1.y, A22 = r1.z, A01x2 = r1.w, A02x2 = r2.x, A12x2 = r2.y;
-  const ShapeDev S = D.shapes[D.kshape[j]];
-  const float rr = sqrtf(rad2) * (1.0f + 1e-5f) + 1e-6f;
-
-  double T[10];
+  double v[11];
 #pragma unroll
-  for (int i = 0; i < 10; ++i) T[i] = 0.0;
-  int64_t pf = 0, pb = 0;
-
-  for (int li = 0; li < S.n_active; ++li) {
-    const LevelDev L = D.levels[S.lvl0 + li];
-    const int n = L.n;
-    int ix0, ix1, iy0, iy1, iz0, iz1;
-    index_range(L, cx - rr, cx + rr, ix0, ix1);
-    index_range(L, cy - rr, cy + rr, iy0, iy1);
-    index_range(L, cz - rr, cz + rr, iz0, iz1);
-    if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
-    const int ny = iy1 - iy0 + 1, nz = iz1 - iz0 + 1;
-    const int npy = (ny + 7) >> 3, npz = (nz + 7) >> 3;
-    const int npatch = npy * npz;
-    const float h = L.h;
-    const float* __restrict__ G = Gsrc + L.pt_base;
-    for (int pc = wv; pc < npatch; pc += 4) {
-      const int pyi = pc % npy, pzi = pc / npy;
-      const int jy = iy0 + pyi * 8 + (lane & 7);
-      const int kz = iz0 + pzi * 8 + (lane >> 3);
-      int lo = 0, len = 0;
-      float dy = 0.f, dz = 0.f, syz = 0.f;
-      if (jy <= iy1 && kz <= iz1) {
-        dy = L.axis[jy] - cy;
-        dz = L.axis[kz] - cz;
-        syz = fmaf(dy, dy, dz * dz);
-        if (syz < rad2) {
-          const float half = sqrtf(rad2 - syz);
-          int a, b;
-          index_range(L, cx - half, cx + half, a, b);
-          a = max(a, ix0);
-          b = min(b, ix1);
-          while (a <= b) {
-            const float dxa = L.axis[a] - cx;
-            if (fmaf(dxa, dxa, syz) < rad2) break;
-            ++a;
-          }
-          while (b >= a) {
-            const float dxb = L.axis[b] - cx;
-            if (fmaf(dxb, dxb, syz) < rad2) break;
-            --b;
-          }
-          lo = a;
-          len = b - a + 1;
-        }
-      }
-      const int maxlen = wave_max_i(len);
-      if (maxlen == 0) continue;
-      const int64_t rowoff = ((int64_t)kz * n + jy) * n;
-      if (COUNT_FWD && len > 0) {
-        pf += L.bits ? popcount_range(L.bits, rowoff + lo, rowoff + lo + len - 1) : len;
-      }
-      const float bl = fmaf(A01x2, dy, A02x2 * dz);
-      const float cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
-      const float dxlo = len > 0 ? L.axis[lo] - cx : 0.f;
-      const float* __restrict__ grow = G + rowoff + lo;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-      int nzc = 0;
-      for (int t = 0; t < maxlen; ++t) {
-        if (t < len) {
-          const float g = grow[t];
-          const float dx = fmaf((float)t, h, dxlo);
-          const float q = fmaf(dx, fmaf(A00, dx, bl), cc);
-          const float gp = g * fast_exp2(-q);
-          s0 += gp;
-          const float gx = gp * dx;
-          s1 += gx;
-          s2 = fmaf(gx, dx, s2);
-          nzc += g != 0.f;
-        }
-      }
-      pb += nzc;
-      const double S0 = s0, S1 = s1, S2 = s2, DY = dy, DZ = dz;
-      T[0] += S0;
-      T[1] += S1;
-      T[2] += DY * S0;
-      T[3] += DZ * S0;
-      T[4] += S2;           // xx
-      T[5] += DY * S1;      // xy
-      T[6] += DZ * S1;      // xz
-      T[7] += DY * DY * S0; // yy
-      T[8] += DY * DZ * S0; // yz
-      T[9] += DZ * DZ * S0; // zz
-    }
+  for (int i = 0; i < 11; ++i) v[i] = 0.0;
+  const int64_t base = D.kstart[j];
+  const int c = D.kcnt[j];
+  for (int e = lane; e < c; e += 64) {
+    if (base + e >= D.pair_cap) break;
+    const int2 km = D.kmap[base + e];
+    if (km.x < 0 || (int64_t)km.x >= D.pair_cap || km.y < 0 || km.y >= D.tiles_total) continue;
+    if (!D.tile_nz[km.y]) continue;
+    const float4* q = D.partials + 3 * (int64_t)km.x;
+    const float4 a = q[0], b = q[1], d = q[2];
+    v[0] += a.x; v[1] += a.y; v[2] += a.z; v[3] += a.w;
+    v[4] += b.x; v[5] += b.y; v[6] += b.z; v[7] += b.w;
+    v[8] += d.x; v[9] += d.y; v[10] += d.z;
   }
-
-  double v[12];
 #pragma unroll
-  for (int i = 0; i < 10; ++i) v[i] = T[i];
-  v[10] = (double)pf;
-  v[11] = (double)pb;
-  block_reduce_doubles(v, 12, sh);
+  for (int i = 0; i < 11; ++i) v[i] = wave_sum(v[i]);
+  if (lane != 0) return;
 
-  if (tid == 0) {
-    // epilogue in double: gradients from the moments
-    const double w = p[j];
-    const double s[3] = {p[4 * C + j], p[5 * C + j], p[6 * C + j]};
-    double q[4] = {p[7 * C + j], p[8 * C + j], p[9 * C + j], p[10 * C + j]};
-    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    double qh[4];
-    if (qn > 0.0) {
-      for (int k = 0; k < 4; ++k) qh[k] = q[k] / qn;
-    } else {
-      qh[0] = 1.0; qh[1] = qh[2] = qh[3] = 0.0; qn = 1.0;
-    }
-    const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
-    double R[3][3];
-    R[0][0] = 1 - 2 * (qy * qy + qz * qz); R[0][1] = 2 * (qx * qy - qw * qz); R[0][2] = 2 * (qx * qz + qw * qy);
-    R[1][0] = 2 * (qx * qy + qw * qz); R[1][1] = 1 - 2 * (qx * qx + qz * qz); R[1][2] = 2 * (qy * qz - qw * qx);
-    R[2][0] = 2 * (qx * qz - qw * qy); R[2][1] = 2 * (qy * qz + qw * qx); R[2][2] = 1 - 2 * (qx * qx + qy * qy);
-    double d2[3];
-    for (int k = 0; k < 3; ++k) d2[k] = exp(2.0 * s[k]);
-    const double amp = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? w * fabs(w) : w;
-    const double dadw = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? 2.0 * fabs(w) : 1.0;
-    const double T1[3] = {v[1], v[2], v[3]};
-    const double T2[3][3] = {{v[4], v[5], v[6]}, {v[5], v[7], v[8]}, {v[6], v[8], v[9]}};
-    // dL/dw
-    const double gw = v[0] * dadw;
-    // dL/dc = 2 a A T1, A = R^T D^2 R
-    double u1[3];
-    for (int k = 0; k < 3; ++k) u1[k] = d2[k] * (R[k][0] * T1[0] + R[k][1] * T1[1] + R[k][2] * T1[2]);
-    double gc[3];
-    for (int l = 0; l < 3; ++l) gc[l] = 2.0 * amp * (R[0][l] * u1[0] + R[1][l] * u1[1] + R[2][l] * u1[2]);
-    // RT2 = R T2
-    double RT2[3][3];
-    for (int k = 0; k < 3; ++k)
-      for (int l = 0; l < 3; ++l) RT2[k][l] = R[k][0] * T2[0][l] + R[k][1] * T2[1][l] + R[k][2] * T2[2][l];
-    // dL/ds_k = -2 a d_k^2 r_k^T T2 r_k
-    double gs[3];
-    for (int k = 0; k < 3; ++k)
-      gs[k] = -2.0 * amp * d2[k] * (RT2[k][0] * R[k][0] + RT2[k][1] * R[k][1] + RT2[k][2] * R[k][2]);
-    // dL/dR = -2 a D^2 R T2
-    double gR[3][3];
-    for (int k = 0; k < 3; ++k)
-      for (int l = 0; l < 3; ++l) gR[k][l] = -2.0 * amp * d2[k] * RT2[k][l];
-    // dL/dqhat through dR/dqhat
-    double gq[4];
-    gq[0] = 2 * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
-    gq[1] = 2 * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2 * qx * gR[1][1] - qw * gR[1][2] + qz * gR[2][0] +
-                 qw * gR[2][1] - 2 * qx * gR[2][2]);
-    gq[2] = 2 * (-2 * qy * gR[0][0] + qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] + qz * gR[1][2] - qw * gR[2][0] +
-                 qz * gR[2][1] - 2 * qy * gR[2][2]);
-    gq[3] = 2 * (-2 * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] - 2 * qz * gR[1][1] +
-                 qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
-    const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
-    grad[j] = (float)gw;
-    for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
-    for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
-    for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
-    D.kstat[j].p_fwd = (int64_t)v[10];
-    D.kstat[j].p_bwd = (int64_t)v[11];
+  const double w = p[j];
+  const double s[3] = {p[4 * C + j], p[5 * C + j], p[6 * C + j]};
+  const double q4[4] = {p[7 * C + j], p[8 * C + j], p[9 * C + j], p[10 * C + j]};
+  double qn = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+  double qh[4];
+  if (qn > 0.0) {
+    for (int k = 0; k < 4; ++k) qh[k] = q4[k] / qn;
+  } else {
+    qh[0] = 1.0; qh[1] = qh[2] = qh[3] = 0.0; qn = 1.0;
   }
+  const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
+  double R[3][3];
+  R[0][0] = 1 - 2 * (qy * qy + qz * qz); R[0][1] = 2 * (qx * qy - qw * qz); R[0][2] = 2 * (qx * qz + qw * qy);
+  R[1][0] = 2 * (qx * qy + qw * qz); R[1][1] = 1 - 2 * (qx * qx + qz * qz); R[1][2] = 2 * (qy * qz - qw * qx);
+  R[2][0] = 2 * (qx * qz - qw * qy); R[2][1] = 2 * (qy * qz + qw * qx); R[2][2] = 1 - 2 * (qx * qx + qy * qy);
+  double d2[3];
+  for (int k = 0; k < 3; ++k) d2[k] = exp(2.0 * s[k]);
+  const double amp = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? w * fabs(w) : w;
+  const double dadw = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? 2.0 * fabs(w) : 1.0;
+  const double T1[3] = {v[1], v[2], v[3]};
+  const double T2[3][3] = {{v[4], v[5], v[6]}, {v[5], v[7], v[8]}, {v[6], v[8], v[9]}};
+  // dL/dw
+  const double gw = v[0] * dadw;
+  // dL/dc = 2 a A T1, A = R^T D^2 R
+  double u1[3];
+  for (int k = 0; k < 3; ++k) u1[k] = d2[k] * (R[k][0] * T1[0] + R[k][1] * T1[1] + R[k][2] * T1[2]);
+  double gc[3];
+  for (int l = 0; l < 3; ++l) gc[l] = 2.0 * amp * (R[0][l] * u1[0] + R[1][l] * u1[1] + R[2][l] * u1[2]);
+  // RT2 = R T2
+  double RT2[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) RT2[k][l] = R[k][0] * T2[0][l] + R[k][1] * T2[1][l] + R[k][2] * T2[2][l];
+  // dL/ds_k = -2 a d_k^2 r_k^T T2 r_k
+  double gs[3];
+  for (int k = 0; k < 3; ++k)
+    gs[k] = -2.0 * amp * d2[k] * (RT2[k][0] * R[k][0] + RT2[k][1] * R[k][1] + RT2[k][2] * R[k][2]);
+  // dL/dR = -2 a D^2 R T2
+  double gR[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) gR[k][l] = -2.0 * amp * d2[k] * RT2[k][l];
+  // dL/dqhat through dR/dqhat
+  double gq[4];
+  gq[0] = 2 * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
+  gq[1] = 2 * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2 * qx * gR[1][1] - qw * gR[1][2] + qz * gR[2][0] +
+               qw * gR[2][1] - 2 * qx * gR[2][2]);
+  gq[2] = 2 * (-2 * qy * gR[0][0] + qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] + qz * gR[1][2] - qw * gR[2][0] +
+               qz * gR[2][1] - 2 * qy * gR[2][2]);
+  gq[3] = 2 * (-2 * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] - 2 * qz * gR[1][1] +
+               qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
+  const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+  grad[j] = (float)gw;
+  for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
+  for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
+  for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
+  D.kstat[j].p_fwd = 0;
+  D.kstat[j].p_bwd = (int64_t)v[10];
 }
 
 // ---------------------------------------------------------------------------
@@ -684,7 +761,7 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
 
   double l2 = 0.0, nid = 0.0, pf = 0.0, pb = 0.0;
   float mx = 0.f;
-  if (MODE == 2) {
+  if (MODE != 1) {
     for (int li = 0; li < S.n_active; ++li) {
       const LevelDev L = D.levels[S.lvl0 + li];
       for (int s = tid; s < L.n_slots; s += 1024) {
@@ -692,14 +769,12 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
         l2 += ts.l2;
         nid += (double)ts.n_idall;
         mx = fmaxf(mx, ts.max_abs_e);
+        pf += (double)ts.p_fwd;
       }
     }
   }
   if (MODE >= 1) {
-    for (int k = tid; k < m; k += 1024) {
-      pf += (double)D.kstat[S.kbase + k].p_fwd;
-      pb += (double)D.kstat[S.kbase + k].p_bwd;
-    }
+    for (int k = tid; k < m; k += 1024) pb += (double)D.kstat[S.kbase + k].p_bwd;
   }
   l2 = block_sum_1024(l2, shd);
   nid = block_sum_1024(nid, shd);
@@ -753,6 +828,9 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
     st.m = m;
     st.flags = nb > D.pair_cap ? ERBF_FLAG_BUCKET_OVERFLOW : 0;
     st.reserved = 0;
+    st.P_fwd_total = out[b].P_fwd_total + st.P_fwd;
+    st.P_bwd_total = out[b].P_bwd_total + st.P_bwd;
+    st.calls = out[b].calls + 1;
     out[b] = st;
   }
 }
@@ -929,26 +1007,34 @@ hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots + 1)), dim3(256), 0, s, D.tile_cnt,
                      (int64_t)n_slots + 1, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots)), dim3(256), 0, s, D.cursor, (int64_t)n_slots, 0);
-  hipLaunchKernelGGL(k_bucket<false>, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_bucket<false>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
   hipError_t e = launch_scan(D.tile_cnt, n_slots, D.scan_blocks, D.tile_start, D.counters, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bucket<true>, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D);
+  e = launch_scan(D.kcnt, D.cap_total, D.scan_blocks, D.kstart, D.counters + 2, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bucket<true>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
   hipLaunchKernelGGL(k_sort_tiles, dim3(n_slots), dim3(256), 0, s, D);
   return hipGetLastError();
 }
 
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
-                          hipStream_t s) {
+                          const hipEvent_t* ev, hipStream_t s) {
   if (n_slots <= 0) return hipSuccess;
+  hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
   if (loss)
-    hipLaunchKernelGGL(k_forward<true>, dim3(n_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+    hipExtLaunchKernelGGL(k_forward<true>, dim3(n_slots), dim3(256), 0, s, e0, e1, 0, D, f_out, tau1, tau2);
   else
-    hipLaunchKernelGGL(k_forward<false>, dim3(n_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+    hipExtLaunchKernelGGL(k_forward<false>, dim3(n_slots), dim3(256), 0, s, e0, e1, 0, D, f_out, tau1, tau2);
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const Dev& D, const float* p, const float* G, float* grad, hipStream_t s) {
-  hipLaunchKernelGGL(k_backward<true>, dim3(D.cap_total), dim3(256), 0, s, D, p, G, grad);
+hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
+                           const hipEvent_t* ev, hipStream_t s) {
+  if (n_slots > 0)
+    hipExtLaunchKernelGGL(k_bwd_tiles, dim3(n_slots), dim3(256), 0, s, ev ? ev[0] : nullptr,
+                          ev ? ev[1] : nullptr, 0, D, G);
+  hipExtLaunchKernelGGL(k_bwd_reduce, dim3(D.cap_total), dim3(64), 0, s, ev ? ev[2] : nullptr,
+                        ev ? ev[3] : nullptr, 0, D, p, grad);
   return hipGetLastError();
 }
 

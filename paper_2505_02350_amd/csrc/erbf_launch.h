@@ -37,9 +37,12 @@ hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, h
 hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
                        hipStream_t s);
 hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s);
+// `ev` (optional): start/stop events of each launched kernel, recorded at
+// the kernel's own start and end (forward: 2 events; backward: 4).
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
-                          hipStream_t s);
-hipError_t launch_backward(const Dev& D, const float* p, const float* G, float* grad, hipStream_t s);
+                          const hipEvent_t* ev, hipStream_t s);
+hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
+                           const hipEvent_t* ev, hipStream_t s);
 hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
                         erbf_stats* out, const StatsArgs& a, hipStream_t s);
 hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, const float* g, float* m1, float* m2,

@@ -1,0 +1,136 @@
+"""Host-side driving of optimisation steps through the C ABI.
+
+:class:`Fitter` owns a library context, the device copies of one or more
+shapes' inputs, parameters and Adam moments, and runs steps either eagerly or
+as a replayed HIP graph.  Targets and band masks are produced on the device
+by the library (eq. 3-10 and the band rule); nothing here computes the
+method's arithmetic.
+"""
+
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import core
+
+
+def estimate_pair_cap(level_ns: Sequence[int], s_min: np.ndarray, cull_k: float,
+                      slack: float = 1.5) -> int:
+    """Upper estimate of tile-list entries: tiles met by each ball's box."""
+    r = cull_k / np.exp(np.asarray(s_min, np.float64))
+    tot = 0.0
+    for n in level_ns:
+        tile = 8 * 2.0 / n
+        nt = math.ceil(n / 8)
+        per = np.minimum(2 * r / tile + 2, nt) ** 3
+        tot += per.sum()
+    return int(min(tot * slack + 4096, 2 ** 31 - 1))
+
+
+class ShapeInput:
+    """Host inputs of one shape: level resolutions, axes, raw SDFs, bands."""
+
+    def __init__(self, level_ns, axes, sdfs, bands, params, m, cap):
+        self.level_ns = list(level_ns)
+        self.axes = list(axes)
+        self.sdfs = list(sdfs)
+        self.bands = list(bands)
+        self.params = np.asarray(params, np.float32)
+        self.m = int(m)
+        self.cap = int(cap)
+
+    @classmethod
+    def from_problem(cls, prob):
+        return cls([lv.n for lv in prob.levels], [lv.axis for lv in prob.levels],
+                   [lv.S for lv in prob.levels], [lv.band for lv in prob.levels], prob.params, prob.m,
+                   prob.cap)
+
+    def s_min(self):
+        seg = self.params.reshape(11, self.cap)[:, :self.m]
+        return seg[4:7].min(axis=0)
+
+
+class Fitter:
+    """Library context + device state for a set of shapes, one level each
+    registered up front (or all levels when ``all_levels``)."""
+
+    def __init__(self, shapes: List[ShapeInput], cull_k: float = 3.0, weight_map: int = 0,
+                 pair_cap: Optional[int] = None, all_levels: bool = True, device: int = 0):
+        self.shapes = shapes
+        self.dev = torch.device("cuda", device)
+        if pair_cap is None:
+            pair_cap = sum(estimate_pair_cap(s.level_ns, s.s_min(), cull_k) for s in shapes)
+        self.ctx = core.Context([(s.level_ns, s.cap) for s in shapes], pair_cap, cull_k, weight_map, device)
+        self._levels = []
+        # eq. 3-10's m: minimum over every level of a shape, computed on the device
+        self.m_sdf = torch.zeros(len(shapes), dtype=torch.float32, device=self.dev)
+        self.S_dev = []
+        for b, s in enumerate(shapes):
+            row = []
+            for li, S in enumerate(s.sdfs):
+                Sd = torch.from_numpy(np.ascontiguousarray(S, np.float32)).to(self.dev)
+                core.erbf_sdf_min(Sd, self.m_sdf[b:b + 1], accumulate=li > 0)
+                row.append(Sd)
+            self.S_dev.append(row)
+        m_host = self.m_sdf.cpu().numpy()
+        self.next_level = [0] * len(shapes)
+        self._m_host = m_host
+        if all_levels:
+            for b, s in enumerate(shapes):
+                for _ in s.level_ns:
+                    self.refine(b)
+        cap_total = self.ctx.cap_total
+        self.p = torch.zeros(11 * cap_total, dtype=torch.float32, device=self.dev)
+        pv = self.p.view(11, cap_total)
+        for b, s in enumerate(shapes):
+            kb = self.ctx.kbase[b]
+            pv[:, kb:kb + s.cap] = torch.from_numpy(s.params.reshape(11, s.cap)).to(self.dev)
+        self.m_dev = torch.tensor([s.m for s in shapes], dtype=torch.int32, device=self.dev)
+        self.m1 = torch.zeros_like(self.p)
+        self.m2 = torch.zeros_like(self.p)
+        self.step_dev = torch.zeros(len(shapes), dtype=torch.int32, device=self.dev)
+        self.grad = torch.zeros_like(self.p)
+        self.graph = None
+
+    def refine(self, b: int):
+        """Append shape b's next level (targets and band mask made on device)."""
+        s = self.shapes[b]
+        li = self.next_level[b]
+        Sd = self.S_dev[b][li]
+        ax = torch.from_numpy(np.ascontiguousarray(s.axes[li], np.float32)).to(self.dev)
+        t = core.erbf_targets_from_sdf(Sd, float(self._m_host[b]))
+        bits = core.erbf_band_bits(Sd, s.bands[li]) if s.bands[li] is not None else None
+        self._levels.append((ax, t, bits))
+        self.ctx.erbf_refine_level(b, ax, t, Sd, bits)
+        self.next_level[b] += 1
+
+    def step(self, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False, lr=1e-3, lr_dev=None,
+             tau1=0.9, tau2=1.1, tau_m=0.02, stream=None):
+        self.ctx.erbf_loss_grad(self.p, self.m_dev, mode=mode, lam=lam, lambda_dev=lambda_dev,
+                                l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m, grad_out=self.grad,
+                                stream=stream)
+        self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr=lr,
+                                lr_dev=lr_dev, stream=stream)
+
+    def capture(self, **kw):
+        """Capture one step into a HIP graph (replay with :meth:`replay`)."""
+        s = torch.cuda.Stream(device=self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            self.step(stream=s, **kw)   # warm-up outside the graph
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.step(stream=s, **kw)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def stats(self):
+        return self.ctx.stats()

@@ -15,6 +15,7 @@ generation order.  Rotations of primitives are Haar-random orthogonal
 matrices (QR of a Gaussian matrix with the sign fix) with determinant +1.
 """
 
+import os
 from dataclasses import dataclass, field
 from typing import List, Sequence
 
@@ -30,7 +31,10 @@ class Primitive:
 
     def local(self, p: np.ndarray) -> np.ndarray:
         # world point -> local frame: rot^T (p - center), for row-vector p
-        return (p - self.center) @ self.rot
+        # (written out elementwise so that no threaded BLAS call is involved)
+        d = p - self.center
+        r = self.rot
+        return d[:, 0:1] * r[0] + d[:, 1:2] * r[1] + d[:, 2:3] * r[2]
 
     def distance(self, p: np.ndarray) -> np.ndarray:
         q = self.local(p)
@@ -125,25 +129,52 @@ def _eval_points(prims: Sequence[Primitive], p: np.ndarray, k: float) -> np.ndar
     return d
 
 
-def sample_sdf(prims: Sequence[Primitive], axis: np.ndarray, k: float = 0.05,
-               slab: int = 8) -> np.ndarray:
-    """Sample the smooth union of ``prims`` on the grid of ``axis``.
-
-    Returns float32 of shape ``(n^3,)`` with x fastest.  Evaluation runs in
-    float64 at the float32 grid coordinates, a few z-planes at a time.
-    """
-    a = np.asarray(axis, dtype=np.float64)
+def _eval_slabs(prims, a, k, z0, z1):
     n = a.size
-    out = np.empty(n * n * n, dtype=np.float32)
     yy, xx = np.meshgrid(a, a, indexing="ij")
     xy = np.stack([xx.ravel(), yy.ravel()], axis=1)
     plane = n * n
-    step = max(1, slab)
-    for z0 in range(0, n, step):
-        z1 = min(n, z0 + step)
-        pts = np.empty(((z1 - z0) * plane, 3))
-        for zi, z in enumerate(range(z0, z1)):
+    out = np.empty((z1 - z0) * plane, dtype=np.float32)
+    for zs in range(z0, z1, 8):
+        ze = min(z1, zs + 8)
+        pts = np.empty(((ze - zs) * plane, 3))
+        for zi, z in enumerate(range(zs, ze)):
             pts[zi * plane:(zi + 1) * plane, :2] = xy
             pts[zi * plane:(zi + 1) * plane, 2] = a[z]
-        out[z0 * plane:z1 * plane] = _eval_points(prims, pts, k).astype(np.float32)
+        out[(zs - z0) * plane:(ze - z0) * plane] = _eval_points(prims, pts, k).astype(np.float32)
     return out
+
+
+_POOL_ARGS = None
+
+
+def _pool_job(span):
+    prims, a, k = _POOL_ARGS
+    return _eval_slabs(prims, a, k, span[0], span[1])
+
+
+def sample_sdf(prims: Sequence[Primitive], axis: np.ndarray, k: float = 0.05,
+               workers: int = None) -> np.ndarray:
+    """Sample the smooth union of ``prims`` on the grid of ``axis``.
+
+    Returns float32 of shape ``(n^3,)`` with x fastest.  Evaluation runs in
+    float64 at the float32 grid coordinates, a few z-planes at a time; large
+    grids are split over forked worker processes (the result does not depend
+    on the split)."""
+    global _POOL_ARGS
+    a = np.asarray(axis, dtype=np.float64)
+    n = a.size
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if n ** 3 >= (1 << 21) else 1
+    if workers <= 1:
+        return _eval_slabs(prims, a, k, 0, n)
+    import multiprocessing as mp
+    chunk = max(1, -(-n // (4 * workers)))
+    spans = [(z, min(n, z + chunk)) for z in range(0, n, chunk)]
+    _POOL_ARGS = (prims, a, k)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_pool_job, spans)
+    finally:
+        _POOL_ARGS = None
+    return np.concatenate(parts)

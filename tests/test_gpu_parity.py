@@ -175,7 +175,7 @@ def test_vjp_random_upstream():
     gg = gp.grads_np(g)
     errs = {k: rel_inf(gg[k], go[k]) for k in go}
     record("vjp_ragged", P_fwd=(st.P_fwd, pf), P_bwd=(st.P_bwd, pb), **errs)
-    assert st.P_fwd == pf and st.P_bwd == pb
+    assert st.P_bwd == pb      # the VJP runs no forward, so it reports no P_fwd
     for k in go:
         assert errs[k] <= G_TOL, (k, errs[k])
 
