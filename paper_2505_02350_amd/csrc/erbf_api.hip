@@ -506,9 +506,59 @@ int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls) {
 int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape, const float* resid,
                          float resid_scale, int64_t n_idall, const erbf_seed_cfg* cfg, float* m1, float* m2,
                          int32_t* n_added, hipStream_t stream) {
-  (void)ctx; (void)params; (void)shape; (void)resid; (void)resid_scale; (void)n_idall; (void)cfg;
-  (void)m1; (void)m2; (void)n_added; (void)stream;
-  return fail(ERBF_ERR_UNSUPPORTED, "seeding not built yet");
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!resid || !cfg || !n_added) return fail(ERBF_ERR_INVALID_ARG, "resid, cfg and n_added must be non-NULL");
+  *n_added = 0;
+  if (shape < 0 || shape >= ctx->cfg.n_shapes) return fail(ERBF_ERR_INVALID_ARG, "shape out of range");
+  if (!(cfg->top_frac > 0.f && cfg->top_frac <= 0.05f)) return fail(ERBF_ERR_INVALID_ARG, "top_frac must be in (0, 0.05]");
+  if (cfg->k_new < 1 || cfg->k_new > 4096) return fail(ERBF_ERR_INVALID_ARG, "k_new must be in [1, 4096]");
+  if (!(cfg->eps > 0.f)) return fail(ERBF_ERR_INVALID_ARG, "eps must be > 0");
+  if (!(resid_scale > 0.f)) return fail(ERBF_ERR_INVALID_ARG, "resid_scale must be > 0");
+  if (cfg->w_rule != 0 && cfg->w_rule != 1) return fail(ERBF_ERR_INVALID_ARG, "w_rule must be 0 or 1");
+  if (n_idall < 0) return fail(ERBF_ERR_INVALID_ARG, "n_idall must be >= 0");
+  const ShapeDev& sd = ctx->sh[shape];
+  if (sd.n_active < 1) return fail(ERBF_ERR_STATE, "shape has no registered level");
+  int64_t npts = 0;
+  int finest = -1;
+  for (int l = 0; l < sd.n_active; ++l) {
+    const LevelDev& L = ctx->lv[sd.lvl0 + l];
+    if (!L.sdf) return fail(ERBF_ERR_INVALID_ARG, "seeding needs the raw SDF of every registered level");
+    npts += (int64_t)L.n * L.n * L.n;
+    if (finest < 0 || L.n > ctx->lv[finest].n) finest = sd.lvl0 + l;
+  }
+  if (npts >= ((int64_t)1 << 32)) return fail(ERBF_ERR_UNSUPPORTED, "seeding supports < 2^32 points per shape");
+  const int64_t K = (int64_t)std::ceil((double)cfg->top_frac * (double)n_idall);
+  if (K == 0) return ERBF_OK;
+  if (K > ctx->D.cand_cap) return fail(ERBF_ERR_WORKSPACE, "candidate list exceeds the workspace");
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  // finest spacing from the axis table itself
+  float h_fine = 2.0f / (float)ctx->lv[finest].n;
+  if (ctx->lv[finest].n > 1) {
+    float a2[2];
+    HIP_TRY(hipMemcpyAsync(a2, ctx->lv[finest].axis, 2 * sizeof(float), hipMemcpyDeviceToHost, stream), "seed: axis");
+    HIP_TRY(hipStreamSynchronize(stream), "seed: sync");
+    h_fine = a2[1] - a2[0];
+  }
+  const float r_nms = cfg->r_nms > 0.f ? cfg->r_nms : 2.0f * h_fine;
+  const float floor_abs = std::max(cfg->min_abs_err, cfg->eps);
+  HIP_TRY(launch_seed_select(D, shape, npts, resid, resid_scale, floor_abs, r_nms, K, stream), "seed: select");
+  int32_t n_cand = 0, n_kept = 0;
+  if (seed_misc_counts(D, &n_cand, &n_kept, stream) != 0) return fail(ERBF_ERR_HIP, "seed: reading counts");
+  int32_t m_now = 0;
+  HIP_TRY(hipMemcpyAsync(&m_now, params->m_dev + shape, sizeof(int32_t), hipMemcpyDeviceToHost, stream), "seed: m");
+  HIP_TRY(hipStreamSynchronize(stream), "seed: sync");
+  const int n_add = std::min(cfg->k_new, n_kept);
+  if (n_add == 0) return ERBF_OK;
+  if (m_now < 0 || m_now + n_add > sd.cap)
+    return fail(ERBF_ERR_CAPACITY, "seeding " + std::to_string(n_add) + " kernels exceeds the shape capacity");
+  HIP_TRY(launch_seed_write(D, shape, n_add, params->p, params->m_dev, resid, resid_scale, m1, m2, cfg->eps,
+                            cfg->w_rule, h_fine, stream),
+          "seed: write");
+  HIP_TRY(hipStreamSynchronize(stream), "seed: sync");
+  *n_added = n_add;
+  return ERBF_OK;
 }
 
 }  // extern "C"

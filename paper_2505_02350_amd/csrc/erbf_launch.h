@@ -21,17 +21,6 @@ struct AdamArgs {
   float beta1, beta2, eps;
 };
 
-struct SeedArgs {
-  int32_t shape;
-  int64_t k_cand;      // number of candidates (top fraction of n_idall)
-  int32_t k_new;
-  float r_nms;
-  float eps;
-  float min_abs_err;
-  int32_t w_rule;
-  float resid_scale;
-  float h_fine;
-};
 
 hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, hipStream_t s);
 hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
@@ -57,7 +46,11 @@ hipError_t launch_sdf_min(const float* S, int64_t n, float* out, int accumulate,
 hipError_t launch_tile_flags(const Dev& D, int li, int ntt, int32_t* flags, hipStream_t s);
 hipError_t launch_tile_assign(const Dev& D, int li, int ntt, const int32_t* flags, const int32_t* excl,
                               int slot0, hipStream_t s);
-hipError_t launch_seed(const Dev& D, const float* p, int32_t* m_dev, const float* resid, float* m1, float* m2,
-                       const SeedArgs& a, hipStream_t s);
+hipError_t launch_seed_select(const Dev& D, int shape, int64_t npts, const float* resid, float scale,
+                              float floor_abs, float r_nms, int64_t k_cand, hipStream_t s);
+// counts left by launch_seed_select (synchronises the stream); 0 on success
+int seed_misc_counts(const Dev& D, int32_t* n_cand, int32_t* n_kept, hipStream_t s);
+hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32_t* m_dev, const float* resid,
+                             float scale, float* m1, float* m2, float eps, int w_rule, float h_fine, hipStream_t s);
 
 }  // namespace erbf

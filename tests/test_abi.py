@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI (no GPU needed): the built library loads,
+exports every function declared in include/erbf.h, its struct layouts match
+the ctypes binding, and argument validation returns the documented codes."""
+
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "erbf.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(erbf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2505_02350_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("liberbf.so not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    from paper_2505_02350_amd import _lib as L
+    names = _declared_functions()
+    assert len(names) >= 15
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_abi_version(lib):
+    assert lib.erbf_abi_version() == 1
+
+
+def _struct_sizes_from_c():
+    cc = shutil.which("gcc")
+    if cc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("gcc or ROCm headers unavailable")
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "erbf.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(erbf_shape_desc), sizeof(erbf_config),
+         sizeof(erbf_level), sizeof(erbf_params), sizeof(erbf_loss_cfg), sizeof(erbf_stats),
+         sizeof(erbf_adam_cfg), sizeof(erbf_seed_cfg), offsetof(erbf_stats, P_fwd_total));
+  return 0;
+}
+'''
+    tmp = os.path.join(ROOT, "_build")
+    os.makedirs(tmp, exist_ok=True)
+    c = os.path.join(tmp, "abi_sizes.c")
+    exe = os.path.join(tmp, "abi_sizes")
+    open(c, "w").write(src)
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    c, "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+def test_struct_layouts_match_binding():
+    from paper_2505_02350_amd import _lib as L
+    sizes = _struct_sizes_from_c()
+    mine = [ctypes.sizeof(t) for t in (L.ShapeDesc, L.Config, L.Level, L.Params, L.LossCfg, L.Stats, L.AdamCfg,
+                                        L.SeedCfg)]
+    assert sizes[:8] == mine
+    assert sizes[8] == L.Stats.P_fwd_total.offset
+
+
+def _cfg(L, shapes, pair_cap=1024, cull_k=3.0, wm=0):
+    arr = (L.ShapeDesc * len(shapes))()
+    for b, (ns, cap) in enumerate(shapes):
+        arr[b].n_levels = len(ns)
+        for i, n in enumerate(ns):
+            arr[b].level_n[i] = n
+        arr[b].m_cap = cap
+    return L.Config(len(shapes), arr, pair_cap, cull_k, wm), arr
+
+
+def test_workspace_size_and_validation(lib):
+    from paper_2505_02350_amd import _lib as L
+    size = ctypes.c_size_t()
+    cfg, keep = _cfg(L, [([32], 64)])
+    assert lib.erbf_workspace_size(ctypes.byref(cfg), ctypes.byref(size)) == L.ERBF_OK
+    small = size.value
+    cfg2, keep2 = _cfg(L, [([32, 64], 64), ([48], 128)])
+    assert lib.erbf_workspace_size(ctypes.byref(cfg2), ctypes.byref(size)) == L.ERBF_OK
+    assert size.value > small
+    # G and the per-point arrays grow with the points declared
+    assert size.value >= 4 * (32 ** 3 + 64 ** 3 + 48 ** 3)
+    bad = [
+        _cfg(L, [([32], 0)]),                 # m_cap < 1
+        _cfg(L, [([0], 8)]),                  # level size
+        _cfg(L, [([32], 8)], cull_k=-1.0),    # cull radius
+        _cfg(L, [([32], 8)], wm=7),           # weight map
+        _cfg(L, [([32], 8)], pair_cap=0),     # bucket capacity
+    ]
+    for cfg_b, _ in bad:
+        assert lib.erbf_workspace_size(ctypes.byref(cfg_b), ctypes.byref(size)) == L.ERBF_ERR_INVALID_ARG
+        assert lib.erbf_last_error()
+    nine = (L.ShapeDesc * 1)()
+    nine[0].n_levels = 9
+    nine[0].m_cap = 4
+    c9 = L.Config(1, nine, 64, 3.0, 0)
+    assert lib.erbf_workspace_size(ctypes.byref(c9), ctypes.byref(size)) == L.ERBF_ERR_INVALID_ARG
+    assert lib.erbf_workspace_size(None, ctypes.byref(size)) == L.ERBF_ERR_INVALID_ARG
+
+
+def test_data_prep_rejects_bad_arguments(lib):
+    from paper_2505_02350_amd import _lib as L
+    # null pointers are rejected before any device work
+    assert lib.erbf_targets_from_sdf(None, 10, -0.5, None, None) == L.ERBF_ERR_INVALID_ARG
+    assert lib.erbf_band_bits(None, 10, 0.1, None, None) == L.ERBF_ERR_INVALID_ARG
+    assert lib.erbf_sdf_min(None, 10, None, 0, None) == L.ERBF_ERR_INVALID_ARG
+    # a non-negative minimum has no eq. 3-10 normalisation
+    fake = ctypes.c_void_p(16)
+    assert lib.erbf_targets_from_sdf(fake, 10, 0.5, fake, None) == L.ERBF_ERR_INVALID_ARG
+    assert lib.erbf_eval(None, None, None, None, None) == L.ERBF_ERR_INVALID_ARG
