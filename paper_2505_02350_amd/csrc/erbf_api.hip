@@ -346,6 +346,17 @@ int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hip
   if (!level->axis) return fail(ERBF_ERR_INVALID_ARG, "level axis is NULL");
   DeviceGuard guard(ctx->device);
   Dev& D = ctx->D;
+  {
+    // index ranges are computed from the nominal spacing: the table must be
+    // the cell-centred grid (to float32 rounding)
+    std::vector<float> ax(L.n);
+    HIP_TRY(hipMemcpy(ax.data(), level->axis, sizeof(float) * L.n, hipMemcpyDeviceToHost), "refine: axis");
+    for (int i = 0; i < L.n; ++i) {
+      const double nominal = -1.0 + (2.0 * i + 1.0) / L.n;
+      if (!(std::fabs((double)ax[i] - nominal) <= 1e-6))
+        return fail(ERBF_ERR_INVALID_ARG, "axis must hold the cell-centred coordinates -1 + (2i+1)/n");
+    }
+  }
   L.axis = level->axis;
   L.target = level->target;
   L.sdf = level->sdf;

@@ -62,6 +62,13 @@ __device__ __forceinline__ void index_range(const LevelDev& L, float c0, float c
   i1 = min(L.n - 1, (int)ceilf(f1) + 1);
 }
 
+__device__ __forceinline__ float tile_lo(const LevelDev& L, int t) {
+  return fmaf((float)(t * kTile), L.h, L.lo) - 2e-6f;
+}
+__device__ __forceinline__ float tile_hi(const LevelDev& L, int t) {
+  return fmaf((float)min(t * kTile + kTile - 1, L.n - 1), L.h, L.lo) + 2e-6f;
+}
+
 __device__ __forceinline__ bool point_active(const uint32_t* bits, int64_t local) {
   if (bits == nullptr) return true;
   return (bits[local >> 5] >> (local & 31)) & 1u;
@@ -178,9 +185,11 @@ __global__ __launch_bounds__(256) void k_bucket(Dev D) {
       int slot = -1;
       if (idx < total) {
         const int tx = tx0 + idx % ntx, ty = ty0 + (idx / ntx) % nty, tz = tz0 + idx / (ntx * nty);
-        const float xlo = L.axis[tx * kTile], xhi = L.axis[min(tx * kTile + kTile - 1, n - 1)];
-        const float ylo = L.axis[ty * kTile], yhi = L.axis[min(ty * kTile + kTile - 1, n - 1)];
-        const float zlo = L.axis[tz * kTile], zhi = L.axis[min(tz * kTile + kTile - 1, n - 1)];
+        // tile point box from the nominal spacing, widened to cover the
+        // rounding of the axis table
+        const float xlo = tile_lo(L, tx), xhi = tile_hi(L, tx);
+        const float ylo = tile_lo(L, ty), yhi = tile_hi(L, ty);
+        const float zlo = tile_lo(L, tz), zhi = tile_hi(L, tz);
         const float ex = fmaxf(fmaxf(xlo - r0.x, r0.x - xhi), 0.f);
         const float ey = fmaxf(fmaxf(ylo - r0.y, r0.y - yhi), 0.f);
         const float ez = fmaxf(fmaxf(zlo - r0.z, r0.z - zhi), 0.f);
@@ -211,8 +220,11 @@ __global__ __launch_bounds__(256) void k_bucket(Dev D) {
 
 // Per-tile ascending sort of the bucket list (fixes the forward's summation
 // order) and the kernel-major map of entries used by the backward reduction.
+// The kernel ids of one list are distinct, so each entry's final position is
+// its rank: the number of smaller ids in the list (read four at a time from
+// LDS with broadcast loads; no barriers inside the count).
 __global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
-  __shared__ int2 buf[4096];
+  __shared__ int4 keys4[1024];
   const int s = blockIdx.x;
   const int64_t beg = min((int64_t)D.tile_start[s], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[s + 1], D.pair_cap);
@@ -220,29 +232,20 @@ __global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
   const int tid = threadIdx.x;
   if (cnt <= 0) return;
   if (cnt <= 4096) {
-    int pw = 1;
-    while (pw < cnt) pw <<= 1;
-    for (int i = tid; i < pw; i += blockDim.x)
-      buf[i] = i < cnt ? make_int2(D.items_raw[beg + i], D.visit_raw[beg + i]) : make_int2(INT32_MAX, 0);
+    int* keys = reinterpret_cast<int*>(keys4);
+    const int c4 = (cnt + 3) >> 2;
+    for (int i = tid; i < 4 * c4; i += blockDim.x) keys[i] = i < cnt ? D.items_raw[beg + i] : INT32_MAX;
     __syncthreads();
-    for (int k = 2; k <= pw; k <<= 1) {
-      for (int jj = k >> 1; jj > 0; jj >>= 1) {
-        for (int i = tid; i < pw; i += blockDim.x) {
-          const int ixj = i ^ jj;
-          if (ixj > i) {
-            const int2 a = buf[i], bb = buf[ixj];
-            const bool up = (i & k) == 0;
-            if ((a.x > bb.x) == up) { buf[i] = bb; buf[ixj] = a; }
-          }
-        }
-        __syncthreads();
-      }
-    }
     for (int i = tid; i < cnt; i += blockDim.x) {
-      const int2 e = buf[i];
-      D.items[beg + i] = e.x;
-      const int64_t km = (int64_t)D.kstart[e.x] + e.y;
-      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + i), s);
+      const int v = keys[i];
+      int rank = 0;
+      for (int k = 0; k < c4; ++k) {
+        const int4 q = keys4[k];
+        rank += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
+      }
+      D.items[beg + rank] = v;
+      const int64_t km = (int64_t)D.kstart[v] + D.visit_raw[beg + i];
+      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + rank), s);
     }
   } else {
     // long list: rank of each (distinct) kernel id
@@ -556,12 +559,14 @@ __global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restric
 
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
-  for (int64_t c0 = beg; c0 < end; c0 += 256) {
-    const bool have = c0 + tid < end;
+  // each wave takes its own groups of 64 kernels, so waves past the end of
+  // the list do no work
+  for (int64_t c0 = beg + 64 * wv; c0 < end; c0 += 256) {
+    const bool have = c0 + lane < end;
     float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
            r2 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (have) {
-      const int j = D.items[c0 + tid];
+      const int j = D.items[c0 + lane];
       r0 = D.rec[3 * j];
       r1 = D.rec[3 * j + 1];
       r2 = D.rec[3 * j + 2];
@@ -604,7 +609,7 @@ __global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restric
     T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
     T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
     if (have) {
-      float4* o = D.partials + 3 * (c0 + tid);
+      float4* o = D.partials + 3 * (c0 + lane);
       o[0] = make_float4(T[0], T[1], T[2], T[3]);
       o[1] = make_float4(T[4], T[5], T[6], T[7]);
       o[2] = make_float4(T[8], T[9], cnt, 0.f);
