@@ -70,6 +70,84 @@ def cpu_baseline(prob, budget_s=15.0, seed=0):
                       f"fwd+loss+bwd in float64 numpy, {dt:.1f} s, {pf + pb} pairs"}
 
 
+def batching_bench(steps, warmup):
+    """64 shapes (grids 32^3..128^3, 256..4096 kernels, per-shape lambda):
+    one batched context with a HIP-graph step vs 64 plain contexts, each with
+    its own graph, replayed one after another.  Aggregate pair throughput."""
+    import torch
+    import synth
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+
+    t0 = time.perf_counter()
+    probs = synth.make_batching()
+    log(f"batching workload generated in {time.perf_counter() - t0:.1f} s")
+    shapes = [ShapeInput.from_problem(p) for p in probs]
+    lams = [p.lam for p in probs]
+    kw = dict(mode=L.MODE_FIXED, lr=1e-3)
+
+    fb = Fitter(shapes, cull_k=3.0)
+    lam_dev = torch.tensor(lams, dtype=torch.float32, device=fb.dev)
+    var_b, times_b = fb.ctx.erbf_autotune(fb.p, fb.m_dev, reps=1, lambda_dev=lam_dev)
+    # equal accuracy: the first step's gradients are bitwise those of the plain fits
+    gb = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lambda_dev=lam_dev).clone()
+    plains = []
+    for b, s in enumerate(shapes):
+        f = Fitter([s], cull_k=3.0)
+        f.ctx.erbf_autotune(f.p, f.m_dev, reps=1, lam=lams[b])
+        g = f.ctx.erbf_loss_grad(f.p, f.m_dev, lam=lams[b])
+        kb, cap = fb.ctx.kbase[b], s.cap
+        same = torch.equal(gb.view(11, -1)[:, kb:kb + cap], g.view(11, -1)[:, :cap])
+        if not same:
+            raise SystemExit(f"batched and plain gradients differ for shape {b}")
+        plains.append(f)
+    torch.cuda.synchronize()
+
+    fb.capture(lambda_dev=lam_dev, **kw)
+    for f, lam in zip(plains, lams):
+        f.capture(lam=lam, **kw)
+    for _ in range(warmup):
+        fb.replay()
+        for f in plains:
+            f.replay()
+    torch.cuda.synchronize()
+
+    fb.ctx.reset_stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fb.replay()
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    pairs_b = sum(st.P_fwd_total + st.P_bwd_total for st in fb.stats())
+
+    for f in plains:
+        f.ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in plains:
+        for _ in range(steps):
+            f.replay()
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    pairs_p = sum(f.stats()[0].P_fwd_total + f.stats()[0].P_bwd_total for f in plains)
+    thr_b, thr_p = pairs_b / wall_b, pairs_p / wall_p
+    log(f"batched {1e3 * wall_b / steps:.2f} ms/step, plain {1e3 * wall_p / steps:.2f} ms per step of all shapes")
+    return {
+        "workload": "64 shapes: smooth unions of 2-10 ellipsoids/tori on 32^3..128^3 grids, 256..4096 ERBFs, "
+                    "per-shape lambda, seed 3",
+        "points": int(sum(p.levels[0].n ** 3 for p in probs)),
+        "kernels": int(sum(p.m for p in probs)),
+        "steps": steps,
+        "batched_ms_per_step": 1e3 * wall_b / steps,
+        "plain_ms_per_step_all_shapes": 1e3 * wall_p / steps,
+        "batched_pairs_per_s": thr_b,
+        "plain_pairs_per_s": thr_p,
+        "speedup": thr_b / thr_p,
+        "batched_variant": var_b,
+        "equal_accuracy": "first-step gradients bitwise equal to the plain fits",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +156,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--graph", action="store_true", help="also time HIP-graph replays of the step")
+    ap.add_argument("--batching", action="store_true", help="add the 64-shape batched-vs-plain comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -191,6 +270,8 @@ def main():
         "graph_ms_per_step": graph_ms,
         "per_level_refine_ms": refine_ms,
     }
+    if args.batching:
+        out["batching"] = batching_bench(max(2, min(args.steps, 10)), 2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)

@@ -254,6 +254,27 @@ int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls);
  * and *n_calls the number of calls recorded.  Clears the records. */
 int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls);
 
+/* ---- launch variants and the autotuner ------------------------------------ */
+
+/* Launch variants of the two per-tile kernels (bit flags; results do not
+ * depend on the variant, only the time does):
+ *   1  forward tiles walked round-robin by a persistent grid
+ *   2  backward tiles walked round-robin by a persistent grid
+ * 0 launches one workgroup per tile for both. */
+#define ERBF_VARIANT_FWD_PERSISTENT 1
+#define ERBF_VARIANT_BWD_PERSISTENT 2
+
+int erbf_set_variant(erbf_ctx* ctx, int32_t variant);
+int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
+
+/* Time erbf_loss_grad under every launch variant (one warm-up and `reps`
+ * timed calls each, HIP events on `stream`), keep the fastest in the context
+ * and return it in *chosen; times_ms (optional) receives the mean time of
+ * each variant [4].  grad_scratch: device [11 * cap_total].  The parameters
+ * are read, not modified.  Synchronous. */
+int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_scratch,
+                  int32_t reps, int32_t* chosen, float* times_ms, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

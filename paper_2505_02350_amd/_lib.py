@@ -101,6 +101,10 @@ _SIGS = [
     ("erbf_adam_step", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V, ctypes.POINTER(AdamCfg), _V]),
     ("erbf_timing_enable", ctypes.c_int, [_V, ctypes.c_int32]),
     ("erbf_timing_read", ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    ("erbf_set_variant", ctypes.c_int, [_V, ctypes.c_int32]),
+    ("erbf_get_variant", ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_int32)]),
+    ("erbf_autotune", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), _V, _V]),
     ("erbf_seed_from_error", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, _V, ctypes.c_float,
                                             ctypes.c_int64, ctypes.POINTER(SeedCfg), _V, _V,
                                             ctypes.POINTER(ctypes.c_int32), _V]),

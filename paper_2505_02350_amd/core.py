@@ -206,6 +206,28 @@ class Context:
         L.check(self.lib.erbf_timing_read(self.handle, ms, ctypes.byref(n)))
         return ms[0], ms[1], ms[2], n.value
 
+    def erbf_set_variant(self, variant: int):
+        L.check(self.lib.erbf_set_variant(self.handle, int(variant)))
+
+    def erbf_get_variant(self) -> int:
+        v = ctypes.c_int32()
+        L.check(self.lib.erbf_get_variant(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def erbf_autotune(self, p, m_dev, reps=3, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
+                      tau1=0.9, tau2=1.1, tau_m=0.02, stream=None):
+        """Choose the fastest launch variant for these parameters; returns
+        (variant, per-variant mean milliseconds)."""
+        pr = self._params(p, m_dev)
+        cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
+                        float(tau2), float(tau_m))
+        scratch = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        chosen = ctypes.c_int32()
+        times = (ctypes.c_float * 4)()
+        L.check(self.lib.erbf_autotune(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(scratch), int(reps),
+                                       ctypes.byref(chosen), times, _stream(stream)))
+        return chosen.value, list(times)
+
     def reset_stats(self):
         self.stats_buf.zero_()
 

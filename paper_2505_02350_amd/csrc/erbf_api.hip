@@ -254,6 +254,12 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.n_shapes = cfg->n_shapes;
   D.cull_k = cfg->cull_k;
   D.weight_map = cfg->weight_map;
+  D.variant = 0;
+  {
+    hipDeviceProp_t prop;
+    const hipError_t pe = hipGetDeviceProperties(&prop, device);
+    D.persistent_wgs = (pe == hipSuccess && prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256) * 8;
+  }
 
   // host mirrors of the level and shape tables
   std::vector<int32_t> kshape(lay.cap_total);
@@ -479,6 +485,68 @@ int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, 
   AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps};
   HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad, m1, m2, step_dev, a, stream), "adam");
   return ERBF_OK;
+}
+
+int erbf_set_variant(erbf_ctx* ctx, int32_t variant) {
+  if (!ctx || variant < 0 || variant > (kVariantFwdPersistent | kVariantBwdPersistent))
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_set_variant: bad arguments");
+  ctx->D.variant = variant;
+  return ERBF_OK;
+}
+
+int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant) {
+  if (!ctx || !variant) return fail(ERBF_ERR_INVALID_ARG, "erbf_get_variant: bad arguments");
+  *variant = ctx->D.variant;
+  return ERBF_OK;
+}
+
+int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_scratch,
+                  int32_t reps, int32_t* chosen, float* times_ms, hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!cfg || !grad_scratch || reps < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_autotune: bad arguments");
+  DeviceGuard guard(ctx->device);
+  const int n_var = (kVariantFwdPersistent | kVariantBwdPersistent) + 1;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "autotune: event");
+  hipError_t ce = hipEventCreate(&e1);
+  if (ce != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(ce, "autotune: event");
+  }
+  const int saved_tmax = ctx->t_max;
+  ctx->t_max = 0;  // no per-kernel timing while tuning
+  int best = 0;
+  float best_ms = 0.f;
+  int status = ERBF_OK;
+  for (int v = 0; v < n_var && status == ERBF_OK; ++v) {
+    ctx->D.variant = v;
+    status = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);  // warm-up
+    if (status != ERBF_OK) break;
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && e == hipSuccess && status == ERBF_OK; ++r)
+      status = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      status = hip_fail(e, "autotune: timing");
+      break;
+    }
+    ms /= (float)reps;
+    if (times_ms) times_ms[v] = ms;
+    if (v == 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  ctx->t_max = saved_tmax;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->D.variant = status == ERBF_OK ? best : 0;
+  if (status == ERBF_OK && chosen) *chosen = best;
+  return status;
 }
 
 int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls) {

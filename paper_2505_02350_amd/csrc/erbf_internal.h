@@ -12,6 +12,10 @@ constexpr int kTile = 8;            // grid points per tile edge (tile = 8^3 poi
 constexpr int kRecF4 = 3;           // float4 per kernel record
 constexpr float kLog2e = 1.4426950408889634f;
 
+// launch variants chosen by the autotuner (bit flags)
+constexpr int kVariantFwdPersistent = 1;   // forward tiles walked by a persistent grid
+constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persistent grid
+
 // Per-level table entry, mirrored on the device.
 struct LevelDev {
   int32_t n, nt;            // points / tiles per axis
@@ -89,6 +93,8 @@ struct Dev {
   int32_t n_shapes;
   float cull_k;
   int32_t weight_map;
+  int32_t variant;          // kVariant* flags
+  int32_t persistent_wgs;   // grid of the persistent variants
 };
 
 }  // namespace erbf

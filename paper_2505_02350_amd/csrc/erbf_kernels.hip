@@ -335,8 +335,8 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ 
 constexpr int kFwdChunk = 256;
 
 template <bool LOSS>
-__global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_out,
-                                                 float tau1, float tau2) {
+__device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float* __restrict__ f_out,
+                                             float tau1, float tau2) {
   __shared__ float4 srec[kFwdChunk * 3];
   __shared__ uint16_t slist[4][kFwdChunk];
   __shared__ int scnt[4][4];
@@ -345,7 +345,6 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
   __shared__ int red_i[4];
   __shared__ int64_t red_p[4];
 
-  const int slot = blockIdx.x;
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
   const int n = L.n, nt = L.nt;
@@ -488,6 +487,25 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
   }
 }
 
+// one workgroup per tile (grid launch) ...
+template <bool LOSS>
+__global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
+  forward_tile<LOSS>(D, blockIdx.x, f_out, tau1, tau2);
+}
+
+// ... or a persistent grid: each workgroup walks the tiles round-robin
+// (slot = blockIdx.x, blockIdx.x + gridDim.x, ...).  The walk depends only on
+// blockIdx and gridDim, so every branch of the loop is uniform and every
+// barrier inside the tile body is reached by the whole workgroup.
+template <bool LOSS>
+__global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __restrict__ f_out, float tau1,
+                                                            float tau2, int n_slots) {
+  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+    forward_tile<LOSS>(D, slot, f_out, tau1, tau2);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // backward, stage 1: one workgroup per active tile.  The tile's points with a
 // non-zero upstream gradient are staged in LDS in (z, y, x) order; each lane
@@ -499,12 +517,11 @@ __global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_ou
 // The moments of each (tile, kernel) entry go to `partials`.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
+__device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc) {
   __shared__ float4 spt[kTile * kTile * kTile];
   __shared__ int srow[kTile * kTile * kTile];
   __shared__ int swc[2][4];
 
-  const int slot = blockIdx.x;
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
   const int n = L.n, nt = L.nt;
@@ -552,7 +569,9 @@ __global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restric
     spt[k] = pt[1];
     srow[k] = prow[1];
   }
-  const int Z = tot0 + tot1;
+  // workgroup-uniform (all threads read the same LDS counts); readfirstlane
+  // makes that visible, so the early exit below is a scalar branch
+  const int Z = __builtin_amdgcn_readfirstlane(tot0 + tot1);
   if (tid == 0) D.tile_nz[slot] = Z > 0;
   if (Z == 0) return;
   __syncthreads();
@@ -614,6 +633,17 @@ __global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restric
       o[1] = make_float4(T[4], T[5], T[6], T[7]);
       o[2] = make_float4(T[8], T[9], cnt, 0.f);
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
+  bwd_tile(D, blockIdx.x, Gsrc);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc, int n_slots) {
+  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+    bwd_tile(D, slot, Gsrc);
+    __syncthreads();
   }
 }
 
@@ -1022,24 +1052,46 @@ hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Launch with start/stop events taken at the kernel's own start and end when
+// timing is requested, otherwise as an ordinary launch (graph-capturable).
+template <typename... Args>
+inline void launch_timed(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
                           const hipEvent_t* ev, hipStream_t s) {
   if (n_slots <= 0) return hipSuccess;
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
-  if (loss)
-    hipExtLaunchKernelGGL(k_forward<true>, dim3(n_slots), dim3(256), 0, s, e0, e1, 0, D, f_out, tau1, tau2);
-  else
-    hipExtLaunchKernelGGL(k_forward<false>, dim3(n_slots), dim3(256), 0, s, e0, e1, 0, D, f_out, tau1, tau2);
+  if (D.variant & kVariantFwdPersistent) {
+    const int grid = std::min(n_slots, D.persistent_wgs);
+    if (loss)
+      launch_timed(k_forward_persistent<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+    else
+      launch_timed(k_forward_persistent<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+  } else if (loss) {
+    launch_timed(k_forward<true>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
+  } else {
+    launch_timed(k_forward<false>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
                            const hipEvent_t* ev, hipStream_t s) {
-  if (n_slots > 0)
-    hipExtLaunchKernelGGL(k_bwd_tiles, dim3(n_slots), dim3(256), 0, s, ev ? ev[0] : nullptr,
-                          ev ? ev[1] : nullptr, 0, D, G);
-  hipExtLaunchKernelGGL(k_bwd_reduce, dim3(D.cap_total), dim3(64), 0, s, ev ? ev[2] : nullptr,
-                        ev ? ev[3] : nullptr, 0, D, p, grad);
+  if (n_slots > 0 && (D.variant & kVariantBwdPersistent)) {
+    const int grid = std::min(n_slots, D.persistent_wgs);
+    launch_timed(k_bwd_tiles_persistent, dim3(grid), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D,
+                 G, n_slots);
+  } else if (n_slots > 0) {
+    launch_timed(k_bwd_tiles, dim3(n_slots), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G);
+  }
+  launch_timed(k_bwd_reduce, dim3(D.cap_total), dim3(64), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
+               grad);
   return hipGetLastError();
 }
 
