@@ -257,6 +257,45 @@ def forward_at_points(pts: np.ndarray, K: Kernels, culled: bool = True) -> np.nd
     return out
 
 
+def allowance_at_points(pts: np.ndarray, K: Kernels, rel: float = 2.0 ** -20):
+    """boundary_allowance (below) at arbitrary points: per point, the sum of
+    |a_j| Phi over kernels whose squared distance lies within rel * r^2 of
+    r^2; also the number of such pairs."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(pts.shape[0])
+    count = 0
+    for i, x in enumerate(pts):
+        delta = x[None, :] - K.c
+        dist2 = np.sum(delta * delta, axis=1)
+        amb = np.abs(dist2 - K.r2) <= rel * K.r2
+        if amb.any():
+            u = np.einsum("mkl,ml->mk", K.R[amb], delta[amb])
+            out[i] = np.sum(np.abs(K.a[amb]) * np.exp(-np.sum((K.d[amb] * u) ** 2, axis=1)))
+            count += int(amb.sum())
+    return out, count
+
+
+def kernel_field(lv: OLevel, K: Kernels, j: int, radius_scale: float = 1.0):
+    """One kernel's term a_j [in ball] Phi_j on its own index box (eq. 3-7,
+    eq. 3-15-1, radius scaled by radius_scale): returns the box bounds
+    (z0, z1, y0, y1, x0, x1) and the values, shape (z, y, x).  Used for local
+    finite differences on large grids, where only this kernel's term moves."""
+    r2 = K.r2[j] * radius_scale ** 2
+    box, dx, dy, dz = _kernel_box(lv, K, j, r2)
+    phi, _ = _phi_and_u(K, j, dx, dy, dz)
+    phi = np.where(dx * dx + dy * dy + dz * dz < r2, phi, 0.0)
+    return box, K.a[j] * phi
+
+
+def subset(K: Kernels, idx) -> Kernels:
+    """The kernels `idx` of K (their terms and gradients are independent of
+    the others')."""
+    idx = np.asarray(idx)
+    out = Kernels(**{f: (getattr(K, f)[idx] if isinstance(getattr(K, f), np.ndarray) else getattr(K, f))
+                     for f in K.__dataclass_fields__})
+    return out
+
+
 def truncation_bound(levels: List[OLevel], K: Kernels) -> List[np.ndarray]:
     """Per-point bound on |f_all - f_culled|: the sum over culled pairs of
     |a_j| exp(-d_min,j^2 ||Delta||^2), which dominates each dropped term."""

@@ -216,3 +216,43 @@ def test_adam_matches_oracle():
     err = np.abs(gp.p.cpu().numpy() - p64).max()
     record("adam", max_abs_err=err)
     assert err < 1e-5
+
+
+def test_tiny_trajectory_100_adam_steps():
+    """100 steps of fixed-lambda training (lr 1e-3, lambda 1e-4) on the GPU
+    and in the float64 oracle from the same start: the loss stays within
+    1e-3 of the oracle's at every step."""
+    torch = _torch()
+    prob = _tiny()
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32)
+    dev = gp.ctx.device
+    cap, m = prob.cap, prob.m
+    m1 = torch.zeros(11 * cap, device=dev)
+    m2 = torch.zeros(11 * cap, device=dev)
+    grad = torch.zeros(11 * cap, device=dev)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    p64 = prob.params.astype(np.float64)
+    o1 = np.zeros_like(p64)
+    o2 = np.zeros_like(p64)
+    worst_l2 = worst_loss = 0.0
+    first_count_diff = None
+    for t in range(1, 101):
+        gp.ctx.erbf_loss_grad(gp.p, gp.m_dev, mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2, grad_out=grad)
+        st = gp.ctx.stats()[0]
+        seg = p64.reshape(11, cap)[:, :m]
+        K = O.make_kernels(seg[0], seg[1:4].T, seg[4:7].T, seg[7:11].T, prob.cull_k)
+        ref = O.step(olv, K, mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2, count_pairs=False)
+        loss_or = ref.loss.L2 + 1e-4 * ref.loss.L1
+        worst_l2 = max(worst_l2, abs(st.L2 - ref.loss.L2) / ref.loss.L2)
+        worst_loss = max(worst_loss, abs(st.loss - loss_or) / loss_or)
+        if first_count_diff is None and st.n_idall != ref.loss.n_idall:
+            first_count_diff = t
+        gp.ctx.erbf_adam_step(gp.p, gp.m_dev, grad, m1, m2, step, lr=1e-3)
+        p64, o1, o2 = O.adam_step(p64, ref.grads.packed(cap), o1, o2, t, 1e-3)
+    torch.cuda.synchronize()
+    p_err = np.abs(gp.p.cpu().numpy().astype(np.float64) - p64).max()
+    record("trajectory_tiny_100", worst_rel_L2=worst_l2, worst_rel_loss=worst_loss,
+           first_step_n_idall_differs=first_count_diff, final_param_max_abs_diff=p_err,
+           L2_last=st.L2)
+    assert worst_l2 <= 1e-3 and worst_loss <= 1e-3

@@ -280,3 +280,18 @@ def test_seed_single_peak_and_ties():
     assert np.array_equal(out.w, [-0.5, 0.5])
     assert out.n_candidates == 3 and out.n_extreme == 2
     assert np.array_equal(out.c[0], pts[p1])
+
+
+def test_kernel_field_sums_to_forward_and_subset_gradients():
+    lv, K, _ = _problem(seed=14, n=12, m=5)
+    f = O.forward([lv], K)[0].reshape(lv.n, lv.n, lv.n)
+    acc = np.zeros_like(f)
+    for j in range(K.m):
+        (z0, z1, y0, y1, x0, x1), v = O.kernel_field(lv, K, j)
+        acc[z0:z1, y0:y1, x0:x1] += v
+    assert np.abs(acc - f).max() < 1e-14
+    G = [np.random.default_rng(1).standard_normal(lv.npts)]
+    full = O.backward([lv], K, G)
+    part = O.backward([lv], O.subset(K, [1, 3]), G)
+    assert np.allclose(part.q, full.q[[1, 3]], rtol=1e-13, atol=0)
+    assert np.allclose(part.c, full.c[[1, 3]], rtol=1e-13, atol=0)

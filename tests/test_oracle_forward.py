@@ -210,3 +210,24 @@ def test_boundary_allowance_counts_only_near_shell():
         d2 = np.sum((pts - K.c[j]) ** 2, axis=1)
         brute += int(np.sum(np.abs(d2 - K.r2[j]) <= 1e-2 * K.r2[j]))
     assert cnt == brute
+
+
+def test_point_evaluation_and_allowance_match_the_grid_versions():
+    # forward_at_points / allowance_at_points against forward / boundary_allowance
+    rng = np.random.default_rng(12)
+    n = 16
+    ax = (-1.0 + (2.0 * np.arange(n) + 1.0) / n).astype(np.float32)
+    lv = O.make_level(n, ax)
+    m = 9
+    K = O.make_kernels(rng.normal(0, 1, m), rng.uniform(-0.6, 0.6, (m, 3)), rng.uniform(1.2, 2.2, (m, 3)),
+                       rng.normal(size=(m, 4)), 3.0)
+    f = O.forward([lv], K)[0]
+    al, cnt = O.boundary_allowance([lv], K, rel=1e-2)
+    idx = rng.choice(n ** 3, 300, replace=False)
+    x = ax.astype(np.float64)
+    pts = np.stack([x[idx % n], x[(idx // n) % n], x[idx // (n * n)]], axis=1)
+    assert np.allclose(O.forward_at_points(pts, K), f[idx], rtol=1e-12, atol=1e-15)
+    ap, _ = O.allowance_at_points(pts, K, rel=1e-2)
+    assert np.allclose(ap, al[0][idx], rtol=1e-12, atol=1e-15)
+    _, call = O.allowance_at_points(O.level_points(lv), K, rel=1e-2)
+    assert call == cnt and cnt > 0
