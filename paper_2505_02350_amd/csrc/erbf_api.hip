@@ -44,9 +44,10 @@ struct Layout {
   int64_t pts_total = 0;
   int64_t cand_cap = 0;
   int scan_blocks = 0;
-  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_cnt, off_tile_start,
-      off_cursor, off_items_raw, off_visit_raw, off_items, off_kcnt, off_kstart, off_kmap, off_partials,
-      off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_kstat,
+  int radix_nb = 0;
+  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_sort_keys[2],
+      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_items, off_kcnt, off_kstart, off_kmap, off_partials,
+      off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_hist, off_cand, off_keep, off_misc;
   size_t bytes = 0;
 };
@@ -94,7 +95,9 @@ Layout make_layout(const erbf_config* cfg) {
     }
   }
   L.cand_cap = L.pts_total / 20 + 1024;
-  L.scan_blocks = (std::max(L.tiles_total, L.cap_total) + 1) / 1024 + 2;
+  // radix-sort blocks: about 4096 bucket entries each at full capacity
+  L.radix_nb = (int)std::min<int64_t>(1024, std::max<int64_t>(32, (cfg->pair_cap + 4095) / 4096));
+  L.scan_blocks = (std::max(std::max(L.tiles_total, L.cap_total), 256 * L.radix_nb) + 1) / 1024 + 2;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   L.off_levels = take(sizeof(LevelDev) * L.n_levels_total);
@@ -102,11 +105,14 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_kshape = take(sizeof(int32_t) * L.cap_total);
   L.off_slot_tile = take(sizeof(int2) * L.tiles_total);
   L.off_tile_map = take(sizeof(int32_t) * L.tiles_total);
-  L.off_tile_cnt = take(sizeof(int32_t) * (L.tiles_total + 1));
   L.off_tile_start = take(sizeof(int32_t) * (L.tiles_total + 1));
-  L.off_cursor = take(sizeof(int32_t) * L.tiles_total);
-  L.off_items_raw = take(sizeof(int32_t) * cfg->pair_cap);
-  L.off_visit_raw = take(sizeof(int32_t) * cfg->pair_cap);
+  for (int k = 0; k < 2; ++k) {
+    L.off_sort_keys[k] = take(sizeof(int32_t) * cfg->pair_cap);
+    L.off_sort_vals[k] = take(sizeof(int32_t) * cfg->pair_cap);
+  }
+  L.off_kj = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_rhist = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 1));
+  L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 1));
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
   L.off_kstart = take(sizeof(int32_t) * (L.cap_total + 1));
@@ -119,7 +125,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_rec = take(sizeof(float4) * 3 * L.cap_total);
   L.off_G = take(sizeof(float) * L.pts_total);
   L.off_tstat = take(sizeof(TileStat) * L.tiles_total);
-  L.off_kstat = take(sizeof(KernStat) * L.cap_total);
+  L.off_tile_pbwd = take(sizeof(int64_t) * L.tiles_total);
   L.off_counters = take(sizeof(int64_t) * 8);
   L.off_hist = take(sizeof(uint32_t) * 65536);
   L.off_cand = take(sizeof(int64_t) * L.cand_cap);
@@ -224,11 +230,14 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.kshape = reinterpret_cast<int32_t*>(w + lay.off_kshape);
   D.slot_tile = reinterpret_cast<int2*>(w + lay.off_slot_tile);
   D.tile_map = reinterpret_cast<int32_t*>(w + lay.off_tile_map);
-  D.tile_cnt = reinterpret_cast<int32_t*>(w + lay.off_tile_cnt);
   D.tile_start = reinterpret_cast<int32_t*>(w + lay.off_tile_start);
-  D.cursor = reinterpret_cast<int32_t*>(w + lay.off_cursor);
-  D.items_raw = reinterpret_cast<int32_t*>(w + lay.off_items_raw);
-  D.visit_raw = reinterpret_cast<int32_t*>(w + lay.off_visit_raw);
+  for (int k = 0; k < 2; ++k) {
+    D.sort_keys[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_keys[k]);
+    D.sort_vals[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_vals[k]);
+  }
+  D.kj = reinterpret_cast<int32_t*>(w + lay.off_kj);
+  D.rhist = reinterpret_cast<int32_t*>(w + lay.off_rhist);
+  D.rhist_ex = reinterpret_cast<int32_t*>(w + lay.off_rhist_ex);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
   D.kstart = reinterpret_cast<int32_t*>(w + lay.off_kstart);
@@ -241,7 +250,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.rec = reinterpret_cast<float4*>(w + lay.off_rec);
   D.G = reinterpret_cast<float*>(w + lay.off_G);
   D.tstat = reinterpret_cast<TileStat*>(w + lay.off_tstat);
-  D.kstat = reinterpret_cast<KernStat*>(w + lay.off_kstat);
+  D.tile_pbwd = reinterpret_cast<int64_t*>(w + lay.off_tile_pbwd);
   D.counters = reinterpret_cast<int64_t*>(w + lay.off_counters);
   D.seed_hist = reinterpret_cast<uint32_t*>(w + lay.off_hist);
   D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
@@ -249,6 +258,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.seed_misc = reinterpret_cast<int32_t*>(w + lay.off_misc);
   D.cand_cap = lay.cand_cap;
   D.pair_cap = cfg->pair_cap;
+  D.radix_nb = lay.radix_nb;
   D.cap_total = lay.cap_total;
   D.tiles_total = lay.tiles_total;
   D.n_shapes = cfg->n_shapes;

@@ -48,11 +48,6 @@ struct TileStat {
   int64_t p_fwd;           // in-ball pairs at active points of the tile
 };
 
-// Per-kernel counters written by the backward pass.
-struct KernStat {
-  int64_t p_fwd;
-  int64_t p_bwd;
-};
 
 // Launch plumbing shared by the .hip translation units.
 struct Dev {
@@ -63,11 +58,12 @@ struct Dev {
   int2* slot_tile;          // [tiles_total] (level index, tile linear id) per active slot
   int32_t* tile_map;        // [tiles_total] slot of each tile or -1
   // buckets
-  int32_t* tile_cnt;        // [tiles_total + 1]
   int32_t* tile_start;      // [tiles_total + 1]
-  int32_t* cursor;          // [tiles_total]
-  int32_t* items_raw;       // [pair_cap] kernel ids in arrival order
-  int32_t* visit_raw;       // [pair_cap] per-kernel visit index of each raw entry
+  int32_t* sort_keys[2];    // [pair_cap] tile slot of each entry (radix ping-pong)
+  int32_t* sort_vals[2];    // [pair_cap] kernel-major index of each entry (ping-pong)
+  int32_t* kj;              // [pair_cap] kernel of each kernel-major entry
+  int32_t* rhist;           // [256 * radix_nb + 1] digit counts per sort block
+  int32_t* rhist_ex;        // [256 * radix_nb + 1] their exclusive scan (digit-major)
   int32_t* items;           // [pair_cap] kernel ids, ascending within each tile
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
   int32_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
@@ -79,8 +75,8 @@ struct Dev {
   float4* rec;              // [3 * cap_total]
   float* G;                 // [pts_total]
   TileStat* tstat;          // [tiles_total]
-  KernStat* kstat;          // [cap_total]
-  int64_t* counters;        // [8]: 0 bucket total
+  int64_t* tile_pbwd;       // [tiles_total] in-ball pairs at non-zero-G points of each tile
+  int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
   // seeding scratch
   uint32_t* seed_hist;      // [65536]
   int64_t* seed_cand;       // [cand_cap]
@@ -95,6 +91,7 @@ struct Dev {
   int32_t weight_map;
   int32_t variant;          // kVariant* flags
   int32_t persistent_wgs;   // grid of the persistent variants
+  int32_t radix_nb;         // blocks of each radix-sort pass
 };
 
 }  // namespace erbf

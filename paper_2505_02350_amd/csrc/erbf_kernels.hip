@@ -146,27 +146,31 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
-// buckets: tiles whose point box meets the (slightly enlarged) ball.
-// One wave per kernel slot; lanes test the tiles of the ball's tile box.  A
-// kernel's tiles are numbered in a fixed order (level, z, y, x): that visit
-// index lets the backward reduce a kernel's per-tile partials in a fixed
-// order.
+// Tile buckets.  One wave per kernel slot; lanes test the tiles of the
+// ball's tile box.  A kernel's tiles are numbered in a fixed order (level,
+// z, y, x): the visit index.  EMIT = false counts each kernel's tiles;
+// EMIT = true writes the entries kernel-major, entry e = kstart[j] + visit,
+// with the tile slot as the sort key.  A stable sort of the kernel-major
+// list by slot then gives every tile's kernels in ascending order, with no
+// atomics and the same result on every run.
 // ---------------------------------------------------------------------------
 
-template <bool SCATTER>
+template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bucket(Dev D) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= D.cap_total) return;
   const float4 r0 = D.rec[3 * j];
   if (r0.w < 0.f) {
-    if (!SCATTER && lane == 0) D.kcnt[j] = 0;
+    if (!EMIT && lane == 0) D.kcnt[j] = 0;
     return;
   }
   const ShapeDev S = D.shapes[D.kshape[j]];
   const float rr = sqrtf(r0.w) * (1.0f + 1e-5f) + 1e-6f;
   const float rc2 = rr * rr;
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  const int64_t e0 = EMIT ? (int64_t)D.kstart[j] : 0;
+  const int cnt_j = EMIT ? D.kcnt[j] : 0;
   int vbase = 0;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bucket(Dev D) {
     index_range(L, r0.y - rr, r0.y + rr, iy0, iy1);
     index_range(L, r0.z - rr, r0.z + rr, iz0, iz1);
     if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
-    const int nt = L.nt, n = L.n;
+    const int nt = L.nt;
     const int tx0 = ix0 / kTile, ty0 = iy0 / kTile, tz0 = iz0 / kTile;
     const int ntx = ix1 / kTile - tx0 + 1, nty = iy1 / kTile - ty0 + 1, ntz = iz1 / kTile - tz0 + 1;
     const int total = ntx * nty * ntz;
@@ -199,65 +203,144 @@ __global__ __launch_bounds__(256) void k_bucket(Dev D) {
         }
       }
       const unsigned long long bal = __ballot(hit);
-      if (hit) {
-        if (SCATTER) {
-          const int v = vbase + __popcll(bal & lt_mask);
-          const int pos = atomicAdd(&D.cursor[slot], 1);
-          const int64_t at = (int64_t)D.tile_start[slot] + pos;
-          if (at < D.pair_cap) {
-            D.items_raw[at] = j;
-            D.visit_raw[at] = v;
-          }
-        } else {
-          atomicAdd(&D.tile_cnt[slot], 1);
+      if (EMIT && hit) {
+        const int v = vbase + __popcll(bal & lt_mask);
+        const int64_t at = e0 + v;
+        if (v < cnt_j && at < D.pair_cap) {
+          D.sort_keys[0][at] = slot;
+          D.kj[at] = j;
         }
       }
       vbase += __popcll(bal);
     }
   }
-  if (!SCATTER && lane == 0) D.kcnt[j] = vbase;
-}
-
-// Per-tile ascending sort of the bucket list (fixes the forward's summation
-// order) and the kernel-major map of entries used by the backward reduction.
-// The kernel ids of one list are distinct, so each entry's final position is
-// its rank: the number of smaller ids in the list (read four at a time from
-// LDS with broadcast loads; no barriers inside the count).
-__global__ __launch_bounds__(256) void k_sort_tiles(Dev D) {
-  __shared__ int4 keys4[1024];
-  const int s = blockIdx.x;
-  const int64_t beg = min((int64_t)D.tile_start[s], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[s + 1], D.pair_cap);
-  const int cnt = (int)(end - beg);
-  const int tid = threadIdx.x;
-  if (cnt <= 0) return;
-  if (cnt <= 4096) {
-    int* keys = reinterpret_cast<int*>(keys4);
-    const int c4 = (cnt + 3) >> 2;
-    for (int i = tid; i < 4 * c4; i += blockDim.x) keys[i] = i < cnt ? D.items_raw[beg + i] : INT32_MAX;
-    __syncthreads();
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const int v = keys[i];
-      int rank = 0;
-      for (int k = 0; k < c4; ++k) {
-        const int4 q = keys4[k];
-        rank += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
-      }
-      D.items[beg + rank] = v;
-      const int64_t km = (int64_t)D.kstart[v] + D.visit_raw[beg + i];
-      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + rank), s);
-    }
+  if (!EMIT) {
+    if (lane == 0) D.kcnt[j] = vbase;
   } else {
-    // long list: rank of each (distinct) kernel id
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const int v = D.items_raw[beg + i];
-      int rank = 0;
-      for (int k = 0; k < cnt; ++k) rank += D.items_raw[beg + k] < v;
-      D.items[beg + rank] = v;
-      const int64_t km = (int64_t)D.kstart[v] + D.visit_raw[beg + i];
-      if (km < D.pair_cap) D.kmap[km] = make_int2((int)(beg + rank), s);
+    // both passes take the same decisions; should they ever differ, the
+    // counted range is still filled, with a slot past every real tile
+    for (int v = vbase + lane; v < cnt_j; v += 64) {
+      const int64_t at = e0 + v;
+      if (at < D.pair_cap) {
+        D.sort_keys[0][at] = D.tiles_total;
+        D.kj[at] = j;
+      }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of the (slot, entry) pairs, up to 8 key bits per
+// pass.  A fixed grid of radix_nb blocks; block b owns one contiguous
+// segment of the entries.  Pass = digit counts per block, an exclusive scan
+// over (digit, block), then a stable scatter: within a block, the rank of an
+// entry among equal digits comes from wave ballots (lanes in entry order)
+// and per-wave running counts, so equal keys keep their order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t bucket_entries(const Dev& D) { return min(D.counters[0], D.pair_cap); }
+
+__device__ __forceinline__ void radix_segment(int64_t n, int nb, int b, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + nb - 1) / nb;
+  lo = min(n, per * b);
+  hi = min(n, lo + per);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(Dev D, const int32_t* __restrict__ keys, int shift, int mask) {
+  __shared__ int cnt[256];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  int64_t lo, hi;
+  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
+  for (int64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
+  __syncthreads();
+  D.rhist[t * D.radix_nb + blockIdx.x] = cnt[t];
+}
+
+constexpr int kRadixPerLane = 8;                     // entries per lane per block iteration
+constexpr int kRadixWaveSpan = 64 * kRadixPerLane;   // consecutive entries of one wave
+constexpr int kRadixSpan = 4 * kRadixWaveSpan;       // entries per block iteration
+
+__global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
+                                                       int32_t* __restrict__ vout, int shift, int mask, int dbits) {
+  __shared__ int run[256];
+  __shared__ int wcnt[4][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  int64_t lo, hi;
+  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
+  run[t] = D.rhist_ex[t * D.radix_nb + blockIdx.x];
+  for (int64_t base = lo; base < hi; base += kRadixSpan) {
+    for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0;
+    __syncthreads();
+    int key[kRadixPerLane], val[kRadixPerLane], rank[kRadixPerLane];
+    bool ok[kRadixPerLane];
+#pragma unroll
+    for (int i = 0; i < kRadixPerLane; ++i) {
+      const int64_t idx = base + w * kRadixWaveSpan + i * 64 + lane;
+      ok[i] = idx < hi;
+      key[i] = ok[i] ? kin[idx] : 0;
+      val[i] = ok[i] ? (vin ? vin[idx] : (int)idx) : 0;
+      const int d = (key[i] >> shift) & mask;
+      // lanes of this wave holding the same digit
+      unsigned long long same = __ballot(ok[i]);
+      for (int b = 0; b < dbits; ++b) {
+        const bool bit = (d >> b) & 1;
+        const unsigned long long bb = __ballot(bit);
+        same &= bit ? bb : ~bb;
+      }
+      const int before = wcnt[w][d];
+      rank[i] = before + __popcll(same & lt);
+      if (ok[i] && (same & lt) == 0) wcnt[w][d] = before + __popcll(same);
+    }
+    __syncthreads();
+    {  // digit t: where each wave's run starts, after the earlier iterations
+      int r = run[t];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        const int c = wcnt[ww][t];
+        wcnt[ww][t] = r;
+        r += c;
+      }
+      run[t] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRadixPerLane; ++i) {
+      if (ok[i]) {
+        const int pos = wcnt[w][(key[i] >> shift) & mask] + rank[i];
+        kout[pos] = key[i];
+        vout[pos] = val[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sorted entries -> per-tile kernel lists and the kernel-major map.
+__global__ __launch_bounds__(256) void k_bucket_finish(Dev D, const int32_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ vals) {
+  const int64_t n = bucket_entries(D);
+  for (int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x; pos < n; pos += (int64_t)gridDim.x * 256) {
+    const int e = vals ? vals[pos] : (int)pos;
+    D.items[pos] = D.kj[e];
+    D.kmap[e] = make_int2((int)pos, keys[pos]);
+  }
+}
+
+// tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots).
+__global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __restrict__ keys, int n_slots) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s > n_slots) return;
+  int64_t lo = 0, hi = bucket_entries(D);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < s) lo = mid + 1;
+    else hi = mid;
+  }
+  D.tile_start[s] = (int)lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -418,14 +501,16 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       if ((mybits >> w) & 1u) {
         int off = prefix[w];
         for (int v = 0; v < wv; ++v) off += scnt[w][v];
-        slist[w][off] = (uint16_t)tid;
+        slist[w][off] = (uint16_t)(tid * (int)sizeof(float4) * 3);   // byte offset of the record
       }
     }
     __syncthreads();
-    const int len = scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3];
+    const int len = __builtin_amdgcn_readfirstlane(scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3]);
+    const char* srec_b = reinterpret_cast<const char*>(srec);
+    uint32_t pf = 0;
     for (int k = 0; k < len; ++k) {
-      const int e = slist[wv][k];
-      const float4 a0 = srec[3 * e], a1 = srec[3 * e + 1], a2 = srec[3 * e + 2];
+      const float4* rp = reinterpret_cast<const float4*>(srec_b + slist[wv][k]);
+      const float4 a0 = rp[0], a1 = rp[1], a2 = rp[2];
       const float dy = py - a0.y, dz = pz - a0.z;
       const float syz = fmaf(dy, dy, dz * dz);
       const float bl = fmaf(a1.w, dy, a2.x * dz);
@@ -439,8 +524,9 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       q1 = in1 ? q1 : INFINITY;
       acc0 = fmaf(a2.z, fast_exp2(-q0), acc0);
       acc1 = fmaf(a2.z, fast_exp2(-q1), acc1);
-      pfw += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
+      pf += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
     }
+    pfw += pf;
     __syncthreads();
   }
 
@@ -518,9 +604,14 @@ __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __rest
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc) {
-  __shared__ float4 spt[kTile * kTile * kTile];
-  __shared__ int srow[kTile * kTile * kTile];
-  __shared__ int swc[2][4];
+  // non-zero points, row by row: row r's points sit at spx[8 r ...], padded
+  // to an even count with inert points (far away, G = 0) so that they are
+  // read two at a time
+  __shared__ float4 spx4[kTile * kTile * kTile / 2];
+  __shared__ float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
+  __shared__ int swr[2][4];
+  __shared__ int64_t spb[4];
+  float2* spx = reinterpret_cast<float2*>(spx4);
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
@@ -529,55 +620,66 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
   const float* __restrict__ G = Gsrc + L.pt_base;
 
-  // stage the non-zero points in local-index order (p = t + 256 h)
-  float4 pt[2];
-  int prow[2];
-  bool nz[2];
+  // thread p = tid + 256 h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
+  // of the tile: eight consecutive lanes hold one row
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  const int rl = lane & ~7;                       // first lane of this lane's row
+  bool row_used[2];
+  int row_cnt[2], row_pos[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int p = tid + 256 * h;
     const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
     float g = 0.f;
     if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
-    nz[h] = g != 0.f;
-    prow[h] = p >> 3;
-    pt[h] = nz[h] ? make_float4(L.axis[xi], L.axis[yi], L.axis[zi], g) : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  const unsigned long long lt_mask = (1ull << lane) - 1ull;
-  unsigned long long bal[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    bal[h] = __ballot(nz[h]);
-    if (lane == 0) swc[h][wv] = __popcll(bal[h]);
+    const bool nz = g != 0.f;
+    const unsigned long long bal = __ballot(nz);
+    const unsigned row_bits = (unsigned)(bal >> rl) & 0xffu;
+    const int r = p >> 3;
+    if (nz) spx[8 * r + __popc(row_bits & ((1u << (lane & 7)) - 1u))] = make_float2(L.axis[xi], g);
+    const int c = __popc(row_bits);
+    row_cnt[h] = c;
+    row_used[h] = c > 0;
+    if ((lane & 7) == 0 && (c & 1)) spx[8 * r + c] = make_float2(1e30f, 0.f);
+    const unsigned long long rb = __ballot((lane & 7) == 0 && c > 0);
+    row_pos[h] = __popcll(rb & lt_mask);
+    if (lane == 0) swr[h][wv] = __popcll(rb);
   }
   __syncthreads();
-  int off0 = 0, tot0 = 0, tot1 = 0;
-  for (int v = 0; v < 4; ++v) {
-    if (v < wv) off0 += swc[0][v];
-    tot0 += swc[0][v];
-    tot1 += swc[1][v];
+  int tot = 0;
+  int base_h[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int v = 0; v < 4; ++v) {
+      if (v == wv) base_h[h] = tot;
+      tot += swr[h][v];
+    }
   }
-  int off1 = tot0;
-  for (int v = 0; v < wv; ++v) off1 += swc[1][v];
-  if (nz[0]) {
-    const int k = off0 + __popcll(bal[0] & lt_mask);
-    spt[k] = pt[0];
-    srow[k] = prow[0];
-  }
-  if (nz[1]) {
-    const int k = off1 + __popcll(bal[1] & lt_mask);
-    spt[k] = pt[1];
-    srow[k] = prow[1];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if ((lane & 7) == 0 && row_used[h]) {
+      const int p = tid + 256 * h;
+      const int yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
+      srow[base_h[h] + row_pos[h]] =
+          make_float4(L.axis[yi], L.axis[zi], __int_as_float(8 * (p >> 3)), __int_as_float((row_cnt[h] + 1) & ~1));
+    }
   }
   // workgroup-uniform (all threads read the same LDS counts); readfirstlane
   // makes that visible, so the early exit below is a scalar branch
-  const int Z = __builtin_amdgcn_readfirstlane(tot0 + tot1);
-  if (tid == 0) D.tile_nz[slot] = Z > 0;
-  if (Z == 0) return;
+  const int R = __builtin_amdgcn_readfirstlane(tot);
+  if (R == 0) {
+    if (tid == 0) {
+      D.tile_nz[slot] = 0;
+      D.tile_pbwd[slot] = 0;
+    }
+    return;
+  }
+  if (tid == 0) D.tile_nz[slot] = 1;
   __syncthreads();
 
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  int64_t pb = 0;   // in-ball pairs at non-zero points (wave-uniform)
   // each wave takes its own groups of 64 kernels, so waves past the end of
   // the list do no work
   for (int64_t c0 = beg + 64 * wv; c0 < end; c0 += 256) {
@@ -595,45 +697,49 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     float T[10];
 #pragma unroll
     for (int i = 0; i < 10; ++i) T[i] = 0.f;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, cnt = 0.f;
-    float dy = 0.f, dz = 0.f, syz = 0.f, bl = 0.f, cc = 0.f;
-    int cur = -1;
-    for (int k = 0; k < Z; ++k) {
-      const float4 P = spt[k];
-      const int row = srow[k];
-      if (row != cur) {
-        T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
-        T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
-        T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
-        s0 = s1 = s2 = 0.f;
-        dy = P.y - cy;
-        dz = P.z - cz;
-        syz = fmaf(dy, dy, dz * dz);
-        bl = fmaf(A01x2, dy, A02x2 * dz);
-        cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
-        cur = row;
+    uint32_t pbg = 0;
+    for (int r = 0; r < R; ++r) {
+      const float4 RW = srow[r];
+      const int k0 = __builtin_amdgcn_readfirstlane(__float_as_int(RW.z)) >> 1;
+      const int kn = __builtin_amdgcn_readfirstlane(__float_as_int(RW.w)) >> 1;
+      const float dy = RW.x - cy;
+      const float dz = RW.y - cz;
+      const float syz = fmaf(dy, dy, dz * dz);
+      const float bl = fmaf(A01x2, dy, A02x2 * dz);
+      const float cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      for (int k = 0; k < kn; ++k) {
+        const float4 PP = spx4[k0 + k];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float px = u ? PP.z : PP.x, pg = u ? PP.w : PP.y;
+          const float dx = px - cx;
+          const bool in = fmaf(dx, dx, syz) < rad2;
+          float q = fmaf(dx, fmaf(A00, dx, bl), cc);
+          q = in ? q : INFINITY;
+          const float g = pg * fast_exp2(-q);
+          s0 += g;
+          const float gx = g * dx;
+          s1 += gx;
+          s2 = fmaf(gx, dx, s2);
+          pbg += __popcll(__ballot(in));
+        }
       }
-      const float dx = P.x - cx;
-      const bool in = fmaf(dx, dx, syz) < rad2;
-      float q = fmaf(dx, fmaf(A00, dx, bl), cc);
-      q = in ? q : INFINITY;
-      const float g = P.w * fast_exp2(-q);
-      s0 += g;
-      const float gx = g * dx;
-      s1 += gx;
-      s2 = fmaf(gx, dx, s2);
-      cnt += in ? 1.f : 0.f;
+      T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
+      T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
+      T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
     }
-    T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
-    T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
-    T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
+    pb += pbg;
     if (have) {
       float4* o = D.partials + 3 * (c0 + lane);
       o[0] = make_float4(T[0], T[1], T[2], T[3]);
       o[1] = make_float4(T[4], T[5], T[6], T[7]);
-      o[2] = make_float4(T[8], T[9], cnt, 0.f);
+      o[2] = make_float4(T[8], T[9], 0.f, 0.f);
     }
   }
+  if (lane == 0) spb[wv] = pb;
+  __syncthreads();
+  if (tid == 0) D.tile_pbwd[slot] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
@@ -661,12 +767,11 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   const float4 r0 = D.rec[3 * j];
   if (r0.w < 0.f) {
     if (lane < 11) grad[lane * C + j] = 0.f;
-    if (lane == 0) { D.kstat[j].p_fwd = 0; D.kstat[j].p_bwd = 0; }
     return;
   }
-  double v[11];
+  double v[10];
 #pragma unroll
-  for (int i = 0; i < 11; ++i) v[i] = 0.0;
+  for (int i = 0; i < 10; ++i) v[i] = 0.0;
   const int64_t base = D.kstart[j];
   const int c = D.kcnt[j];
   for (int e = lane; e < c; e += 64) {
@@ -678,10 +783,10 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
     const float4 a = q[0], b = q[1], d = q[2];
     v[0] += a.x; v[1] += a.y; v[2] += a.z; v[3] += a.w;
     v[4] += b.x; v[5] += b.y; v[6] += b.z; v[7] += b.w;
-    v[8] += d.x; v[9] += d.y; v[10] += d.z;
+    v[8] += d.x; v[9] += d.y;
   }
 #pragma unroll
-  for (int i = 0; i < 11; ++i) v[i] = wave_sum(v[i]);
+  for (int i = 0; i < 10; ++i) v[i] = wave_sum(v[i]);
   if (lane != 0) return;
 
   const double w = p[j];
@@ -738,8 +843,6 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
   for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
   for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
-  D.kstat[j].p_fwd = 0;
-  D.kstat[j].p_bwd = (int64_t)v[10];
 }
 
 // ---------------------------------------------------------------------------
@@ -809,7 +912,10 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
     }
   }
   if (MODE >= 1) {
-    for (int k = tid; k < m; k += 1024) pb += (double)D.kstat[S.kbase + k].p_bwd;
+    for (int li = 0; li < S.n_active; ++li) {
+      const LevelDev L = D.levels[S.lvl0 + li];
+      for (int s = tid; s < L.n_slots; s += 1024) pb += (double)D.tile_pbwd[L.slot0 + s];
+    }
   }
   l2 = block_sum_1024(l2, shd);
   nid = block_sum_1024(nid, shd);
@@ -1039,16 +1145,30 @@ hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, 
 
 hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
   if (n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots + 1)), dim3(256), 0, s, D.tile_cnt,
-                     (int64_t)n_slots + 1, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(gridstride(n_slots)), dim3(256), 0, s, D.cursor, (int64_t)n_slots, 0);
   hipLaunchKernelGGL(k_bucket<false>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
-  hipError_t e = launch_scan(D.tile_cnt, n_slots, D.scan_blocks, D.tile_start, D.counters, s);
-  if (e != hipSuccess) return e;
-  e = launch_scan(D.kcnt, D.cap_total, D.scan_blocks, D.kstart, D.counters + 2, s);
+  hipError_t e = launch_scan(D.kcnt, D.cap_total, D.scan_blocks, D.kstart, D.counters, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bucket<true>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_sort_tiles, dim3(n_slots), dim3(256), 0, s, D);
+  // keys are slots (< n_slots) or the filler tiles_total: sort on just
+  // enough bits, at most 8 per pass
+  int bits = 0;
+  while ((1ll << bits) <= (int64_t)D.tiles_total) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int dbits = passes ? (bits + passes - 1) / passes : 0;
+  const int32_t* vals = nullptr;     // identity: entry e holds value e
+  int cur = 0;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * dbits, mask = (1 << dbits) - 1;
+    hipLaunchKernelGGL(k_radix_hist, dim3(D.radix_nb), dim3(256), 0, s, D, D.sort_keys[cur], shift, mask);
+    e = launch_scan(D.rhist, 256 * D.radix_nb, D.scan_blocks, D.rhist_ex, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(D.radix_nb), dim3(256), 0, s, D, D.sort_keys[cur], vals,
+                       D.sort_keys[cur ^ 1], D.sort_vals[cur ^ 1], shift, mask, dbits);
+    cur ^= 1;
+    vals = D.sort_vals[cur];
+  }
+  hipLaunchKernelGGL(k_bucket_finish, dim3(gridstride(D.pair_cap)), dim3(256), 0, s, D, D.sort_keys[cur], vals);
+  hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.sort_keys[cur], n_slots);
   return hipGetLastError();
 }
 
