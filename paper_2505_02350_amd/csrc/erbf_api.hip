@@ -45,10 +45,11 @@ struct Layout {
   int64_t cand_cap = 0;
   int scan_blocks = 0;
   int radix_nb = 0;
-  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_sort_keys[2],
-      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_items, off_kcnt, off_kstart, off_kmap, off_partials,
+  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_kslot, off_sort_keys[2],
+      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
+      off_partials,
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
-      off_counters, off_hist, off_cand, off_keep, off_misc;
+      off_counters, off_stat_part, off_stat_ab, off_hist, off_cand, off_keep, off_misc;
   size_t bytes = 0;
 };
 
@@ -109,15 +110,20 @@ Layout make_layout(const erbf_config* cfg) {
   for (int k = 0; k < 2; ++k) {
     L.off_sort_keys[k] = take(sizeof(int32_t) * cfg->pair_cap);
     L.off_sort_vals[k] = take(sizeof(int32_t) * cfg->pair_cap);
+    L.off_sort_j[k] = take(sizeof(int32_t) * cfg->pair_cap);
   }
   L.off_kj = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_kslot = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_tile_keys = take(sizeof(int32_t) * cfg->pair_cap);
+  L.off_tile_e = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_rhist = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 1));
-  L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 1));
+  L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 256));
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
   L.off_kstart = take(sizeof(int32_t) * (L.cap_total + 1));
-  L.off_kmap = take(sizeof(int2) * cfg->pair_cap);
-  L.off_partials = take(sizeof(float4) * 3 * cfg->pair_cap);
+  L.off_kblock = take(sizeof(int32_t) * (L.cap_total / 4 + 1));
+  L.off_kblock_ex = take(sizeof(int32_t) * (L.cap_total / 4 + 2));
+  L.off_partials = take(sizeof(float2) * 5 * cfg->pair_cap);
   L.off_tile_nz = take(sizeof(int32_t) * L.tiles_total);
   L.off_scan = take(sizeof(int32_t) * L.scan_blocks);
   L.off_rflags = take(sizeof(int32_t) * (L.max_level_tiles + 1));
@@ -127,6 +133,8 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_tstat = take(sizeof(TileStat) * L.tiles_total);
   L.off_tile_pbwd = take(sizeof(int64_t) * L.tiles_total);
   L.off_counters = take(sizeof(int64_t) * 8);
+  L.off_stat_part = take(sizeof(StatPart) * kStatParts * cfg->n_shapes);
+  L.off_stat_ab = take(sizeof(double2) * cfg->n_shapes);
   L.off_hist = take(sizeof(uint32_t) * 65536);
   L.off_cand = take(sizeof(int64_t) * L.cand_cap);
   L.off_keep = take(sizeof(int64_t) * L.cand_cap);
@@ -234,15 +242,20 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   for (int k = 0; k < 2; ++k) {
     D.sort_keys[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_keys[k]);
     D.sort_vals[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_vals[k]);
+    D.sort_j[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_j[k]);
   }
   D.kj = reinterpret_cast<int32_t*>(w + lay.off_kj);
+  D.kslot = reinterpret_cast<int32_t*>(w + lay.off_kslot);
+  D.tile_keys = reinterpret_cast<int32_t*>(w + lay.off_tile_keys);
+  D.tile_e = reinterpret_cast<int32_t*>(w + lay.off_tile_e);
   D.rhist = reinterpret_cast<int32_t*>(w + lay.off_rhist);
   D.rhist_ex = reinterpret_cast<int32_t*>(w + lay.off_rhist_ex);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
   D.kstart = reinterpret_cast<int32_t*>(w + lay.off_kstart);
-  D.kmap = reinterpret_cast<int2*>(w + lay.off_kmap);
-  D.partials = reinterpret_cast<float4*>(w + lay.off_partials);
+  D.kblock = reinterpret_cast<int32_t*>(w + lay.off_kblock);
+  D.kblock_ex = reinterpret_cast<int32_t*>(w + lay.off_kblock_ex);
+  D.partials = reinterpret_cast<float2*>(w + lay.off_partials);
   D.tile_nz = reinterpret_cast<int32_t*>(w + lay.off_tile_nz);
   D.scan_blocks = reinterpret_cast<int32_t*>(w + lay.off_scan);
   c->rflags = reinterpret_cast<int32_t*>(w + lay.off_rflags);
@@ -252,6 +265,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.tstat = reinterpret_cast<TileStat*>(w + lay.off_tstat);
   D.tile_pbwd = reinterpret_cast<int64_t*>(w + lay.off_tile_pbwd);
   D.counters = reinterpret_cast<int64_t*>(w + lay.off_counters);
+  D.stat_part = reinterpret_cast<StatPart*>(w + lay.off_stat_part);
+  D.stat_ab = reinterpret_cast<double2*>(w + lay.off_stat_ab);
   D.seed_hist = reinterpret_cast<uint32_t*>(w + lay.off_hist);
   D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
   D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);

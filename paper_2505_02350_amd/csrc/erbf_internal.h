@@ -49,6 +49,14 @@ struct TileStat {
 };
 
 
+// Slice sums of the step statistics (one per stats block).
+constexpr int kStatParts = 64;   // blocks per shape; one wave sums them
+struct StatPart {
+  double l2, nid, pf, pb, l1, num, den;
+  float mx;
+  int32_t pad;
+};
+
 // Launch plumbing shared by the .hip translation units.
 struct Dev {
   // tables
@@ -59,16 +67,21 @@ struct Dev {
   int32_t* tile_map;        // [tiles_total] slot of each tile or -1
   // buckets
   int32_t* tile_start;      // [tiles_total + 1]
-  int32_t* sort_keys[2];    // [pair_cap] tile slot of each entry (radix ping-pong)
-  int32_t* sort_vals[2];    // [pair_cap] kernel-major index of each entry (ping-pong)
+  int32_t* kslot;           // [pair_cap] tile slot of each kernel-major entry (sort input, kept)
   int32_t* kj;              // [pair_cap] kernel of each kernel-major entry
+  int32_t* sort_keys[2];    // [pair_cap] radix ping-pong between passes
+  int32_t* sort_vals[2];    // [pair_cap]
+  int32_t* sort_j[2];       // [pair_cap]
   int32_t* rhist;           // [256 * radix_nb + 1] digit counts per sort block
-  int32_t* rhist_ex;        // [256 * radix_nb + 1] their exclusive scan (digit-major)
-  int32_t* items;           // [pair_cap] kernel ids, ascending within each tile
+  int32_t* rhist_ex;        // [256 * radix_nb + 256] prefix within each digit's row, then row totals
+  int32_t* tile_keys;       // [pair_cap] tile slot of each tile-major entry (sorted)
+  int32_t* tile_e;          // [pair_cap] kernel-major index of each tile-major entry
+  int32_t* items;           // [pair_cap] kernel of each tile-major entry: ascending within a tile
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
   int32_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
-  int2* kmap;               // [pair_cap] (entry, tile slot) of each kernel's entries, visit order
-  float4* partials;         // [3 * pair_cap] backward moments of each (tile, kernel) entry
+  int32_t* kblock;          // [cap_total / 4 + 1] kcnt summed over each count block (four kernels)
+  int32_t* kblock_ex;       // [cap_total / 4 + 2] exclusive scan of kblock
+  float2* partials;         // [5 * pair_cap] the 10 backward moments of each entry, kernel-major
   int32_t* tile_nz;         // [tiles_total] tile has a non-zero upstream gradient
   int32_t* scan_blocks;     // [scan block sums]
   // per step
@@ -77,6 +90,8 @@ struct Dev {
   TileStat* tstat;          // [tiles_total]
   int64_t* tile_pbwd;       // [tiles_total] in-ball pairs at non-zero-G points of each tile
   int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
+  StatPart* stat_part;      // [n_shapes * kStatParts]
+  double2* stat_ab;         // [n_shapes] alpha, beta of eq. 3-21 for the last loss call
   // seeding scratch
   uint32_t* seed_hist;      // [65536]
   int64_t* seed_cand;       // [cand_cap]

@@ -146,204 +146,6 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
-// Tile buckets.  One wave per kernel slot; lanes test the tiles of the
-// ball's tile box.  A kernel's tiles are numbered in a fixed order (level,
-// z, y, x): the visit index.  EMIT = false counts each kernel's tiles;
-// EMIT = true writes the entries kernel-major, entry e = kstart[j] + visit,
-// with the tile slot as the sort key.  A stable sort of the kernel-major
-// list by slot then gives every tile's kernels in ascending order, with no
-// atomics and the same result on every run.
-// ---------------------------------------------------------------------------
-
-template <bool EMIT>
-__global__ __launch_bounds__(256) void k_bucket(Dev D) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= D.cap_total) return;
-  const float4 r0 = D.rec[3 * j];
-  if (r0.w < 0.f) {
-    if (!EMIT && lane == 0) D.kcnt[j] = 0;
-    return;
-  }
-  const ShapeDev S = D.shapes[D.kshape[j]];
-  const float rr = sqrtf(r0.w) * (1.0f + 1e-5f) + 1e-6f;
-  const float rc2 = rr * rr;
-  const unsigned long long lt_mask = (1ull << lane) - 1ull;
-  const int64_t e0 = EMIT ? (int64_t)D.kstart[j] : 0;
-  const int cnt_j = EMIT ? D.kcnt[j] : 0;
-  int vbase = 0;
-  for (int li = 0; li < S.n_active; ++li) {
-    const LevelDev L = D.levels[S.lvl0 + li];
-    int ix0, ix1, iy0, iy1, iz0, iz1;
-    index_range(L, r0.x - rr, r0.x + rr, ix0, ix1);
-    index_range(L, r0.y - rr, r0.y + rr, iy0, iy1);
-    index_range(L, r0.z - rr, r0.z + rr, iz0, iz1);
-    if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) continue;
-    const int nt = L.nt;
-    const int tx0 = ix0 / kTile, ty0 = iy0 / kTile, tz0 = iz0 / kTile;
-    const int ntx = ix1 / kTile - tx0 + 1, nty = iy1 / kTile - ty0 + 1, ntz = iz1 / kTile - tz0 + 1;
-    const int total = ntx * nty * ntz;
-    for (int base = 0; base < total; base += 64) {
-      const int idx = base + lane;
-      bool hit = false;
-      int slot = -1;
-      if (idx < total) {
-        const int tx = tx0 + idx % ntx, ty = ty0 + (idx / ntx) % nty, tz = tz0 + idx / (ntx * nty);
-        // tile point box from the nominal spacing, widened to cover the
-        // rounding of the axis table
-        const float xlo = tile_lo(L, tx), xhi = tile_hi(L, tx);
-        const float ylo = tile_lo(L, ty), yhi = tile_hi(L, ty);
-        const float zlo = tile_lo(L, tz), zhi = tile_hi(L, tz);
-        const float ex = fmaxf(fmaxf(xlo - r0.x, r0.x - xhi), 0.f);
-        const float ey = fmaxf(fmaxf(ylo - r0.y, r0.y - yhi), 0.f);
-        const float ez = fmaxf(fmaxf(zlo - r0.z, r0.z - zhi), 0.f);
-        if (ex * ex + ey * ey + ez * ez < rc2) {
-          slot = D.tile_map[L.tmap0 + (tz * nt + ty) * nt + tx];
-          hit = slot >= 0;
-        }
-      }
-      const unsigned long long bal = __ballot(hit);
-      if (EMIT && hit) {
-        const int v = vbase + __popcll(bal & lt_mask);
-        const int64_t at = e0 + v;
-        if (v < cnt_j && at < D.pair_cap) {
-          D.sort_keys[0][at] = slot;
-          D.kj[at] = j;
-        }
-      }
-      vbase += __popcll(bal);
-    }
-  }
-  if (!EMIT) {
-    if (lane == 0) D.kcnt[j] = vbase;
-  } else {
-    // both passes take the same decisions; should they ever differ, the
-    // counted range is still filled, with a slot past every real tile
-    for (int v = vbase + lane; v < cnt_j; v += 64) {
-      const int64_t at = e0 + v;
-      if (at < D.pair_cap) {
-        D.sort_keys[0][at] = D.tiles_total;
-        D.kj[at] = j;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Stable LSD radix sort of the (slot, entry) pairs, up to 8 key bits per
-// pass.  A fixed grid of radix_nb blocks; block b owns one contiguous
-// segment of the entries.  Pass = digit counts per block, an exclusive scan
-// over (digit, block), then a stable scatter: within a block, the rank of an
-// entry among equal digits comes from wave ballots (lanes in entry order)
-// and per-wave running counts, so equal keys keep their order.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int64_t bucket_entries(const Dev& D) { return min(D.counters[0], D.pair_cap); }
-
-__device__ __forceinline__ void radix_segment(int64_t n, int nb, int b, int64_t& lo, int64_t& hi) {
-  const int64_t per = (n + nb - 1) / nb;
-  lo = min(n, per * b);
-  hi = min(n, lo + per);
-}
-
-__global__ __launch_bounds__(256) void k_radix_hist(Dev D, const int32_t* __restrict__ keys, int shift, int mask) {
-  __shared__ int cnt[256];
-  const int t = threadIdx.x;
-  cnt[t] = 0;
-  __syncthreads();
-  int64_t lo, hi;
-  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
-  for (int64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
-  __syncthreads();
-  D.rhist[t * D.radix_nb + blockIdx.x] = cnt[t];
-}
-
-constexpr int kRadixPerLane = 8;                     // entries per lane per block iteration
-constexpr int kRadixWaveSpan = 64 * kRadixPerLane;   // consecutive entries of one wave
-constexpr int kRadixSpan = 4 * kRadixWaveSpan;       // entries per block iteration
-
-__global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __restrict__ kin,
-                                                       const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
-                                                       int32_t* __restrict__ vout, int shift, int mask, int dbits) {
-  __shared__ int run[256];
-  __shared__ int wcnt[4][256];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  int64_t lo, hi;
-  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
-  run[t] = D.rhist_ex[t * D.radix_nb + blockIdx.x];
-  for (int64_t base = lo; base < hi; base += kRadixSpan) {
-    for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0;
-    __syncthreads();
-    int key[kRadixPerLane], val[kRadixPerLane], rank[kRadixPerLane];
-    bool ok[kRadixPerLane];
-#pragma unroll
-    for (int i = 0; i < kRadixPerLane; ++i) {
-      const int64_t idx = base + w * kRadixWaveSpan + i * 64 + lane;
-      ok[i] = idx < hi;
-      key[i] = ok[i] ? kin[idx] : 0;
-      val[i] = ok[i] ? (vin ? vin[idx] : (int)idx) : 0;
-      const int d = (key[i] >> shift) & mask;
-      // lanes of this wave holding the same digit
-      unsigned long long same = __ballot(ok[i]);
-      for (int b = 0; b < dbits; ++b) {
-        const bool bit = (d >> b) & 1;
-        const unsigned long long bb = __ballot(bit);
-        same &= bit ? bb : ~bb;
-      }
-      const int before = wcnt[w][d];
-      rank[i] = before + __popcll(same & lt);
-      if (ok[i] && (same & lt) == 0) wcnt[w][d] = before + __popcll(same);
-    }
-    __syncthreads();
-    {  // digit t: where each wave's run starts, after the earlier iterations
-      int r = run[t];
-#pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
-        const int c = wcnt[ww][t];
-        wcnt[ww][t] = r;
-        r += c;
-      }
-      run[t] = r;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kRadixPerLane; ++i) {
-      if (ok[i]) {
-        const int pos = wcnt[w][(key[i] >> shift) & mask] + rank[i];
-        kout[pos] = key[i];
-        vout[pos] = val[i];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Sorted entries -> per-tile kernel lists and the kernel-major map.
-__global__ __launch_bounds__(256) void k_bucket_finish(Dev D, const int32_t* __restrict__ keys,
-                                                       const int32_t* __restrict__ vals) {
-  const int64_t n = bucket_entries(D);
-  for (int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x; pos < n; pos += (int64_t)gridDim.x * 256) {
-    const int e = vals ? vals[pos] : (int)pos;
-    D.items[pos] = D.kj[e];
-    D.kmap[e] = make_int2((int)pos, keys[pos]);
-  }
-}
-
-// tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots).
-__global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __restrict__ keys, int n_slots) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  if (s > n_slots) return;
-  int64_t lo = 0, hi = bucket_entries(D);
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < s) lo = mid + 1;
-    else hi = mid;
-  }
-  D.tile_start[s] = (int)lo;
-}
-
-// ---------------------------------------------------------------------------
 // exclusive scan of int32 counts (three passes, 1024 elements per block)
 // ---------------------------------------------------------------------------
 
@@ -407,6 +209,379 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ 
   int total;
   const int e = block_excl_scan_1024(i < n ? in[i] : 0, sh, total);
   if (i <= n) out[i] = blocks[blockIdx.x] + e;  // out has n + 1 entries
+}
+
+// Single-block exclusive scan of n <= 1024 * PER values; out[n] = total.
+// Each thread owns PER consecutive values, read with independent loads.
+template <int PER>
+__global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict__ in, int n,
+                                                      int32_t* __restrict__ out, int64_t* __restrict__ total_out) {
+  __shared__ int sh[32];
+  const int t = threadIdx.x;
+  const int lo = t * PER;
+  int v[PER];
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    v[u] = lo + u < n ? in[lo + u] : 0;
+    sum += v[u];
+  }
+  int total;
+  int run = block_excl_scan_1024(sum, sh, total);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (lo + u < n) out[lo + u] = run;
+    run += v[u];
+  }
+  if (t == 0) {
+    out[n] = total;
+    if (total_out) *total_out = total;
+  }
+}
+
+// exclusive scan of n values into out[0..n], the total also to *total_out
+hipError_t launch_scan_any(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Tile buckets.  One wave per kernel slot; lanes test the tiles of the
+// ball's tile box.  A kernel's tiles are numbered in a fixed order (level,
+// z, y, x): the visit index.  The count pass counts each kernel's tiles; the
+// emit pass writes the entries kernel-major, entry e = kstart[j] + visit,
+// with the tile slot as the sort key.  A stable sort of the kernel-major
+// list by slot then gives every tile's kernels in ascending order, with no
+// atomics and the same result on every run.
+// ---------------------------------------------------------------------------
+
+// Walks kernel j's tile boxes (j wave-uniform) in visit order (level, z, y,
+// x) and returns the number of tiles hit.  A tile is hit when the ball,
+// widened slightly, reaches the tile's point box (fixed expression, so both
+// walks below take the same decisions) and the tile is in use.
+__device__ __forceinline__ float ball_box_e2(const LevelDev& L, const float4& r0, int ty, int tz) {
+  const float ey = fmaxf(fmaxf(tile_lo(L, ty) - r0.y, r0.y - tile_hi(L, ty)), 0.f);
+  const float ez = fmaxf(fmaxf(tile_lo(L, tz) - r0.z, r0.z - tile_hi(L, tz)), 0.f);
+  return fmaf(ey, ey, ez * ez);
+}
+__device__ __forceinline__ bool ball_box_hit(const LevelDev& L, const float4& r0, float e2, int tx, float rc2) {
+  const float ex = fmaxf(fmaxf(tile_lo(L, tx) - r0.x, r0.x - tile_hi(L, tx)), 0.f);
+  return fmaf(ex, ex, e2) < rc2;
+}
+
+struct BallBox {
+  float rc2;
+  int tx0, tx1, ty0, nty, tz0, ntz;
+};
+
+__device__ __forceinline__ bool ball_box(const LevelDev& L, const float4& r0, BallBox& B) {
+  const float rr = sqrtf(r0.w) * (1.0f + 1e-5f) + 1e-6f;
+  B.rc2 = rr * rr;
+  int ix0, ix1, iy0, iy1, iz0, iz1;
+  index_range(L, r0.x - rr, r0.x + rr, ix0, ix1);
+  index_range(L, r0.y - rr, r0.y + rr, iy0, iy1);
+  index_range(L, r0.z - rr, r0.z + rr, iz0, iz1);
+  if (ix0 > ix1 || iy0 > iy1 || iz0 > iz1) return false;
+  B.tx0 = ix0 / kTile;
+  B.tx1 = ix1 / kTile;
+  B.ty0 = iy0 / kTile;
+  B.nty = iy1 / kTile - B.ty0 + 1;
+  B.tz0 = iz0 / kTile;
+  B.ntz = iz1 / kTile - B.tz0 + 1;
+  return true;
+}
+
+// Count walk: lanes own rows of tiles (y, z) and step along x, so a row's
+// y and z distances are formed once.
+__device__ __forceinline__ int bucket_count_walk(const Dev& D, const int j, const int lane) {
+  const float4 r0 = D.rec[3 * j];
+  if (r0.w < 0.f) return 0;
+  const ShapeDev S = D.shapes[D.kshape[j]];
+  int total = 0;
+  for (int li = 0; li < S.n_active; ++li) {
+    const LevelDev L = D.levels[S.lvl0 + li];
+    BallBox B;
+    if (!ball_box(L, r0, B)) continue;
+    const int nrows = B.nty * B.ntz;
+    for (int rb = 0; rb < nrows; rb += 64) {
+      const int r = rb + lane;
+      int cnt = 0;
+      if (r < nrows) {
+        const int qz = r / B.nty, ty = B.ty0 + (r - qz * B.nty), tz = B.tz0 + qz;
+        const float e2 = ball_box_e2(L, r0, ty, tz);
+        if (e2 < B.rc2) {
+          const int row0 = L.tmap0 + (tz * L.nt + ty) * L.nt;
+          for (int tx = B.tx0; tx <= B.tx1; ++tx)
+            if (ball_box_hit(L, r0, e2, tx, B.rc2) && D.tile_map[row0 + tx] >= 0) ++cnt;
+        }
+      }
+      total += (int)wave_sum(cnt);
+    }
+  }
+  return total;
+}
+
+// Emit walk: lanes own consecutive box tiles, so consecutive entries are
+// written by consecutive lanes.  Writes entries e0 + visit for visits
+// below cnt_j.
+__device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, const int lane, const int64_t e0,
+                                                 const int cnt_j) {
+  const float4 r0 = D.rec[3 * j];
+  int vbase = 0;
+  if (r0.w >= 0.f) {
+    const ShapeDev S = D.shapes[D.kshape[j]];
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    for (int li = 0; li < S.n_active; ++li) {
+      const LevelDev L = D.levels[S.lvl0 + li];
+      BallBox B;
+      if (!ball_box(L, r0, B)) continue;
+      const int ntx = B.tx1 - B.tx0 + 1, nxy = ntx * B.nty, total = nxy * B.ntz;
+      // box index -> (x, y, z) by a float reciprocal: exact while
+      // (quotient + 1) * divisor < 2^21, which keeps the rounding error
+      // below the 0.5 / divisor gap to the next integer; larger boxes take
+      // the integer division
+      const bool small_box = total + nxy < (1 << 21);
+      const float inv_x = 1.0f / (float)ntx, inv_xy = 1.0f / (float)nxy;
+      for (int base = 0; base < total; base += 64) {
+        const int idx = base + lane;
+        int slot = -1;
+        if (idx < total) {
+          int qz, qy, qx;
+          if (small_box) {
+            qz = (int)(((float)idx + 0.5f) * inv_xy);
+            const int rem = idx - qz * nxy;
+            qy = (int)(((float)rem + 0.5f) * inv_x);
+            qx = rem - qy * ntx;
+          } else {
+            qz = idx / nxy;
+            qy = (idx % nxy) / ntx;
+            qx = idx % ntx;
+          }
+          const int tx = B.tx0 + qx, ty = B.ty0 + qy, tz = B.tz0 + qz;
+          const float e2 = ball_box_e2(L, r0, ty, tz);
+          if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2))
+            slot = D.tile_map[L.tmap0 + (tz * L.nt + ty) * L.nt + tx];
+        }
+        const bool hit = slot >= 0;
+        const unsigned long long bal = __ballot(hit);
+        if (hit) {
+          const int v = vbase + __popcll(bal & lt_mask);
+          const int64_t at = e0 + v;
+          if (v < cnt_j && at < D.pair_cap) {
+            D.kslot[at] = slot;
+            D.kj[at] = j;
+          }
+        }
+        vbase += __popcll(bal);
+      }
+    }
+  }
+  // both walks take the same decisions; should they ever differ, the
+  // counted range is still filled, with a slot past every real tile
+  for (int v = vbase + lane; v < cnt_j; v += 64) {
+    const int64_t at = e0 + v;
+    if (at < D.pair_cap) {
+      D.kslot[at] = D.tiles_total;
+      D.kj[at] = j;
+    }
+  }
+}
+
+// Count pass: kcnt per kernel (one wave each) and the sum of each block's
+// four kernels.
+__global__ __launch_bounds__(256) void k_bucket_count(Dev D) {
+  __shared__ int wc[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+  const int c = j < D.cap_total ? bucket_count_walk(D, j, lane) : 0;
+  if (lane == 0) {
+    if (j < D.cap_total) D.kcnt[j] = c;
+    wc[w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) D.kblock[blockIdx.x] = (wc[0] + wc[1]) + (wc[2] + wc[3]);
+}
+
+// Emit pass: kstart from the scanned block sums, then the entries.
+__global__ __launch_bounds__(256) void k_bucket_emit(Dev D) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+  if (j >= D.cap_total) return;
+  int e0 = D.kblock_ex[blockIdx.x];
+  for (int k = 0; k < w; ++k) e0 += D.kcnt[4 * blockIdx.x + k];
+  if (lane == 0) D.kstart[j] = e0;
+  bucket_emit_walk(D, j, lane, e0, D.kcnt[j]);
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of the (slot, entry) pairs, up to 8 key bits per
+// pass.  A fixed grid of radix_nb blocks; block b owns one contiguous
+// segment of the entries.  Pass = digit counts per block, an exclusive scan
+// over (digit, block), then a stable scatter: within a block, the rank of an
+// entry among equal digits comes from wave ballots (lanes in entry order)
+// and per-wave running counts, so equal keys keep their order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t bucket_entries(const Dev& D) { return min(D.counters[0], D.pair_cap); }
+
+__device__ __forceinline__ void radix_segment(int64_t n, int nb, int b, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + nb - 1) / nb;
+  lo = min(n, per * b);
+  hi = min(n, lo + per);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(Dev D, const int32_t* __restrict__ keys, int shift, int mask) {
+  __shared__ int cnt[256];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  int64_t lo, hi;
+  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
+  for (int64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
+  __syncthreads();
+  D.rhist[t * D.radix_nb + blockIdx.x] = cnt[t];
+}
+
+// Row d of the digit counts (one value per sort block) -> exclusive prefix
+// within the row; the row totals go after the rows.
+__global__ __launch_bounds__(1024) void k_radix_rowscan(Dev D) {
+  __shared__ int sh[32];
+  const int d = blockIdx.x, b = threadIdx.x, nb = D.radix_nb;
+  int total;
+  const int e = block_excl_scan_1024(b < nb ? D.rhist[d * nb + b] : 0, sh, total);
+  if (b < nb) D.rhist_ex[d * nb + b] = e;
+  if (b == 0) D.rhist_ex[256 * nb + d] = total;
+}
+
+// exclusive scan over a 256-thread block
+__device__ __forceinline__ int block_excl_scan_256(int v, int* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  int base = 0;
+  for (int k = 0; k < w; ++k) base += sh[k];
+  __syncthreads();
+  return base + x - v;
+}
+
+constexpr int kRadixPerLane = 8;                     // entries per lane per block iteration
+constexpr int kRadixWaveSpan = 64 * kRadixPerLane;   // consecutive entries of one wave
+constexpr int kRadixSpan = 4 * kRadixWaveSpan;       // entries per block iteration
+
+// Moves (key, entry, kernel) triples; vin == nullptr means entry = index.
+// STAGE: each iteration's entries are first placed in LDS in (digit, wave,
+// rank) order, so that the global stores of one digit's run are contiguous
+// (worth it when neighbouring entries hold different digits, as in the
+// kernel-major input of the first pass).
+template <bool STAGE>
+__global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin,
+                                                       const int32_t* __restrict__ jin, int32_t* __restrict__ kout,
+                                                       int32_t* __restrict__ vout, int32_t* __restrict__ jout,
+                                                       int shift, int mask, int dbits) {
+  __shared__ int run[256];
+  __shared__ int wcnt[4][256];   // per-wave digit counts, then global starts
+  __shared__ int lcnt[4][256];   // starts within this iteration's staged run
+  __shared__ int sws[4];
+  __shared__ int4 stage[STAGE ? kRadixSpan : 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  int64_t lo, hi;
+  radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
+  // digit t starts after all smaller digits, then after digit t of the
+  // earlier blocks
+  const int dbase = block_excl_scan_256(D.rhist_ex[256 * D.radix_nb + t], sws);
+  run[t] = dbase + D.rhist_ex[t * D.radix_nb + blockIdx.x];
+  for (int64_t base = lo; base < hi; base += kRadixSpan) {
+    for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0;
+    __syncthreads();
+    int key[kRadixPerLane], val[kRadixPerLane], kid[kRadixPerLane], rank[kRadixPerLane];
+    bool ok[kRadixPerLane];
+#pragma unroll
+    for (int i = 0; i < kRadixPerLane; ++i) {
+      const int64_t idx = base + w * kRadixWaveSpan + i * 64 + lane;
+      ok[i] = idx < hi;
+      key[i] = ok[i] ? kin[idx] : 0;
+      val[i] = ok[i] ? (vin ? vin[idx] : (int)idx) : 0;
+      kid[i] = ok[i] ? jin[idx] : 0;
+      const int d = (key[i] >> shift) & mask;
+      // lanes of this wave holding the same digit
+      unsigned long long same = __ballot(ok[i]);
+      for (int b = 0; b < dbits; ++b) {
+        const bool bit = (d >> b) & 1;
+        const unsigned long long bb = __ballot(bit);
+        same &= bit ? bb : ~bb;
+      }
+      const int before = wcnt[w][d];
+      rank[i] = before + __popcll(same & lt);
+      if (ok[i] && (same & lt) == 0) wcnt[w][d] = before + __popcll(same);
+    }
+    __syncthreads();
+    {  // digit t: where each wave's run starts, globally and in the stage
+      int c[4], tot = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        c[ww] = wcnt[ww][t];
+        tot += c[ww];
+      }
+      int l = STAGE ? block_excl_scan_256(tot, sws) : 0;
+      int g = run[t];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        wcnt[ww][t] = g;
+        if (STAGE) lcnt[ww][t] = l;
+        g += c[ww];
+        l += c[ww];
+      }
+      run[t] = g;
+    }
+    __syncthreads();
+    if (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kRadixPerLane; ++i) {
+        if (ok[i]) {
+          const int d = (key[i] >> shift) & mask;
+          stage[lcnt[w][d] + rank[i]] = make_int4(key[i], val[i], kid[i], wcnt[w][d] + rank[i]);
+        }
+      }
+      __syncthreads();
+      const int nit = (int)min((int64_t)kRadixSpan, hi - base);
+      for (int q = t; q < nit; q += 256) {
+        const int4 e = stage[q];
+        kout[e.w] = e.x;
+        vout[e.w] = e.y;
+        jout[e.w] = e.z;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kRadixPerLane; ++i) {
+        if (ok[i]) {
+          const int pos = wcnt[w][(key[i] >> shift) & mask] + rank[i];
+          kout[pos] = key[i];
+          vout[pos] = val[i];
+          jout[pos] = kid[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots).
+__global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __restrict__ keys, int n_slots) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s > n_slots) return;
+  int64_t lo = 0, hi = bucket_entries(D);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < s) lo = mid + 1;
+    else hi = mid;
+  }
+  D.tile_start[s] = (int)lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -686,8 +861,10 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     const bool have = c0 + lane < end;
     float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
            r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    int e_out = 0;
     if (have) {
       const int j = D.items[c0 + lane];
+      e_out = D.tile_e[c0 + lane];
       r0 = D.rec[3 * j];
       r1 = D.rec[3 * j + 1];
       r2 = D.rec[3 * j + 2];
@@ -731,10 +908,9 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     }
     pb += pbg;
     if (have) {
-      float4* o = D.partials + 3 * (c0 + lane);
-      o[0] = make_float4(T[0], T[1], T[2], T[3]);
-      o[1] = make_float4(T[4], T[5], T[6], T[7]);
-      o[2] = make_float4(T[8], T[9], 0.f, 0.f);
+      float2* o = D.partials + 5 * (int64_t)e_out;   // kernel-major: the reduce reads it in order
+#pragma unroll
+      for (int i = 0; i < 5; ++i) o[i] = make_float2(T[2 * i], T[2 * i + 1]);
     }
   }
   if (lane == 0) spb[wv] = pb;
@@ -776,14 +952,15 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   const int c = D.kcnt[j];
   for (int e = lane; e < c; e += 64) {
     if (base + e >= D.pair_cap) break;
-    const int2 km = D.kmap[base + e];
-    if (km.x < 0 || (int64_t)km.x >= D.pair_cap || km.y < 0 || km.y >= D.tiles_total) continue;
-    if (!D.tile_nz[km.y]) continue;
-    const float4* q = D.partials + 3 * (int64_t)km.x;
-    const float4 a = q[0], b = q[1], d = q[2];
-    v[0] += a.x; v[1] += a.y; v[2] += a.z; v[3] += a.w;
-    v[4] += b.x; v[5] += b.y; v[6] += b.z; v[7] += b.w;
-    v[8] += d.x; v[9] += d.y;
+    const int sl = D.kslot[base + e];
+    if (sl < 0 || sl >= D.tiles_total || !D.tile_nz[sl]) continue;
+    const float2* q = D.partials + 5 * (base + e);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const float2 a = q[i];
+      v[2 * i] += a.x;
+      v[2 * i + 1] += a.y;
+    }
   }
 #pragma unroll
   for (int i = 0; i < 10; ++i) v[i] = wave_sum(v[i]);
@@ -846,87 +1023,71 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
 }
 
 // ---------------------------------------------------------------------------
-// per-shape statistics, eq. 3-21 weights and gradient combination
-// one workgroup of 1024 threads per shape
+// Step statistics and the loss weights of eq. 3-21.  Per shape: kStatParts
+// blocks each sum a fixed slice of the shape's tiles and kernels; one wave
+// then sums the slices in a fixed order, decides alpha and beta and writes
+// the statistics; a grid-wide pass applies the weights to the gradient.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double block_sum_1024(double v, double* sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   v = wave_sum(v);
   if (lane == 0) sh[wv] = v;
   __syncthreads();
-  double r = 0.0;
-  if (tid == 0) {
-    for (int i = 0; i < 16; ++i) r += sh[i];
-    sh[16] = r;
-  }
-  __syncthreads();
-  r = sh[16];
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
   __syncthreads();
   return r;
 }
 
-__device__ __forceinline__ float block_max_1024(float v, float* sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+__device__ __forceinline__ float block_max_256(float v, float* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   v = wave_max_f(v);
   if (lane == 0) sh[wv] = v;
   __syncthreads();
-  if (tid == 0) {
-    float r = 0.f;
-    for (int i = 0; i < 16; ++i) r = fmaxf(r, sh[i]);
-    sh[16] = r;
-  }
-  __syncthreads();
-  const float r = sh[16];
+  const float r = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
   __syncthreads();
   return r;
 }
 
-// mode: 0 eval (bucket stats only), 1 vjp (adds pair counts), 2 loss (everything)
+// MODE 0: forward statistics; 1: backward pair count only; 2: both, plus
+// the sums of eq. 3-21 and L1 over the weights.
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__ p,
-                                                const int32_t* __restrict__ m_dev,
-                                                float* __restrict__ grad, erbf_stats* __restrict__ out,
-                                                StatsArgs a) {
-  __shared__ double shd[17];
-  __shared__ float shf[17];
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restrict__ p,
+                                                    const int32_t* __restrict__ m_dev,
+                                                    const float* __restrict__ grad) {
+  __shared__ double shd[4];
+  __shared__ float shf[4];
+  const int part = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const ShapeDev S = D.shapes[b];
   const int m = min(max(m_dev[b], 0), S.cap);
-  const int C = D.cap_total;
-  const int64_t nb = D.counters[0];
-
-  double l2 = 0.0, nid = 0.0, pf = 0.0, pb = 0.0;
+  double l2 = 0.0, nid = 0.0, pf = 0.0, pb = 0.0, l1 = 0.0, num = 0.0, den = 0.0;
   float mx = 0.f;
-  if (MODE != 1) {
-    for (int li = 0; li < S.n_active; ++li) {
-      const LevelDev L = D.levels[S.lvl0 + li];
-      for (int s = tid; s < L.n_slots; s += 1024) {
-        const TileStat ts = D.tstat[L.slot0 + s];
+  // this block's slice of the shape's tiles (levels in order)
+  int tot = 0;
+  for (int li = 0; li < S.n_active; ++li) tot += D.levels[S.lvl0 + li].n_slots;
+  const int per = (tot + kStatParts - 1) / kStatParts;
+  const int lo = part * per, hi = min(tot, lo + per);
+  int acc = 0;
+  for (int li = 0; li < S.n_active; ++li) {
+    const LevelDev L = D.levels[S.lvl0 + li];
+    const int a0 = max(lo, acc), a1 = min(hi, acc + L.n_slots);
+    for (int x = a0 + tid; x < a1; x += 256) {
+      const int sl = L.slot0 + (x - acc);
+      if (MODE != 1) {
+        const TileStat ts = D.tstat[sl];
         l2 += ts.l2;
         nid += (double)ts.n_idall;
         mx = fmaxf(mx, ts.max_abs_e);
         pf += (double)ts.p_fwd;
       }
+      if (MODE >= 1) pb += (double)D.tile_pbwd[sl];
     }
+    acc += L.n_slots;
   }
-  if (MODE >= 1) {
-    for (int li = 0; li < S.n_active; ++li) {
-      const LevelDev L = D.levels[S.lvl0 + li];
-      for (int s = tid; s < L.n_slots; s += 1024) pb += (double)D.tile_pbwd[L.slot0 + s];
-    }
-  }
-  l2 = block_sum_1024(l2, shd);
-  nid = block_sum_1024(nid, shd);
-  pf = block_sum_1024(pf, shd);
-  pb = block_sum_1024(pb, shd);
-  mx = block_max_1024(mx, shf);
-
-  double alpha = 1.0, beta = 0.0, l1 = 0.0;
   if (MODE == 2) {
-    double num = 0.0, den = 0.0;
-    for (int k = tid; k < m; k += 1024) {
+    const int kper = (m + kStatParts - 1) / kStatParts;
+    const int k0 = part * kper, k1 = min(m, k0 + kper);
+    for (int k = k0 + tid; k < k1; k += 256) {
       const float w = p[S.kbase + k];
       const double g1 = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
       const double g2 = grad[S.kbase + k];
@@ -934,31 +1095,48 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
       num += (g1 - g2) * g1;
       den += (g2 - g1) * (g2 - g1);
     }
-    l1 = block_sum_1024(l1, shd);
-    num = block_sum_1024(num, shd);
-    den = block_sum_1024(den, shd);
+  }
+  StatPart sp;
+  sp.l2 = block_sum_256(l2, shd);
+  sp.nid = block_sum_256(nid, shd);
+  sp.pf = block_sum_256(pf, shd);
+  sp.pb = block_sum_256(pb, shd);
+  sp.l1 = block_sum_256(l1, shd);
+  sp.num = block_sum_256(num, shd);
+  sp.den = block_sum_256(den, shd);
+  sp.mx = block_max_256(mx, shf);
+  sp.pad = 0;
+  if (tid == 0) D.stat_part[b * kStatParts + part] = sp;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void k_stats_final(Dev D, const int32_t* __restrict__ m_dev,
+                                                    erbf_stats* __restrict__ out, StatsArgs a) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const ShapeDev S = D.shapes[b];
+  const int m = min(max(m_dev[b], 0), S.cap);
+  StatPart sp = {};
+  if (lane < kStatParts) sp = D.stat_part[b * kStatParts + lane];
+  const double l2 = wave_sum(sp.l2), nid = wave_sum(sp.nid), pf = wave_sum(sp.pf), pb = wave_sum(sp.pb);
+  const double l1 = wave_sum(sp.l1), num = wave_sum(sp.num), den = wave_sum(sp.den);
+  const float mx = wave_max_f(sp.mx);
+  if (lane != 0) return;
+  double alpha = 1.0, beta = 0.0;
+  if (MODE == 2) {
     if (a.mode == ERBF_MODE_FIXED) {
       beta = a.lambda_dev ? (double)a.lambda_dev[b] : (double)a.lambda;
     } else if (a.mode == ERBF_MODE_DYNAMIC && a.l1_active && mx < a.tau_m) {
       alpha = den > 0.0 ? fmin(fmax(num / den, 0.0), 1.0) : 1.0;
       beta = 1.0 - alpha;
     }
-    // combine: alpha * dL2 + beta * sign(w) on w; alpha * dL2 elsewhere
-    for (int k = tid; k < m; k += 1024) {
-      const int jj = S.kbase + k;
-      const float w = p[jj];
-      const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
-      grad[jj] = (float)(alpha * (double)grad[jj] + beta * sg);
-      if (alpha != 1.0) {
-        for (int seg = 1; seg < 11; ++seg) grad[seg * C + jj] = (float)(alpha * (double)grad[seg * C + jj]);
-      }
-    }
   }
-  if (tid == 0 && out) {
+  D.stat_ab[b] = make_double2(alpha, beta);
+  if (out) {
+    const int64_t nb = D.counters[0];
     erbf_stats st;
     st.L2 = l2;
-    st.L1 = l1;
-    st.loss = alpha * l2 + beta * l1;
+    st.L1 = MODE == 2 ? l1 : 0.0;
+    st.loss = alpha * l2 + beta * st.L1;
     st.alpha = alpha;
     st.beta = beta;
     st.n_idall = (int64_t)nid;
@@ -973,6 +1151,25 @@ __global__ __launch_bounds__(1024) void k_stats(Dev D, const float* __restrict__
     st.P_bwd_total = out[b].P_bwd_total + st.P_bwd;
     st.calls = out[b].calls + 1;
     out[b] = st;
+  }
+}
+
+// combine: alpha * dL2 + beta * sign(w) on w; alpha * dL2 on the rest
+__global__ __launch_bounds__(256) void k_stats_apply(Dev D, const float* __restrict__ p,
+                                                     const int32_t* __restrict__ m_dev, float* __restrict__ grad) {
+  const int jj = blockIdx.x * 256 + threadIdx.x;
+  if (jj >= D.cap_total) return;
+  const int b = D.kshape[jj];
+  const ShapeDev S = D.shapes[b];
+  const int m = min(max(m_dev[b], 0), S.cap);
+  if (jj - S.kbase >= m) return;
+  const double2 ab = D.stat_ab[b];
+  const int C = D.cap_total;
+  const float w = p[jj];
+  const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
+  grad[jj] = (float)(ab.x * (double)grad[jj] + ab.y * sg);
+  if (ab.x != 1.0) {
+    for (int seg = 1; seg < 11; ++seg) grad[seg * C + jj] = (float)(ab.x * (double)grad[seg * C + jj]);
   }
 }
 
@@ -1143,32 +1340,56 @@ hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, 
   return hipGetLastError();
 }
 
+hipError_t launch_scan_any(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
+                           hipStream_t s) {
+  if (n <= 1024 * 4)
+    hipLaunchKernelGGL(k_scan_single<4>, dim3(1), dim3(1024), 0, s, in, n, out, total);
+  else if (n <= 1024 * 16)
+    hipLaunchKernelGGL(k_scan_single<16>, dim3(1), dim3(1024), 0, s, in, n, out, total);
+  else
+    return launch_scan(in, n, blocks, out, total, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
   if (n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bucket<false>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
-  hipError_t e = launch_scan(D.kcnt, D.cap_total, D.scan_blocks, D.kstart, D.counters, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bucket<true>, dim3(nblk(D.cap_total, 4)), dim3(256), 0, s, D);
+  const int nkb = (int)nblk(D.cap_total, 4);   // count/emit blocks, four kernels each
+  hipLaunchKernelGGL(k_bucket_count, dim3(nkb), dim3(256), 0, s, D);
+  {
+    const hipError_t e = launch_scan_any(D.kblock, nkb, D.scan_blocks, D.kblock_ex, D.counters, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
   // keys are slots (< n_slots) or the filler tiles_total: sort on just
   // enough bits, at most 8 per pass
   int bits = 0;
   while ((1ll << bits) <= (int64_t)D.tiles_total) ++bits;
   const int passes = (bits + 7) / 8;
   const int dbits = passes ? (bits + passes - 1) / passes : 0;
-  const int32_t* vals = nullptr;     // identity: entry e holds value e
-  int cur = 0;
+  // pass 0 reads the kernel-major entries (kept for the backward reduce);
+  // the last pass writes the tile lists
+  const int32_t* kin = D.kslot;
+  const int32_t* vin = nullptr;     // identity: entry e holds value e
+  const int32_t* jin = D.kj;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * dbits, mask = (1 << dbits) - 1;
-    hipLaunchKernelGGL(k_radix_hist, dim3(D.radix_nb), dim3(256), 0, s, D, D.sort_keys[cur], shift, mask);
-    e = launch_scan(D.rhist, 256 * D.radix_nb, D.scan_blocks, D.rhist_ex, nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(D.radix_nb), dim3(256), 0, s, D, D.sort_keys[cur], vals,
-                       D.sort_keys[cur ^ 1], D.sort_vals[cur ^ 1], shift, mask, dbits);
-    cur ^= 1;
-    vals = D.sort_vals[cur];
+    const bool last = pass == passes - 1;
+    int32_t* kout = last ? D.tile_keys : D.sort_keys[pass & 1];
+    int32_t* vout = last ? D.tile_e : D.sort_vals[pass & 1];
+    int32_t* jout = last ? D.items : D.sort_j[pass & 1];
+    hipLaunchKernelGGL(k_radix_hist, dim3(D.radix_nb), dim3(256), 0, s, D, kin, shift, mask);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(1024), 0, s, D);
+    if (pass == 0)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(D.radix_nb), dim3(256), 0, s, D, kin, vin, jin, kout, vout, jout,
+                         shift, mask, dbits);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(D.radix_nb), dim3(256), 0, s, D, kin, vin, jin, kout, vout,
+                         jout, shift, mask, dbits);
+    kin = kout;
+    vin = vout;
+    jin = jout;
   }
-  hipLaunchKernelGGL(k_bucket_finish, dim3(gridstride(D.pair_cap)), dim3(256), 0, s, D, D.sort_keys[cur], vals);
-  hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.sort_keys[cur], n_slots);
+  hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.tile_keys, n_slots);
   return hipGetLastError();
 }
 
@@ -1217,12 +1438,18 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
 
 hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
                         erbf_stats* out, const StatsArgs& a, hipStream_t s) {
-  if (mode == 0)
-    hipLaunchKernelGGL(k_stats<0>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_stats<1>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
-  else
-    hipLaunchKernelGGL(k_stats<2>, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, grad, out, a);
+  const dim3 parts(kStatParts, D.n_shapes);
+  if (mode == 0) {
+    hipLaunchKernelGGL(k_stats_part<0>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL(k_stats_final<0>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL(k_stats_part<1>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL(k_stats_final<1>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+  } else {
+    hipLaunchKernelGGL(k_stats_part<2>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+    hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
+  }
   return hipGetLastError();
 }
 
