@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 FWD_FLOP_PER_PAIR = 25.0   # delta 3, ball test 5, quadric 14, exp2 1, accumulate 2
 BWD_FLOP_PER_PAIR = 43.0   # + g 1, T0 1, g*delta 3, T1 3, T2 12
 FP32_VECTOR_PEAK = 157.3e12
+COPY_CAL_BYTES = 256 * 1024 * 1024
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_snapshot.md")
 
 
 def log(*a):
@@ -157,6 +159,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--graph", action="store_true", help="also time HIP-graph replays of the step")
     ap.add_argument("--batching", action="store_true", help="add the 64-shape batched-vs-plain comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help=f"copy {COPY_CAL_BYTES} bytes device-to-device before the warm-up (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -180,6 +185,15 @@ def main():
         refine_ms.append(1e3 * (time.perf_counter() - r0))
     torch.cuda.synchronize()
     log(f"device set-up {time.perf_counter() - t0:.1f} s; refine ms {refine_ms}")
+
+    if args.copy_calibration:
+        src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=fit.dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: 3 device copies of {COPY_CAL_BYTES} bytes")
 
     kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
     for _ in range(args.warmup):
@@ -212,9 +226,16 @@ def main():
     # kernel only sums per-tile moments
     bwd_rate = BWD_FLOP_PER_PAIR * P_bwd / K / (bt_avg * 1e-3)
     if bt_avg >= fwd_avg:
-        dom, ach, t_dom = "k_bwd_tiles (backward moments)", bwd_rate, bt_avg
+        dom, dom_short, ach, t_dom = "k_bwd_tiles (backward moments)", "k_bwd_tiles", bwd_rate, bt_avg
     else:
-        dom, ach, t_dom = "k_forward (forward + loss)", fwd_rate, fwd_avg
+        dom, dom_short, ach, t_dom = "k_forward (forward + loss)", "k_forward", fwd_rate, fwd_avg
+    # HBM bytes per launch from the committed counter summary, if it was
+    # taken on the current kernel source
+    from paper_2505_02350_amd.prof_summary import read_traffic
+    tb = read_traffic(TRAFFIC_FILE)
+    traffic = None
+    if tb is not None and dom_short in tb.get("kernels", {}):
+        traffic = tb["kernels"][dom_short]["traffic_bytes_per_launch"]
     log(f"timed {K} steps: {ms_per_step:.3f} ms/step; forward {fwd_avg:.3f} ms, backward tiles "
         f"{bt_avg:.3f} ms, reduce {br_avg:.3f} ms")
 
@@ -261,7 +282,7 @@ def main():
             "peak": FP32_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": ach / FP32_VECTOR_PEAK,
-            "traffic": None,
+            "traffic": traffic,
         },
         "kernels_ms": {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
                        "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12},
