@@ -12,8 +12,12 @@ and the network output is
 
 Readings of the paper taken here (each also listed in the design notes):
 
-* orientation is a unit quaternion q/|q| (Hamilton, (w, x, y, z)) instead of
-  the three Euler angles of eq. 3-6;
+* orientation is a unit quaternion q/|q| (Hamilton, (w, x, y, z)) by
+  default; the Euler-angle form of eq. 3-6 is the alternative, read as
+  R = Rz(theta_z) Ry(theta_y) Rx(theta_x) with the standard right-handed axis
+  rotations (the printed Ry carries a transposed sign), and its angle
+  gradients derived from dL/dR by the chain rule rather than taken from
+  Appendix A;
 * the optimised scale is s = ln d (per axis);
 * the cull predicate is strict, ||x - c_j||^2 < r_j^2 with
   r_j = k_cull / min_k d_jk (eq. 3-15-1 with eps = exp(-k_cull^2));
@@ -132,6 +136,44 @@ def quat_rot_jacobian(qhat: np.ndarray) -> np.ndarray:
     return J
 
 
+ORIENT_QUATERNION = 0
+ORIENT_EULER = 1
+
+
+def _axis_rotations(theta: np.ndarray):
+    """Rx(tx), Ry(ty), Rz(tz) and their angle derivatives, each (m, 3, 3)."""
+    m = theta.shape[0]
+    out = []
+    for k, t in enumerate((theta[:, 0], theta[:, 1], theta[:, 2])):
+        c, s = np.cos(t), np.sin(t)
+        R = np.zeros((m, 3, 3))
+        dR = np.zeros((m, 3, 3))
+        i, j = [(1, 2), (2, 0), (0, 1)][k]      # the plane the rotation turns
+        R[:, k, k] = 1.0
+        R[:, i, i] = c
+        R[:, j, j] = c
+        R[:, i, j] = -s
+        R[:, j, i] = s
+        dR[:, i, i] = -s
+        dR[:, j, j] = -s
+        dR[:, i, j] = -c
+        dR[:, j, i] = c
+        out.append((R, dR))
+    return out
+
+
+def euler_to_rot(theta: np.ndarray) -> np.ndarray:
+    """R = Rz(theta_z) Ry(theta_y) Rx(theta_x) (eq. 3-6), shape (m, 3, 3)."""
+    (Rx, _), (Ry, _), (Rz, _) = _axis_rotations(np.asarray(theta, np.float64).reshape(-1, 3))
+    return Rz @ Ry @ Rx
+
+
+def euler_rot_jacobian(theta: np.ndarray) -> np.ndarray:
+    """dR_ab / dtheta_k of :func:`euler_to_rot`, shape (m, 3, 3, 3)."""
+    (Rx, dRx), (Ry, dRy), (Rz, dRz) = _axis_rotations(np.asarray(theta, np.float64).reshape(-1, 3))
+    return np.stack([Rz @ Ry @ dRx, Rz @ dRy @ Rx, dRz @ Ry @ Rx], axis=1)
+
+
 @dataclass
 class Kernels:
     w: np.ndarray      # (m,)
@@ -146,6 +188,7 @@ class Kernels:
     dadw: np.ndarray   # (m,)
     r2: np.ndarray     # (m,) squared cull radius
     weight_map: int
+    orientation: int = ORIENT_QUATERNION   # q holds (theta_x, theta_y, theta_z, -) for Euler
 
     @property
     def m(self):
@@ -153,23 +196,32 @@ class Kernels:
 
 
 def kernels_from_packed(p: np.ndarray, m: int, cap: int, cull_k: float,
-                        weight_map: int = 0) -> Kernels:
+                        weight_map: int = 0, orientation: int = ORIENT_QUATERNION) -> Kernels:
     seg = np.asarray(p, dtype=np.float32).reshape(11, cap)[:, :m].astype(np.float64)
-    return make_kernels(seg[0], seg[1:4].T, seg[4:7].T, seg[7:11].T, cull_k, weight_map)
+    return make_kernels(seg[0], seg[1:4].T, seg[4:7].T, seg[7:11].T, cull_k, weight_map, orientation)
 
 
-def make_kernels(w, c, s, q, cull_k: float, weight_map: int = 0) -> Kernels:
+def make_kernels(w, c, s, q, cull_k: float, weight_map: int = 0,
+                 orientation: int = ORIENT_QUATERNION) -> Kernels:
     """Derived per-kernel quantities.
 
     a = w|w| (eq. 3-26) for weight_map 0, a = w for weight_map 1;
-    r = k_cull / min_k d_k (eq. 3-15 with lambda_j = min_k d_jk^2)."""
+    r = k_cull / min_k d_k (eq. 3-15 with lambda_j = min_k d_jk^2);
+    R from the quaternion q/|q|, or from the Euler angles q[:, :3] (eq. 3-6)."""
     w = np.asarray(w, np.float64).reshape(-1)
     c = np.asarray(c, np.float64).reshape(-1, 3)
     s = np.asarray(s, np.float64).reshape(-1, 3)
     q = np.asarray(q, np.float64).reshape(-1, 4)
-    qn = np.linalg.norm(q, axis=1)
-    qhat = q / qn[:, None]
-    R = quat_to_rot(qhat)
+    if orientation == ORIENT_EULER:
+        qn = np.ones(q.shape[0])
+        qhat = q.copy()
+        R = euler_to_rot(q[:, :3])
+    elif orientation == ORIENT_QUATERNION:
+        qn = np.linalg.norm(q, axis=1)
+        qhat = q / qn[:, None]
+        R = quat_to_rot(qhat)
+    else:
+        raise ValueError("orientation must be 0 (quaternion) or 1 (Euler angles)")
     d = np.exp(s)
     if weight_map == 0:
         a = w * np.abs(w)
@@ -180,7 +232,7 @@ def make_kernels(w, c, s, q, cull_k: float, weight_map: int = 0) -> Kernels:
     else:
         raise ValueError("weight_map must be 0 (signed square) or 1 (linear)")
     r = cull_k / d.min(axis=1)
-    return Kernels(w, c, s, q, qn, qhat, R, d, a, dadw, r * r, weight_map)
+    return Kernels(w, c, s, q, qn, qhat, R, d, a, dadw, r * r, weight_map, orientation)
 
 
 # ---------------------------------------------------------------------------
@@ -459,10 +511,15 @@ def backward(levels: List[OLevel], K: Kernels, G: List[np.ndarray],
     gs = -2.0 * a[:, None] * d2 * Su2
     gc = 2.0 * a[:, None] * np.einsum("mkl,mk->ml", K.R, d2 * Su)
     gR = -2.0 * a[:, None, None] * d2[:, :, None] * SuD
-    J = quat_rot_jacobian(K.qhat)
-    gqhat = np.einsum("mkab,mab->mk", J, gR)
-    proj = gqhat - K.qhat * np.sum(K.qhat * gqhat, axis=1, keepdims=True)
-    gq = proj / K.qn[:, None]
+    if K.orientation == ORIENT_EULER:
+        # dL/dtheta_k = sum_ab dL/dR_ab dR_ab/dtheta_k; the fourth slot is unused
+        gth = np.einsum("mkab,mab->mk", euler_rot_jacobian(K.q[:, :3]), gR)
+        gq = np.concatenate([gth, np.zeros((m, 1))], axis=1)
+    else:
+        J = quat_rot_jacobian(K.qhat)
+        gqhat = np.einsum("mkab,mab->mk", J, gR)
+        proj = gqhat - K.qhat * np.sum(K.qhat * gqhat, axis=1, keepdims=True)
+        gq = proj / K.qn[:, None]
     return Grads(gw, gc, gs, gq, S0)
 
 
@@ -547,7 +604,8 @@ class SeedOut:
 
 def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
          top_frac: float = 0.01, k_new: int = 256, r_nms: Optional[float] = None,
-         eps: float = 1e-7, min_abs_err: float = 0.0, w_rule: int = 0) -> SeedOut:
+         eps: float = 1e-7, min_abs_err: float = 0.0, w_rule: int = 0,
+         orientation: int = ORIENT_QUATERNION) -> SeedOut:
     """New kernels at local extrema of |E| (Algorithm 2).
 
     1. candidates: the ceil(top_frac * n_idall) id_all points of largest |E|
@@ -559,7 +617,8 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
     4. eq. 3-24: c = x_i; w = -sign(E)|E| (w_rule 0) or -sign(E) sqrt|E|
        (w_rule 1); d = sqrt(ln(|E| / eps)) / dbar on all axes with
        dbar = max(|S_i|, h_finest) standing in for the distance to the
-       nearest surface sample; orientation zero (identity quaternion).
+       nearest surface sample; orientation zero (identity quaternion, or zero
+       Euler angles).
     Global indices run over the levels in order, x fastest inside a level."""
     offs = np.cumsum([0] + [lv.npts for lv in levels])
     absE = np.concatenate([np.abs(np.asarray(e, np.float64)) for e in E])
@@ -626,7 +685,8 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
         s = np.repeat(np.log(d)[:, None], 3, axis=1)
     else:
         s = np.zeros((0, 3))
-    q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (kept.size, 1))
+    ident = [0.0, 0.0, 0.0, 0.0] if orientation == ORIENT_EULER else [1.0, 0.0, 0.0, 0.0]
+    q = np.tile(np.array(ident), (kept.size, 1))
     return SeedOut(kept, w, c, s, q, int(cand.size), int(kept.size))
 
 

@@ -27,7 +27,7 @@ from typing import List, Optional
 import numpy as np
 
 from .grid import axis_coords, grid_points
-from .params import init_params_from_points, init_params_in_shell, pack_params
+from .params import random_euler_angles, init_params_from_points, init_params_in_shell, pack_params
 from .sdf import random_shape, sample_sdf, sphere
 
 LN = np.log
@@ -59,6 +59,7 @@ class Problem:
     cap: int
     cull_k: float = 3.0
     weight_map: int = 0         # 0: a = w|w| ; 1: a = w
+    orientation: int = 0        # 0: quaternion ; 1: Euler angles in the first three q slots
     lr: float = 1e-3
     lam: float = 1e-4
     steps: int = 1
@@ -172,7 +173,7 @@ def make_diff(seed: int = 4, n: int = 512, m: int = 65536) -> Problem:
 
 def make_custom(seed: int, ns, m: int, log_scale_range, kinds=("ellipsoid",) * 4,
                 bands=None, cap: int = None, cull_k: float = 3.0, weight_map: int = 0,
-                center_band: float = 0.05) -> Problem:
+                center_band: float = 0.05, orientation: int = 0) -> Problem:
     """Small problems for tests: any level list, any kernel count."""
     rng = _rng(seed)
     prims = random_shape(list(kinds), rng)
@@ -183,6 +184,8 @@ def make_custom(seed: int, ns, m: int, log_scale_range, kinds=("ellipsoid",) * 4
     while np.count_nonzero(np.abs(sd) < band) < m:
         band *= 1.5
     w, c, s, q = init_params_from_points(pts, sd, m, log_scale_range, rng, band=band)
+    if orientation == 1:
+        q = random_euler_angles(m, rng)
     cap = m if cap is None else cap
     return Problem(f"custom{seed}", levels, pack_params(w, c, s, q, cap), m, cap,
-                   cull_k=cull_k, weight_map=weight_map, extra={"prims": prims})
+                   cull_k=cull_k, weight_map=weight_map, orientation=orientation, extra={"prims": prims})

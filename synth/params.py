@@ -27,6 +27,14 @@ def random_unit_quaternions(m: int, rng: np.random.Generator) -> np.ndarray:
     return np.stack([qw, qx, qy, qz], axis=1)
 
 
+def random_euler_angles(m: int, rng: np.random.Generator) -> np.ndarray:
+    """(m, 4) orientation slots holding three angles uniform in [-pi, pi)
+    and a zero fourth slot (the Euler-angle parameterisation)."""
+    out = np.zeros((m, 4))
+    out[:, :3] = rng.uniform(-np.pi, np.pi, size=(m, 3))
+    return out
+
+
 def pack_params(w, c, s, q, cap: int = None) -> np.ndarray:
     """Pack per-kernel arrays into the float32 SoA layout."""
     w = np.asarray(w, dtype=np.float64).reshape(-1)

@@ -9,10 +9,10 @@ import oracle as O
 import synth
 
 
-def _problem(seed=0, n=12, m=5, lo=1.2, hi=2.0, wm=0, bands=None):
+def _problem(seed=0, n=12, m=5, lo=1.2, hi=2.0, wm=0, bands=None, orientation=0):
     p = synth.make_custom(seed, [n], m, (lo, hi), kinds=("ellipsoid", "torus"),
-                          weight_map=wm, bands=bands)
-    K = O.kernels_from_packed(p.params, p.m, p.cap, 3.0, wm)
+                          weight_map=wm, bands=bands, orientation=orientation)
+    K = O.kernels_from_packed(p.params, p.m, p.cap, 3.0, wm, orientation)
     lv0 = p.levels[0]
     mS = O.sdf_min([lv0.S])
     t = O.targets_from_sdf(lv0.S, mS).astype(np.float32)
@@ -58,7 +58,7 @@ def _fd_grads(lv, K, idall, h=1e-6, kernels=(0, 1, 2)):
     base = dict(w=K.w.copy(), c=K.c.copy(), s=K.s.copy(), q=K.q.copy())
 
     def L(fields):
-        Kp = O.make_kernels(fields["w"], fields["c"], fields["s"], fields["q"], 3.0, K.weight_map)
+        Kp = O.make_kernels(fields["w"], fields["c"], fields["s"], fields["q"], 3.0, K.weight_map, K.orientation)
         return O.l2_frozen([lv], Kp, idall, culled=False)
 
     for name, width in (("w", 1), ("c", 3), ("s", 3), ("q", 4)):
@@ -78,9 +78,9 @@ def _fd_grads(lv, K, idall, h=1e-6, kernels=(0, 1, 2)):
     return out
 
 
-@pytest.mark.parametrize("wm", [0, 1])
-def test_gradients_match_central_differences(wm):
-    lv, K, _ = _problem(seed=11, n=12, m=5, wm=wm)
+@pytest.mark.parametrize("wm,orientation", [(0, 0), (1, 0), (0, 1)])
+def test_gradients_match_central_differences(wm, orientation):
+    lv, K, _ = _problem(seed=11, n=12, m=5, wm=wm, orientation=orientation)
     assert np.all(np.abs(K.w) > 1e-4)
     f = O.forward([lv], K, culled=False)
     lo = O.loss([lv], f, K)
@@ -88,7 +88,10 @@ def test_gradients_match_central_differences(wm):
     G = [2.0 * e for e in lo.E]
     gr = O.backward([lv], K, G, culled=False)
     kern = (0, 2, 4)
-    fd = _fd_grads(lv, K, lo.idall, kernels=kern)
+    # the angle gradients are about 1e-4 of the loss, so the difference
+    # quotient needs a wider step to stay above rounding (its truncation
+    # error at 1e-4 is near 1e-8)
+    fd = _fd_grads(lv, K, lo.idall, h=1e-4 if orientation else 1e-6, kernels=kern)
     ana = {"w": gr.w[list(kern)][:, None], "c": gr.c[list(kern)], "s": gr.s[list(kern)],
            "q": gr.q[list(kern)]}
     for name in ana:
@@ -295,3 +298,13 @@ def test_kernel_field_sums_to_forward_and_subset_gradients():
     part = O.backward([lv], O.subset(K, [1, 3]), G)
     assert np.allclose(part.q, full.q[[1, 3]], rtol=1e-13, atol=0)
     assert np.allclose(part.c, full.c[[1, 3]], rtol=1e-13, atol=0)
+
+
+def test_euler_isotropic_kernels_have_zero_angle_gradient():
+    lv, K, p = _problem(seed=15, n=12, m=4, orientation=O.ORIENT_EULER)
+    iso = O.make_kernels(K.w, K.c, np.repeat(K.s[:, :1], 3, axis=1), K.q, 3.0, 0, O.ORIENT_EULER)
+    f = O.forward([lv], iso)
+    lo = O.loss([lv], f, iso)
+    gr = O.backward([lv], iso, [2.0 * e for e in lo.E])
+    assert np.abs(gr.q).max() <= 1e-12 * max(1.0, np.abs(gr.c).max())
+    assert np.all(gr.q[:, 3] == 0.0)

@@ -231,3 +231,53 @@ def test_point_evaluation_and_allowance_match_the_grid_versions():
     assert np.allclose(ap, al[0][idx], rtol=1e-12, atol=1e-15)
     _, call = O.allowance_at_points(O.level_points(lv), K, rel=1e-2)
     assert call == cnt and cnt > 0
+
+
+def _hamilton(p, q):
+    w1, x1, y1, z1 = p
+    w2, x2, y2, z2 = q
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_euler_rotation_is_the_quaternion_composition():
+    # Rz Ry Rx equals the rotation of the Hamilton product qz * qy * qx of the
+    # three axis quaternions: pins the composition order and every sign
+    # against the (separately pinned) quaternion matrix
+    rng = np.random.default_rng(21)
+    th = rng.uniform(-math.pi, math.pi, size=(50, 3))
+    R = O.euler_to_rot(th)
+    for a, (tx, ty, tz) in enumerate(th):
+        qx = np.array([math.cos(tx / 2), math.sin(tx / 2), 0, 0])
+        qy = np.array([math.cos(ty / 2), 0, math.sin(ty / 2), 0])
+        qz = np.array([math.cos(tz / 2), 0, 0, math.sin(tz / 2)])
+        q = _hamilton(qz, _hamilton(qy, qx))
+        assert np.abs(O.quat_to_rot(q[None])[0] - R[a]).max() < 1e-14
+    assert np.abs(O.euler_to_rot(np.zeros((1, 3)))[0] - np.eye(3)).max() == 0.0
+
+
+def test_euler_worked_examples():
+    # the hand-derived single-axis examples, with the angle on that axis
+    slot = {"x": 0, "y": 1, "z": 2}
+    for ax, ang, ox, oy, oz, d1, d2, d3, ex in _read_golden("rotation_worked_examples.txt"):
+        th = [0.0, 0.0, 0.0, 0.0]
+        th[slot[ax]] = math.radians(float(ang))
+        d = np.array([float(d1), float(d2), float(d3)])
+        c = np.array([0.1, -0.2, 0.3])
+        K = O.make_kernels([1.0], [c], [np.log(d)], [th], 100.0, orientation=O.ORIENT_EULER)
+        x = c + np.array([float(ox), float(oy), float(oz)])
+        got = O.forward_at_points(x[None], K, culled=False)[0]
+        assert got == pytest.approx(math.exp(-float(ex)), rel=1e-13)
+
+
+def test_euler_jacobian_matches_differences():
+    rng = np.random.default_rng(22)
+    th = rng.uniform(-3, 3, size=(20, 3))
+    J = O.euler_rot_jacobian(th)
+    h = 1e-6
+    for k in range(3):
+        tp, tm = th.copy(), th.copy()
+        tp[:, k] += h
+        tm[:, k] -= h
+        fd = (O.euler_to_rot(tp) - O.euler_to_rot(tm)) / (2 * h)
+        assert np.abs(fd - J[:, k]).max() < 1e-9
