@@ -12,8 +12,11 @@
  *     f(x) = sum_j a_j [ |x - c_j|^2 < r_j^2 ] exp(-| D_j R_j (x - c_j) |^2)
  *     a_j  = w_j |w_j|  (ERBF_WEIGHT_SIGNED_SQUARE)   or   w_j (ERBF_WEIGHT_LINEAR)
  *     D_j  = diag(exp(s_j)),  R_j = R(q_j / |q_j|),  r_j = cull_k / min_k exp(s_jk)
- * Orientation is a quaternion (w, x, y, z) in place of the paper's Euler
- * angles (eq. 3-6); scales are optimised as logarithms s = ln d.
+ * Orientation is a quaternion (w, x, y, z) by default (ERBF_ORIENT_QUATERNION);
+ * the paper's Euler angles (eq. 3-6, read as R = Rz(tz) Ry(ty) Rx(tx) with the
+ * standard right-handed axis rotations) are ERBF_ORIENT_EULER, with the
+ * angles (tx, ty, tz) in the first three orientation slots and the fourth
+ * unused (its gradient is 0).  Scales are optimised as logarithms s = ln d.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -55,7 +58,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 1
+#define ERBF_ABI_VERSION 2
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -73,6 +76,9 @@ enum {
 #define ERBF_FLAG_BUCKET_OVERFLOW 1  /* bucket list exceeded pair_cap: f, loss, grads invalid */
 
 enum { ERBF_WEIGHT_SIGNED_SQUARE = 0, ERBF_WEIGHT_LINEAR = 1 };
+
+/* Orientation parameterisations (Section 3.2). */
+enum { ERBF_ORIENT_QUATERNION = 0, ERBF_ORIENT_EULER = 1 };
 
 /* Loss-weight modes (Section 3.3, eq. 3-14 and eq. 3-21; Algorithm 3). */
 enum {
@@ -99,6 +105,8 @@ typedef struct {
   float cull_k;       /* cull radius factor: r = cull_k / min d (eq. 3-15 with
                          eps = exp(-cull_k^2)); > 0 */
   int32_t weight_map; /* ERBF_WEIGHT_SIGNED_SQUARE (eq. 3-26) or ERBF_WEIGHT_LINEAR */
+  int32_t orientation; /* ERBF_ORIENT_QUATERNION or ERBF_ORIENT_EULER (eq. 3-6); also
+                          decides the identity rotation that seeding writes */
 } erbf_config;
 
 /* A grid level (eq. 3-16: the training set is the union of the levels

@@ -25,6 +25,8 @@ FLAG_BUCKET_OVERFLOW = 1
 
 MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
+ORIENT_QUATERNION, ORIENT_EULER = 0, 1
+ABI_VERSION = 2
 
 
 class ErbfError(RuntimeError):
@@ -41,7 +43,7 @@ class ShapeDesc(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("n_shapes", ctypes.c_int32), ("shapes", ctypes.POINTER(ShapeDesc)),
                 ("pair_cap", ctypes.c_int64), ("cull_k", ctypes.c_float),
-                ("weight_map", ctypes.c_int32)]
+                ("weight_map", ctypes.c_int32), ("orientation", ctypes.c_int32)]
 
 
 class Level(ctypes.Structure):
@@ -128,7 +130,7 @@ def load(path: str = None):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.erbf_abi_version() != 1:
+    if lib.erbf_abi_version() != ABI_VERSION:
         raise ImportError("liberbf.so ABI version mismatch")
     if path is None:
         _lib = lib

@@ -62,7 +62,8 @@ class Context:
     """One library context: shapes, their grid levels and the workspace."""
 
     def __init__(self, shapes: Sequence, pair_cap: int, cull_k: float = 3.0,
-                 weight_map: int = L.WEIGHT_SIGNED_SQUARE, device: int = 0):
+                 weight_map: int = L.WEIGHT_SIGNED_SQUARE, device: int = 0,
+                 orientation: int = L.ORIENT_QUATERNION):
         """shapes: sequence of (level_ns, m_cap)."""
         self.lib = L.load()
         self.device = torch.device("cuda", device)
@@ -78,7 +79,7 @@ class Context:
             self.level_ns.append(ns)
             self.m_caps.append(int(mcap))
         self._descs = descs
-        cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map))
+        cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map), int(orientation))
         self._cfg = cfg
         nbytes = ctypes.c_size_t()
         L.check(self.lib.erbf_workspace_size(ctypes.byref(cfg), ctypes.byref(nbytes)))

@@ -61,6 +61,8 @@ int validate_config(const erbf_config* cfg) {
   if (!(cfg->cull_k > 0.f) || !std::isfinite(cfg->cull_k)) return fail(ERBF_ERR_INVALID_ARG, "cull_k must be > 0");
   if (cfg->weight_map != ERBF_WEIGHT_SIGNED_SQUARE && cfg->weight_map != ERBF_WEIGHT_LINEAR)
     return fail(ERBF_ERR_INVALID_ARG, "unknown weight_map");
+  if (cfg->orientation != ERBF_ORIENT_QUATERNION && cfg->orientation != ERBF_ORIENT_EULER)
+    return fail(ERBF_ERR_INVALID_ARG, "unknown orientation");
   if (cfg->pair_cap < 1 || cfg->pair_cap > (int64_t)INT32_MAX)
     return fail(ERBF_ERR_INVALID_ARG, "pair_cap must be in [1, 2^31)");
   int64_t cap = 0, tiles = 0;
@@ -279,6 +281,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.n_shapes = cfg->n_shapes;
   D.cull_k = cfg->cull_k;
   D.weight_map = cfg->weight_map;
+  D.orientation = cfg->orientation;
   D.variant = 0;
   {
     hipDeviceProp_t prop;

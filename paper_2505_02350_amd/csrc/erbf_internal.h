@@ -104,6 +104,7 @@ struct Dev {
   int32_t n_shapes;
   float cull_k;
   int32_t weight_map;
+  int32_t orientation;      // ERBF_ORIENT_*
   int32_t variant;          // kVariant* flags
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass

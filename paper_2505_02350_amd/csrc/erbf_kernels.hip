@@ -108,24 +108,36 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
     const float w = p[j];
     const float cx = p[C + j], cy = p[2 * C + j], cz = p[3 * C + j];
     const float s0 = p[4 * C + j], s1 = p[5 * C + j], s2 = p[6 * C + j];
-    float qw = p[7 * C + j], qx = p[8 * C + j], qy = p[9 * C + j], qz = p[10 * C + j];
-    const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
-    if (qn2 > 0.f) {
-      const float inv = 1.0f / sqrtf(qn2);
-      qw *= inv; qx *= inv; qy *= inv; qz *= inv;
-    } else {
-      qw = 1.f; qx = qy = qz = 0.f;
-    }
     float R[3][3];
-    R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
-    R[0][1] = 2.f * (qx * qy - qw * qz);
-    R[0][2] = 2.f * (qx * qz + qw * qy);
-    R[1][0] = 2.f * (qx * qy + qw * qz);
-    R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
-    R[1][2] = 2.f * (qy * qz - qw * qx);
-    R[2][0] = 2.f * (qx * qz - qw * qy);
-    R[2][1] = 2.f * (qy * qz + qw * qx);
-    R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+    if (D.orientation == ERBF_ORIENT_EULER) {
+      // eq. 3-6: R = Rz(theta_z) Ry(theta_y) Rx(theta_x), angles in the
+      // first three orientation slots
+      float sx, cx_, sy, cy_, sz, cz_;
+      sincosf(p[7 * C + j], &sx, &cx_);
+      sincosf(p[8 * C + j], &sy, &cy_);
+      sincosf(p[9 * C + j], &sz, &cz_);
+      R[0][0] = cz_ * cy_; R[0][1] = cz_ * sy * sx - sz * cx_; R[0][2] = cz_ * sy * cx_ + sz * sx;
+      R[1][0] = sz * cy_;  R[1][1] = sz * sy * sx + cz_ * cx_; R[1][2] = sz * sy * cx_ - cz_ * sx;
+      R[2][0] = -sy;       R[2][1] = cy_ * sx;                 R[2][2] = cy_ * cx_;
+    } else {
+      float qw = p[7 * C + j], qx = p[8 * C + j], qy = p[9 * C + j], qz = p[10 * C + j];
+      const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
+      if (qn2 > 0.f) {
+        const float inv = 1.0f / sqrtf(qn2);
+        qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+      } else {
+        qw = 1.f; qx = qy = qz = 0.f;
+      }
+      R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
+      R[0][1] = 2.f * (qx * qy - qw * qz);
+      R[0][2] = 2.f * (qx * qz + qw * qy);
+      R[1][0] = 2.f * (qx * qy + qw * qz);
+      R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
+      R[1][2] = 2.f * (qy * qz - qw * qx);
+      R[2][0] = 2.f * (qx * qz - qw * qy);
+      R[2][1] = 2.f * (qy * qz + qw * qx);
+      R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+    }
     const float d2[3] = {expf(2.f * s0), expf(2.f * s1), expf(2.f * s2)};
     float A[3][3];
 #pragma unroll
@@ -935,6 +947,33 @@ __global__ __launch_bounds__(256) void k_bwd_tiles_persistent(Dev D, const float
 // float64 and turns them into gradients (Appendix A; quaternion chain rule).
 // ---------------------------------------------------------------------------
 
+// Rotation about axis k (0 = x, 1 = y, 2 = z) by angle t and its derivative
+// in t (the standard right-handed matrices).
+__device__ __forceinline__ void axis_rotation(int k, double t, double M[3][3], double dM[3][3]) {
+  const double c = cos(t), s = sin(t);
+  const int i = k == 0 ? 1 : (k == 1 ? 2 : 0), jj = k == 0 ? 2 : (k == 1 ? 0 : 1);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      M[a][b] = 0.0;
+      dM[a][b] = 0.0;
+    }
+  M[k][k] = 1.0;
+  M[i][i] = c; M[jj][jj] = c; M[i][jj] = -s; M[jj][i] = s;
+  dM[i][i] = -s; dM[jj][jj] = -s; dM[i][jj] = -c; dM[jj][i] = c;
+}
+
+__device__ __forceinline__ void mat3_mul(const double A[3][3], const double B[3][3], double Cm[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Cm[a][b] = A[a][0] * B[0][b] + A[a][1] * B[1][b] + A[a][2] * B[2][b];
+}
+
+__device__ __forceinline__ double mat3_dot(const double A[3][3], const double B[3][3]) {
+  double r = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) r += A[a][b] * B[a][b];
+  return r;
+}
+
 __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restrict__ p,
                                                    float* __restrict__ grad) {
   const int j = blockIdx.x;
@@ -969,18 +1008,29 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   const double w = p[j];
   const double s[3] = {p[4 * C + j], p[5 * C + j], p[6 * C + j]};
   const double q4[4] = {p[7 * C + j], p[8 * C + j], p[9 * C + j], p[10 * C + j]};
-  double qn = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
-  double qh[4];
-  if (qn > 0.0) {
-    for (int k = 0; k < 4; ++k) qh[k] = q4[k] / qn;
+  const bool euler = D.orientation == ERBF_ORIENT_EULER;
+  double qn = 1.0;
+  double qh[4] = {1.0, 0.0, 0.0, 0.0};
+  double R[3][3], Rx[3][3], Ry[3][3], Rz[3][3], dRx[3][3], dRy[3][3], dRz[3][3];
+  if (euler) {
+    axis_rotation(0, q4[0], Rx, dRx);
+    axis_rotation(1, q4[1], Ry, dRy);
+    axis_rotation(2, q4[2], Rz, dRz);
+    double RyRx[3][3];
+    mat3_mul(Ry, Rx, RyRx);
+    mat3_mul(Rz, RyRx, R);
   } else {
-    qh[0] = 1.0; qh[1] = qh[2] = qh[3] = 0.0; qn = 1.0;
+    qn = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+    if (qn > 0.0) {
+      for (int k = 0; k < 4; ++k) qh[k] = q4[k] / qn;
+    } else {
+      qn = 1.0;
+    }
+    const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
+    R[0][0] = 1 - 2 * (qy * qy + qz * qz); R[0][1] = 2 * (qx * qy - qw * qz); R[0][2] = 2 * (qx * qz + qw * qy);
+    R[1][0] = 2 * (qx * qy + qw * qz); R[1][1] = 1 - 2 * (qx * qx + qz * qz); R[1][2] = 2 * (qy * qz - qw * qx);
+    R[2][0] = 2 * (qx * qz - qw * qy); R[2][1] = 2 * (qy * qz + qw * qx); R[2][2] = 1 - 2 * (qx * qx + qy * qy);
   }
-  const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
-  double R[3][3];
-  R[0][0] = 1 - 2 * (qy * qy + qz * qz); R[0][1] = 2 * (qx * qy - qw * qz); R[0][2] = 2 * (qx * qz + qw * qy);
-  R[1][0] = 2 * (qx * qy + qw * qz); R[1][1] = 1 - 2 * (qx * qx + qz * qz); R[1][2] = 2 * (qy * qz - qw * qx);
-  R[2][0] = 2 * (qx * qz - qw * qy); R[2][1] = 2 * (qy * qz + qw * qx); R[2][2] = 1 - 2 * (qx * qx + qy * qy);
   double d2[3];
   for (int k = 0; k < 3; ++k) d2[k] = exp(2.0 * s[k]);
   const double amp = D.weight_map == ERBF_WEIGHT_SIGNED_SQUARE ? w * fabs(w) : w;
@@ -1006,7 +1056,26 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   double gR[3][3];
   for (int k = 0; k < 3; ++k)
     for (int l = 0; l < 3; ++l) gR[k][l] = -2.0 * amp * d2[k] * RT2[k][l];
-  // dL/dqhat through dR/dqhat
+  grad[j] = (float)gw;
+  for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
+  for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
+  if (euler) {
+    // dL/dtheta_k = <dL/dR, dR/dtheta_k>: Rz Ry dRx, Rz dRy Rx, dRz Ry Rx
+    double T[3][3], U[3][3], dR[3][3];
+    mat3_mul(Ry, dRx, T);
+    mat3_mul(Rz, T, dR);
+    grad[7 * C + j] = (float)mat3_dot(gR, dR);
+    mat3_mul(dRy, Rx, T);
+    mat3_mul(Rz, T, dR);
+    grad[8 * C + j] = (float)mat3_dot(gR, dR);
+    mat3_mul(Ry, Rx, U);
+    mat3_mul(dRz, U, dR);
+    grad[9 * C + j] = (float)mat3_dot(gR, dR);
+    grad[10 * C + j] = 0.f;
+    return;
+  }
+  // dL/dqhat through dR/dqhat, then the projection through q / |q|
+  const double qw = qh[0], qx = qh[1], qy = qh[2], qz = qh[3];
   double gq[4];
   gq[0] = 2 * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
   gq[1] = 2 * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2 * qx * gR[1][1] - qw * gR[1][2] + qz * gR[2][0] +
@@ -1016,9 +1085,6 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   gq[3] = 2 * (-2 * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] - 2 * qz * gR[1][1] +
                qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
   const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
-  grad[j] = (float)gw;
-  for (int l = 0; l < 3; ++l) grad[(1 + l) * C + j] = (float)gc[l];
-  for (int k = 0; k < 3; ++k) grad[(4 + k) * C + j] = (float)gs[k];
   for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
 }
 

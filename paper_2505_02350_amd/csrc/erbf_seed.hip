@@ -277,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_seed_write(Dev D, int shape, float* __
     p[4 * C + slot] = s;
     p[5 * C + slot] = s;
     p[6 * C + slot] = s;
-    p[7 * C + slot] = 1.f;
+    p[7 * C + slot] = D.orientation == ERBF_ORIENT_EULER ? 0.f : 1.f;   // identity rotation
     p[8 * C + slot] = 0.f;
     p[9 * C + slot] = 0.f;
     p[10 * C + slot] = 0.f;

@@ -58,12 +58,14 @@ class Fitter:
     registered up front (or all levels when ``all_levels``)."""
 
     def __init__(self, shapes: List[ShapeInput], cull_k: float = 3.0, weight_map: int = 0,
-                 pair_cap: Optional[int] = None, all_levels: bool = True, device: int = 0):
+                 pair_cap: Optional[int] = None, all_levels: bool = True, device: int = 0,
+                 orientation: int = L.ORIENT_QUATERNION):
         self.shapes = shapes
         self.dev = torch.device("cuda", device)
         if pair_cap is None:
             pair_cap = sum(estimate_pair_cap(s.level_ns, s.s_min(), cull_k) for s in shapes)
-        self.ctx = core.Context([(s.level_ns, s.cap) for s in shapes], pair_cap, cull_k, weight_map, device)
+        self.ctx = core.Context([(s.level_ns, s.cap) for s in shapes], pair_cap, cull_k, weight_map, device,
+                                orientation)
         self._levels = []
         # eq. 3-10's m: minimum over every level of a shape, computed on the device
         self.m_sdf = torch.zeros(len(shapes), dtype=torch.float32, device=self.dev)

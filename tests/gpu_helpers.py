@@ -64,7 +64,8 @@ class GpuProblem:
         nl = len(prob.levels) if n_levels is None else n_levels
         wm = prob.weight_map if weight_map is None else weight_map
         self.ctx = core.Context([([lv.n for lv in prob.levels[:nl]], prob.cap)],
-                                pair_cap or pair_cap_estimate(prob), prob.cull_k, wm)
+                                pair_cap or pair_cap_estimate(prob), prob.cull_k, wm,
+                                orientation=prob.orientation)
         dev = self.ctx.device
         self.axes, self.tgts, self.sdfs, self.bits = [], [], [], []
         for li, lv in enumerate(prob.levels[:nl]):

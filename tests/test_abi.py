@@ -39,7 +39,8 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 
 def test_abi_version(lib):
-    assert lib.erbf_abi_version() == 1
+    from paper_2505_02350_amd import _lib as L
+    assert lib.erbf_abi_version() == L.ABI_VERSION == 2
 
 
 def _struct_sizes_from_c():
@@ -105,6 +106,9 @@ def test_workspace_size_and_validation(lib):
         _cfg(L, [([32], 8)], wm=7),           # weight map
         _cfg(L, [([32], 8)], pair_cap=0),     # bucket capacity
     ]
+    orient = _cfg(L, [([32], 8)])
+    orient[0].orientation = 7                 # orientation mode
+    bad.append(orient)
     for cfg_b, _ in bad:
         assert lib.erbf_workspace_size(ctypes.byref(cfg_b), ctypes.byref(size)) == L.ERBF_ERR_INVALID_ARG
         assert lib.erbf_last_error()

@@ -64,3 +64,25 @@ def test_autograd_second_call_and_optimizer_step():
     # the backward holds no point-kernel pairs: the graph saved only p and m
     f = layer()
     assert f.grad_fn is not None and len(f.grad_fn.saved_tensors) == 2
+
+
+def test_autograd_euler_orientation():
+    torch = _torch()
+    from paper_2505_02350_amd.autograd import ERBFLayer
+    prob = synth.make_custom(43, [16, 24], 30, (1.6, 2.6), kinds=("ellipsoid", "torus"), bands=[None, 0.2],
+                             orientation=1)
+    olv, _, _ = oracle_levels(prob, with_targets=False)
+    gp = GpuProblem(prob, None)
+    layer = ERBFLayer(gp.ctx, gp.p, gp.m_dev)
+    rng = np.random.default_rng(6)
+    u = [rng.standard_normal(lv.npts).astype(np.float32) for lv in olv]
+    (layer() * torch.from_numpy(np.concatenate(u)).to(gp.ctx.device)).sum().backward()
+    torch.cuda.synchronize()
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k, 0, prob.orientation)
+    gr = O.backward(olv, K, [np.where(lv.act(), uu.astype(np.float64), 0.0) for lv, uu in zip(olv, u)])
+    gg = gp.grads_np(layer.p.grad)
+    go = oracle_grads_dict(gr)
+    errs = {k: rel_inf(gg[k], go[k]) for k in go}
+    record("autograd_euler", **errs)
+    for k in go:
+        assert errs[k] <= 1e-4, (k, errs[k])

@@ -102,7 +102,7 @@ def _loss_case(name, prob, mode, lam=0.0, l1_active=False, tau_m=TAU_M, wm=None)
     torch.cuda.synchronize()
     st = gp.ctx.stats()[0]
     K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k,
-                              prob.weight_map if wm is None else wm)
+                              prob.weight_map if wm is None else wm, prob.orientation)
     f_or = _check_f(name + "_f", gp, olv, K, gp.split_points(f))
     # mask decisions whose float32/float64 outcome could differ
     amb = 0
@@ -154,6 +154,14 @@ def test_loss_grad_dynamic_alpha():
 
 def test_loss_grad_linear_weights():
     _loss_case("loss_linear", _ragged_problem(25), O.MODE_L2, wm=1)
+
+
+def test_loss_grad_euler_orientation():
+    # Euler angles (eq. 3-6) in place of the quaternion; eq. 3-21 active
+    prob = synth.make_custom(28, [12, 20], 24, (1.6, 2.6), kinds=("ellipsoid", "torus", "box"),
+                             bands=[None, 0.15], orientation=1)
+    gp, g, st = _loss_case("loss_euler", prob, O.MODE_DYNAMIC, l1_active=True, tau_m=10.0)
+    assert not np.any(gp.grads_np(g)["q"][:, 3])
 
 
 def test_vjp_random_upstream():

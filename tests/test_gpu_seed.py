@@ -26,15 +26,16 @@ def _residual_field(lvs, seed, frac=0.7, decimals=2):
     return E, ida
 
 
-def _seed_case(name, levels_n, k_new, top_frac, seed, m0=16, cap=600, min_abs_err=0.0, w_rule=0, bands=None):
+def _seed_case(name, levels_n, k_new, top_frac, seed, m0=16, cap=600, min_abs_err=0.0, w_rule=0, bands=None,
+               orientation=0):
     torch = _torch()
-    prob = synth.make_custom(seed, levels_n, m0, (1.5, 2.5), bands=bands, cap=cap)
+    prob = synth.make_custom(seed, levels_n, m0, (1.5, 2.5), bands=bands, cap=cap, orientation=orientation)
     olv, t32, _ = oracle_levels(prob)
     gp = GpuProblem(prob, t32)
     E, ida = _residual_field(olv, seed + 100)
     tf = float(np.float32(top_frac))
     out = O.seed(olv, [e.astype(np.float64) for e in E], ida, top_frac=tf, k_new=k_new,
-                 min_abs_err=float(np.float32(min_abs_err)), w_rule=w_rule)
+                 min_abs_err=float(np.float32(min_abs_err)), w_rule=w_rule, orientation=orientation)
     resid = torch.from_numpy(np.concatenate(E)).to(gp.ctx.device)
     m1 = torch.full((11 * gp.ctx.cap_total,), 7.0, device=gp.ctx.device)
     m2 = torch.full_like(m1, 9.0)
@@ -65,6 +66,11 @@ def test_seed_two_levels_matches_oracle():
 
 def test_seed_k_new_limits_and_sqrt_rule():
     _seed_case("seed_knew", [24], k_new=5, top_frac=0.05, seed=32, w_rule=1)
+
+
+def test_seed_euler_orientation_writes_zero_angles():
+    gp, out = _seed_case("seed_euler", [16, 24], k_new=32, top_frac=0.02, seed=36, orientation=1)
+    assert out.index.size > 0 and not np.any(out.q)
 
 
 def test_seed_min_abs_err_floor():
