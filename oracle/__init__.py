@@ -17,3 +17,4 @@ their docstring.
 """
 
 from .erbf import *  # noqa: F401,F403
+from . import schedule  # noqa: F401,E402
