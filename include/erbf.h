@@ -133,6 +133,9 @@ typedef struct {
   int32_t l1_active;       /* dynamic mode: L1 term scheduled on (eq. l1_activate) */
   float tau1, tau2;        /* id_all thresholds of eq. 3-18 (paper: 0.9, 1.1) */
   float tau_m;             /* max-error gate of eq. l1_activate2 (paper: 0.02) */
+  const int32_t* l1_active_dev; /* device [n_shapes] per-shape L1 flags (the
+                                   control state's l1_active), or NULL to use
+                                   l1_active for every shape */
 } erbf_loss_cfg;
 
 /* Per-shape step statistics, written to device memory by erbf_loss_grad. */
@@ -247,6 +250,65 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
                          const float* resid, float resid_scale, int64_t n_idall,
                          const erbf_seed_cfg* cfg, float* m1, float* m2, int32_t* n_added,
                          hipStream_t stream);
+
+/* ---- training control (Algorithm 3) -------------------------------------- */
+
+/* Constants of Algorithm 3 (paper values in parentheses). */
+typedef struct {
+  int32_t k_l2;      /* window of eq. l1_activate, 1 .. 32 (10) */
+  float tau_l2;      /* threshold on the standard deviation of L2 over the window (0.5) */
+  int32_t k_l1;      /* window of eq. add_activate, 1 .. 64 (50) */
+  float tau_l1;      /* threshold on max - min of the effective basis count (5) */
+  float tau_d;       /* eq. 3-27 / b_f threshold on |w| (0.01) */
+  int32_t T_e, M_e;  /* the final L2 phase runs from epoch T_e to M_e (1600, 2000); T_e < M_e */
+  float lr0;         /* learning rate before the final phase (0.01) */
+  float lr_final;    /* learning rate at T_e, annealed by cosine (1e-3) ... */
+  float lr_min;      /* ... down to lr_min at M_e (1e-5) */
+  int32_t refine_epochs[4]; /* epochs after which the next grid level is requested,
+                               0 = unused (400, 800) */
+} erbf_sched_cfg;
+
+/* Per-shape control state: caller-owned device arrays.  The scalar fields
+ * hold n_shapes entries, l2_ring n_shapes * k_l2 and bf_ring n_shapes * k_l1.
+ * After erbf_sched_step for epoch e: epoch = e; l1_active feeds the next
+ * erbf_loss_cfg.l1_active_dev; lr feeds the next erbf_adam_cfg.lr_dev;
+ * add_request asks the caller to add kernels (erbf_seed_from_error,
+ * Algorithm 2); refine_request asks for the next grid level
+ * (erbf_refine_level); b_f is the effective basis count and n_pruned the
+ * kernels removed by eq. 3-27 in this call. */
+typedef struct {
+  int32_t* epoch;
+  int32_t* l1_active;
+  int32_t* final_phase;
+  int32_t* add_request;
+  int32_t* refine_request;
+  int32_t* b_f;
+  int32_t* n_pruned;
+  float* lr;
+  double* l2_ring;
+  int32_t* bf_ring;
+} erbf_sched_state;
+
+/* Reset the control state (epoch 0, L1 off, lr = lr0).  INVALID_ARG for a
+ * bad configuration or a NULL array. */
+int erbf_sched_init(erbf_ctx* ctx, const erbf_sched_cfg* cfg, const erbf_sched_state* state,
+                    hipStream_t stream);
+
+/* Algorithm 3's control after one step (erbf_loss_grad, then erbf_adam_step)
+ * of every shape, on the device and in its order: record L2 (from
+ * stats_dev, written by the step's erbf_loss_grad) and the effective basis
+ * count b_f = #{|w| >= tau_d} after the update; outside the final phase,
+ * prune by eq. 3-27 when epoch % k_l2 == 0, L1 is on and epoch < T_e
+ * (kernels with |w| < tau_d leave; the others, their Adam moments m1/m2
+ * (optional) and their order are kept, m_dev shrinks); turn L1 on when the
+ * population standard deviation of the last k_l2 L2 values is below tau_l2
+ * (eq. l1_activate); request new kernels and turn L1 off when L1 is on and
+ * the last k_l1 counts vary by less than tau_l1 (eq. add_activate); at
+ * epoch T_e enter the final phase (L1 off, no pruning or adding, cosine
+ * learning rate).  No host synchronisation; capturable. */
+int erbf_sched_step(erbf_ctx* ctx, const erbf_params* params, const erbf_sched_cfg* cfg,
+                    const erbf_sched_state* state, const erbf_stats* stats_dev, float* m1, float* m2,
+                    hipStream_t stream);
 
 /* ---- measurement --------------------------------------------------------- */
 

@@ -58,7 +58,7 @@ class Params(ctypes.Structure):
 class LossCfg(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lambda_", ctypes.c_float), ("lambda_dev", ctypes.c_void_p),
                 ("l1_active", ctypes.c_int32), ("tau1", ctypes.c_float), ("tau2", ctypes.c_float),
-                ("tau_m", ctypes.c_float)]
+                ("tau_m", ctypes.c_float), ("l1_active_dev", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +78,19 @@ class AdamCfg(ctypes.Structure):
 class SeedCfg(ctypes.Structure):
     _fields_ = [("top_frac", ctypes.c_float), ("k_new", ctypes.c_int32), ("r_nms", ctypes.c_float),
                 ("eps", ctypes.c_float), ("min_abs_err", ctypes.c_float), ("w_rule", ctypes.c_int32)]
+
+
+class SchedCfg(ctypes.Structure):
+    _fields_ = [("k_l2", ctypes.c_int32), ("tau_l2", ctypes.c_float), ("k_l1", ctypes.c_int32),
+                ("tau_l1", ctypes.c_float), ("tau_d", ctypes.c_float), ("T_e", ctypes.c_int32),
+                ("M_e", ctypes.c_int32), ("lr0", ctypes.c_float), ("lr_final", ctypes.c_float),
+                ("lr_min", ctypes.c_float), ("refine_epochs", ctypes.c_int32 * 4)]
+
+
+class SchedState(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("epoch", "l1_active", "final_phase", "add_request", "refine_request", "b_f", "n_pruned", "lr",
+                 "l2_ring", "bf_ring")]
 
 
 STATS_BYTES = ctypes.sizeof(Stats)
@@ -110,6 +123,9 @@ _SIGS = [
     ("erbf_seed_from_error", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, _V, ctypes.c_float,
                                             ctypes.c_int64, ctypes.POINTER(SeedCfg), _V, _V,
                                             ctypes.POINTER(ctypes.c_int32), _V]),
+    ("erbf_sched_init", ctypes.c_int, [_V, ctypes.POINTER(SchedCfg), ctypes.POINTER(SchedState), _V]),
+    ("erbf_sched_step", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(SchedCfg),
+                                       ctypes.POINTER(SchedState), _V, _V, _V, _V]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]

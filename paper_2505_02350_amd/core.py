@@ -159,12 +159,12 @@ class Context:
 
     def erbf_loss_grad(self, p, m_dev, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
                        tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None, G_out=None,
-                       stream=None):
+                       l1_active_dev=None, stream=None):
         if grad_out is None:
             grad_out = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
         pr = self._params(p, m_dev)
         cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
-                        float(tau2), float(tau_m))
+                        float(tau2), float(tau_m), _ptr(l1_active_dev))
         L.check(self.lib.erbf_loss_grad(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(grad_out),
                                         _ptr(self.stats_buf), _ptr(f_out), _ptr(G_out), _stream(stream)))
         return grad_out
@@ -196,6 +196,17 @@ class Context:
                                               float(resid_scale), int(n_idall), ctypes.byref(cfg), _ptr(m1),
                                               _ptr(m2), ctypes.byref(n_added), _stream(stream)))
         return n_added.value
+
+    # ---- training control (Algorithm 3) ----------------------------------------
+    def erbf_sched_init(self, cfg, state: "SchedState", stream=None):
+        L.check(self.lib.erbf_sched_init(self.handle, ctypes.byref(cfg), ctypes.byref(state.c), _stream(stream)))
+
+    def erbf_sched_step(self, p, m_dev, cfg, state: "SchedState", m1=None, m2=None, stream=None):
+        """Control after a step; reads this context's stats of the last
+        erbf_loss_grad call."""
+        pr = self._params(p, m_dev)
+        L.check(self.lib.erbf_sched_step(self.handle, ctypes.byref(pr), ctypes.byref(cfg), ctypes.byref(state.c),
+                                         _ptr(self.stats_buf), _ptr(m1), _ptr(m2), _stream(stream)))
 
     def erbf_timing_enable(self, max_calls: int):
         L.check(self.lib.erbf_timing_enable(self.handle, int(max_calls)))
@@ -254,3 +265,31 @@ def erbf_band_bits(S: torch.Tensor, band: float, bits: torch.Tensor = None, stre
         bits = torch.empty((S.numel() + 31) // 32, dtype=torch.int32, device=S.device)
     L.check(L.load().erbf_band_bits(_ptr(S), S.numel(), float(band), _ptr(bits), _stream(stream)))
     return bits
+
+
+def sched_cfg(k_l2=10, tau_l2=0.5, k_l1=50, tau_l1=5.0, tau_d=0.01, T_e=1600, M_e=2000, lr0=0.01,
+              lr_final=1e-3, lr_min=1e-5, refine_epochs=(400, 800)):
+    """Algorithm 3's constants (defaults: the paper's values)."""
+    ep = (ctypes.c_int32 * 4)(*(list(refine_epochs) + [0] * (4 - len(refine_epochs))))
+    return L.SchedCfg(int(k_l2), float(tau_l2), int(k_l1), float(tau_l1), float(tau_d), int(T_e), int(M_e),
+                      float(lr0), float(lr_final), float(lr_min), ep)
+
+
+class SchedState:
+    """Device arrays of the training-control state of every shape of a
+    context (see erbf_sched_state in include/erbf.h)."""
+
+    def __init__(self, ctx: "Context", cfg):
+        dev, n = ctx.device, ctx.n_shapes
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.epoch = torch.zeros(n, **i32)
+        self.l1_active = torch.zeros(n, **i32)
+        self.final_phase = torch.zeros(n, **i32)
+        self.add_request = torch.zeros(n, **i32)
+        self.refine_request = torch.zeros(n, **i32)
+        self.b_f = torch.zeros(n, **i32)
+        self.n_pruned = torch.zeros(n, **i32)
+        self.lr = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.l2_ring = torch.zeros(n * cfg.k_l2, dtype=torch.float64, device=dev)
+        self.bf_ring = torch.zeros(n * cfg.k_l1, **i32)
+        self.c = L.SchedState(*[_ptr(getattr(self, f)) for f, _ in L.SchedState._fields_])

@@ -49,7 +49,7 @@ struct Layout {
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
-      off_counters, off_stat_part, off_stat_ab, off_hist, off_cand, off_keep, off_misc;
+      off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_hist, off_cand, off_keep, off_misc;
   size_t bytes = 0;
 };
 
@@ -137,6 +137,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_counters = take(sizeof(int64_t) * 8);
   L.off_stat_part = take(sizeof(StatPart) * kStatParts * cfg->n_shapes);
   L.off_stat_ab = take(sizeof(double2) * cfg->n_shapes);
+  L.off_prune_flag = take(sizeof(int32_t) * cfg->n_shapes);
   L.off_hist = take(sizeof(uint32_t) * 65536);
   L.off_cand = take(sizeof(int64_t) * L.cand_cap);
   L.off_keep = take(sizeof(int64_t) * L.cand_cap);
@@ -269,6 +270,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.counters = reinterpret_cast<int64_t*>(w + lay.off_counters);
   D.stat_part = reinterpret_cast<StatPart*>(w + lay.off_stat_part);
   D.stat_ab = reinterpret_cast<double2*>(w + lay.off_stat_ab);
+  D.prune_flag = reinterpret_cast<int32_t*>(w + lay.off_prune_flag);
   D.seed_hist = reinterpret_cast<uint32_t*>(w + lay.off_hist);
   D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
   D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);
@@ -465,6 +467,7 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   a.lambda = cfg->lambda;
   a.lambda_dev = cfg->lambda_dev;
   a.l1_active = cfg->l1_active;
+  a.l1_active_dev = cfg->l1_active_dev;
   a.tau_m = cfg->tau_m;
   HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream), "loss: stats");
   if (G_out)
@@ -607,6 +610,43 @@ int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls) {
   for (int i = 0; i < 3; ++i) ms[i] = acc[i];
   if (n_calls) *n_calls = ctx->t_used;
   ctx->t_used = 0;
+  return ERBF_OK;
+}
+
+namespace {
+int check_sched(const erbf_ctx* ctx, const erbf_sched_cfg* cfg, const erbf_sched_state* st) {
+  if (!ctx || !cfg || !st) return fail(ERBF_ERR_INVALID_ARG, "ctx, cfg and state must be non-NULL");
+  if (cfg->k_l2 < 1 || cfg->k_l2 > 32 || cfg->k_l1 < 1 || cfg->k_l1 > 64)
+    return fail(ERBF_ERR_INVALID_ARG, "k_l2 must be in [1, 32] and k_l1 in [1, 64]");
+  if (!(cfg->T_e < cfg->M_e) || cfg->T_e < 1) return fail(ERBF_ERR_INVALID_ARG, "need 1 <= T_e < M_e");
+  if (!(cfg->tau_d >= 0.f) || !(cfg->lr0 > 0.f) || !(cfg->lr_final > 0.f) || !(cfg->lr_min > 0.f))
+    return fail(ERBF_ERR_INVALID_ARG, "tau_d >= 0 and positive learning rates required");
+  if (!st->epoch || !st->l1_active || !st->final_phase || !st->add_request || !st->refine_request || !st->b_f ||
+      !st->n_pruned || !st->lr || !st->l2_ring || !st->bf_ring)
+    return fail(ERBF_ERR_INVALID_ARG, "every control-state array must be non-NULL");
+  return ERBF_OK;
+}
+}  // namespace
+
+int erbf_sched_init(erbf_ctx* ctx, const erbf_sched_cfg* cfg, const erbf_sched_state* state, hipStream_t stream) {
+  int rc = check_sched(ctx, cfg, state);
+  if (rc) return rc;
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(launch_sched_init(ctx->D, *state, *cfg, stream), "sched: init");
+  return ERBF_OK;
+}
+
+int erbf_sched_step(erbf_ctx* ctx, const erbf_params* params, const erbf_sched_cfg* cfg,
+                    const erbf_sched_state* state, const erbf_stats* stats_dev, float* m1, float* m2,
+                    hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  rc = check_sched(ctx, cfg, state);
+  if (rc) return rc;
+  if (!stats_dev) return fail(ERBF_ERR_INVALID_ARG, "stats_dev must be non-NULL");
+  DeviceGuard guard(ctx->device);
+  HIP_TRY(launch_sched_step(ctx->D, params->p, params->p, params->m_dev, m1, m2, *state, *cfg, stats_dev, stream),
+          "sched: step");
   return ERBF_OK;
 }
 

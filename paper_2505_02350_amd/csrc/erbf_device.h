@@ -1,0 +1,56 @@
+// Small device helpers shared by the HIP translation units (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace erbf {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// exclusive scan over a 1024-thread block (16 waves); also returns the total
+__device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int& total) {
+  // 1024 threads, 16 waves
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int s = lane < 16 ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) sh[16 + lane] = s;
+  }
+  __syncthreads();
+  total = sh[31];
+  const int wbase = wv > 0 ? sh[16 + wv - 1] : 0;
+  const int r = wbase + x - v;
+  __syncthreads();
+  return r;
+}
+
+}  // namespace erbf

@@ -91,6 +91,7 @@ struct Dev {
   int64_t* tile_pbwd;       // [tiles_total] in-ball pairs at non-zero-G points of each tile
   int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
   StatPart* stat_part;      // [n_shapes * kStatParts]
+  int32_t* prune_flag;      // [n_shapes] eq. 3-27 due after this step (training control)
   double2* stat_ab;         // [n_shapes] alpha, beta of eq. 3-21 for the last loss call
   // seeding scratch
   uint32_t* seed_hist;      // [65536]

@@ -2,7 +2,8 @@
 //
 //   prologue   per-kernel record: centre, squared cull radius, log2(e)-scaled
 //              quadric A = R^T diag(d^2) R, amplitude (eq. 3-7, 3-26, 3-15)
-//   bucket     tile -> kernel lists: count, exclusive scan, scatter, per-tile sort
+//   bucket     tile -> kernel lists: per-kernel count, scan, kernel-major emit,
+//              stable radix sort by tile slot (no atomics)
 //   forward    point-centric gather over the tile's kernel list staged in LDS,
 //              fused residual / id_all mask / loss partials (eq. 3-9, 3-15-1,
 //              3-18, 3-19)
@@ -21,6 +22,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "erbf_device.h"
 #include "erbf_internal.h"
 #include "erbf_launch.h"
 
@@ -31,25 +33,6 @@ namespace erbf {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // Conservative index range of the points whose coordinate may lie in
 // [c0, c1] on a level (the exact predicate is applied afterwards).
@@ -161,33 +144,6 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
 // exclusive scan of int32 counts (three passes, 1024 elements per block)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int& total) {
-  // 1024 threads, 16 waves
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  if (wv == 0) {
-    int s = lane < 16 ? sh[lane] : 0;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      const int y = __shfl_up(s, o, 64);
-      if (lane >= o) s += y;
-    }
-    if (lane < 16) sh[16 + lane] = s;
-  }
-  __syncthreads();
-  total = sh[31];
-  const int wbase = wv > 0 ? sh[16 + wv - 1] : 0;
-  const int r = wbase + x - v;
-  __syncthreads();
-  return r;
-}
 
 __global__ __launch_bounds__(1024) void k_scan_reduce(const int32_t* __restrict__ in, int n,
                                                       int32_t* __restrict__ blocks) {
@@ -1191,7 +1147,8 @@ __global__ __launch_bounds__(64) void k_stats_final(Dev D, const int32_t* __rest
   if (MODE == 2) {
     if (a.mode == ERBF_MODE_FIXED) {
       beta = a.lambda_dev ? (double)a.lambda_dev[b] : (double)a.lambda;
-    } else if (a.mode == ERBF_MODE_DYNAMIC && a.l1_active && mx < a.tau_m) {
+    } else if (a.mode == ERBF_MODE_DYNAMIC && (a.l1_active_dev ? a.l1_active_dev[b] : a.l1_active) &&
+               mx < a.tau_m) {
       alpha = den > 0.0 ? fmin(fmax(num / den, 0.0), 1.0) : 1.0;
       beta = 1.0 - alpha;
     }

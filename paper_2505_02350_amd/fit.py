@@ -136,3 +136,48 @@ class Fitter:
 
     def stats(self):
         return self.ctx.stats()
+
+    def fit_schedule(self, steps: int, cfg=None, tau1: float = 0.9, tau2: float = 1.1, tau_m: float = 0.02,
+                     top_frac: float = 0.01, k_new: int = 256, min_abs_err: float = 0.0, stream=None):
+        """Algorithm 3 on every shape for `steps` full-batch steps.
+
+        Each step: loss and gradient with eq. 3-21 gated by the device control
+        state, Adam with the state's learning rate, then the control itself
+        (pruning by eq. 3-27 happens there, on the device).  When the control
+        asks for new kernels (eq. add_activate) the shape is seeded from the
+        step's residual (Algorithm 2); when it asks for the next grid level,
+        the level is appended (eq. 3-16).  Returns the control state and a
+        per-step log of (L2, m, b_f, l1_active, n_added, n_pruned) per shape.
+        """
+        cfg = cfg or core.sched_cfg()
+        st = core.SchedState(self.ctx, cfg)
+        self.ctx.erbf_sched_init(cfg, st, stream=stream)
+        G = torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev)
+        log = []
+        for _ in range(steps):
+            self.ctx.erbf_loss_grad(self.p, self.m_dev, mode=L.MODE_DYNAMIC, l1_active_dev=st.l1_active, tau1=tau1,
+                                    tau2=tau2, tau_m=tau_m, grad_out=self.grad, G_out=G, stream=stream)
+            self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr_dev=st.lr,
+                                    stream=stream)
+            self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, stream=stream)
+            torch.cuda.synchronize(self.dev)
+            stats = self.ctx.stats()
+            add = st.add_request.cpu().tolist()
+            ref = st.refine_request.cpu().tolist()
+            m_now = self.m_dev.cpu().tolist()
+            row = []
+            for b, s in enumerate(self.shapes):
+                n_added = 0
+                room = s.cap - m_now[b]
+                if add[b] and room > 0 and stats[b].n_idall > 0:
+                    n_added = self.ctx.erbf_seed_from_error(self.p, self.m_dev, b, G, 0.5, stats[b].n_idall,
+                                                            top_frac=top_frac, k_new=min(k_new, room),
+                                                            min_abs_err=min_abs_err, m1=self.m1, m2=self.m2,
+                                                            stream=stream)
+                if ref[b] and self.next_level[b] < len(s.level_ns):
+                    self.refine(b)
+                row.append(dict(L2=stats[b].L2, m=m_now[b] + n_added, l1=bool(st.l1_active[b].item()),
+                                b_f=int(st.b_f[b].item()), n_added=n_added,
+                                n_pruned=int(st.n_pruned[b].item())))
+            log.append(row)
+        return st, log
