@@ -718,3 +718,32 @@ def step(levels: List[OLevel], K: Kernels, mode: int = MODE_FIXED, lam: float = 
     al, be = loss_weights(mode, lam, l1_active, lo.max_abs_E, tau_m, gr.w, K.w)
     pf, pb = pair_counts(levels, K, G) if count_pairs else (0, 0)
     return StepOut(f, lo, G, gr, al, be, combine(gr, K.w, al, be), pf, pb)
+
+
+# ---------------------------------------------------------------------------
+# Mini-batch step (Algorithm 3, inner loop over batches of B_s points)
+# ---------------------------------------------------------------------------
+
+
+def batch_masks(levels: List[OLevel], batch: np.ndarray) -> List[np.ndarray]:
+    """Per-level boolean masks of the points of a batch given as indices into
+    the concatenation of the levels' points (level order, x fastest)."""
+    batch = np.asarray(batch, np.int64)
+    out, base = [], 0
+    for lv in levels:
+        m = np.zeros(lv.npts, bool)
+        sel = batch[(batch >= base) & (batch < base + lv.npts)] - base
+        m[sel] = True
+        out.append(m)
+        base += lv.npts
+    return out
+
+
+def step_batch(levels: List[OLevel], K: Kernels, batch: np.ndarray, mode: int = MODE_FIXED, lam: float = 0.0,
+               l1_active: bool = False, tau1=0.9, tau2=1.1, tau_m=0.02) -> StepOut:
+    """One mini-batch step: the loss of eq. 3-19 and its gradient over the
+    batch's points only (id_all, L2, max|E| and eq. 3-21 taken on the batch),
+    with the batch a set of indices into the concatenated points."""
+    bm = batch_masks(levels, batch)
+    blv = [OLevel(lv.n, lv.axis, lv.act() & m, lv.t, lv.S) for lv, m in zip(levels, bm)]
+    return step(blv, K, mode=mode, lam=lam, l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m)

@@ -308,3 +308,22 @@ def test_euler_isotropic_kernels_have_zero_angle_gradient():
     gr = O.backward([lv], iso, [2.0 * e for e in lo.E])
     assert np.abs(gr.q).max() <= 1e-12 * max(1.0, np.abs(gr.c).max())
     assert np.all(gr.q[:, 3] == 0.0)
+
+
+def test_batch_step_reduces_to_the_full_step_and_is_additive():
+    lv, K, p = _problem(seed=16, n=12, m=6, lo=1.3, hi=2.1)
+    full = O.step([lv], K)
+    everything = O.step_batch([lv], K, np.arange(lv.npts))
+    assert everything.loss.L2 == full.loss.L2 and everything.P_fwd == full.P_fwd
+    assert np.array_equal(everything.grads.q, full.grads.q)
+    # a partition into three batches: L2, counts and L2 gradients add up
+    perm = np.random.default_rng(4).permutation(lv.npts)
+    parts = [O.step_batch([lv], K, perm[i::3]) for i in range(3)]
+    assert abs(sum(b.loss.L2 for b in parts) - full.loss.L2) <= 1e-12 * full.loss.L2
+    assert sum(b.loss.n_idall for b in parts) == full.loss.n_idall
+    assert sum(b.P_fwd for b in parts) == full.P_fwd and sum(b.P_bwd for b in parts) == full.P_bwd
+    for k in ("w", "c", "s", "q"):
+        tot = sum(getattr(b.grads_l2, k) for b in parts)
+        ref = getattr(full.grads_l2, k)
+        assert np.abs(tot - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert max(b.loss.max_abs_E for b in parts) == full.loss.max_abs_E
