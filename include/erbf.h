@@ -107,6 +107,7 @@ typedef struct {
   int32_t weight_map; /* ERBF_WEIGHT_SIGNED_SQUARE (eq. 3-26) or ERBF_WEIGHT_LINEAR */
   int32_t orientation; /* ERBF_ORIENT_QUATERNION or ERBF_ORIENT_EULER (eq. 3-6); also
                           decides the identity rotation that seeding writes */
+  int32_t batch_cap;   /* largest point count of an erbf_loss_grad_batch call, >= 0 */
 } erbf_config;
 
 /* A grid level (eq. 3-16: the training set is the union of the levels
@@ -226,6 +227,19 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
 int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
                    float* grad_out, erbf_stats* stats_dev, float* f_out, float* G_out,
                    hipStream_t stream);
+
+/* One mini-batch step's loss and gradient (Algorithm 3, the inner loop over
+ * batches of B_s shuffled points): as erbf_loss_grad, but f, the id_all mask,
+ * E, L2, max|E| (hence the gate of eq. 3-21), the pair counts and the
+ * gradient cover only the batch.  pts: device [n_pts] distinct indices into
+ * the context's per-point arrays (shape-major over the declared levels, x
+ * fastest), 0 <= n_pts <= batch_cap; indices outside the registered
+ * levels' active points contribute nothing.  f_out: optional device
+ * [n_pts], f at the batch points in batch order.  The bucket lists are
+ * rebuilt from the current parameters as in erbf_loss_grad. */
+int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+                         const int64_t* pts, int32_t n_pts, float* grad_out, erbf_stats* stats_dev,
+                         float* f_out, hipStream_t stream);
 
 /* Vector-Jacobian product of erbf_eval: grad_out = (df/dtheta)^T grad_f,
  * grad_f: device [n_points] (entries at inactive points are ignored).

@@ -43,7 +43,7 @@ class ShapeDesc(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("n_shapes", ctypes.c_int32), ("shapes", ctypes.POINTER(ShapeDesc)),
                 ("pair_cap", ctypes.c_int64), ("cull_k", ctypes.c_float),
-                ("weight_map", ctypes.c_int32), ("orientation", ctypes.c_int32)]
+                ("weight_map", ctypes.c_int32), ("orientation", ctypes.c_int32), ("batch_cap", ctypes.c_int32)]
 
 
 class Level(ctypes.Structure):
@@ -112,6 +112,8 @@ _SIGS = [
     ("erbf_refine_level", ctypes.c_int, [_V, ctypes.c_int32, ctypes.POINTER(Level), _V]),
     ("erbf_eval", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V]),
     ("erbf_loss_grad", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, _V, _V, _V, _V]),
+    ("erbf_loss_grad_batch", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, ctypes.c_int32,
+                                            _V, _V, _V, _V]),
     ("erbf_vjp", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V]),
     ("erbf_adam_step", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V, ctypes.POINTER(AdamCfg), _V]),
     ("erbf_timing_enable", ctypes.c_int, [_V, ctypes.c_int32]),

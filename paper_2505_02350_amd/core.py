@@ -63,7 +63,7 @@ class Context:
 
     def __init__(self, shapes: Sequence, pair_cap: int, cull_k: float = 3.0,
                  weight_map: int = L.WEIGHT_SIGNED_SQUARE, device: int = 0,
-                 orientation: int = L.ORIENT_QUATERNION):
+                 orientation: int = L.ORIENT_QUATERNION, batch_cap: int = 0):
         """shapes: sequence of (level_ns, m_cap)."""
         self.lib = L.load()
         self.device = torch.device("cuda", device)
@@ -79,7 +79,9 @@ class Context:
             self.level_ns.append(ns)
             self.m_caps.append(int(mcap))
         self._descs = descs
-        cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map), int(orientation))
+        cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map), int(orientation),
+                       int(batch_cap))
+        self.batch_cap = int(batch_cap)
         self._cfg = cfg
         nbytes = ctypes.c_size_t()
         L.check(self.lib.erbf_workspace_size(ctypes.byref(cfg), ctypes.byref(nbytes)))
@@ -167,6 +169,22 @@ class Context:
                         float(tau2), float(tau_m), _ptr(l1_active_dev))
         L.check(self.lib.erbf_loss_grad(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(grad_out),
                                         _ptr(self.stats_buf), _ptr(f_out), _ptr(G_out), _stream(stream)))
+        return grad_out
+
+    def erbf_loss_grad_batch(self, p, m_dev, pts, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
+                             tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None, l1_active_dev=None,
+                             stream=None):
+        """One mini-batch loss + gradient; pts: int64 device tensor of point indices."""
+        if pts.dtype != torch.int64:
+            raise ValueError("pts must be int64")
+        if grad_out is None:
+            grad_out = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        pr = self._params(p, m_dev)
+        cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
+                        float(tau2), float(tau_m), _ptr(l1_active_dev))
+        L.check(self.lib.erbf_loss_grad_batch(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(pts),
+                                              int(pts.numel()), _ptr(grad_out), _ptr(self.stats_buf), _ptr(f_out),
+                                              _stream(stream)))
         return grad_out
 
     def erbf_vjp(self, p, m_dev, grad_f, grad_out=None, stats=False, stream=None):

@@ -49,7 +49,8 @@ struct Layout {
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
-      off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_hist, off_cand, off_keep, off_misc;
+      off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
+      off_b_shape, off_hist, off_cand, off_keep, off_misc;
   size_t bytes = 0;
 };
 
@@ -63,6 +64,7 @@ int validate_config(const erbf_config* cfg) {
     return fail(ERBF_ERR_INVALID_ARG, "unknown weight_map");
   if (cfg->orientation != ERBF_ORIENT_QUATERNION && cfg->orientation != ERBF_ORIENT_EULER)
     return fail(ERBF_ERR_INVALID_ARG, "unknown orientation");
+  if (cfg->batch_cap < 0 || cfg->batch_cap > (1 << 28)) return fail(ERBF_ERR_INVALID_ARG, "batch_cap out of range");
   if (cfg->pair_cap < 1 || cfg->pair_cap > (int64_t)INT32_MAX)
     return fail(ERBF_ERR_INVALID_ARG, "pair_cap must be in [1, 2^31)");
   int64_t cap = 0, tiles = 0;
@@ -138,6 +140,12 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_stat_part = take(sizeof(StatPart) * kStatParts * cfg->n_shapes);
   L.off_stat_ab = take(sizeof(double2) * cfg->n_shapes);
   L.off_prune_flag = take(sizeof(int32_t) * cfg->n_shapes);
+  const size_t bc = (size_t)std::max(cfg->batch_cap, 1);
+  L.off_b_l2 = take(sizeof(double) * bc);
+  L.off_b_abs = take(sizeof(float) * bc);
+  L.off_b_id = take(sizeof(int32_t) * bc);
+  L.off_b_pf = take(sizeof(int32_t) * bc);
+  L.off_b_shape = take(sizeof(int32_t) * bc);
   L.off_hist = take(sizeof(uint32_t) * 65536);
   L.off_cand = take(sizeof(int64_t) * L.cand_cap);
   L.off_keep = take(sizeof(int64_t) * L.cand_cap);
@@ -271,6 +279,13 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.stat_part = reinterpret_cast<StatPart*>(w + lay.off_stat_part);
   D.stat_ab = reinterpret_cast<double2*>(w + lay.off_stat_ab);
   D.prune_flag = reinterpret_cast<int32_t*>(w + lay.off_prune_flag);
+  D.b_l2 = reinterpret_cast<double*>(w + lay.off_b_l2);
+  D.b_abs = reinterpret_cast<float*>(w + lay.off_b_abs);
+  D.b_id = reinterpret_cast<int32_t*>(w + lay.off_b_id);
+  D.b_pf = reinterpret_cast<int32_t*>(w + lay.off_b_pf);
+  D.b_shape = reinterpret_cast<int32_t*>(w + lay.off_b_shape);
+  D.batch_cap = cfg->batch_cap;
+  D.n_levels_total = lay.n_levels_total;
   D.seed_hist = reinterpret_cast<uint32_t*>(w + lay.off_hist);
   D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
   D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);
@@ -473,6 +488,36 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   if (G_out)
     HIP_TRY(hipMemcpyAsync(G_out, D.G, sizeof(float) * ctx->lay.pts_total, hipMemcpyDeviceToDevice, stream),
             "loss: copy G");
+  return ERBF_OK;
+}
+
+int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, const int64_t* pts,
+                         int32_t n_pts, float* grad_out, erbf_stats* stats_dev, float* f_out, hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!cfg || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "cfg and grad_out must be non-NULL");
+  if (cfg->mode < ERBF_MODE_FIXED || cfg->mode > ERBF_MODE_L2) return fail(ERBF_ERR_INVALID_ARG, "unknown mode");
+  if (n_pts < 0 || n_pts > ctx->D.batch_cap) return fail(ERBF_ERR_INVALID_ARG, "n_pts must be in [0, batch_cap]");
+  if (n_pts > 0 && !pts) return fail(ERBF_ERR_INVALID_ARG, "pts must be non-NULL");
+  for (const ShapeDev& s : ctx->sh)
+    for (int l = 0; l < s.n_active; ++l)
+      if (!ctx->lv[s.lvl0 + l].target) return fail(ERBF_ERR_INVALID_ARG, "a registered level has no target");
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  // G is zero outside the batch, so the tile backward sees the batch only
+  HIP_TRY(launch_fill_f32(D.G, ctx->lay.pts_total, 0.f, stream), "batch: clear G");
+  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "batch: prologue");
+  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "batch: buckets");
+  StatsArgs a{};
+  a.mode = cfg->mode;
+  a.lambda = cfg->lambda;
+  a.lambda_dev = cfg->lambda_dev;
+  a.l1_active = cfg->l1_active;
+  a.l1_active_dev = cfg->l1_active_dev;
+  a.tau_m = cfg->tau_m;
+  HIP_TRY(launch_batch_step(D, ctx->slots_used, pts, n_pts, params->p, params->m_dev, grad_out, f_out, stats_dev,
+                            cfg->tau1, cfg->tau2, a, stream),
+          "batch: step");
   return ERBF_OK;
 }
 

@@ -92,6 +92,12 @@ struct Dev {
   int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
   StatPart* stat_part;      // [n_shapes * kStatParts]
   int32_t* prune_flag;      // [n_shapes] eq. 3-27 due after this step (training control)
+  // mini-batch records, one per batch point (batch order)
+  double* b_l2;             // [batch_cap] E^2
+  float* b_abs;             // [batch_cap] |E|
+  int32_t* b_id;            // [batch_cap] point in id_all
+  int32_t* b_pf;            // [batch_cap] in-ball pairs at the point
+  int32_t* b_shape;         // [batch_cap] shape of the point, -1 if not a training point
   double2* stat_ab;         // [n_shapes] alpha, beta of eq. 3-21 for the last loss call
   // seeding scratch
   uint32_t* seed_hist;      // [65536]
@@ -109,6 +115,8 @@ struct Dev {
   int32_t variant;          // kVariant* flags
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass
+  int32_t n_levels_total;   // entries of `levels` (ordered by pt_base)
+  int32_t batch_cap;        // largest mini-batch
 };
 
 }  // namespace erbf

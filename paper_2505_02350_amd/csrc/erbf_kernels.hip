@@ -736,6 +736,72 @@ __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __rest
 }
 
 // ---------------------------------------------------------------------------
+// mini-batch forward: one wave per batch point walks the kernel list of the
+// point's tile (lanes strided over the list, then a fixed butterfly), then
+// forms E and G = 2E at the point and its loss records (eq. 3-9, 3-15-1,
+// 3-18, 3-19 restricted to the batch)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __restrict__ pts, int n_pts,
+                                                       float* __restrict__ f_out, float tau1, float tau2) {
+  const int lane = threadIdx.x & 63;
+  const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (k >= n_pts) return;
+  const int64_t gi = pts[k];
+  // the level holding point gi (levels are ordered by pt_base)
+  int li = 0;
+  for (int a = 1; a < D.n_levels_total; ++a)
+    if (D.levels[a].pt_base <= gi) li = a;
+  const LevelDev L = D.levels[li];
+  const int n = L.n, nt = L.nt;
+  const int64_t local = gi - L.pt_base;
+  const bool valid = gi >= 0 && L.axis != nullptr && local >= 0 && local < (int64_t)n * n * n &&
+                     point_active(L.bits, local);
+  int slot = -1;
+  int xi = 0, yi = 0, zi = 0;
+  if (valid) {
+    xi = (int)(local % n);
+    yi = (int)((local / n) % n);
+    zi = (int)(local / ((int64_t)n * n));
+    slot = D.tile_map[L.tmap0 + ((zi / kTile) * nt + yi / kTile) * nt + xi / kTile];
+  }
+  float acc = 0.f;
+  int cnt = 0;
+  if (slot >= 0) {
+    const float px = L.axis[xi], py = L.axis[yi], pz = L.axis[zi];
+    const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+    const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+    for (int64_t e = beg + lane; e < end; e += 64) {
+      const int j = D.items[e];
+      const float4 a0 = D.rec[3 * j], a1 = D.rec[3 * j + 1], a2 = D.rec[3 * j + 2];
+      const float dx = px - a0.x, dy = py - a0.y, dz = pz - a0.z;
+      const bool in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < a0.w;
+      float q = fmaf(dx, fmaf(a1.x, dx, fmaf(a1.w, dy, a2.x * dz)), fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz));
+      q = in ? q : INFINITY;
+      acc = fmaf(a2.z, fast_exp2(-q), acc);
+      cnt += in ? 1 : 0;
+    }
+  }
+  const float f = wave_sum(acc);
+  const int pf = wave_sum(cnt);
+  if (lane != 0) return;
+  float E = 0.f;
+  bool id = false;
+  if (valid && L.target) {
+    const float t = L.target[local];
+    id = (tau1 < t && t < tau2) || (t <= tau1 && f > tau1) || (t >= tau2 && f < tau2);
+    E = id ? f - t : 0.f;
+  }
+  if (valid) D.G[gi] = 2.f * E;
+  if (f_out) f_out[k] = valid ? f : 0.f;
+  D.b_l2[k] = (double)E * (double)E;
+  D.b_abs[k] = fabsf(E);
+  D.b_id[k] = id ? 1 : 0;
+  D.b_pf[k] = valid ? pf : 0;
+  D.b_shape[k] = valid ? L.shape : -1;
+}
+
+// ---------------------------------------------------------------------------
 // backward, stage 1: one workgroup per active tile.  The tile's points with a
 // non-zero upstream gradient are staged in LDS in (z, y, x) order; each lane
 // owns one kernel of the tile's list and walks those points, so every branch
@@ -1073,10 +1139,12 @@ __device__ __forceinline__ float block_max_256(float v, float* sh) {
 
 // MODE 0: forward statistics; 1: backward pair count only; 2: both, plus
 // the sums of eq. 3-21 and L1 over the weights.
-template <int MODE>
+// BATCH: the forward part comes from the mini-batch records (n_pts of them)
+// instead of the tile statistics.
+template <int MODE, bool BATCH>
 __global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restrict__ p,
                                                     const int32_t* __restrict__ m_dev,
-                                                    const float* __restrict__ grad) {
+                                                    const float* __restrict__ grad, int n_pts) {
   __shared__ double shd[4];
   __shared__ float shf[4];
   const int part = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
@@ -1095,7 +1163,7 @@ __global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restri
     const int a0 = max(lo, acc), a1 = min(hi, acc + L.n_slots);
     for (int x = a0 + tid; x < a1; x += 256) {
       const int sl = L.slot0 + (x - acc);
-      if (MODE != 1) {
+      if (MODE != 1 && !BATCH) {
         const TileStat ts = D.tstat[sl];
         l2 += ts.l2;
         nid += (double)ts.n_idall;
@@ -1105,6 +1173,18 @@ __global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restri
       if (MODE >= 1) pb += (double)D.tile_pbwd[sl];
     }
     acc += L.n_slots;
+  }
+  if (BATCH) {
+    // this block's slice of the batch, the shape's points only
+    const int bper = (n_pts + kStatParts - 1) / kStatParts;
+    const int b0 = part * bper, b1 = min(n_pts, b0 + bper);
+    for (int k = b0 + tid; k < b1; k += 256) {
+      if (D.b_shape[k] != b) continue;
+      l2 += D.b_l2[k];
+      nid += (double)D.b_id[k];
+      mx = fmaxf(mx, D.b_abs[k]);
+      pf += (double)D.b_pf[k];
+    }
   }
   if (MODE == 2) {
     const int kper = (m + kStatParts - 1) / kStatParts;
@@ -1463,16 +1543,30 @@ hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m
                         erbf_stats* out, const StatsArgs& a, hipStream_t s) {
   const dim3 parts(kStatParts, D.n_shapes);
   if (mode == 0) {
-    hipLaunchKernelGGL(k_stats_part<0>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL((k_stats_part<0, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
     hipLaunchKernelGGL(k_stats_final<0>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
   } else if (mode == 1) {
-    hipLaunchKernelGGL(k_stats_part<1>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL((k_stats_part<1, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
     hipLaunchKernelGGL(k_stats_final<1>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
   } else {
-    hipLaunchKernelGGL(k_stats_part<2>, parts, dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL((k_stats_part<2, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
     hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
     hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int n_pts, const float* p,
+                             const int32_t* m_dev, float* grad, float* f_out, erbf_stats* out, float tau1, float tau2,
+                             const StatsArgs& a, hipStream_t s) {
+  if (n_pts > 0)
+    hipLaunchKernelGGL(k_batch_forward, dim3(nblk(n_pts, 4)), dim3(256), 0, s, D, pts, n_pts, f_out, tau1, tau2);
+  hipError_t e = launch_backward(D, n_slots, p, D.G, grad, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stats_part<2, true>), dim3(kStatParts, D.n_shapes), dim3(256), 0, s, D, p, m_dev, grad,
+                     n_pts);
+  hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+  hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
   return hipGetLastError();
 }
 

@@ -53,6 +53,9 @@ hipError_t launch_seed_select(const Dev& D, int shape, int64_t npts, const float
 int seed_misc_counts(const Dev& D, int32_t* n_cand, int32_t* n_kept, hipStream_t s);
 hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32_t* m_dev, const float* resid,
                              float scale, float* m1, float* m2, float eps, int w_rule, float h_fine, hipStream_t s);
+hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int n_pts, const float* p,
+                             const int32_t* m_dev, float* grad, float* f_out, erbf_stats* out, float tau1, float tau2,
+                             const StatsArgs& a, hipStream_t s);
 hipError_t launch_sched_init(const Dev& D, const erbf_sched_state& st, const erbf_sched_cfg& a, hipStream_t s);
 hipError_t launch_sched_step(const Dev& D, const float* p_const, float* p, int32_t* m_dev, float* m1, float* m2,
                              const erbf_sched_state& st, const erbf_sched_cfg& a, const erbf_stats* stats,

@@ -59,13 +59,13 @@ class Fitter:
 
     def __init__(self, shapes: List[ShapeInput], cull_k: float = 3.0, weight_map: int = 0,
                  pair_cap: Optional[int] = None, all_levels: bool = True, device: int = 0,
-                 orientation: int = L.ORIENT_QUATERNION):
+                 orientation: int = L.ORIENT_QUATERNION, batch_cap: int = 0):
         self.shapes = shapes
         self.dev = torch.device("cuda", device)
         if pair_cap is None:
             pair_cap = sum(estimate_pair_cap(s.level_ns, s.s_min(), cull_k) for s in shapes)
         self.ctx = core.Context([(s.level_ns, s.cap) for s in shapes], pair_cap, cull_k, weight_map, device,
-                                orientation)
+                                orientation, batch_cap)
         self._levels = []
         # eq. 3-10's m: minimum over every level of a shape, computed on the device
         self.m_sdf = torch.zeros(len(shapes), dtype=torch.float32, device=self.dev)
@@ -181,3 +181,36 @@ class Fitter:
                                 n_pruned=int(st.n_pruned[b].item())))
             log.append(row)
         return st, log
+
+    def training_points(self, b: int) -> np.ndarray:
+        """Indices (into the context's per-point arrays) of shape b's training
+        points: every point of its registered levels inside the level's band."""
+        s = self.shapes[b]
+        out = []
+        for li in range(self.next_level[b]):
+            S = np.asarray(s.sdfs[li], np.float32).reshape(-1)
+            keep = np.abs(S) < np.float32(s.bands[li]) if s.bands[li] is not None else np.ones(S.size, bool)
+            out.append(self.ctx.pt_base[b][li] + np.nonzero(keep)[0])
+        return np.concatenate(out).astype(np.int64)
+
+    def fit_minibatch(self, epochs: int, batch_size: int, seed: int = 0, mode=L.MODE_FIXED, lam=0.0,
+                      lr=1e-3, tau1=0.9, tau2=1.1, tau_m=0.02, l1_active=False, stream=None):
+        """Mini-batch epochs (Algorithm 3's inner loop): each epoch shuffles the
+        training points of every shape (seeded permutation, an input) and
+        takes one loss + gradient + Adam step per batch of `batch_size`
+        points.  Returns the per-batch L2 of shape 0."""
+        if batch_size > self.ctx.batch_cap:
+            raise ValueError("batch_size exceeds the context's batch_cap")
+        pts = np.concatenate([self.training_points(b) for b in range(len(self.shapes))])
+        log = []
+        for ep in range(epochs):
+            perm = np.random.default_rng([seed, ep]).permutation(pts.size)
+            order = torch.from_numpy(pts[perm]).to(self.dev)
+            for i in range(0, pts.size, batch_size):
+                idx = order[i:i + batch_size]
+                self.ctx.erbf_loss_grad_batch(self.p, self.m_dev, idx, mode=mode, lam=lam, l1_active=l1_active,
+                                              tau1=tau1, tau2=tau2, tau_m=tau_m, grad_out=self.grad, stream=stream)
+                self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr=lr,
+                                        stream=stream)
+                log.append(self.ctx.stats()[0].L2)
+        return log

@@ -56,7 +56,7 @@ def pair_cap_estimate(prob, slack=2.0):
 class GpuProblem:
     """A one-shape library context holding `prob`'s levels and parameters."""
 
-    def __init__(self, prob, targets, pair_cap=None, weight_map=None, n_levels=None):
+    def __init__(self, prob, targets, pair_cap=None, weight_map=None, n_levels=None, batch_cap=0):
         import torch
         from paper_2505_02350_amd import core
         self.torch = torch
@@ -65,7 +65,7 @@ class GpuProblem:
         wm = prob.weight_map if weight_map is None else weight_map
         self.ctx = core.Context([([lv.n for lv in prob.levels[:nl]], prob.cap)],
                                 pair_cap or pair_cap_estimate(prob), prob.cull_k, wm,
-                                orientation=prob.orientation)
+                                orientation=prob.orientation, batch_cap=batch_cap)
         dev = self.ctx.device
         self.axes, self.tgts, self.sdfs, self.bits = [], [], [], []
         for li, lv in enumerate(prob.levels[:nl]):

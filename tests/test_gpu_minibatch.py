@@ -1,0 +1,128 @@
+"""Mini-batch steps (Algorithm 3's inner loop over batches of B_s points)
+through the C ABI: parity with the oracle's batch step, additivity over a
+partition of the training points, and mini-batch epochs."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import TAU1, TAU2, GpuProblem, oracle_grads_dict, oracle_levels, record, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _problem(seed):
+    return synth.make_custom(seed, [12, 20], 24, (1.6, 2.6), kinds=("ellipsoid", "torus", "box"),
+                             bands=[None, 0.15])
+
+
+def _training_points(olv):
+    out, base = [], 0
+    for lv in olv:
+        out.append(base + np.nonzero(lv.act())[0])
+        base += lv.npts
+    return np.concatenate(out).astype(np.int64)
+
+
+def _ambiguous(olv, f, idx_mask):
+    n = 0
+    for lv, fo, m in zip(olv, f, idx_mask):
+        near = ((np.abs(fo - TAU1) < 1e-5) & (lv.t <= TAU1)) | ((np.abs(fo - TAU2) < 1e-5) & (lv.t >= TAU2))
+        n += int((near & m).sum())
+    return n
+
+
+@pytest.mark.parametrize("mode", [O.MODE_FIXED, O.MODE_DYNAMIC])
+def test_minibatch_step_matches_oracle(mode):
+    torch = _torch()
+    prob = _problem(61)
+    olv, t32, _ = oracle_levels(prob)
+    pts = _training_points(olv)
+    batch = np.random.default_rng(5).permutation(pts)[: int(0.4 * pts.size)]
+    gp = GpuProblem(prob, t32, batch_cap=batch.size)
+    f = torch.zeros(batch.size, device=gp.ctx.device)
+    kw = dict(mode=mode, lam=1e-4, l1_active=True, tau1=TAU1, tau2=TAU2, tau_m=10.0)
+    g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
+    torch.cuda.synchronize()
+    st = gp.ctx.stats()[0]
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    ref = O.step_batch(olv, K, batch, **kw)
+    assert _ambiguous(olv, ref.f, O.batch_masks(olv, batch)) == 0
+    f_or = np.concatenate(ref.f)[batch]
+    fmax = np.abs(np.concatenate(ref.f)).max()
+    e_f = float(np.abs(f.cpu().numpy() - f_or).max() / fmax)
+    go, gg = oracle_grads_dict(ref.grads), gp.grads_np(g)
+    errs = {k: rel_inf(gg[k], go[k]) for k in go}
+    record(f"minibatch_mode{mode}", e_f=e_f, n_idall=(st.n_idall, ref.loss.n_idall), P_fwd=(st.P_fwd, ref.P_fwd),
+           P_bwd=(st.P_bwd, ref.P_bwd), alpha=(st.alpha, ref.alpha), **errs)
+    assert e_f <= 1e-5
+    assert st.n_idall == ref.loss.n_idall and st.P_fwd == ref.P_fwd and st.P_bwd == ref.P_bwd
+    assert abs(st.L2 - ref.loss.L2) <= 1e-5 * ref.loss.L2 and abs(st.max_abs_E - ref.loss.max_abs_E) <= 1e-5
+    assert abs(st.alpha - ref.alpha) <= 1e-5
+    for k in go:
+        assert errs[k] <= 1e-4, (k, errs[k])
+
+
+def test_minibatch_partition_adds_up_to_the_full_batch():
+    torch = _torch()
+    prob = _problem(62)
+    olv, t32, _ = oracle_levels(prob)
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    full_or = O.step(olv, K, tau1=TAU1, tau2=TAU2)
+    all_mask = [lv.act() for lv in olv]
+    assert _ambiguous(olv, full_or.f, all_mask) == 0
+    pts = _training_points(olv)
+    parts = np.array_split(np.random.default_rng(6).permutation(pts), 3)
+    gp = GpuProblem(prob, t32, batch_cap=max(p.size for p in parts))
+    dev = gp.ctx.device
+    kw = dict(mode=O.MODE_L2, tau1=TAU1, tau2=TAU2)
+    gfull = gp.ctx.erbf_loss_grad(gp.p, gp.m_dev, **kw).clone()
+    torch.cuda.synchronize()
+    sf = gp.ctx.stats()[0]
+    acc = np.zeros(11 * prob.cap)
+    L2 = 0.0
+    cnt = np.zeros(3, np.int64)
+    for part in parts:
+        g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(part).to(dev), **kw)
+        torch.cuda.synchronize()
+        s = gp.ctx.stats()[0]
+        acc += g.cpu().numpy().astype(np.float64)
+        L2 += s.L2
+        cnt += (s.n_idall, s.P_fwd, s.P_bwd)
+    assert tuple(cnt) == (sf.n_idall, sf.P_fwd, sf.P_bwd)
+    assert abs(L2 - sf.L2) <= 1e-6 * sf.L2
+    full = gfull.cpu().numpy().astype(np.float64).reshape(11, prob.cap)
+    acc = acc.reshape(11, prob.cap)
+    for name, rows in (("w", [0]), ("c", [1, 2, 3]), ("s", [4, 5, 6]), ("q", [7, 8, 9, 10])):
+        err = rel_inf(acc[rows], full[rows])
+        record(f"minibatch_partition_{name}", err=err)
+        assert err <= 1e-5, (name, err)
+
+
+def test_minibatch_epochs_reduce_the_loss_and_repeat_bitwise():
+    torch = _torch()
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    prob = synth.make_tiny()
+
+    def run():
+        fit = Fitter([ShapeInput.from_problem(prob)], cull_k=prob.cull_k, batch_cap=10000)
+        log = fit.fit_minibatch(3, 10000, seed=9, mode=O.MODE_FIXED, lam=1e-4, lr=1e-3, tau1=TAU1, tau2=TAU2)
+        g = fit.ctx.erbf_loss_grad(fit.p, fit.m_dev, lam=1e-4, tau1=TAU1, tau2=TAU2)
+        torch.cuda.synchronize()
+        return fit, log, fit.ctx.stats()[0].L2
+
+    fit0 = Fitter([ShapeInput.from_problem(prob)], cull_k=prob.cull_k)
+    fit0.ctx.erbf_loss_grad(fit0.p, fit0.m_dev, lam=1e-4, tau1=TAU1, tau2=TAU2)
+    torch.cuda.synchronize()
+    L2_start = fit0.ctx.stats()[0].L2
+    fit, log, L2_end = run()
+    record("minibatch_epochs", L2_start=L2_start, L2_end=L2_end, batches=len(log))
+    assert len(log) == 3 * 4 and L2_end < L2_start
+    fit2, log2, _ = run()
+    assert torch.equal(fit.p, fit2.p) and log == log2
