@@ -747,3 +747,58 @@ def step_batch(levels: List[OLevel], K: Kernels, batch: np.ndarray, mode: int = 
     bm = batch_masks(levels, batch)
     blv = [OLevel(lv.n, lv.axis, lv.act() & m, lv.t, lv.S) for lv, m in zip(levels, bm)]
     return step(blv, K, mode=mode, lam=lam, l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m)
+
+
+# ---------------------------------------------------------------------------
+# Inscribed-sphere initialisation: Algorithm 1 with eq. 3-11 / eq. 3-12
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class InitOut:
+    index: np.ndarray   # chosen points (indices into the levels' concatenated points)
+    c: np.ndarray       # (M, 3) centres
+    w: np.ndarray       # (M,) weights: the normalised target at the centre
+    r: np.ndarray       # (M,) sphere radii
+    s: np.ndarray       # (M, 3) log axis lengths from eq. 3-12 (isotropic)
+    dhat: np.ndarray    # (M,) distance to the nearest other centre
+    n_left: int         # candidates no sphere covers (non-zero only when m_max stopped the rounds)
+
+
+def inscribed_sphere_init(levels: List[OLevel], gamma: float = 1e-3, m_max: Optional[int] = None) -> InitOut:
+    """Algorithm 1: among the interior points (1 < t < 2, eq. 3-10) of the
+    active points of `levels`, repeatedly take the point farthest from the
+    surface (distance |S|, ties to the lower index) as a centre with weight t,
+    and drop every point within that distance of it; stop when none is left
+    (or after m_max centres).  Squared distances are ((dx^2 + dy^2) + dz^2)
+    in float64, compared with r^2 (the sphere's interior and boundary).  Then eq. 3-12: d = 2 sqrt(-ln(gamma / w^2)) /
+    dhat on all three axes, dhat the distance to the nearest other centre
+    (2, the domain's width, for a single centre), identity rotation."""
+    P, T, R = [], [], []
+    for lv in levels:
+        pts = level_points(lv)
+        keep = lv.act() & (lv.t > 1.0) & (lv.t < 2.0)
+        P.append(np.where(keep[:, None], pts, np.nan))
+        T.append(np.where(keep, lv.t, np.nan))
+        R.append(np.where(keep, np.abs(lv.S), -1.0))
+    P, T, R = np.concatenate(P), np.concatenate(T), np.concatenate(R)
+    alive = R >= 0.0
+    chosen = []
+    while alive.any() and (m_max is None or len(chosen) < m_max):
+        cand = np.flatnonzero(alive)
+        k = int(cand[np.argmax(R[cand])])       # first maximum: the lowest index among ties
+        chosen.append(k)
+        d2 = ((P[cand, 0] - P[k, 0]) ** 2 + (P[cand, 1] - P[k, 1]) ** 2) + (P[cand, 2] - P[k, 2]) ** 2
+        alive[cand[d2 <= R[k] * R[k]]] = False
+    idx = np.asarray(chosen, np.int64)
+    c, w, r = P[idx], T[idx], R[idx]
+    M = idx.size
+    if M > 1:
+        dd = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+        np.fill_diagonal(dd, np.inf)
+        dhat = dd.min(axis=1)
+    else:
+        dhat = np.full(M, 2.0)
+    d = 2.0 * np.sqrt(-np.log(gamma / (w * w))) / dhat
+    s = np.repeat(np.log(d)[:, None], 3, axis=1)
+    return InitOut(idx, c, w, r, s, dhat, int(alive.sum()))

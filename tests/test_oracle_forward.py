@@ -281,3 +281,57 @@ def test_euler_jacobian_matches_differences():
         tm[:, k] -= h
         fd = (O.euler_to_rot(tp) - O.euler_to_rot(tm)) / (2 * h)
         assert np.abs(fd - J[:, k]).max() < 1e-9
+
+
+def _sphere_level(n, radius=0.5):
+    ax = (-1.0 + (2.0 * np.arange(n) + 1.0) / n).astype(np.float32)
+    z, y, x = np.meshgrid(ax.astype(np.float64), ax, ax, indexing="ij")
+    S = (np.sqrt(x * x + y * y + z * z) - radius).astype(np.float32).reshape(-1)
+    m = O.sdf_min([S])
+    t = O.targets_from_sdf(S, m).astype(np.float32)
+    return O.make_level(n, ax, t=t, S=S)
+
+
+def test_inscribed_sphere_init_greedy_properties():
+    lv = _sphere_level(24)
+    out = O.inscribed_sphere_init([lv])
+    pts = O.level_points(lv)
+    interior = (lv.t > 1) & (lv.t < 2)
+    # the first sphere sits where |S| is largest (the grid points nearest the
+    # centre), with the largest target
+    assert out.r[0] == np.abs(lv.S[interior]).max() and out.w[0] == lv.t[out.index[0]]
+    # greedy order: radii do not increase; each centre lies outside every
+    # earlier sphere; every interior point lies inside some sphere
+    assert np.all(np.diff(out.r) <= 0)
+    for a in range(1, out.index.size):
+        d2 = ((out.c[:a] - out.c[a]) ** 2).sum(1)
+        assert np.all(d2 > out.r[:a] ** 2)
+    d2 = ((pts[interior][:, None, :] - out.c[None]) ** 2).sum(-1)
+    assert np.all((d2 <= out.r[None] ** 2).any(axis=1)) and out.n_left == 0
+    # each centre is the deepest candidate (lowest index among equals) that
+    # no earlier sphere covers
+    cand = np.flatnonzero(interior)
+    depth = np.abs(lv.S[cand])
+    for a in range(out.index.size):
+        free = np.ones(cand.size, bool)
+        for q in range(a):
+            free &= ((pts[cand] - out.c[q]) ** 2).sum(1) > out.r[q] ** 2
+        top = depth[free].max()
+        assert out.index[a] == cand[free][depth[free] == top].min()
+    # eq. 3-11 holds at the nearest other centre's half distance
+    d = np.exp(out.s[:, 0])
+    assert np.allclose(out.w ** 2 * np.exp(-(d * out.dhat / 2) ** 2), 1e-3, rtol=1e-12)
+    assert np.all(out.s[:, 0] == out.s[:, 1]) and np.all(out.s[:, 1] == out.s[:, 2])
+
+
+def test_inscribed_sphere_init_cap_and_single_centre():
+    lv = _sphere_level(16)
+    full = O.inscribed_sphere_init([lv])
+    part = O.inscribed_sphere_init([lv], m_max=3)
+    assert np.array_equal(part.index, full.index[:3])
+    pts = O.level_points(lv)
+    interior = (lv.t > 1) & (lv.t < 2)
+    d2 = ((pts[interior][:, None, :] - part.c[None]) ** 2).sum(-1)
+    assert part.n_left == int((~(d2 <= part.r[None] ** 2).any(axis=1)).sum()) > 0
+    one = O.inscribed_sphere_init([lv], m_max=1)
+    assert one.dhat[0] == 2.0 and one.index.size == 1
