@@ -150,6 +150,85 @@ def batching_bench(steps, warmup):
     }
 
 
+def init_bench(reps=3, with_cpu=True):
+    """Inscribed-sphere initialisation (Algorithm 1, eq. 3-11/3-12) of the
+    large workload's shape on its 64^3 starting level, then on 64^3 + 128^3
+    (kernel capacity 16384).  Each call is synchronous; the figure is the
+    median wall time of `reps` calls after one untimed call."""
+    import torch
+    import synth
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    prob = synth.make_large()
+    fit = Fitter([ShapeInput.from_problem(prob)], cull_k=prob.cull_k, all_levels=False)
+    rows = []
+    for nl in (1, 2):
+        fit.refine(0)
+        times = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nc, left = fit.ctx.erbf_init_inscribed(fit.p, fit.m_dev, 0, gamma=1e-3, m1=fit.m1, m2=fit.m2)
+            times.append(time.perf_counter() - t0)
+        ms = 1e3 * float(np.median(times[1:]))
+        interior = int(sum(np.count_nonzero(lv.S < 0) for lv in prob.levels[:nl]))
+        rows.append({"levels": "+".join(f"{lv.n}^3" for lv in prob.levels[:nl]), "points_S_negative": interior,
+                     "centres": nc, "uncovered": left, "ms": ms, "us_per_round": 1e3 * ms / (nc + 1)})
+        log(f"inscribed-sphere init on {rows[-1]['levels']}: {nc} centres, {left} uncovered, {ms:.2f} ms")
+    out = {"workload": "large: shape of seed 2 (12 boxes + 6 capsules + 4 tori), gamma 1e-3, capacity 16384",
+           "runs": rows}
+    if with_cpu:
+        import oracle as O
+        S_all = [lv.S for lv in prob.levels]
+        msdf = O.sdf_min(S_all)
+        lv0 = prob.levels[0]
+        olv = O.make_level(lv0.n, lv0.axis, t=O.targets_from_sdf(lv0.S, msdf).astype(np.float32), S=lv0.S)
+        t0 = time.perf_counter()
+        ref = O.inscribed_sphere_init([olv], gamma=float(np.float32(1e-3)), m_max=prob.cap)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1e3 * cpu_s, "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole 64^3 initialisation ({ref.index.size} centres)"}
+    return out
+
+
+def minibatch_bench(steps, warmup, batch=10000):
+    """Mini-batch steps of Algorithm 3 (B_s = 10000 points per batch, loss +
+    gradient + Adam) on the large snapshot workload, batches drawn from one
+    seeded permutation of its training points."""
+    import torch
+    import synth
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    prob = synth.make_large_snapshot()
+    fit = Fitter([ShapeInput.from_problem(prob)], cull_k=prob.cull_k, all_levels=True, batch_cap=batch)
+    pts = fit.training_points(0)
+    order = torch.from_numpy(pts[np.random.default_rng(0).permutation(pts.size)]).to(fit.dev)
+    nb = pts.size // batch
+
+    def one(i):
+        idx = order[(i % nb) * batch:(i % nb + 1) * batch]
+        fit.ctx.erbf_loss_grad_batch(fit.p, fit.m_dev, idx, mode=L.MODE_DYNAMIC, l1_active=True, grad_out=fit.grad)
+        fit.ctx.erbf_adam_step(fit.p, fit.m_dev, fit.grad, fit.m1, fit.m2, fit.step_dev, lr=prob.lr)
+
+    for i in range(warmup):
+        one(i)
+    torch.cuda.synchronize()
+    fit.ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = fit.stats()[0]
+    ms = 1e3 * wall / steps
+    log(f"mini-batch: {ms:.3f} ms per batch of {batch}")
+    return {"workload": "large_snapshot, batches of 10000 training points (seeded permutation)",
+            "batch": batch, "steps": steps, "ms_per_batch": ms,
+            "pairs_per_s": (st.P_fwd_total + st.P_bwd_total) / wall,
+            "batches_per_epoch": int(-(-pts.size // batch)),
+            "ms_per_epoch": ms * (-(-pts.size // batch))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +238,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--graph", action="store_true", help="also time HIP-graph replays of the step")
     ap.add_argument("--batching", action="store_true", help="add the 64-shape batched-vs-plain comparison")
+    ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
+    ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help=f"copy {COPY_CAL_BYTES} bytes device-to-device before the warm-up (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -293,6 +374,10 @@ def main():
     }
     if args.batching:
         out["batching"] = batching_bench(max(2, min(args.steps, 10)), 2)
+    if args.init:
+        out["init"] = init_bench(with_cpu=not args.no_cpu_baseline)
+    if args.minibatch:
+        out["minibatch"] = minibatch_bench(max(args.steps, 20), args.warmup)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)

@@ -27,7 +27,8 @@
  *  - Calls that take a hipStream_t only enqueue work on that stream; they do
  *    not synchronise and are safe to capture into a hipGraph, except the
  *    calls documented as "synchronous" (erbf_ctx_create,
- *    erbf_refine_level, erbf_seed_from_error, erbf_autotune).
+ *    erbf_refine_level, erbf_seed_from_error, erbf_init_inscribed,
+ *    erbf_autotune).
  *  - A context holds one or more independent shapes (the batched extension);
  *    a plain fit is a context with one shape.  Kernels of all shapes share
  *    one global index space: shape b owns slots [kbase_b, kbase_b + cap_b),
@@ -264,6 +265,28 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
                          const float* resid, float resid_scale, int64_t n_idall,
                          const erbf_seed_cfg* cfg, float* m1, float* m2, int32_t* n_added,
                          hipStream_t stream);
+
+/* Initial kernels of `shape` from maximal inscribed spheres (Algorithm 1,
+ * eq. 3-11, eq. 3-12), replacing its live kernels.  Candidates are the
+ * training points of the shape's registered levels with 1 < target < 2
+ * (eq. 3-10, interior points) and a finite raw SDF.  Each round takes the
+ * candidate of largest |S| (its distance to the surface; ties to the lower
+ * point index, levels in registration order, x fastest) as a centre c with
+ * weight w = its target, and drops every candidate within distance |S| of
+ * it (squared distances in double precision, each product and sum rounded
+ * separately); rounds end when no candidate is left or after
+ * min(max_centres, m_cap) centres (max_centres <= 0: m_cap).  Each centre
+ * then gets d1 = d2 = d3 = 2 sqrt(-ln(gamma / w^2)) / dhat, dhat the distance
+ * to the nearest other centre (2 for a single centre), stored as s = ln d,
+ * and the identity rotation.  The shape's Adam moments in m1/m2 (either may
+ * be NULL) are cleared.  Every registered level needs `target` and `sdf`;
+ * gamma in (0, 1) (paper: 1e-3).  Synchronous; *n_centres receives the
+ * number of kernels (also written to m_dev[shape]) and *n_left the
+ * candidates no sphere covers (non-zero only when the limit stopped the
+ * rounds). */
+int erbf_init_inscribed(erbf_ctx* ctx, const erbf_params* params, int32_t shape, float gamma,
+                        int32_t max_centres, float* m1, float* m2, int32_t* n_centres,
+                        int64_t* n_left, hipStream_t stream);
 
 /* ---- training control (Algorithm 3) -------------------------------------- */
 

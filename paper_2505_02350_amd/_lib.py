@@ -125,6 +125,9 @@ _SIGS = [
     ("erbf_seed_from_error", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, _V, ctypes.c_float,
                                             ctypes.c_int64, ctypes.POINTER(SeedCfg), _V, _V,
                                             ctypes.POINTER(ctypes.c_int32), _V]),
+    ("erbf_init_inscribed", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_float,
+                                           ctypes.c_int32, _V, _V, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int64), _V]),
     ("erbf_sched_init", ctypes.c_int, [_V, ctypes.POINTER(SchedCfg), ctypes.POINTER(SchedState), _V]),
     ("erbf_sched_step", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(SchedCfg),
                                        ctypes.POINTER(SchedState), _V, _V, _V, _V]),

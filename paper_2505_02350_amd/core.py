@@ -215,6 +215,17 @@ class Context:
                                               _ptr(m2), ctypes.byref(n_added), _stream(stream)))
         return n_added.value
 
+    def erbf_init_inscribed(self, p, m_dev, shape, gamma=1e-3, max_centres=0, m1=None, m2=None, stream=None):
+        """Initial kernels of `shape` from inscribed spheres (Algorithm 1,
+        eq. 3-12); returns (centres, candidates left uncovered)."""
+        pr = self._params(p, m_dev)
+        n_c = ctypes.c_int32(0)
+        n_left = ctypes.c_int64(0)
+        L.check(self.lib.erbf_init_inscribed(self.handle, ctypes.byref(pr), int(shape), float(gamma),
+                                             int(max_centres), _ptr(m1), _ptr(m2), ctypes.byref(n_c),
+                                             ctypes.byref(n_left), _stream(stream)))
+        return n_c.value, n_left.value
+
     # ---- training control (Algorithm 3) ----------------------------------------
     def erbf_sched_init(self, cfg, state: "SchedState", stream=None):
         L.check(self.lib.erbf_sched_init(self.handle, ctypes.byref(cfg), ctypes.byref(state.c), _stream(stream)))

@@ -43,6 +43,8 @@ struct Layout {
   int max_level_tiles = 0;
   int64_t pts_total = 0;
   int64_t cand_cap = 0;
+  int64_t init_words = 0;   // candidate mask words of the inscribed-sphere initialisation
+  int64_t init_cand = 0;    // its candidate list capacity: points of the largest shape
   int scan_blocks = 0;
   int radix_nb = 0;
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_kslot, off_sort_keys[2],
@@ -50,7 +52,7 @@ struct Layout {
       off_partials,
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
-      off_b_shape, off_hist, off_cand, off_keep, off_misc;
+      off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init;
   size_t bytes = 0;
 };
 
@@ -150,6 +152,13 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_cand = take(sizeof(int64_t) * L.cand_cap);
   L.off_keep = take(sizeof(int64_t) * L.cand_cap);
   L.off_misc = take(sizeof(int32_t) * 64);
+  L.init_words = L.pts_total / 32 + 1;
+  for (int b = 0; b < cfg->n_shapes; ++b) {
+    int64_t np = 0;
+    for (int l = 0; l < cfg->shapes[b].n_levels; ++l) np += (int64_t)cfg->shapes[b].level_n[l] * cfg->shapes[b].level_n[l] * cfg->shapes[b].level_n[l];
+    L.init_cand = std::max(L.init_cand, np + 1);
+  }
+  L.off_init = take(sizeof(uint32_t) * ((size_t)L.init_words + 2 * (size_t)L.init_cand + 8));
   L.bytes = o;
   return L;
 }
@@ -290,6 +299,9 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.seed_cand = reinterpret_cast<int64_t*>(w + lay.off_cand);
   D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);
   D.seed_misc = reinterpret_cast<int32_t*>(w + lay.off_misc);
+  D.init_scratch = reinterpret_cast<uint32_t*>(w + lay.off_init);
+  D.init_words = lay.init_words;
+  D.init_cand_cap = lay.init_cand;
   D.cand_cap = lay.cand_cap;
   D.pair_cap = cfg->pair_cap;
   D.radix_nb = lay.radix_nb;
@@ -750,6 +762,35 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
           "seed: write");
   HIP_TRY(hipStreamSynchronize(stream), "seed: sync");
   *n_added = n_add;
+  return ERBF_OK;
+}
+
+int erbf_init_inscribed(erbf_ctx* ctx, const erbf_params* params, int32_t shape, float gamma, int32_t max_centres,
+                        float* m1, float* m2, int32_t* n_centres, int64_t* n_left, hipStream_t stream) {
+  int rc = check_params(ctx, params);
+  if (rc) return rc;
+  if (!n_centres || !n_left) return fail(ERBF_ERR_INVALID_ARG, "n_centres and n_left must be non-NULL");
+  *n_centres = 0;
+  *n_left = 0;
+  if (shape < 0 || shape >= ctx->cfg.n_shapes) return fail(ERBF_ERR_INVALID_ARG, "shape out of range");
+  if (!(gamma > 0.f && gamma < 1.f)) return fail(ERBF_ERR_INVALID_ARG, "gamma must be in (0, 1)");
+  const ShapeDev& sd = ctx->sh[shape];
+  if (sd.n_active < 1) return fail(ERBF_ERR_STATE, "shape has no registered level");
+  int64_t npts = 0;
+  for (int l = 0; l < sd.n_active; ++l) {
+    const LevelDev& L = ctx->lv[sd.lvl0 + l];
+    if (!L.sdf || !L.target)
+      return fail(ERBF_ERR_INVALID_ARG, "initialisation needs the targets and the raw SDF of every registered level");
+    npts += (int64_t)L.n * L.n * L.n;
+  }
+  if (npts >= (int64_t)UINT32_MAX) return fail(ERBF_ERR_UNSUPPORTED, "initialisation supports < 2^32 - 1 points per shape");
+  const int m_max = max_centres <= 0 ? sd.cap : std::min(max_centres, sd.cap);
+  DeviceGuard guard(ctx->device);
+  const Dev& D = ctx->D;
+  HIP_TRY(launch_init_inscribed(D, shape, (uint32_t)npts, m_max, sd.cap, gamma, params->p, params->m_dev, m1, m2,
+                                stream),
+          "init: launch");
+  if (init_results(D, n_centres, n_left, stream) != 0) return fail(ERBF_ERR_HIP, "init: reading counts");
   return ERBF_OK;
 }
 

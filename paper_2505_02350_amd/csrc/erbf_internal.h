@@ -104,6 +104,11 @@ struct Dev {
   int64_t* seed_cand;       // [cand_cap]
   int64_t* seed_keep;       // [cand_cap]
   int32_t* seed_misc;       // [64]
+  // inscribed-sphere initialisation scratch: candidate mask (init_words),
+  // two candidate lists (init_cand_cap each) and 8 result words
+  uint32_t* init_scratch;   // [init_words + 2 * init_cand_cap + 8]
+  int64_t init_words;       // pts_total / 32 + 1
+  int64_t init_cand_cap;    // points of the largest shape (all its levels)
   int64_t cand_cap;
   int64_t pair_cap;
   int32_t cap_total;
