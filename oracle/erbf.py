@@ -94,6 +94,21 @@ def band_mask(S: np.ndarray, band: float) -> np.ndarray:
     return np.abs(np.asarray(S, dtype=np.float64)) < band
 
 
+def octree_mask(S_parent: np.ndarray, n_parent: int, parent_active: Optional[np.ndarray] = None) -> np.ndarray:
+    """Points of the octree layer below a level (eq. 3-16's G^i on an octree,
+    read on cell-centred grids): level 2n's points are the centres of the
+    eight children of each level-n cell that is subdivided.  A cell is
+    subdivided when it exists (its centre is an active point of level n) and
+    may meet the surface: |S(centre)| <= sqrt(3)/n, the half-diagonal of a
+    cell of width 2/n (a signed distance changes by at most the distance
+    moved).  Returns the (2n)^3 mask, x fastest."""
+    n = int(n_parent)
+    sub = np.abs(np.asarray(S_parent, np.float64).reshape(n, n, n)) <= math.sqrt(3.0) / n
+    if parent_active is not None:
+        sub &= np.asarray(parent_active, bool).reshape(n, n, n)
+    return sub.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2).reshape(-1)
+
+
 # ---------------------------------------------------------------------------
 # Per-kernel quantities (eq. 3-7, eq. 3-26, eq. 3-15)
 # ---------------------------------------------------------------------------

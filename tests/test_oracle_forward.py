@@ -335,3 +335,44 @@ def test_inscribed_sphere_init_cap_and_single_centre():
     assert part.n_left == int((~(d2 <= part.r[None] ** 2).any(axis=1)).sum()) > 0
     one = O.inscribed_sphere_init([lv], m_max=1)
     assert one.dhat[0] == 2.0 and one.index.size == 1
+
+
+def _plane_level(n, x0):
+    ax = (-1.0 + (2.0 * np.arange(n) + 1.0) / n).astype(np.float32)
+    z, y, x = np.meshgrid(ax.astype(np.float64), ax, ax, indexing="ij")
+    return ax, (x - x0).astype(np.float32).reshape(-1)
+
+
+def test_octree_mask_plane_count():
+    # plane x = 0.1 on an 8^3 level: cell centres -0.875 ... 0.875 in steps of
+    # 0.25; only x = 0.125 lies within sqrt(3)/8 = 0.2165 of the plane
+    # (-0.125 is 0.225 away), so one slab of 64 parent cells is subdivided:
+    # 512 children, in the two child x-slices 8 and 9 of 16
+    _, S = _plane_level(8, 0.1)
+    m = O.octree_mask(S, 8).reshape(16, 16, 16)
+    assert m.sum() == 512
+    assert np.all(m[:, :, 8:10]) and not m[:, :, :8].any() and not m[:, :, 10:].any()
+
+
+def test_octree_mask_covers_the_surface_and_nests():
+    # exact sphere distance: every cell of any depth that can meet the surface
+    # (|S(centre)| <= its half-diagonal) is present, and a child is present
+    # only under a present parent
+    n0 = 6
+    prev = None
+    S_prev = _sphere_level(n0, 0.55).S
+    for depth in range(3):
+        n = n0 * 2 ** depth
+        child = O.octree_mask(S_prev, n, prev)
+        lv = _sphere_level(2 * n, 0.55)
+        meets = np.abs(lv.S) <= np.sqrt(3.0) / (2 * n)
+        if depth == 0:
+            assert np.all(child[meets])
+        else:
+            # under the recursion a cell is present iff every ancestor may
+            # meet the surface; cells meeting it have such ancestors
+            assert np.all(child[meets])
+            par = prev.reshape(n, n, n).repeat(2, 0).repeat(2, 1).repeat(2, 2).reshape(-1)
+            assert not np.any(child & ~par)
+        assert child.sum() < child.size
+        prev, S_prev = child, lv.S
