@@ -208,6 +208,19 @@ int erbf_targets_from_sdf(const float* S, int64_t n, float m, float* t, hipStrea
  * ceil(n/32) words; trailing bits are 0. */
 int erbf_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t stream);
 
+/* The octree layer below a level (eq. 3-16 on an octree, Section 3.4.2):
+ * the training points of the level with 2 n_parent points per axis that are
+ * the children of subdivided cells of the level with n_parent points per
+ * axis.  A parent cell (width 2/n_parent, centred on its grid point) is
+ * subdivided when it is present (its bit in parent_bits; every cell when
+ * parent_bits is NULL) and |S_parent| <= sqrt(3)/n_parent, its
+ * half-diagonal, compared in double.  S_parent: device [n_parent^3] raw
+ * signed distance, x fastest; child_bits: device [ceil((2 n_parent)^3/32)]
+ * words in erbf_level.active_bits form (trailing bits 0).  n_parent in
+ * 1 .. 1024. */
+int erbf_octree_bits(const float* S_parent, const uint32_t* parent_bits, int32_t n_parent,
+                     uint32_t* child_bits, hipStream_t stream);
+
 /* ---- the step ------------------------------------------------------------ */
 
 /* Append the next level of `shape` (eq. 3-16 / Algorithm 3: training starts

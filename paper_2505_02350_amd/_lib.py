@@ -109,6 +109,7 @@ _SIGS = [
     ("erbf_sdf_min", ctypes.c_int, [_V, ctypes.c_int64, _V, ctypes.c_int, _V]),
     ("erbf_targets_from_sdf", ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_float, _V, _V]),
     ("erbf_band_bits", ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_float, _V, _V]),
+    ("erbf_octree_bits", ctypes.c_int, [_V, _V, ctypes.c_int32, _V, _V]),
     ("erbf_refine_level", ctypes.c_int, [_V, ctypes.c_int32, ctypes.POINTER(Level), _V]),
     ("erbf_eval", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V]),
     ("erbf_loss_grad", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, _V, _V, _V, _V]),

@@ -296,6 +296,18 @@ def erbf_band_bits(S: torch.Tensor, band: float, bits: torch.Tensor = None, stre
     return bits
 
 
+def erbf_octree_bits(S_parent: torch.Tensor, n_parent: int, parent_bits: torch.Tensor = None,
+                     bits: torch.Tensor = None, stream=None):
+    """Active bits of the octree layer (2 n_parent points per axis) below a
+    level of n_parent points per axis."""
+    nc = 2 * int(n_parent)
+    if bits is None:
+        bits = torch.empty((nc ** 3 + 31) // 32, dtype=torch.int32, device=S_parent.device)
+    L.check(L.load().erbf_octree_bits(_ptr(S_parent), _ptr(parent_bits), int(n_parent), _ptr(bits),
+                                      _stream(stream)))
+    return bits
+
+
 def sched_cfg(k_l2=10, tau_l2=0.5, k_l1=50, tau_l1=5.0, tau_d=0.01, T_e=1600, M_e=2000, lr0=0.01,
               lr_final=1e-3, lr_min=1e-5, refine_epochs=(400, 800)):
     """Algorithm 3's constants (defaults: the paper's values)."""

@@ -397,6 +397,14 @@ int erbf_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStr
   return ERBF_OK;
 }
 
+int erbf_octree_bits(const float* S_parent, const uint32_t* parent_bits, int32_t n_parent, uint32_t* child_bits,
+                     hipStream_t stream) {
+  if (!S_parent || !child_bits || n_parent < 1 || n_parent > 1024)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_octree_bits: bad arguments");
+  HIP_TRY(launch_octree_bits(S_parent, parent_bits, n_parent, child_bits, stream), "erbf_octree_bits");
+  return ERBF_OK;
+}
+
 int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hipStream_t stream) {
   if (!ctx || !level) return fail(ERBF_ERR_INVALID_ARG, "ctx and level must be non-NULL");
   if (shape < 0 || shape >= ctx->cfg.n_shapes) return fail(ERBF_ERR_INVALID_ARG, "shape out of range");

@@ -1358,6 +1358,28 @@ __global__ __launch_bounds__(256) void k_band_bits(const float* __restrict__ S, 
   }
 }
 
+// octree layer below a level of np points per axis: child point (i, j, k)
+// of the 2np level is kept iff its parent cell (i/2, j/2, k/2) is present
+// (parent bit, or every cell when pbits is null) and |S(parent)| <= thr
+__global__ __launch_bounds__(256) void k_octree_bits(const float* __restrict__ Sp, const uint32_t* __restrict__ pbits,
+                                                     int np, double thr, uint32_t* __restrict__ bits) {
+  const int nc = 2 * np;
+  const int64_t n = (int64_t)nc * nc * nc;
+  const int64_t nw = (n + 31) >> 5;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int64_t g = w * 32 + b;
+      if (g >= n) break;
+      const int i = (int)(g % nc), j = (int)((g / nc) % nc), k = (int)(g / ((int64_t)nc * nc));
+      const int64_t pg = ((int64_t)(k >> 1) * np + (j >> 1)) * np + (i >> 1);
+      const bool present = !pbits || ((pbits[pg >> 5] >> (pg & 31)) & 1u);
+      if (present && (double)fabsf(Sp[pg]) <= thr) v |= 1u << b;
+    }
+    bits[w] = v;
+  }
+}
+
 // order-preserving float -> int key
 __device__ __forceinline__ int fkey(float f) {
   const int i = __float_as_int(f);
@@ -1602,6 +1624,15 @@ hipError_t launch_targets(const float* S, int64_t n, float m, float* t, hipStrea
 
 hipError_t launch_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t s) {
   hipLaunchKernelGGL(k_band_bits, dim3(gridstride((n + 31) / 32)), dim3(256), 0, s, S, n, band, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_octree_bits(const float* Sp, const uint32_t* pbits, int np, uint32_t* bits, hipStream_t s) {
+  const int64_t nc = 2 * (int64_t)np;
+  // half-diagonal of a parent cell (width 2/np), in double
+  const double thr = std::sqrt(3.0) / (double)np;
+  hipLaunchKernelGGL(k_octree_bits, dim3(gridstride((nc * nc * nc + 31) / 32)), dim3(256), 0, s, Sp, pbits, np, thr,
+                     bits);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_targets(const float* S, int64_t n, float m, float* t, hipStream_t s);
 hipError_t launch_band_bits(const float* S, int64_t n, float band, uint32_t* bits, hipStream_t s);
+hipError_t launch_octree_bits(const float* Sp, const uint32_t* pbits, int np, uint32_t* bits, hipStream_t s);
 hipError_t launch_sdf_min(const float* S, int64_t n, float* out, int accumulate, int* key_scratch,
                           hipStream_t s);
 hipError_t launch_tile_flags(const Dev& D, int li, int ntt, int32_t* flags, hipStream_t s);

@@ -31,13 +31,15 @@ def estimate_pair_cap(level_ns: Sequence[int], s_min: np.ndarray, cull_k: float,
 
 
 class ShapeInput:
-    """Host inputs of one shape: level resolutions, axes, raw SDFs, bands."""
+    """Host inputs of one shape: level resolutions, axes, raw SDFs, bands, and
+    which levels are octree layers below the previous one."""
 
-    def __init__(self, level_ns, axes, sdfs, bands, params, m, cap):
+    def __init__(self, level_ns, axes, sdfs, bands, params, m, cap, octree=None):
         self.level_ns = list(level_ns)
         self.axes = list(axes)
         self.sdfs = list(sdfs)
         self.bands = list(bands)
+        self.octree = list(octree) if octree is not None else [False] * len(self.level_ns)
         self.params = np.asarray(params, np.float32)
         self.m = int(m)
         self.cap = int(cap)
@@ -46,7 +48,7 @@ class ShapeInput:
     def from_problem(cls, prob):
         return cls([lv.n for lv in prob.levels], [lv.axis for lv in prob.levels],
                    [lv.S for lv in prob.levels], [lv.band for lv in prob.levels], prob.params, prob.m,
-                   prob.cap)
+                   prob.cap, [lv.octree for lv in prob.levels])
 
     def s_min(self):
         seg = self.params.reshape(11, self.cap)[:, :self.m]
@@ -79,6 +81,7 @@ class Fitter:
             self.S_dev.append(row)
         m_host = self.m_sdf.cpu().numpy()
         self.next_level = [0] * len(shapes)
+        self._bits = [[] for _ in shapes]
         self._m_host = m_host
         if all_levels:
             for b, s in enumerate(shapes):
@@ -104,7 +107,11 @@ class Fitter:
         Sd = self.S_dev[b][li]
         ax = torch.from_numpy(np.ascontiguousarray(s.axes[li], np.float32)).to(self.dev)
         t = core.erbf_targets_from_sdf(Sd, float(self._m_host[b]))
-        bits = core.erbf_band_bits(Sd, s.bands[li]) if s.bands[li] is not None else None
+        if s.octree[li]:
+            bits = core.erbf_octree_bits(self.S_dev[b][li - 1], s.level_ns[li - 1], self._bits[b][li - 1])
+        else:
+            bits = core.erbf_band_bits(Sd, s.bands[li]) if s.bands[li] is not None else None
+        self._bits[b].append(bits)
         self._levels.append((ax, t, bits))
         self.ctx.erbf_refine_level(b, ax, t, Sd, bits)
         self.next_level[b] += 1
@@ -189,7 +196,11 @@ class Fitter:
         out = []
         for li in range(self.next_level[b]):
             S = np.asarray(s.sdfs[li], np.float32).reshape(-1)
-            keep = np.abs(S) < np.float32(s.bands[li]) if s.bands[li] is not None else np.ones(S.size, bool)
+            if self._bits[b][li] is not None:
+                words = self._bits[b][li].cpu().numpy().view(np.uint32)
+                keep = np.unpackbits(words.view(np.uint8), bitorder="little")[:S.size].astype(bool)
+            else:
+                keep = np.ones(S.size, bool)
             out.append(self.ctx.pt_base[b][li] + np.nonzero(keep)[0])
         return np.concatenate(out).astype(np.int64)
 

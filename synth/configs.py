@@ -39,12 +39,16 @@ class LevelData:
     axis: np.ndarray            # float32 (n,)
     S: np.ndarray               # float32 (n^3,) raw signed distance, x fastest
     band: Optional[float] = None  # training points restricted to |S| < band
+    octree: bool = False        # training points: the octree layer below the previous level
 
     @property
     def npts(self) -> int:
         return self.n ** 3
 
     def active_mask(self) -> Optional[np.ndarray]:
+        if self.octree:
+            raise ValueError("an octree level's points follow from its parent level; the library and the "
+                             "oracle each build them")
         if self.band is None:
             return None
         return np.abs(self.S.astype(np.float64)) < self.band
@@ -93,11 +97,14 @@ def _large_shape(rng):
     return random_shape(["box"] * 12 + ["capsule"] * 6 + ["torus"] * 4, rng)
 
 
-def _levels(prims, ns, bands):
+def _levels(prims, ns, bands, octree=None):
     out = []
-    for n, b in zip(ns, bands):
+    octree = octree or [False] * len(ns)
+    for li, (n, b, o) in enumerate(zip(ns, bands, octree)):
+        if o and (li == 0 or ns[li - 1] * 2 != n or b is not None):
+            raise ValueError("an octree level doubles the previous level and has no band")
         ax = axis_coords(n)
-        out.append(LevelData(n, ax, sample_sdf(prims, ax), b))
+        out.append(LevelData(n, ax, sample_sdf(prims, ax), b, bool(o)))
     return out
 
 
@@ -105,7 +112,7 @@ def _union_points(levels):
     pts, sd = [], []
     for lv in levels:
         p = grid_points(lv.axis)
-        act = lv.active_mask()
+        act = None if lv.octree else lv.active_mask()
         if act is not None:
             p, s_ = p[act], lv.S[act]
         else:
@@ -173,12 +180,12 @@ def make_diff(seed: int = 4, n: int = 512, m: int = 65536) -> Problem:
 
 def make_custom(seed: int, ns, m: int, log_scale_range, kinds=("ellipsoid",) * 4,
                 bands=None, cap: int = None, cull_k: float = 3.0, weight_map: int = 0,
-                center_band: float = 0.05, orientation: int = 0) -> Problem:
+                center_band: float = 0.05, orientation: int = 0, octree=None) -> Problem:
     """Small problems for tests: any level list, any kernel count."""
     rng = _rng(seed)
     prims = random_shape(list(kinds), rng)
     bands = bands or [None] * len(ns)
-    levels = _levels(prims, ns, bands)
+    levels = _levels(prims, ns, bands, octree)
     pts, sd = _union_points(levels)
     band = center_band
     while np.count_nonzero(np.abs(sd) < band) < m:

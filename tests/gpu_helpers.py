@@ -33,10 +33,15 @@ def oracle_levels(prob, with_targets=True):
     S_all = [lv.S for lv in prob.levels]
     m = O.sdf_min(S_all)
     out, t32 = [], []
-    for lv in prob.levels:
+    for li, lv in enumerate(prob.levels):
         t = O.targets_from_sdf(lv.S, m).astype(np.float32) if with_targets else None
         t32.append(t)
-        out.append(O.make_level(lv.n, lv.axis, active=lv.active_mask(), t=t, S=lv.S))
+        if lv.octree:
+            par = prob.levels[li - 1]
+            act = O.octree_mask(par.S, par.n, out[-1].active)
+        else:
+            act = lv.active_mask()
+        out.append(O.make_level(lv.n, lv.axis, active=act, t=t, S=lv.S))
     return out, t32, m
 
 
@@ -72,7 +77,10 @@ class GpuProblem:
             ax = torch.from_numpy(np.asarray(lv.axis, np.float32)).to(dev)
             S = torch.from_numpy(np.asarray(lv.S, np.float32)).to(dev)
             t = None if targets is None or targets[li] is None else torch.from_numpy(targets[li]).to(dev)
-            bits = core.erbf_band_bits(S, lv.band) if lv.band is not None else None
+            if lv.octree:
+                bits = core.erbf_octree_bits(self.sdfs[li - 1], prob.levels[li - 1].n, self.bits[li - 1])
+            else:
+                bits = core.erbf_band_bits(S, lv.band) if lv.band is not None else None
             self.axes.append(ax)
             self.tgts.append(t)
             self.sdfs.append(S)
