@@ -61,11 +61,61 @@ def make_level(n, axis, active=None, t=None, S=None) -> OLevel:
     return OLevel(int(n), np.asarray(axis, dtype=np.float64), act, f64(t), f64(S))
 
 
-def level_points(lv: OLevel) -> np.ndarray:
-    """(n^3, 3) coordinates, x fastest."""
+def level_points(lv) -> np.ndarray:
+    """(n^3, 3) coordinates, x fastest (the sample slots of a sample set)."""
+    if isinstance(lv, OSamples):
+        out = np.full((lv.cap, 3), np.nan)
+        out[:lv.pts.shape[0]] = lv.pts
+        return out
     a = lv.axis
     z, y, x = np.meshgrid(a, a, a, indexing="ij")
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+@dataclass
+class OSamples:
+    """Surface samples P with label 1 (eq. 3-10 gives 1 on the surface; the
+    training set of Section 3.4.2 is V = {G, P}).  `cap` index slots, the
+    first K = len(pts) hold the samples (float64 copies of float32
+    coordinates); `active` optionally restricts them (a mini-batch)."""
+    pts: np.ndarray
+    cap: int
+    active: Optional[np.ndarray] = None
+
+    @property
+    def npts(self):
+        return self.cap
+
+    @property
+    def t(self):
+        return np.ones(self.cap)
+
+    def act(self):
+        if self.active is not None:
+            return self.active
+        m = np.zeros(self.cap, bool)
+        m[:self.pts.shape[0]] = True
+        return m
+
+
+def make_samples(pts, cap=None, active=None) -> OSamples:
+    p = np.asarray(pts, np.float64).reshape(-1, 3)
+    return OSamples(p, p.shape[0] if cap is None else int(cap),
+                    None if active is None else np.asarray(active, bool).reshape(-1))
+
+
+def _sample_pairs(P: OSamples, K, j: int, radius2: Optional[float]):
+    """Indices of kernel j's candidate samples (those in the ball's bounding
+    box, or all) and their offsets from the centre."""
+    x = P.pts
+    if radius2 is None:
+        idx = np.arange(x.shape[0])
+    else:
+        r = math.sqrt(radius2)
+        inbox = np.all(np.abs(x - K.c[j][None, :]) <= r * (1 + 1e-9) + 1e-12, axis=1)
+        idx = np.flatnonzero(inbox)
+    d = x[idx] - K.c[j][None, :]
+    return idx, d[:, 0], d[:, 1], d[:, 2]
 
 
 # ---------------------------------------------------------------------------
@@ -292,6 +342,19 @@ def forward(levels: List[OLevel], K: Kernels, culled: bool = True,
     multiplies individual kernels' cull radii (used for finite differences)."""
     out = []
     for lv in levels:
+        if isinstance(lv, OSamples):
+            f = np.zeros(lv.cap)
+            for j in range(K.m):
+                r2 = None
+                if culled:
+                    r2 = K.r2[j] * (1.0 if radius_scale is None else radius_scale[j] ** 2)
+                idx, dx, dy, dz = _sample_pairs(lv, K, j, r2)
+                phi, _ = _phi_and_u(K, j, dx, dy, dz)
+                if r2 is not None:
+                    phi = np.where(dx * dx + dy * dy + dz * dz < r2, phi, 0.0)
+                f[idx] += K.a[j] * phi
+            out.append(np.where(lv.act(), f, 0.0))
+            continue
         f = np.zeros((lv.n, lv.n, lv.n))
         for j in range(K.m):
             r2 = None
@@ -368,6 +431,14 @@ def truncation_bound(levels: List[OLevel], K: Kernels) -> List[np.ndarray]:
     |a_j| exp(-d_min,j^2 ||Delta||^2), which dominates each dropped term."""
     out = []
     for lv in levels:
+        if isinstance(lv, OSamples):
+            b = np.zeros(lv.cap)
+            for j in range(K.m):
+                idx, dx, dy, dz = _sample_pairs(lv, K, j, None)
+                dist2 = dx * dx + dy * dy + dz * dz
+                b[idx] += np.where(dist2 < K.r2[j], 0.0, abs(K.a[j]) * np.exp(-K.d[j].min() ** 2 * dist2))
+            out.append(b)
+            continue
         b = np.zeros((lv.n, lv.n, lv.n))
         for j in range(K.m):
             (z0, z1, y0, y1, x0, x1), dx, dy, dz = _kernel_box(lv, K, j, None)
@@ -384,6 +455,19 @@ def boundary_allowance(levels: List[OLevel], K: Kernels, rel: float = 2.0 ** -20
     Returns per-level arrays of sum |a_j| Phi over such pairs, and the count."""
     out, count = [], 0
     for lv in levels:
+        if isinstance(lv, OSamples):
+            b = np.zeros(lv.cap)
+            act = lv.act()
+            for j in range(K.m):
+                idx, dx, dy, dz = _sample_pairs(lv, K, j, K.r2[j] * (1 + 4 * rel))
+                dist2 = dx * dx + dy * dy + dz * dz
+                amb = (np.abs(dist2 - K.r2[j]) <= rel * K.r2[j]) & act[idx]
+                if amb.any():
+                    phi, _ = _phi_and_u(K, j, dx, dy, dz)
+                    b[idx] += np.where(amb, abs(K.a[j]) * phi, 0.0)
+                    count += int(amb.sum())
+            out.append(b)
+            continue
         b = np.zeros((lv.n, lv.n, lv.n))
         for j in range(K.m):
             (z0, z1, y0, y1, x0, x1), dx, dy, dz = _kernel_box(lv, K, j, K.r2[j] * (1 + 4 * rel))
@@ -403,6 +487,16 @@ def pair_counts(levels: List[OLevel], K: Kernels, G: Optional[List[np.ndarray]] 
     """P_fwd: in-ball pairs at active points; P_bwd: those with G != 0."""
     pf = pb = 0
     for li, lv in enumerate(levels):
+        if isinstance(lv, OSamples):
+            act = lv.act()
+            g1 = None if G is None else np.asarray(G[li])
+            for j in range(K.m):
+                idx, dx, dy, dz = _sample_pairs(lv, K, j, K.r2[j])
+                inb = (dx * dx + dy * dy + dz * dz < K.r2[j]) & act[idx]
+                pf += int(inb.sum())
+                if g1 is not None:
+                    pb += int((inb & (g1[idx] != 0)).sum())
+            continue
         act = lv.act().reshape(lv.n, lv.n, lv.n)
         g3 = None if G is None else G[li].reshape(lv.n, lv.n, lv.n)
         for j in range(K.m):
@@ -500,16 +594,22 @@ def backward(levels: List[OLevel], K: Kernels, G: List[np.ndarray],
     Su2 = np.zeros((m, 3))
     SuD = np.zeros((m, 3, 3))
     for lv, g in zip(levels, G):
-        g3 = np.asarray(g, np.float64).reshape(lv.n, lv.n, lv.n)
+        samples = isinstance(lv, OSamples)
+        g3 = np.asarray(g, np.float64) if samples else np.asarray(g, np.float64).reshape(lv.n, lv.n, lv.n)
         for j in range(m):
             r2 = None
             if culled:
                 r2 = K.r2[j] * (1.0 if radius_scale is None else radius_scale[j] ** 2)
-            (z0, z1, y0, y1, x0, x1), dx, dy, dz = _kernel_box(lv, K, j, r2)
+            if samples:
+                idx, dx, dy, dz = _sample_pairs(lv, K, j, r2)
+                gsel = g3[idx]
+            else:
+                (z0, z1, y0, y1, x0, x1), dx, dy, dz = _kernel_box(lv, K, j, r2)
+                gsel = g3[z0:z1, y0:y1, x0:x1]
             phi, u = _phi_and_u(K, j, dx, dy, dz)
             if r2 is not None:
                 phi = np.where(dx * dx + dy * dy + dz * dz < r2, phi, 0.0)
-            gp = g3[z0:z1, y0:y1, x0:x1] * phi
+            gp = gsel * phi
             if not gp.any():
                 continue
             delta = (dx, dy, dz)
@@ -760,7 +860,8 @@ def step_batch(levels: List[OLevel], K: Kernels, batch: np.ndarray, mode: int = 
     batch's points only (id_all, L2, max|E| and eq. 3-21 taken on the batch),
     with the batch a set of indices into the concatenated points."""
     bm = batch_masks(levels, batch)
-    blv = [OLevel(lv.n, lv.axis, lv.act() & m, lv.t, lv.S) for lv, m in zip(levels, bm)]
+    blv = [OSamples(lv.pts, lv.cap, lv.act() & m) if isinstance(lv, OSamples) else
+           OLevel(lv.n, lv.axis, lv.act() & m, lv.t, lv.S) for lv, m in zip(levels, bm)]
     return step(blv, K, mode=mode, lam=lam, l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m)
 
 
@@ -780,33 +881,56 @@ class InitOut:
     n_left: int         # candidates no sphere covers (non-zero only when m_max stopped the rounds)
 
 
-def inscribed_sphere_init(levels: List[OLevel], gamma: float = 1e-3, m_max: Optional[int] = None) -> InitOut:
+def inscribed_sphere_init(levels, gamma: float = 1e-3, m_max: Optional[int] = None) -> InitOut:
     """Algorithm 1: among the interior points (1 < t < 2, eq. 3-10) of the
-    active points of `levels`, repeatedly take the point farthest from the
-    surface (distance |S|, ties to the lower index) as a centre with weight t,
-    and drop every point within that distance of it; stop when none is left
-    (or after m_max centres).  Squared distances are ((dx^2 + dy^2) + dz^2)
-    in float64, compared with r^2 (the sphere's interior and boundary).  Then eq. 3-12: d = 2 sqrt(-ln(gamma / w^2)) /
-    dhat on all three axes, dhat the distance to the nearest other centre
-    (2, the domain's width, for a single centre), identity rotation."""
-    P, T, R = [], [], []
+    active points of the grid levels in `levels`, repeatedly take the point
+    farthest from the surface as a centre with weight t, and drop every point
+    within that distance of it; stop when none is left (or after m_max
+    centres).  The distance to the surface is the distance to the nearest
+    surface sample when `levels` holds sample sets (OSamples), else |S|.
+    Squared distances are ((dx^2 + dy^2) + dz^2) in float64, compared with
+    r^2 (the sphere's interior and boundary).  With samples, r^2 is that
+    minimum squared distance and the order of depth uses it rounded to
+    float32 (ties to the lower index); without, the order uses |S|.  Then
+    eq. 3-12: d = 2 sqrt(-ln(gamma / w^2)) / dhat on all three axes, dhat the
+    distance to the nearest other centre (2, the domain's width, for a single
+    centre), identity rotation."""
+    samples = [lv for lv in levels if isinstance(lv, OSamples)]
+    SP = np.concatenate([lv.pts[lv.act()[:lv.pts.shape[0]]] for lv in samples]) if samples else None
+    P, T, R2, KEY = [], [], [], []
     for lv in levels:
+        if isinstance(lv, OSamples):
+            P.append(np.full((lv.cap, 3), np.nan))
+            T.append(np.full(lv.cap, np.nan))
+            R2.append(np.full(lv.cap, -1.0))
+            KEY.append(np.full(lv.cap, -1.0))
+            continue
         pts = level_points(lv)
         keep = lv.act() & (lv.t > 1.0) & (lv.t < 2.0)
         P.append(np.where(keep[:, None], pts, np.nan))
         T.append(np.where(keep, lv.t, np.nan))
-        R.append(np.where(keep, np.abs(lv.S), -1.0))
-    P, T, R = np.concatenate(P), np.concatenate(T), np.concatenate(R)
-    alive = R >= 0.0
+        if SP is None:
+            r = np.abs(lv.S)
+            R2.append(np.where(keep, r * r, -1.0))
+            KEY.append(np.where(keep, r, -1.0))
+        else:
+            r2 = np.full(lv.npts, -1.0)
+            for i in np.flatnonzero(keep):
+                d = SP - pts[i][None, :]
+                r2[i] = (((d[:, 0] * d[:, 0]) + (d[:, 1] * d[:, 1])) + (d[:, 2] * d[:, 2])).min()
+            R2.append(r2)
+            KEY.append(np.where(keep, r2.astype(np.float32).astype(np.float64), -1.0))
+    P, T, R2, KEY = np.concatenate(P), np.concatenate(T), np.concatenate(R2), np.concatenate(KEY)
+    alive = KEY >= 0.0
     chosen = []
     while alive.any() and (m_max is None or len(chosen) < m_max):
         cand = np.flatnonzero(alive)
-        k = int(cand[np.argmax(R[cand])])       # first maximum: the lowest index among ties
+        k = int(cand[np.argmax(KEY[cand])])     # first maximum: the lowest index among ties
         chosen.append(k)
         d2 = ((P[cand, 0] - P[k, 0]) ** 2 + (P[cand, 1] - P[k, 1]) ** 2) + (P[cand, 2] - P[k, 2]) ** 2
-        alive[cand[d2 <= R[k] * R[k]]] = False
+        alive[cand[d2 <= R2[k]]] = False
     idx = np.asarray(chosen, np.int64)
-    c, w, r = P[idx], T[idx], R[idx]
+    c, w, r = P[idx], T[idx], np.sqrt(R2[idx])
     M = idx.size
     if M > 1:
         dd = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(-1))
