@@ -38,10 +38,14 @@
  *    each segment cap_total floats long; the live kernels of shape b are
  *    slots kbase_b .. kbase_b + m_b - 1, m_b = m_dev[b].  Slots past m_b are
  *    ignored and their gradients written as 0.
- *  - Grid points: every level of every shape is a uniform cell-centred grid
- *    of n^3 points (axis table given by the caller, x fastest:
- *    idx = (k n + j) n + i).  Per-point arrays of a call (targets, f, G) are
- *    the concatenation over shapes (outer) and their active levels (inner).
+ *  - Grid points: every grid level of every shape is a uniform cell-centred
+ *    grid of n^3 points (axis table given by the caller, x fastest:
+ *    idx = (k n + j) n + i).  A sample level instead holds up to
+ *    level_samples surface samples P (label 1; the training set of Section
+ *    3.4.2 is V = {G, P}) in that many index slots, in the caller's order.
+ *    Per-point arrays of a call (targets, f, G) are the concatenation over
+ *    shapes (outer) and their declared levels (inner), n^3 or level_samples
+ *    entries each.
  *  - Every call returns ERBF_OK or a negative error code; erbf_last_error()
  *    returns a thread-local message for the last failure.  No exception
  *    crosses the ABI.  Device-side conditions that cannot be returned
@@ -59,7 +63,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 2
+#define ERBF_ABI_VERSION 3
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -90,12 +94,16 @@ enum {
 
 typedef struct erbf_ctx erbf_ctx;
 
-/* One shape: its grid levels (coarse to fine, appended by erbf_refine_level
- * in this order) and its kernel capacity. */
+/* One shape: its levels (appended by erbf_refine_level in this order) and
+ * its kernel capacity.  A level is a grid level (level_samples 0) or a
+ * surface-sample level (level_samples > 0: up to that many samples, binned
+ * for the kernel lists into the 8^3-cell tiles of a grid of level_n cells
+ * per axis; about 256 samples per occupied tile suits the kernels). */
 typedef struct {
   int32_t n_levels;                  /* 1 .. ERBF_MAX_LEVELS */
-  int32_t level_n[ERBF_MAX_LEVELS];  /* points per axis of each level, 1 .. 2048 */
+  int32_t level_n[ERBF_MAX_LEVELS];  /* points (or binning cells) per axis of each level, 1 .. 2048 */
   int32_t m_cap;                     /* kernel slots of this shape, >= 1 */
+  int32_t level_samples[ERBF_MAX_LEVELS]; /* 0: grid level; > 0: sample capacity, <= 2^26 */
 } erbf_shape_desc;
 
 typedef struct {
@@ -111,9 +119,12 @@ typedef struct {
   int32_t batch_cap;   /* largest point count of an erbf_loss_grad_batch call, >= 0 */
 } erbf_config;
 
-/* A grid level (eq. 3-16: the training set is the union of the levels
+/* A level (eq. 3-16: the training set is the union of the levels
  * registered so far).  All arrays are device memory owned by the caller and
- * must stay valid for the context's lifetime. */
+ * must stay valid for the context's lifetime.  A grid level gives axis,
+ * target, sdf and active_bits; a sample level gives only samples and
+ * n_samples (its targets are 1, eq. 3-10 on the surface; the other fields
+ * are ignored). */
 typedef struct {
   int32_t n;                    /* points per axis; must equal the declared level_n */
   const float* axis;            /* [n] increasing cell-centred coordinates in [-1, 1] */
@@ -121,6 +132,8 @@ typedef struct {
   const float* sdf;             /* [n^3] raw signed distance, or NULL; required for seeding */
   const uint32_t* active_bits;  /* [ceil(n^3/32)] training-point mask (bit i%32 of word i/32),
                                    or NULL for all points */
+  const float* samples;         /* sample level: [n_samples * 3] x, y, z in [-1, 1] */
+  int64_t n_samples;            /* sample level: 0 .. its declared capacity */
 } erbf_level;
 
 typedef struct {

@@ -26,7 +26,7 @@ FLAG_BUCKET_OVERFLOW = 1
 MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
 ORIENT_QUATERNION, ORIENT_EULER = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class ErbfError(RuntimeError):
@@ -37,7 +37,7 @@ class ErbfError(RuntimeError):
 
 class ShapeDesc(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("level_n", ctypes.c_int32 * MAX_LEVELS),
-                ("m_cap", ctypes.c_int32)]
+                ("m_cap", ctypes.c_int32), ("level_samples", ctypes.c_int32 * MAX_LEVELS)]
 
 
 class Config(ctypes.Structure):
@@ -48,7 +48,8 @@ class Config(ctypes.Structure):
 
 class Level(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("axis", ctypes.c_void_p), ("target", ctypes.c_void_p),
-                ("sdf", ctypes.c_void_p), ("active_bits", ctypes.c_void_p)]
+                ("sdf", ctypes.c_void_p), ("active_bits", ctypes.c_void_p), ("samples", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64)]
 
 
 class Params(ctypes.Structure):

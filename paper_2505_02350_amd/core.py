@@ -64,20 +64,26 @@ class Context:
     def __init__(self, shapes: Sequence, pair_cap: int, cull_k: float = 3.0,
                  weight_map: int = L.WEIGHT_SIGNED_SQUARE, device: int = 0,
                  orientation: int = L.ORIENT_QUATERNION, batch_cap: int = 0):
-        """shapes: sequence of (level_ns, m_cap)."""
+        """shapes: sequence of (level_ns, m_cap) or (level_ns, m_cap,
+        level_samples): level_samples[i] > 0 makes level i a surface-sample
+        level of that capacity, binned on a grid of level_ns[i] cells."""
         self.lib = L.load()
         self.device = torch.device("cuda", device)
         descs = (L.ShapeDesc * len(shapes))()
         self.level_ns = []
+        self.level_samples = []
         self.m_caps = []
-        for b, (ns, mcap) in enumerate(shapes):
-            ns = [int(n) for n in ns]
+        for b, sh in enumerate(shapes):
+            ns, mcap = [int(n) for n in sh[0]], int(sh[1])
+            samp = [int(v) for v in sh[2]] if len(sh) > 2 and sh[2] is not None else [0] * len(ns)
             descs[b].n_levels = len(ns)
             for i, n in enumerate(ns):
                 descs[b].level_n[i] = n
-            descs[b].m_cap = int(mcap)
+                descs[b].level_samples[i] = samp[i]
+            descs[b].m_cap = mcap
             self.level_ns.append(ns)
-            self.m_caps.append(int(mcap))
+            self.level_samples.append(samp)
+            self.m_caps.append(mcap)
         self._descs = descs
         cfg = L.Config(len(shapes), descs, int(pair_cap), float(cull_k), int(weight_map), int(orientation),
                        int(batch_cap))
@@ -102,11 +108,11 @@ class Context:
         # per-point offsets (shape-major over declared levels)
         self.pt_base = []
         off = 0
-        for ns in self.level_ns:
+        for ns, samp in zip(self.level_ns, self.level_samples):
             row = []
-            for n in ns:
+            for n, k in zip(ns, samp):
                 row.append(off)
-                off += n ** 3
+                off += k if k > 0 else n ** 3
             self.pt_base.append(row)
         self.n_active = [0] * self.n_shapes
         self._keep = []   # device arrays the context points into
@@ -132,8 +138,22 @@ class Context:
                 raise ValueError(f"{name} must be float32")
         if active_bits is not None and active_bits.dtype != torch.int32:
             raise ValueError("active_bits must be int32 words")
-        lvl = L.Level(n, _ptr(axis), _ptr(target), _ptr(sdf), _ptr(active_bits))
+        lvl = L.Level(n, _ptr(axis), _ptr(target), _ptr(sdf), _ptr(active_bits), None, 0)
         self._keep.append((axis, target, sdf, active_bits))
+        L.check(self.lib.erbf_refine_level(self.handle, shape, ctypes.byref(lvl), _stream(stream)))
+        self.n_active[shape] += 1
+
+    def erbf_refine_samples(self, shape: int, xyz: torch.Tensor, stream=None):
+        """Register shape's next level, a surface-sample level: xyz float32
+        [K, 3] device coordinates in [-1, 1] (label 1)."""
+        li = self.n_active[shape]
+        n = self.level_ns[shape][li]
+        if self.level_samples[shape][li] <= 0:
+            raise ValueError("the next declared level is not a sample level")
+        if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+            raise ValueError("xyz must be a contiguous float32 [K, 3] tensor")
+        lvl = L.Level(n, None, None, None, None, _ptr(xyz), int(xyz.shape[0]))
+        self._keep.append((xyz,))
         L.check(self.lib.erbf_refine_level(self.handle, shape, ctypes.byref(lvl), _stream(stream)))
         self.n_active[shape] += 1
 

@@ -52,7 +52,9 @@ struct Layout {
       off_partials,
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
-      off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init;
+      off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init, off_samp_pos, off_samp_start, off_samp_slot,
+      off_samp_slots;
+  int64_t samp_total = 0, samp_start_total = 0, samp_tiles = 0;
   size_t bytes = 0;
 };
 
@@ -78,6 +80,8 @@ int validate_config(const erbf_config* cfg) {
     for (int l = 0; l < s.n_levels; ++l) {
       const int n = s.level_n[l];
       if (n < 1 || n > 2048) return fail(ERBF_ERR_INVALID_ARG, "level_n out of range");
+      if (s.level_samples[l] < 0 || s.level_samples[l] > (1 << 26))
+        return fail(ERBF_ERR_INVALID_ARG, "level_samples out of range");
       const int64_t nt = (n + kTile - 1) / kTile;
       tiles += nt * nt * nt;
     }
@@ -98,7 +102,14 @@ Layout make_layout(const erbf_config* cfg) {
       const int nt = (n + kTile - 1) / kTile;
       L.tiles_total += nt * nt * nt;
       L.max_level_tiles = std::max(L.max_level_tiles, nt * nt * nt);
-      L.pts_total += (int64_t)n * n * n;
+      if (s.level_samples[l] > 0) {
+        L.pts_total += s.level_samples[l];
+        L.samp_total += s.level_samples[l];
+        L.samp_start_total += (int64_t)nt * nt * nt + 1;
+        L.samp_tiles += (int64_t)nt * nt * nt;
+      } else {
+        L.pts_total += (int64_t)n * n * n;
+      }
     }
   }
   L.cand_cap = L.pts_total / 20 + 1024;
@@ -155,10 +166,17 @@ Layout make_layout(const erbf_config* cfg) {
   L.init_words = L.pts_total / 32 + 1;
   for (int b = 0; b < cfg->n_shapes; ++b) {
     int64_t np = 0;
-    for (int l = 0; l < cfg->shapes[b].n_levels; ++l) np += (int64_t)cfg->shapes[b].level_n[l] * cfg->shapes[b].level_n[l] * cfg->shapes[b].level_n[l];
+    for (int l = 0; l < cfg->shapes[b].n_levels; ++l) {
+      const int64_t n = cfg->shapes[b].level_n[l];
+      np += cfg->shapes[b].level_samples[l] > 0 ? cfg->shapes[b].level_samples[l] : n * n * n;
+    }
     L.init_cand = std::max(L.init_cand, np + 1);
   }
-  L.off_init = take(sizeof(uint32_t) * ((size_t)L.init_words + 2 * (size_t)L.init_cand + 8));
+  L.off_init = take(sizeof(uint32_t) * ((size_t)L.init_words + 4 * (size_t)L.init_cand + 8));
+  L.off_samp_pos = take(sizeof(float4) * (size_t)std::max<int64_t>(L.samp_total, 1));
+  L.off_samp_start = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_start_total, 1));
+  L.off_samp_slot = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_total, 1));
+  L.off_samp_slots = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_tiles, 1));
   L.bytes = o;
   return L;
 }
@@ -174,6 +192,7 @@ struct erbf_ctx {
   std::vector<LevelDev> lv;
   std::vector<ShapeDev> sh;
   int slots_used = 0;
+  int64_t samp_used = 0, samp_start_used = 0;   // sample arrays handed to registered levels
   int32_t* rflags = nullptr;
   int32_t* rexcl = nullptr;
   // optional kernel timing: six events per recorded call (start/stop of the
@@ -300,6 +319,11 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.seed_keep = reinterpret_cast<int64_t*>(w + lay.off_keep);
   D.seed_misc = reinterpret_cast<int32_t*>(w + lay.off_misc);
   D.init_scratch = reinterpret_cast<uint32_t*>(w + lay.off_init);
+  D.samp_pos = reinterpret_cast<float4*>(w + lay.off_samp_pos);
+  D.samp_start = reinterpret_cast<int32_t*>(w + lay.off_samp_start);
+  D.samp_slot = reinterpret_cast<int32_t*>(w + lay.off_samp_slot);
+  D.samp_slots = reinterpret_cast<int32_t*>(w + lay.off_samp_slots);
+  D.n_samp_slots = 0;
   D.init_words = lay.init_words;
   D.init_cand_cap = lay.init_cand;
   D.cand_cap = lay.cand_cap;
@@ -343,9 +367,13 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
       L.pt_base = pbase;
       L.h = 2.0f / (float)L.n;
       L.lo = -1.0f + 1.0f / (float)L.n;
+      L.kind = s.level_samples[l] > 0 ? kLevelSamples : kLevelGrid;
+      L.npts = L.kind == kLevelSamples ? (int64_t)s.level_samples[l] : (int64_t)L.n * L.n * L.n;
+      // grid tiles: their points' box (plus rounding); sample tiles: their cells
+      L.pad = L.kind == kLevelSamples ? 0.5f * L.h + 2e-6f : 2e-6f;
       c->lv.push_back(L);
       tmap += L.nt * L.nt * L.nt;
-      pbase += (int64_t)L.n * L.n * L.n;
+      pbase += L.npts;
     }
     sd.n_pts = pbase - sd.pt_base;
     for (int k = 0; k < s.m_cap; ++k) kshape[kbase + k] = b;
@@ -405,6 +433,102 @@ int erbf_octree_bits(const float* S_parent, const uint32_t* parent_bits, int32_t
   return ERBF_OK;
 }
 
+// A sample level: the samples are binned on the host (a set-up call that
+// already synchronises), stably by tile so that each tile's samples keep the
+// caller's order; the tiles holding samples become the level's slots in
+// ascending tile order, as for a grid level.
+static int refine_samples(erbf_ctx* ctx, int32_t shape, ShapeDev& sd, int li, LevelDev& L, const erbf_level* level,
+                          hipStream_t stream) {
+  const int64_t cap = L.npts, K = level->n_samples;
+  if (K < 0 || K > cap) return fail(ERBF_ERR_INVALID_ARG, "n_samples must be in [0, the declared capacity]");
+  if (K > 0 && !level->samples) return fail(ERBF_ERR_INVALID_ARG, "samples is NULL");
+  DeviceGuard guard(ctx->device);
+  Dev& D = ctx->D;
+  std::vector<float> xyz((size_t)(3 * K));
+  if (K > 0)
+    HIP_TRY(hipMemcpy(xyz.data(), level->samples, sizeof(float) * 3 * K, hipMemcpyDeviceToHost), "refine: samples");
+  const int n = L.n, nt = L.nt, ntt = nt * nt * nt;
+  const double cell = 2.0 / n;
+  std::vector<int32_t> tile((size_t)K);
+  for (int64_t i = 0; i < K; ++i) {
+    int t3[3];
+    for (int a = 0; a < 3; ++a) {
+      const float v = xyz[3 * i + a];
+      if (!(v >= -1.f && v <= 1.f)) return fail(ERBF_ERR_INVALID_ARG, "samples must lie in [-1, 1]^3");
+      t3[a] = std::min(n - 1, std::max(0, (int)std::floor(((double)v + 1.0) / cell))) / kTile;
+    }
+    tile[i] = (t3[2] * nt + t3[1]) * nt + t3[0];
+  }
+  std::vector<int64_t> order((size_t)K);
+  for (int64_t i = 0; i < K; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return tile[a] < tile[b]; });
+  std::vector<int32_t> flags(ntt, 0), rank(ntt, -1);
+  for (int64_t i = 0; i < K; ++i) flags[tile[i]] = 1;
+  int n_act = 0;
+  for (int t = 0; t < ntt; ++t)
+    if (flags[t]) rank[t] = n_act++;
+  std::vector<float4> pos((size_t)std::max<int64_t>(K, 1));
+  std::vector<int32_t> start(n_act + 1, 0), sslot((size_t)cap, -1), slots(std::max(n_act, 1));
+  for (int64_t k = 0; k < K; ++k) {
+    const int64_t i = order[k];
+    float4 q;
+    q.x = xyz[3 * i];
+    q.y = xyz[3 * i + 1];
+    q.z = xyz[3 * i + 2];
+    int32_t ii = (int32_t)i;
+    std::memcpy(&q.w, &ii, sizeof(float));
+    pos[k] = q;
+    start[rank[tile[i]] + 1] += 1;
+    sslot[i] = ctx->slots_used + rank[tile[i]];
+  }
+  for (int r = 0; r < n_act; ++r) {
+    start[r + 1] += start[r];
+    slots[r] = ctx->slots_used + r;
+  }
+  const Layout& lay = ctx->lay;
+  if (ctx->samp_used + cap > lay.samp_total || ctx->samp_start_used + ntt + 1 > lay.samp_start_total ||
+      D.n_samp_slots + n_act > lay.samp_tiles)
+    return fail(ERBF_ERR_STATE, "sample arrays exhausted");
+  L.spos = D.samp_pos + ctx->samp_used;
+  L.sstart = D.samp_start + ctx->samp_start_used;
+  L.sslot = D.samp_slot + ctx->samp_used;
+  L.sxyz = level->samples;
+  L.n_samples = (int32_t)K;
+  L.axis = nullptr;
+  L.target = nullptr;
+  L.sdf = nullptr;
+  L.bits = nullptr;
+  if (K > 0)
+    HIP_TRY(hipMemcpy(const_cast<float4*>(L.spos), pos.data(), sizeof(float4) * K, hipMemcpyHostToDevice),
+            "refine: sample positions");
+  HIP_TRY(hipMemcpy(const_cast<int32_t*>(L.sstart), start.data(), sizeof(int32_t) * (n_act + 1),
+                    hipMemcpyHostToDevice),
+          "refine: sample starts");
+  HIP_TRY(hipMemcpy(const_cast<int32_t*>(L.sslot), sslot.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice),
+          "refine: sample slots");
+  if (n_act > 0)
+    HIP_TRY(hipMemcpy(D.samp_slots + D.n_samp_slots, slots.data(), sizeof(int32_t) * n_act, hipMemcpyHostToDevice),
+            "refine: sample slot list");
+  HIP_TRY(hipMemcpy(ctx->rflags, flags.data(), sizeof(int32_t) * ntt, hipMemcpyHostToDevice), "refine: flags");
+  HIP_TRY(hipMemcpy(&D.levels[li], &L, sizeof(LevelDev), hipMemcpyHostToDevice), "refine: level table");
+  HIP_TRY(launch_scan(ctx->rflags, ntt, D.scan_blocks, ctx->rexcl, D.counters + 1, stream), "refine: scan");
+  HIP_TRY(launch_tile_assign(D, li, ntt, ctx->rflags, ctx->rexcl, ctx->slots_used, stream), "refine: assign");
+  HIP_TRY(launch_fill_f32(D.G + L.pt_base, cap, 0.f, stream), "refine: clear G");
+  HIP_TRY(hipStreamSynchronize(stream), "refine: sync");
+  L.slot0 = ctx->slots_used;
+  L.n_slots = n_act;
+  ctx->slots_used += n_act;
+  ctx->samp_used += cap;
+  ctx->samp_start_used += ntt + 1;
+  D.n_samp_slots += n_act;
+  sd.n_active += 1;
+  if (sd.n_active == 1) sd.slot0 = L.slot0;
+  sd.n_slots += L.n_slots;
+  HIP_TRY(hipMemcpy(&D.levels[li], &L, sizeof(LevelDev), hipMemcpyHostToDevice), "refine: level table");
+  HIP_TRY(hipMemcpy(&D.shapes[shape], &sd, sizeof(ShapeDev), hipMemcpyHostToDevice), "refine: shape table");
+  return ERBF_OK;
+}
+
 int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hipStream_t stream) {
   if (!ctx || !level) return fail(ERBF_ERR_INVALID_ARG, "ctx and level must be non-NULL");
   if (shape < 0 || shape >= ctx->cfg.n_shapes) return fail(ERBF_ERR_INVALID_ARG, "shape out of range");
@@ -414,6 +538,7 @@ int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hip
   const int li = sd.lvl0 + sd.n_active;
   LevelDev& L = ctx->lv[li];
   if (level->n != L.n) return fail(ERBF_ERR_INVALID_ARG, "level n differs from the declared level_n");
+  if (L.kind == kLevelSamples) return refine_samples(ctx, shape, sd, li, L, level, stream);
   if (!level->axis) return fail(ERBF_ERR_INVALID_ARG, "level axis is NULL");
   DeviceGuard guard(ctx->device);
   Dev& D = ctx->D;
@@ -461,7 +586,7 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l) {
       const LevelDev& L = ctx->lv[s.lvl0 + l];
-      if (L.bits) HIP_TRY(launch_fill_f32(f_out + L.pt_base, (int64_t)L.n * L.n * L.n, 0.f, stream), "eval: clear");
+      if (L.bits || L.kind == kLevelSamples) HIP_TRY(launch_fill_f32(f_out + L.pt_base, L.npts, 0.f, stream), "eval: clear");
     }
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "eval: prologue");
   HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "eval: buckets");
@@ -481,14 +606,16 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   if (cfg->mode < ERBF_MODE_FIXED || cfg->mode > ERBF_MODE_L2) return fail(ERBF_ERR_INVALID_ARG, "unknown mode");
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l)
-      if (!ctx->lv[s.lvl0 + l].target) return fail(ERBF_ERR_INVALID_ARG, "a registered level has no target");
+      if (ctx->lv[s.lvl0 + l].kind == kLevelGrid && !ctx->lv[s.lvl0 + l].target)
+        return fail(ERBF_ERR_INVALID_ARG, "a registered grid level has no target");
   DeviceGuard guard(ctx->device);
   const Dev& D = ctx->D;
   if (f_out)
     for (const ShapeDev& s : ctx->sh)
       for (int l = 0; l < s.n_active; ++l) {
         const LevelDev& L = ctx->lv[s.lvl0 + l];
-        if (L.bits) HIP_TRY(launch_fill_f32(f_out + L.pt_base, (int64_t)L.n * L.n * L.n, 0.f, stream), "loss: clear");
+        if (L.bits || L.kind == kLevelSamples)
+          HIP_TRY(launch_fill_f32(f_out + L.pt_base, L.npts, 0.f, stream), "loss: clear");
       }
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "loss: prologue");
   HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "loss: buckets");
@@ -521,7 +648,8 @@ int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_lo
   if (n_pts > 0 && !pts) return fail(ERBF_ERR_INVALID_ARG, "pts must be non-NULL");
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l)
-      if (!ctx->lv[s.lvl0 + l].target) return fail(ERBF_ERR_INVALID_ARG, "a registered level has no target");
+      if (ctx->lv[s.lvl0 + l].kind == kLevelGrid && !ctx->lv[s.lvl0 + l].target)
+        return fail(ERBF_ERR_INVALID_ARG, "a registered grid level has no target");
   DeviceGuard guard(ctx->device);
   const Dev& D = ctx->D;
   // G is zero outside the batch, so the tile backward sees the batch only
@@ -553,7 +681,7 @@ int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, floa
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l) {
       const LevelDev& L = ctx->lv[s.lvl0 + l];
-      HIP_TRY(launch_mask_copy(D, s.lvl0 + l, (int64_t)L.n * L.n * L.n, grad_f, stream), "vjp: mask");
+      HIP_TRY(launch_mask_copy(D, s.lvl0 + l, L.npts, grad_f, stream), "vjp: mask");
     }
   const hipEvent_t* ev = tev_call(ctx);
   HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
@@ -735,10 +863,12 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
   int finest = -1;
   for (int l = 0; l < sd.n_active; ++l) {
     const LevelDev& L = ctx->lv[sd.lvl0 + l];
-    if (!L.sdf) return fail(ERBF_ERR_INVALID_ARG, "seeding needs the raw SDF of every registered level");
-    npts += (int64_t)L.n * L.n * L.n;
+    npts += L.npts;
+    if (L.kind != kLevelGrid) continue;   // surface samples are not seeded
+    if (!L.sdf) return fail(ERBF_ERR_INVALID_ARG, "seeding needs the raw SDF of every registered grid level");
     if (finest < 0 || L.n > ctx->lv[finest].n) finest = sd.lvl0 + l;
   }
+  if (finest < 0) return fail(ERBF_ERR_STATE, "shape has no registered grid level");
   if (npts >= ((int64_t)1 << 32)) return fail(ERBF_ERR_UNSUPPORTED, "seeding supports < 2^32 points per shape");
   const int64_t K = (int64_t)std::ceil((double)cfg->top_frac * (double)n_idall);
   if (K == 0) return ERBF_OK;
@@ -784,19 +914,24 @@ int erbf_init_inscribed(erbf_ctx* ctx, const erbf_params* params, int32_t shape,
   if (!(gamma > 0.f && gamma < 1.f)) return fail(ERBF_ERR_INVALID_ARG, "gamma must be in (0, 1)");
   const ShapeDev& sd = ctx->sh[shape];
   if (sd.n_active < 1) return fail(ERBF_ERR_STATE, "shape has no registered level");
-  int64_t npts = 0;
+  int64_t npts = 0, n_samples = 0;
   for (int l = 0; l < sd.n_active; ++l) {
     const LevelDev& L = ctx->lv[sd.lvl0 + l];
+    npts += L.npts;
+    if (L.kind != kLevelGrid) {
+      n_samples += L.n_samples;
+      continue;
+    }
     if (!L.sdf || !L.target)
-      return fail(ERBF_ERR_INVALID_ARG, "initialisation needs the targets and the raw SDF of every registered level");
-    npts += (int64_t)L.n * L.n * L.n;
+      return fail(ERBF_ERR_INVALID_ARG,
+                  "initialisation needs the targets and the raw SDF of every registered grid level");
   }
   if (npts >= (int64_t)UINT32_MAX) return fail(ERBF_ERR_UNSUPPORTED, "initialisation supports < 2^32 - 1 points per shape");
   const int m_max = max_centres <= 0 ? sd.cap : std::min(max_centres, sd.cap);
   DeviceGuard guard(ctx->device);
   const Dev& D = ctx->D;
-  HIP_TRY(launch_init_inscribed(D, shape, (uint32_t)npts, m_max, sd.cap, gamma, params->p, params->m_dev, m1, m2,
-                                stream),
+  HIP_TRY(launch_init_inscribed(D, shape, (uint32_t)npts, n_samples > 0, m_max, sd.cap, gamma, params->p,
+                                params->m_dev, m1, m2, stream),
           "init: launch");
   if (init_results(D, n_centres, n_left, stream) != 0) return fail(ERBF_ERR_HIP, "init: reading counts");
   return ERBF_OK;

@@ -18,6 +18,11 @@
 // ((dx*dx + dy*dy) + dz*dz) <= r*r, so the chosen centres are reproducible
 // exactly by a float64 evaluation of the same expression.
 //
+// With surface samples registered for the shape (sample levels), the
+// distance to the surface is, as in the algorithm, the distance to the
+// nearest sample: its square r^2 (double, each operation rounded) is the
+// sphere's squared radius and, rounded to float, the depth order.
+//
 // eq. 3-12 then gives each centre the isotropic scale
 // d = 2 sqrt(-ln(gamma / w^2)) / dhat, dhat the distance to the nearest other
 // centre (2, the width of the domain, when there is a single centre), and the
@@ -37,15 +42,24 @@ namespace erbf {
 
 namespace {
 
+// scratch of the initialisation: nearest-sample squared distances (double,
+// per shape point), candidate mask, two candidate lists, result words
+__device__ __forceinline__ double* init_dmin2(const Dev& D) { return reinterpret_cast<double*>(D.init_scratch); }
+__device__ __forceinline__ uint32_t* init_mask(const Dev& D) { return D.init_scratch + 2 * D.init_cand_cap; }
+__device__ __forceinline__ uint32_t* init_list(const Dev& D, int which) {
+  return init_mask(D) + D.init_words + which * D.init_cand_cap;
+}
+__device__ __forceinline__ uint32_t* init_res(const Dev& D) { return init_list(D, 2); }
+
 // level and grid indices of a shape-local point index (the shape's active
-// levels are contiguous, each x fastest); the shape has < 2^32 points
+// levels are contiguous, each x fastest); the shape has < 2^32 points.  For
+// a point of a sample level only the level is meaningful.
 __device__ __forceinline__ const LevelDev* init_locate(const Dev& D, const ShapeDev& S, uint32_t g, uint32_t& loc,
                                                        int& i, int& j, int& k) {
   uint32_t off = 0;
   int l = 0;
   for (; l < S.n_active - 1; ++l) {
-    const uint32_t n = (uint32_t)D.levels[S.lvl0 + l].n;
-    const uint32_t np = n * n * n;
+    const uint32_t np = (uint32_t)D.levels[S.lvl0 + l].npts;
     if (g - off < np) break;
     off += np;
   }
@@ -70,7 +84,7 @@ __device__ __forceinline__ double dist2_rounded(double dx, double dy, double dz)
 // candidate mask: bit b of word w is point 32 w + b of the shape
 __global__ __launch_bounds__(256) void k_init_mark(Dev D, int shape, uint32_t npts, uint32_t nw) {
   const ShapeDev S = D.shapes[shape];
-  uint32_t* mask = D.init_scratch;
+  uint32_t* mask = init_mask(D);
   for (uint32_t w = blockIdx.x * 256u + threadIdx.x; w < nw; w += gridDim.x * 256u) {
     uint32_t word = 0u;
     for (int b = 0; b < 32; ++b) {
@@ -79,6 +93,7 @@ __global__ __launch_bounds__(256) void k_init_mark(Dev D, int shape, uint32_t np
       uint32_t loc;
       int i, j, k;
       const LevelDev* L = init_locate(D, S, g, loc, i, j, k);
+      if (L->kind != kLevelGrid) continue;   // samples are on the surface, never interior
       const bool act = !L->bits || ((L->bits[loc >> 5] >> (loc & 31u)) & 1u);
       const float t = L->target[loc];
       const float sv = L->sdf[loc];
@@ -88,14 +103,54 @@ __global__ __launch_bounds__(256) void k_init_mark(Dev D, int shape, uint32_t np
   }
 }
 
+// nearest-sample squared distance of every candidate: blocks of 256 points
+// stream the shape's samples through LDS; blocks without a candidate leave
+__global__ __launch_bounds__(256) void k_init_nearest(Dev D, int shape, uint32_t npts) {
+  __shared__ float4 sp[256];
+  const ShapeDev S = D.shapes[shape];
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t* mask = init_mask(D);
+  const bool cand = g < npts && ((mask[g >> 5] >> (g & 31u)) & 1u);
+  if (!__syncthreads_or(cand ? 1 : 0)) return;
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if (cand) {
+    uint32_t loc;
+    int i, j, k;
+    const LevelDev* L = init_locate(D, S, g, loc, i, j, k);
+    px = (double)L->axis[i];
+    py = (double)L->axis[j];
+    pz = (double)L->axis[k];
+  }
+  double best = INFINITY;
+  for (int l = 0; l < S.n_active; ++l) {
+    const LevelDev& L = D.levels[S.lvl0 + l];
+    if (L.kind != kLevelSamples) continue;
+    for (int s0 = 0; s0 < L.n_samples; s0 += 256) {
+      const int q = s0 + (int)threadIdx.x;
+      __syncthreads();
+      if (q < L.n_samples) sp[threadIdx.x] = make_float4(L.sxyz[3 * q], L.sxyz[3 * q + 1], L.sxyz[3 * q + 2], 0.f);
+      __syncthreads();
+      const int nq = min(256, L.n_samples - s0);
+      if (cand)
+        for (int u = 0; u < nq; ++u) {
+          const float4 P = sp[u];
+          best = fmin(best, dist2_rounded((double)P.x - px, (double)P.y - py, (double)P.z - pz));
+        }
+    }
+  }
+  if (cand) init_dmin2(D)[g] = best;
+}
+
 // agent-scope load: bypasses this CU's vector cache, so it sees bits that
 // other waves cleared with atomics
 __device__ __forceinline__ uint32_t load_word(const uint32_t* a) {
   return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// sort key of a candidate: larger |S| first
-__device__ __forceinline__ uint32_t depth_key(const Dev& D, const ShapeDev& S, uint32_t g) {
+// sort key of a candidate: deeper first (|S|, or the nearest-sample
+// squared distance rounded to float)
+__device__ __forceinline__ uint32_t depth_key(const Dev& D, const ShapeDev& S, uint32_t g, bool samples) {
+  if (samples) return ~__float_as_uint((float)init_dmin2(D)[g]);
   uint32_t loc;
   int i, j, k;
   const LevelDev* L = init_locate(D, S, g, loc, i, j, k);
@@ -103,9 +158,10 @@ __device__ __forceinline__ uint32_t depth_key(const Dev& D, const ShapeDev& S, u
 }
 
 struct InitSlot {
+  double r2;          // squared sphere radius
   int32_t e;          // position in the sorted candidate list, INT32_MAX if none
   uint32_t g;         // point index
-  float x, y, z, r;
+  float x, y, z, r;   // centre; r bounds the radius from above (index boxes)
 };
 
 // The greedy rounds, one workgroup:
@@ -120,7 +176,7 @@ struct InitSlot {
 //      block loaded later starts from the current cover.
 // Writes centre, weight and identity rotation of each centre, the count to
 // m_dev and (count, uncovered candidates) to the result words.
-__global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t nw, int m_max,
+__global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t nw, int samples, int m_max,
                                                       float* __restrict__ p, int32_t* __restrict__ m_dev) {
   __shared__ int scan_sh[32];
   __shared__ uint32_t hist[256];
@@ -128,10 +184,10 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
   __shared__ uint32_t cnt[16][256];
   __shared__ InitSlot slot[2][16];
   __shared__ uint32_t left_sh[16];
-  uint32_t* mask = D.init_scratch;
-  uint32_t* A = D.init_scratch + D.init_words;
-  uint32_t* Bv = A + D.init_cand_cap;
-  uint32_t* res = Bv + D.init_cand_cap;
+  uint32_t* mask = init_mask(D);
+  uint32_t* A = init_list(D, 0);
+  uint32_t* Bv = init_list(D, 1);
+  uint32_t* res = init_res(D);
   const ShapeDev S = D.shapes[shape];
   const int C = D.cap_total;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -162,7 +218,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
     if (tid < 256) hist[tid] = 0u;
     __syncthreads();
     for (uint32_t e = (uint32_t)tid; e < n_in; e += 1024u)
-      atomicAdd(&hist[(depth_key(D, S, src[e]) >> shift) & 255u], 1u);
+      atomicAdd(&hist[(depth_key(D, S, src[e], samples) >> shift) & 255u], 1u);
     __syncthreads();
     if (tid < 64) {
       // exclusive scan of the 256 digit counts by one wave, 4 per lane
@@ -185,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
       const uint32_t e = c0 + (uint32_t)tid;
       const bool valid = e < n_in;
       const uint32_t g = valid ? src[e] : 0u;
-      const uint32_t d = valid ? (depth_key(D, S, g) >> shift) & 255u : 0u;
+      const uint32_t d = valid ? (depth_key(D, S, g, samples) >> shift) & 255u : 0u;
       // lanes of this wave holding the same digit
       uint64_t match = __ballot(valid);
 #pragma unroll
@@ -218,6 +274,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
   bool unc = false;           // my entry is a candidate no sphere covers yet
   uint32_t my_g = 0u;
   float mx = 0.f, my = 0.f, mz = 0.f, mr = 0.f;
+  double mr2 = 0.0;
   bool need_load = true;
   for (int it = 0; m < m_max; ++it) {
     if (need_load) {
@@ -233,7 +290,13 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
         mx = L->axis[i];
         my = L->axis[j];
         mz = L->axis[k];
-        mr = fabsf(L->sdf[loc]);
+        if (samples) {
+          mr2 = init_dmin2(D)[my_g];
+          mr = (float)sqrt(mr2) * (1.0f + 1e-6f) + 1e-30f;
+        } else {
+          mr = fabsf(L->sdf[loc]);
+          mr2 = (double)mr * (double)mr;
+        }
       }
       need_load = false;
     }
@@ -247,6 +310,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
       sl.y = my;
       sl.z = mz;
       sl.r = mr;
+      sl.r2 = mr2;
       slot[it & 1][wv] = sl;
     }
     __syncthreads();
@@ -261,7 +325,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
       continue;
     }
     const double cx = (double)cs.x, cy = (double)cs.y, cz = (double)cs.z;
-    const double r2 = (double)cs.r * (double)cs.r;
+    const double r2 = cs.r2;
     if (tid == 0) {
       uint32_t loc;
       int i, j, k;
@@ -284,6 +348,10 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
     for (int l = 0; l < S.n_active; ++l) {
       const LevelDev& L = D.levels[S.lvl0 + l];
       const int n = L.n;
+      if (L.kind != kLevelGrid) {   // samples are never candidates
+        off += (uint32_t)L.npts;
+        continue;
+      }
       int lo3[3], hi3[3];
       const float cc[3] = {cs.x, cs.y, cs.z};
 #pragma unroll
@@ -310,7 +378,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
             }
           }
       }
-      off += (uint32_t)n * (uint32_t)n * (uint32_t)n;
+      off += (uint32_t)L.npts;
     }
   }
   __syncthreads();
@@ -378,12 +446,13 @@ __global__ __launch_bounds__(256) void k_init_scale(Dev D, int shape, float gamm
 
 }  // namespace
 
-hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, int m_max, int cap, float gamma, float* p,
-                                 int32_t* m_dev, float* m1, float* m2, hipStream_t s) {
+hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, bool samples, int m_max, int cap, float gamma,
+                                 float* p, int32_t* m_dev, float* m1, float* m2, hipStream_t s) {
   const uint32_t nw = (npts + 31u) / 32u;
   const unsigned gm = (unsigned)std::max<uint32_t>(1u, std::min<uint32_t>((nw + 255u) / 256u, 4096u));
   hipLaunchKernelGGL(k_init_mark, dim3(gm), dim3(256), 0, s, D, shape, npts, nw);
-  hipLaunchKernelGGL(k_init_greedy, dim3(1), dim3(1024), 0, s, D, shape, nw, m_max, p, m_dev);
+  if (samples) hipLaunchKernelGGL(k_init_nearest, dim3((npts + 255u) / 256u), dim3(256), 0, s, D, shape, npts);
+  hipLaunchKernelGGL(k_init_greedy, dim3(1), dim3(1024), 0, s, D, shape, nw, samples ? 1 : 0, m_max, p, m_dev);
   hipLaunchKernelGGL(k_init_scale, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, D, shape, gamma, p, m_dev,
                      m1, m2);
   return hipGetLastError();
@@ -391,8 +460,8 @@ hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, int m_m
 
 int init_results(const Dev& D, int32_t* n_centres, int64_t* n_left, hipStream_t s) {
   uint32_t r[2];
-  if (hipMemcpyAsync(r, D.init_scratch + D.init_words + 2 * D.init_cand_cap, sizeof(r), hipMemcpyDeviceToHost,
-                     s) != hipSuccess)
+  const uint32_t* res = D.init_scratch + 2 * D.init_cand_cap + D.init_words + 2 * D.init_cand_cap;
+  if (hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, s) != hipSuccess)
     return -1;
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
   *n_centres = (int32_t)r[0];

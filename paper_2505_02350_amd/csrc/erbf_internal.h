@@ -16,19 +16,31 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kVariantFwdPersistent = 1;   // forward tiles walked by a persistent grid
 constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persistent grid
 
+constexpr int kLevelGrid = 0;      // cell-centred grid of n^3 points
+constexpr int kLevelSamples = 1;   // surface samples binned into the tiles of an n^3-cell grid
+
 // Per-level table entry, mirrored on the device.
 struct LevelDev {
-  int32_t n, nt;            // points / tiles per axis
+  int32_t n, nt;            // points (sample levels: binning cells) / tiles per axis
   int32_t shape;            // owning shape
   int32_t slot0;            // first active-tile slot of this level
   int32_t n_slots;          // active tiles
   int32_t tmap0;            // offset of this level's tile map (nt^3 int32)
   int64_t pt_base;          // offset of this level in per-point arrays
+  int64_t npts;             // entries in per-point arrays: n^3, or the sample capacity
   float lo, h;              // axis[0] and nominal spacing 2/n (used for index ranges only)
+  float pad;                // tile boxes reach this far past their outer points (samples: the
+                            // half cell, so the boxes tile space)
+  int32_t kind;             // kLevelGrid or kLevelSamples
+  int32_t n_samples;        // sample levels: samples registered
   const float* axis;
   const float* target;
   const float* sdf;
   const uint32_t* bits;
+  const float* sxyz;        // sample levels: the caller's [n_samples * 3] coordinates
+  const float4* spos;       // sample levels: samples by tile (x, y, z, original index as int bits)
+  const int32_t* sstart;    // sample levels: [n_slots + 1] first spos entry of each active tile
+  const int32_t* sslot;     // sample levels: [capacity] tile slot of each sample, -1 if none
 };
 
 // Per-shape table entry, mirrored on the device.
@@ -104,9 +116,16 @@ struct Dev {
   int64_t* seed_cand;       // [cand_cap]
   int64_t* seed_keep;       // [cand_cap]
   int32_t* seed_misc;       // [64]
-  // inscribed-sphere initialisation scratch: candidate mask (init_words),
-  // two candidate lists (init_cand_cap each) and 8 result words
-  uint32_t* init_scratch;   // [init_words + 2 * init_cand_cap + 8]
+  // sample levels
+  float4* samp_pos;         // [total sample capacity]
+  int32_t* samp_start;      // [sum over sample levels of tiles + 1]
+  int32_t* samp_slot;       // [total sample capacity]
+  int32_t* samp_slots;      // [sample-level tiles] slots of every active sample tile
+  int32_t n_samp_slots;     // entries of samp_slots in use
+  // inscribed-sphere initialisation scratch: nearest-sample squared
+  // distances (double, init_cand_cap), candidate mask (init_words), two
+  // candidate lists (init_cand_cap each) and 8 result words
+  uint32_t* init_scratch;   // [4 * init_cand_cap + init_words + 8]
   int64_t init_words;       // pts_total / 32 + 1
   int64_t init_cand_cap;    // points of the largest shape (all its levels)
   int64_t cand_cap;

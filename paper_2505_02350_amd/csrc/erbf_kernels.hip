@@ -46,10 +46,10 @@ __device__ __forceinline__ void index_range(const LevelDev& L, float c0, float c
 }
 
 __device__ __forceinline__ float tile_lo(const LevelDev& L, int t) {
-  return fmaf((float)(t * kTile), L.h, L.lo) - 2e-6f;
+  return fmaf((float)(t * kTile), L.h, L.lo) - L.pad;
 }
 __device__ __forceinline__ float tile_hi(const LevelDev& L, int t) {
-  return fmaf((float)min(t * kTile + kTile - 1, L.n - 1), L.h, L.lo) + 2e-6f;
+  return fmaf((float)min(t * kTile + kTile - 1, L.n - 1), L.h, L.lo) + L.pad;
 }
 
 __device__ __forceinline__ bool point_active(const uint32_t* bits, int64_t local) {
@@ -573,6 +573,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
+  if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_forward
   const int n = L.n, nt = L.nt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
@@ -755,20 +756,31 @@ __global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __r
   const LevelDev L = D.levels[li];
   const int n = L.n, nt = L.nt;
   const int64_t local = gi - L.pt_base;
-  const bool valid = gi >= 0 && L.axis != nullptr && local >= 0 && local < (int64_t)n * n * n &&
-                     point_active(L.bits, local);
+  const bool samples = L.kind == kLevelSamples;
+  bool valid;
+  if (samples)
+    valid = gi >= 0 && L.sxyz != nullptr && local >= 0 && local < (int64_t)L.n_samples;
+  else
+    valid = gi >= 0 && L.axis != nullptr && local >= 0 && local < (int64_t)n * n * n && point_active(L.bits, local);
   int slot = -1;
-  int xi = 0, yi = 0, zi = 0;
-  if (valid) {
-    xi = (int)(local % n);
-    yi = (int)((local / n) % n);
-    zi = (int)(local / ((int64_t)n * n));
+  float px = 0.f, py = 0.f, pz = 0.f;
+  if (valid && samples) {
+    slot = L.sslot[local];
+    px = L.sxyz[3 * local];
+    py = L.sxyz[3 * local + 1];
+    pz = L.sxyz[3 * local + 2];
+  } else if (valid) {
+    const int xi = (int)(local % n);
+    const int yi = (int)((local / n) % n);
+    const int zi = (int)(local / ((int64_t)n * n));
     slot = D.tile_map[L.tmap0 + ((zi / kTile) * nt + yi / kTile) * nt + xi / kTile];
+    px = L.axis[xi];
+    py = L.axis[yi];
+    pz = L.axis[zi];
   }
   float acc = 0.f;
   int cnt = 0;
   if (slot >= 0) {
-    const float px = L.axis[xi], py = L.axis[yi], pz = L.axis[zi];
     const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
     const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
     for (int64_t e = beg + lane; e < end; e += 64) {
@@ -787,8 +799,8 @@ __global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __r
   if (lane != 0) return;
   float E = 0.f;
   bool id = false;
-  if (valid && L.target) {
-    const float t = L.target[local];
+  if (valid && (samples || L.target)) {
+    const float t = samples ? 1.f : L.target[local];   // surface samples carry label 1
     id = (tau1 < t && t < tau2) || (t <= tau1 && f > tau1) || (t >= tau2 && f < tau2);
     E = id ? f - t : 0.f;
   }
@@ -799,6 +811,175 @@ __global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __r
   D.b_id[k] = id ? 1 : 0;
   D.b_pf[k] = valid ? pf : 0;
   D.b_shape[k] = valid ? L.shape : -1;
+}
+
+// ---------------------------------------------------------------------------
+// surface samples (label 1, eq. 3-10 on the surface).  A sample level bins
+// its samples into the 8^3-cell tiles of an n^3-cell grid; a tile's box is
+// its cells (the level's pad is half a cell), so every sample lies in its
+// tile's box and the tile's kernel list, built like a grid tile's, holds
+// every kernel whose ball reaches it.  One workgroup per active sample tile;
+// the pair arithmetic is the grid kernels' expression for expression.
+// ---------------------------------------------------------------------------
+
+template <bool LOSS>
+__global__ __launch_bounds__(256) void k_sample_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
+  __shared__ float4 srec[kFwdChunk * 3];
+  __shared__ double red_d[4];
+  __shared__ float red_f[4];
+  __shared__ int red_i[4];
+  __shared__ int64_t red_p[4];
+  const int slot = D.samp_slots[blockIdx.x];
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  double l2 = 0.0;
+  float mxe = 0.f;
+  int cnt_id = 0;
+  int64_t pfw = 0;
+  for (int sb = s0; sb < s1; sb += 256) {
+    const int si = sb + tid;
+    const bool valid = si < s1;
+    const float4 P = valid ? L.spos[si] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+    float acc = 0.f;
+    int pf = 0;
+    for (int64_t c0 = beg; c0 < end; c0 += kFwdChunk) {
+      const int cnt = (int)min((int64_t)kFwdChunk, end - c0);
+      __syncthreads();   // the previous chunk's records are no longer read
+      if (tid < cnt) {
+        const int j = D.items[c0 + tid];
+        srec[3 * tid] = D.rec[3 * j];
+        srec[3 * tid + 1] = D.rec[3 * j + 1];
+        srec[3 * tid + 2] = D.rec[3 * j + 2];
+      }
+      __syncthreads();
+      for (int k = 0; k < cnt; ++k) {
+        const float4 a0 = srec[3 * k], a1 = srec[3 * k + 1], a2 = srec[3 * k + 2];
+        const float dx = P.x - a0.x, dy = P.y - a0.y, dz = P.z - a0.z;
+        const bool in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < a0.w;
+        float q = fmaf(dx, fmaf(a1.x, dx, fmaf(a1.w, dy, a2.x * dz)), fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz));
+        q = in ? q : INFINITY;
+        acc = fmaf(a2.z, fast_exp2(-q), acc);
+        pf += in ? 1 : 0;
+      }
+    }
+    if (valid) {
+      const int64_t idx = L.pt_base + __float_as_int(P.w);
+      if (f_out) f_out[idx] = acc;
+      if (LOSS) {
+        const float t = 1.f, f = acc;
+        const bool id = (tau1 < t && t < tau2) || (t <= tau1 && f > tau1) || (t >= tau2 && f < tau2);
+        const float E = id ? f - t : 0.f;
+        D.G[idx] = 2.f * E;
+        l2 += (double)E * (double)E;
+        mxe = fmaxf(mxe, fabsf(E));
+        cnt_id += id ? 1 : 0;
+      }
+      pfw += pf;
+    }
+  }
+  l2 = wave_sum(l2);
+  mxe = wave_max_f(mxe);
+  cnt_id = wave_sum(cnt_id);
+  pfw = wave_sum(pfw);
+  if (lane == 0) { red_d[wv] = l2; red_f[wv] = mxe; red_i[wv] = cnt_id; red_p[wv] = pfw; }
+  __syncthreads();
+  if (tid == 0) {
+    TileStat ts;
+    ts.l2 = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+    ts.max_abs_e = fmaxf(fmaxf(red_f[0], red_f[1]), fmaxf(red_f[2], red_f[3]));
+    ts.n_idall = red_i[0] + red_i[1] + red_i[2] + red_i[3];
+    ts.p_fwd = (red_p[0] + red_p[1]) + (red_p[2] + red_p[3]);
+    D.tstat[slot] = ts;
+  }
+}
+
+// backward moments of a sample tile: lanes own kernels of the list (64 per
+// wave, 256 per round), the tile's samples are staged in LDS with their G,
+// and each lane sums T0 = sum g, T1 = sum g D, T2 = sum g D D^T over them in
+// order (g = G exp(-D^T A D)), stored at the entry's kernel-major index
+__global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restrict__ Gsrc) {
+  constexpr int kStage = 1024;
+  __shared__ float4 sp[kStage];
+  __shared__ int64_t spb[4];
+  const int slot = D.samp_slots[blockIdx.x];
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
+  int nz = 0;
+  for (int si = s0 + tid; si < s1; si += 256) nz |= Gsrc[L.pt_base + __float_as_int(L.spos[si].w)] != 0.f ? 1 : 0;
+  if (!__syncthreads_or(nz)) {
+    if (tid == 0) {
+      D.tile_nz[slot] = 0;
+      D.tile_pbwd[slot] = 0;
+    }
+    return;
+  }
+  if (tid == 0) D.tile_nz[slot] = 1;
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  int64_t pb = 0;
+  for (int64_t c0 = beg; c0 < end; c0 += 256) {
+    const int64_t e = c0 + 64 * wv + lane;
+    const bool have = e < end;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
+           r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    int e_out = 0;
+    if (have) {
+      const int j = D.items[e];
+      e_out = D.tile_e[e];
+      r0 = D.rec[3 * j];
+      r1 = D.rec[3 * j + 1];
+      r2 = D.rec[3 * j + 2];
+    }
+    float T[10];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) T[i] = 0.f;
+    uint32_t pbg = 0;
+    for (int sb = s0; sb < s1; sb += kStage) {
+      const int ns = min(kStage, s1 - sb);
+      __syncthreads();   // the previous stage is no longer read
+      for (int q = tid; q < ns; q += 256) {
+        const float4 P = L.spos[sb + q];
+        sp[q] = make_float4(P.x, P.y, P.z, Gsrc[L.pt_base + __float_as_int(P.w)]);
+      }
+      __syncthreads();
+      for (int k = 0; k < ns; ++k) {
+        const float4 P = sp[k];
+        const float dx = P.x - r0.x, dy = P.y - r0.y, dz = P.z - r0.z;
+        const bool in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < r0.w;
+        float q = fmaf(dx, fmaf(r1.x, dx, fmaf(r1.w, dy, r2.x * dz)), fmaf(dy, fmaf(r1.y, dy, r2.y * dz), r1.z * dz * dz));
+        q = in ? q : INFINITY;
+        const float g = P.w * fast_exp2(-q);
+        const float gx = g * dx, gy = g * dy, gz = g * dz;
+        T[0] += g;
+        T[1] += gx;
+        T[2] += gy;
+        T[3] += gz;
+        T[4] = fmaf(gx, dx, T[4]);
+        T[5] = fmaf(gx, dy, T[5]);
+        T[6] = fmaf(gx, dz, T[6]);
+        T[7] = fmaf(gy, dy, T[7]);
+        T[8] = fmaf(gy, dz, T[8]);
+        T[9] = fmaf(gz, dz, T[9]);
+        pbg += (in && P.w != 0.f) ? 1u : 0u;
+      }
+    }
+    pb += pbg;
+    if (have) {
+      float2* o = D.partials + 5 * (int64_t)e_out;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) o[i] = make_float2(T[2 * i], T[2 * i + 1]);
+    }
+  }
+  pb = wave_sum(pb);
+  if (lane == 0) spb[wv] = pb;
+  __syncthreads();
+  if (tid == 0) D.tile_pbwd[slot] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -824,6 +1005,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
+  if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_bwd
   const int n = L.n, nt = L.nt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
@@ -1316,11 +1498,12 @@ __global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, cons
 // G[idx] = src[idx] * active(idx) over every point of the active levels.
 __global__ __launch_bounds__(256) void k_mask_copy(Dev D, int li, const float* __restrict__ src) {
   const LevelDev L = D.levels[li];
-  const int64_t npts = (int64_t)L.n * L.n * L.n;
+  const int64_t npts = L.npts;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npts;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t idx = L.pt_base + k;
-    D.G[idx] = point_active(L.bits, k) ? src[idx] : 0.f;
+    const bool act = L.kind == kLevelSamples ? k < (int64_t)L.n_samples : point_active(L.bits, k);
+    D.G[idx] = act ? src[idx] : 0.f;
   }
 }
 
@@ -1544,6 +1727,12 @@ hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, fl
   } else {
     launch_timed(k_forward<false>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
   }
+  if (D.n_samp_slots > 0) {
+    if (loss)
+      hipLaunchKernelGGL(k_sample_forward<true>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+    else
+      hipLaunchKernelGGL(k_sample_forward<false>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+  }
   return hipGetLastError();
 }
 
@@ -1556,6 +1745,7 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
   } else if (n_slots > 0) {
     launch_timed(k_bwd_tiles, dim3(n_slots), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G);
   }
+  if (D.n_samp_slots > 0) hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots), dim3(256), 0, s, D, G);
   launch_timed(k_bwd_reduce, dim3(D.cap_total), dim3(64), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
                grad);
   return hipGetLastError();

@@ -57,8 +57,8 @@ hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32
 hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int n_pts, const float* p,
                              const int32_t* m_dev, float* grad, float* f_out, erbf_stats* out, float tau1, float tau2,
                              const StatsArgs& a, hipStream_t s);
-hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, int m_max, int cap, float gamma, float* p,
-                                 int32_t* m_dev, float* m1, float* m2, hipStream_t s);
+hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, bool samples, int m_max, int cap, float gamma,
+                                 float* p, int32_t* m_dev, float* m1, float* m2, hipStream_t s);
 // (centres, uncovered candidates) left by launch_init_inscribed (synchronises the stream); 0 on success
 int init_results(const Dev& D, int32_t* n_centres, int64_t* n_left, hipStream_t s);
 hipError_t launch_sched_init(const Dev& D, const erbf_sched_state& st, const erbf_sched_cfg& a, hipStream_t s);

@@ -57,6 +57,24 @@ __device__ __forceinline__ bool prefix_match(uint64_t k, uint64_t prefix, int d)
   return (k >> sh) == (prefix >> sh);
 }
 
+// residual of shape-local point i for seeding: surface samples are not
+// seeded (their entries read as 0)
+__device__ __forceinline__ float seed_resid(const Dev& D, const ShapeDev& S, const float* __restrict__ resid,
+                                            int64_t i, bool samples) {
+  if (samples) {
+    int64_t off = 0;
+    for (int li = 0; li < S.n_active; ++li) {
+      const LevelDev& L = D.levels[S.lvl0 + li];
+      if (i < off + L.npts) {
+        if (L.kind != kLevelGrid) return 0.f;
+        break;
+      }
+      off += L.npts;
+    }
+  }
+  return resid[S.pt_base + i];
+}
+
 // histogram pass over the shape's points
 __global__ __launch_bounds__(256) void k_sel_hist_points(Dev D, int shape, const float* __restrict__ resid,
                                                          int d) {
@@ -65,12 +83,14 @@ __global__ __launch_bounds__(256) void k_sel_hist_points(Dev D, int shape, const
   const uint64_t prefix = M->prefix;
   // points of the active levels are contiguous from S.pt_base
   int64_t npts = 0;
+  bool samples = false;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
-    npts += (int64_t)L.n * L.n * L.n;
+    npts += L.npts;
+    samples |= L.kind != kLevelGrid;
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = point_key(resid[S.pt_base + i], (uint32_t)i);
+    const uint64_t k = point_key(seed_resid(D, S, resid, i, samples), (uint32_t)i);
     if (prefix_match(k, prefix, d)) atomicAdd(&D.seed_hist[digit(k, d)], 1u);
   }
 }
@@ -134,12 +154,14 @@ __global__ __launch_bounds__(256) void k_collect_cand(Dev D, int shape, const fl
   SeedMisc* M = reinterpret_cast<SeedMisc*>(D.seed_misc);
   const uint64_t T = M->prefix;
   int64_t npts = 0;
+  bool samples = false;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
-    npts += (int64_t)L.n * L.n * L.n;
+    npts += L.npts;
+    samples |= L.kind != kLevelGrid;
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (int64_t)gridDim.x * blockDim.x) {
-    const float r = resid[S.pt_base + i];
+    const float r = seed_resid(D, S, resid, i, samples);
     const uint64_t k = point_key(r, (uint32_t)i);
     if (k <= T && fabsf(r * scale) > floor_abs) {
       const int at = atomicAdd(&M->n_cand, 1);
@@ -154,8 +176,9 @@ __device__ __forceinline__ int locate(const Dev& D, const ShapeDev& S, int64_t g
   int64_t off = 0;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
-    const int64_t np = (int64_t)L.n * L.n * L.n;
+    const int64_t np = L.npts;
     if (g < off + np) {
+      if (L.kind != kLevelGrid) return 0;
       const int64_t loc = g - off;
       li_out = S.lvl0 + li;
       i = (int)(loc % L.n);
@@ -186,6 +209,10 @@ __global__ __launch_bounds__(256) void k_nms(Dev D, int shape, const float* __re
     for (int l = 0; l < S.n_active && ok; ++l) {
       const LevelDev L = D.levels[S.lvl0 + l];
       const int n = L.n;
+      if (L.kind != kLevelGrid) {   // samples do not suppress
+        off += L.npts;
+        continue;
+      }
       // conservative index ranges, then the exact distance test
       int x0 = max(0, (int)floorf((xi - r_nms - L.lo) / L.h) - 1), x1 = min(n - 1, (int)ceilf((xi + r_nms - L.lo) / L.h) + 1);
       int y0 = max(0, (int)floorf((yi - r_nms - L.lo) / L.h) - 1), y1 = min(n - 1, (int)ceilf((yi + r_nms - L.lo) / L.h) + 1);
@@ -204,7 +231,7 @@ __global__ __launch_bounds__(256) void k_nms(Dev D, int shape, const float* __re
           }
         }
       }
-      off += (int64_t)n * n * n;
+      off += L.npts;
     }
     if (ok) {
       const int at = atomicAdd(&M->n_kept, 1);

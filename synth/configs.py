@@ -28,7 +28,7 @@ import numpy as np
 
 from .grid import axis_coords, grid_points
 from .params import random_euler_angles, init_params_from_points, init_params_in_shell, pack_params
-from .sdf import random_shape, sample_sdf, sphere
+from .sdf import random_shape, sample_sdf, sphere, surface_samples
 
 LN = np.log
 
@@ -40,12 +40,16 @@ class LevelData:
     S: np.ndarray               # float32 (n^3,) raw signed distance, x fastest
     band: Optional[float] = None  # training points restricted to |S| < band
     octree: bool = False        # training points: the octree layer below the previous level
+    samples: Optional[np.ndarray] = None  # a surface-sample level: float32 (K, 3) points of P
+    sample_cap: int = 0         # its index slots (>= K); n is then its binning grid
 
     @property
     def npts(self) -> int:
-        return self.n ** 3
+        return self.sample_cap if self.samples is not None else self.n ** 3
 
     def active_mask(self) -> Optional[np.ndarray]:
+        if self.samples is not None:
+            raise ValueError("a sample level has no grid mask")
         if self.octree:
             raise ValueError("an octree level's points follow from its parent level; the library and the "
                              "oracle each build them")
@@ -111,6 +115,8 @@ def _levels(prims, ns, bands, octree=None):
 def _union_points(levels):
     pts, sd = [], []
     for lv in levels:
+        if lv.samples is not None:
+            continue
         p = grid_points(lv.axis)
         act = None if lv.octree else lv.active_mask()
         if act is not None:
@@ -180,12 +186,18 @@ def make_diff(seed: int = 4, n: int = 512, m: int = 65536) -> Problem:
 
 def make_custom(seed: int, ns, m: int, log_scale_range, kinds=("ellipsoid",) * 4,
                 bands=None, cap: int = None, cull_k: float = 3.0, weight_map: int = 0,
-                center_band: float = 0.05, orientation: int = 0, octree=None) -> Problem:
+                center_band: float = 0.05, orientation: int = 0, octree=None, samples=None) -> Problem:
     """Small problems for tests: any level list, any kernel count."""
     rng = _rng(seed)
     prims = random_shape(list(kinds), rng)
     bands = bands or [None] * len(ns)
     levels = _levels(prims, ns, bands, octree)
+    if samples is not None:
+        # (position in the level list, sample count, binning cells per axis, capacity or None)
+        at, count, nbin = samples[:3]
+        cap_s = samples[3] if len(samples) > 3 and samples[3] is not None else count
+        P = surface_samples(prims, count, _rng(seed + 7919))
+        levels.insert(at, LevelData(int(nbin), None, None, None, False, P, int(cap_s)))
     pts, sd = _union_points(levels)
     band = center_band
     while np.count_nonzero(np.abs(sd) < band) < m:

@@ -129,6 +129,30 @@ def _eval_points(prims: Sequence[Primitive], p: np.ndarray, k: float) -> np.ndar
     return d
 
 
+def surface_samples(prims: Sequence[Primitive], count: int, rng: np.random.Generator, k: float = 0.05,
+                    iters: int = 12) -> np.ndarray:
+    """``count`` points on the zero set of the smooth union of ``prims``
+    (the surface samples P): uniform draws in [-1, 1]^3 near the surface,
+    moved onto it by Newton steps along a central-difference gradient.
+    Returns float32 (count, 3), inside [-1, 1]^3, |S| below 1e-5."""
+    out = []
+    have = 0
+    e = 1e-5
+    while have < count:
+        p = rng.uniform(-1.0, 1.0, size=(max(4 * count, 4096), 3))
+        p = p[np.abs(_eval_points(prims, p, k)) < 0.05]
+        for _ in range(iters):
+            d = _eval_points(prims, p, k)
+            g = np.stack([(_eval_points(prims, p + e * u, k) - _eval_points(prims, p - e * u, k)) / (2 * e)
+                          for u in np.eye(3)], axis=1)
+            p = p - (d / np.maximum(np.sum(g * g, axis=1), 1e-12))[:, None] * g
+        p = p.astype(np.float32)
+        ok = np.all(np.abs(p) <= 1.0, axis=1) & (np.abs(_eval_points(prims, p.astype(np.float64), k)) < 1e-5)
+        out.append(p[ok])
+        have += int(ok.sum())
+    return np.concatenate(out)[:count]
+
+
 def _eval_slabs(prims, a, k, z0, z1):
     n = a.size
     yy, xx = np.meshgrid(a, a, indexing="ij")

@@ -30,10 +30,14 @@ def record(name, **vals):
 
 
 def oracle_levels(prob, with_targets=True):
-    S_all = [lv.S for lv in prob.levels]
+    S_all = [lv.S for lv in prob.levels if lv.samples is None]
     m = O.sdf_min(S_all)
     out, t32 = [], []
     for li, lv in enumerate(prob.levels):
+        if lv.samples is not None:
+            out.append(O.make_samples(lv.samples, lv.sample_cap))
+            t32.append(None)
+            continue
         t = O.targets_from_sdf(lv.S, m).astype(np.float32) if with_targets else None
         t32.append(t)
         if lv.octree:
@@ -68,12 +72,20 @@ class GpuProblem:
         self.prob = prob
         nl = len(prob.levels) if n_levels is None else n_levels
         wm = prob.weight_map if weight_map is None else weight_map
-        self.ctx = core.Context([([lv.n for lv in prob.levels[:nl]], prob.cap)],
+        samp = [lv.sample_cap if lv.samples is not None else 0 for lv in prob.levels[:nl]]
+        self.ctx = core.Context([([lv.n for lv in prob.levels[:nl]], prob.cap, samp)],
                                 pair_cap or pair_cap_estimate(prob), prob.cull_k, wm,
                                 orientation=prob.orientation, batch_cap=batch_cap)
         dev = self.ctx.device
         self.axes, self.tgts, self.sdfs, self.bits = [], [], [], []
         for li, lv in enumerate(prob.levels[:nl]):
+            if lv.samples is not None:
+                xyz = torch.from_numpy(np.ascontiguousarray(lv.samples, np.float32)).to(dev)
+                for lst, v in ((self.axes, None), (self.tgts, None), (self.sdfs, None), (self.bits, None)):
+                    lst.append(v)
+                self.samples = xyz
+                self.ctx.erbf_refine_samples(0, xyz)
+                continue
             ax = torch.from_numpy(np.asarray(lv.axis, np.float32)).to(dev)
             S = torch.from_numpy(np.asarray(lv.S, np.float32)).to(dev)
             t = None if targets is None or targets[li] is None else torch.from_numpy(targets[li]).to(dev)
@@ -96,7 +108,8 @@ class GpuProblem:
         out = []
         for li, n in enumerate(self.ctx.level_ns[0][:self.ctx.n_active[0]]):
             b = self.ctx.pt_base[0][li]
-            out.append(a[b:b + n ** 3])
+            k = self.ctx.level_samples[0][li]
+            out.append(a[b:b + (k if k > 0 else n ** 3)])
         return out
 
     def grads_np(self, g):

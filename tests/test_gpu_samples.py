@@ -1,0 +1,144 @@
+"""Surface samples P (label 1; the training set V = {G, P} of Section 3.4.2)
+on the device against the oracle: the full step with a sample level between
+two grid levels, one crowded sample tile, the VJP, a mini-batch mixing grid
+points and samples, seeding next to samples, and the inscribed-sphere
+initialisation with the nearest-sample depth of Algorithm 1."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import TAU1, TAU2, GpuProblem, oracle_grads_dict, oracle_levels, record, rel_inf
+from test_gpu_parity import _loss_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _problem(seed, nbin=32, count=3000, cap=3010, levels=(16, 24), m=40, kcap=None):
+    return synth.make_custom(seed, list(levels), m, (1.6, 2.6), kinds=("ellipsoid", "torus", "capsule"),
+                             samples=(1, count, nbin, cap), cap=kcap)
+
+
+def test_step_with_samples_between_grid_levels():
+    prob = _problem(81)
+    gp, g, st = _loss_case("loss_samples", prob, O.MODE_DYNAMIC, l1_active=True, tau_m=10.0)
+    # every sample is a training point with label 1
+    assert st.n_idall >= 3000
+
+
+def test_step_with_one_crowded_sample_tile():
+    # an 8-cell binning grid: all 5000 samples share one tile (several
+    # 256-sample passes in the forward, several 1024-sample stages in the
+    # backward)
+    prob = _problem(82, nbin=8, count=5000, cap=5000)
+    _loss_case("loss_samples_one_tile", prob, O.MODE_FIXED, lam=1e-4)
+
+
+def test_vjp_with_samples():
+    torch = _torch()
+    prob = _problem(83)
+    olv, t32, _ = oracle_levels(prob, with_targets=False)
+    gp = GpuProblem(prob, None)
+    rng = np.random.default_rng(4)
+    up = rng.normal(size=gp.ctx.n_points).astype(np.float32)
+    g = gp.ctx.erbf_vjp(gp.p, gp.m_dev, torch.from_numpy(up).to(gp.ctx.device))
+    torch.cuda.synchronize()
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    G, base = [], 0
+    for lv in olv:
+        G.append(np.where(lv.act(), up[base:base + lv.npts].astype(np.float64), 0.0))
+        base += lv.npts
+    ref = O.backward(olv, K, G)
+    go, gg = oracle_grads_dict(ref), gp.grads_np(g)
+    errs = {k: rel_inf(gg[k], go[k]) for k in go}
+    record("vjp_samples", **errs)
+    for k in go:
+        assert errs[k] <= 1e-4, (k, errs[k])
+
+
+def test_minibatch_mixing_grid_points_and_samples():
+    torch = _torch()
+    prob = _problem(84)
+    olv, t32, _ = oracle_levels(prob)
+    pts, base = [], 0
+    for lv in olv:
+        pts.append(base + np.nonzero(lv.act())[0])
+        base += lv.npts
+    pts = np.concatenate(pts).astype(np.int64)
+    batch = np.random.default_rng(6).permutation(pts)[: int(0.3 * pts.size)]
+    gp = GpuProblem(prob, t32, batch_cap=batch.size)
+    f = torch.zeros(batch.size, device=gp.ctx.device)
+    kw = dict(mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2)
+    g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
+    torch.cuda.synchronize()
+    st = gp.ctx.stats()[0]
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    ref = O.step_batch(olv, K, batch, **kw)
+    f_or = np.concatenate(ref.f)[batch]
+    e_f = float(np.abs(f.cpu().numpy() - f_or).max() / np.abs(f_or).max())
+    go, gg = oracle_grads_dict(ref.grads), gp.grads_np(g)
+    errs = {k: rel_inf(gg[k], go[k]) for k in go}
+    n_samp = int(((batch >= gp.ctx.pt_base[0][1]) & (batch < gp.ctx.pt_base[0][2])).sum())
+    record("minibatch_samples", e_f=e_f, batch_samples=n_samp, n_idall=(st.n_idall, ref.loss.n_idall),
+           P_fwd=(st.P_fwd, ref.P_fwd), P_bwd=(st.P_bwd, ref.P_bwd), **errs)
+    assert n_samp > 100
+    assert e_f <= 1e-5
+    assert st.n_idall == ref.loss.n_idall and st.P_fwd == ref.P_fwd and st.P_bwd == ref.P_bwd
+    assert abs(st.L2 - ref.loss.L2) <= 1e-5 * ref.loss.L2
+    for k in go:
+        assert errs[k] <= 1e-4, (k, errs[k])
+
+
+def test_seeding_next_to_samples_ignores_them():
+    # the same grid residual seeds the same kernels with and without a
+    # sample level registered, whatever the residual at the samples
+    torch = _torch()
+    prob = _problem(85, kcap=200)
+    plain = synth.make_custom(85, [16, 24], 40, (1.6, 2.6), kinds=("ellipsoid", "torus", "capsule"), cap=200)
+    _, t32, _ = oracle_levels(prob)
+    _, t32p, _ = oracle_levels(plain)
+    rng = np.random.default_rng(7)
+    out = []
+    for pr, tt in ((prob, t32), (plain, t32p)):
+        gp = GpuProblem(pr, tt)
+        parts, gi = [], 0
+        for lv in pr.levels:
+            if lv.samples is not None:
+                parts.append(rng.normal(size=lv.npts).astype(np.float32) * 5.0)
+            else:
+                parts.append(np.random.default_rng(100 + gi).normal(size=lv.npts).astype(np.float32))
+                gi += 1
+        resid = torch.from_numpy(np.concatenate(parts)).to(gp.ctx.device)
+        n_grid = sum(lv.npts for lv in pr.levels if lv.samples is None)
+        n = gp.ctx.erbf_seed_from_error(gp.p, gp.m_dev, 0, resid, 1.0, n_grid, top_frac=0.01, k_new=32,
+                                        r_nms=0.0, eps=1e-7)
+        torch.cuda.synchronize()
+        P = gp.p.cpu().numpy().reshape(11, pr.cap)
+        out.append((n, P[:, pr.m:pr.m + n].copy()))
+    assert out[0][0] == out[1][0] > 0
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_init_with_samples_uses_the_nearest_sample_depth():
+    torch = _torch()
+    prob = _problem(86, nbin=32, count=2000, cap=2000)
+    prob.cap = 4096
+    prob.params = np.zeros(11 * prob.cap, np.float32)
+    prob.m = 0
+    lv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32, pair_cap=1 << 20)
+    nc, left = gp.ctx.erbf_init_inscribed(gp.p, gp.m_dev, 0, gamma=float(np.float32(1e-3)))
+    torch.cuda.synchronize()
+    ref = O.inscribed_sphere_init(lv, gamma=float(np.float32(1e-3)), m_max=prob.cap)
+    assert nc == ref.index.size > 10 and left == ref.n_left
+    P = gp.p.cpu().numpy().reshape(11, prob.cap)[:, :nc].astype(np.float64)
+    assert np.array_equal(P[0], ref.w) and np.array_equal(P[1:4].T, ref.c)
+    err_s = float(np.abs(P[4:7].T - ref.s).max())
+    record("init_samples", centres=nc, left=left, err_s=err_s)
+    assert err_s <= 1e-6 * max(1.0, float(np.abs(ref.s).max()))
