@@ -229,6 +229,42 @@ def minibatch_bench(steps, warmup, batch=10000):
             "ms_per_epoch": ms * (-(-pts.size // batch))}
 
 
+def variant_bench(kind, steps, warmup):
+    """The step on a variant of the large snapshot: octree layers in place of
+    the band (kind "octree"), or the snapshot plus 40 000 surface samples
+    (kind "samples", the paper's sample count)."""
+    import torch
+    import synth
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    if kind == "octree":
+        prob = synth.make_large_snapshot(octree=True)
+        what = "64^3 + octree layers 128^3, 256^3 (parent |S| <= half-diagonal), 16384 ERBFs, seed 2"
+    else:
+        prob = synth.make_large_snapshot(samples=40000)
+        what = "large_snapshot + 40000 surface samples (label 1) binned on 64^3 cells, 16384 ERBFs, seed 2"
+    fit = Fitter([ShapeInput.from_problem(prob)], cull_k=prob.cull_k, all_levels=True)
+    kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
+    for _ in range(warmup):
+        fit.step(**kw)
+    torch.cuda.synchronize()
+    fit.ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fit.step(**kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = fit.stats()[0]
+    if st.flags:
+        raise SystemExit(f"{kind}: bucket overflow")
+    pts = int(fit.training_points(0).size)
+    log(f"{kind}: {1e3 * wall / steps:.3f} ms/step over {pts} training points")
+    return {"workload": what, "training_points": pts, "steps": steps, "ms_per_step": 1e3 * wall / steps,
+            "pairs_per_s": (st.P_fwd_total + st.P_bwd_total) / wall,
+            "P_fwd_per_step": st.P_fwd_total / steps, "P_bwd_per_step": st.P_bwd_total / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +276,8 @@ def main():
     ap.add_argument("--batching", action="store_true", help="add the 64-shape batched-vs-plain comparison")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
+    ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
+    ap.add_argument("--samples", action="store_true", help="add the step with 40000 surface samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help=f"copy {COPY_CAL_BYTES} bytes device-to-device before the warm-up (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -378,6 +416,10 @@ def main():
         out["init"] = init_bench(with_cpu=not args.no_cpu_baseline)
     if args.minibatch:
         out["minibatch"] = minibatch_bench(max(args.steps, 20), args.warmup)
+    if args.octree:
+        out["octree"] = variant_bench("octree", args.steps, args.warmup)
+    if args.samples:
+        out["samples"] = variant_bench("samples", args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)

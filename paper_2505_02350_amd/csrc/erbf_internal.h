@@ -16,6 +16,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kVariantFwdPersistent = 1;   // forward tiles walked by a persistent grid
 constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persistent grid
 
+constexpr int kSampSplit = 16;     // workgroups per active sample tile (parts of its kernel list)
 constexpr int kLevelGrid = 0;      // cell-centred grid of n^3 points
 constexpr int kLevelSamples = 1;   // surface samples binned into the tiles of an n^3-cell grid
 
@@ -122,6 +123,9 @@ struct Dev {
   int32_t* samp_slot;       // [total sample capacity]
   int32_t* samp_slots;      // [sample-level tiles] slots of every active sample tile
   int32_t n_samp_slots;     // entries of samp_slots in use
+  float* samp_f;            // [total sample capacity * kSampSplit] forward sum of each (sample, list part)
+  int32_t* samp_c;          // [total sample capacity * kSampSplit] its in-ball pair count
+  int64_t* samp_pb;         // [sample-level tiles * kSampSplit] backward pair counts of each list part
   // inscribed-sphere initialisation scratch: nearest-sample squared
   // distances (double, init_cand_cap), candidate mask (init_words), two
   // candidate lists (init_cand_cap each) and 8 result words

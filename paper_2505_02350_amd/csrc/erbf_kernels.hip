@@ -822,9 +822,63 @@ __global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __r
 // the pair arithmetic is the grid kernels' expression for expression.
 // ---------------------------------------------------------------------------
 
-template <bool LOSS>
-__global__ __launch_bounds__(256) void k_sample_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
+// Each active sample tile's kernel list is cut into kSampSplit contiguous
+// parts (in the backward, whole rounds of 256 kernels), one workgroup each.  Forward: the part's kernel records are staged
+// in LDS and every lane takes one sample of the tile, so a record serves
+// 256 samples; each (sample, part) sum goes to a scratch slot, and a second
+// pass adds a sample's parts in order, forms E and G and the tile's
+// statistics.  Backward: every lane takes one kernel of the part and walks
+// the tile's samples, staged in LDS with their G.
+__global__ __launch_bounds__(256) void k_sample_forward(Dev D) {
   __shared__ float4 srec[kFwdChunk * 3];
+  const int slot = D.samp_slots[blockIdx.x];
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  const int tid = threadIdx.x;
+  const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  const int64_t part = (end - beg + kSampSplit - 1) / kSampSplit;
+  const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
+  const int64_t gbase = L.spos - D.samp_pos;   // this level's first entry of the sorted sample arrays
+  for (int sb = s0; sb < s1; sb += 256) {
+    const int si = sb + tid;
+    const bool valid = si < s1;
+    const float4 P = valid ? L.spos[si] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+    float acc = 0.f;
+    int cnt = 0;
+    for (int64_t c0 = rb; c0 < re; c0 += kFwdChunk) {
+      const int nc = (int)min((int64_t)kFwdChunk, re - c0);
+      __syncthreads();   // the previous chunk's records are no longer read
+      if (tid < nc) {
+        const int j = D.items[c0 + tid];
+        srec[3 * tid] = D.rec[3 * j];
+        srec[3 * tid + 1] = D.rec[3 * j + 1];
+        srec[3 * tid + 2] = D.rec[3 * j + 2];
+      }
+      __syncthreads();
+      for (int k = 0; k < nc; ++k) {
+        const float4 a0 = srec[3 * k], a1 = srec[3 * k + 1], a2 = srec[3 * k + 2];
+        const float dx = P.x - a0.x, dy = P.y - a0.y, dz = P.z - a0.z;
+        const bool in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < a0.w;
+        float q = fmaf(dx, fmaf(a1.x, dx, fmaf(a1.w, dy, a2.x * dz)), fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz));
+        q = in ? q : INFINITY;
+        acc = fmaf(a2.z, fast_exp2(-q), acc);
+        cnt += in ? 1 : 0;
+      }
+    }
+    if (valid) {
+      const int64_t o = (gbase + si) * kSampSplit + blockIdx.y;
+      D.samp_f[o] = acc;
+      D.samp_c[o] = cnt;
+    }
+  }
+}
+
+// per sample tile: each sample's parts added in order, f, E = f - 1 and
+// G = 2E, and the tile's statistics
+template <bool LOSS>
+__global__ __launch_bounds__(256) void k_sample_fwd_final(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
   __shared__ double red_d[4];
   __shared__ float red_f[4];
   __shared__ int red_i[4];
@@ -834,52 +888,32 @@ __global__ __launch_bounds__(256) void k_sample_forward(Dev D, float* __restrict
   const LevelDev L = D.levels[lt.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
-  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  const int64_t gbase = L.spos - D.samp_pos;
   double l2 = 0.0;
   float mxe = 0.f;
   int cnt_id = 0;
   int64_t pfw = 0;
-  for (int sb = s0; sb < s1; sb += 256) {
-    const int si = sb + tid;
-    const bool valid = si < s1;
-    const float4 P = valid ? L.spos[si] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
-    float acc = 0.f;
+  for (int si = s0 + tid; si < s1; si += 256) {
+    float f = 0.f;
     int pf = 0;
-    for (int64_t c0 = beg; c0 < end; c0 += kFwdChunk) {
-      const int cnt = (int)min((int64_t)kFwdChunk, end - c0);
-      __syncthreads();   // the previous chunk's records are no longer read
-      if (tid < cnt) {
-        const int j = D.items[c0 + tid];
-        srec[3 * tid] = D.rec[3 * j];
-        srec[3 * tid + 1] = D.rec[3 * j + 1];
-        srec[3 * tid + 2] = D.rec[3 * j + 2];
-      }
-      __syncthreads();
-      for (int k = 0; k < cnt; ++k) {
-        const float4 a0 = srec[3 * k], a1 = srec[3 * k + 1], a2 = srec[3 * k + 2];
-        const float dx = P.x - a0.x, dy = P.y - a0.y, dz = P.z - a0.z;
-        const bool in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < a0.w;
-        float q = fmaf(dx, fmaf(a1.x, dx, fmaf(a1.w, dy, a2.x * dz)), fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz));
-        q = in ? q : INFINITY;
-        acc = fmaf(a2.z, fast_exp2(-q), acc);
-        pf += in ? 1 : 0;
-      }
+    const int64_t o = (gbase + si) * kSampSplit;
+#pragma unroll
+    for (int y = 0; y < kSampSplit; ++y) {
+      f += D.samp_f[o + y];
+      pf += D.samp_c[o + y];
     }
-    if (valid) {
-      const int64_t idx = L.pt_base + __float_as_int(P.w);
-      if (f_out) f_out[idx] = acc;
-      if (LOSS) {
-        const float t = 1.f, f = acc;
-        const bool id = (tau1 < t && t < tau2) || (t <= tau1 && f > tau1) || (t >= tau2 && f < tau2);
-        const float E = id ? f - t : 0.f;
-        D.G[idx] = 2.f * E;
-        l2 += (double)E * (double)E;
-        mxe = fmaxf(mxe, fabsf(E));
-        cnt_id += id ? 1 : 0;
-      }
-      pfw += pf;
+    const int64_t idx = L.pt_base + __float_as_int(L.spos[si].w);
+    if (f_out) f_out[idx] = f;
+    if (LOSS) {
+      const float t = 1.f;   // surface samples carry label 1
+      const bool id = (tau1 < t && t < tau2) || (t <= tau1 && f > tau1) || (t >= tau2 && f < tau2);
+      const float E = id ? f - t : 0.f;
+      D.G[idx] = 2.f * E;
+      l2 += (double)E * (double)E;
+      mxe = fmaxf(mxe, fabsf(E));
+      cnt_id += id ? 1 : 0;
     }
+    pfw += pf;
   }
   l2 = wave_sum(l2);
   mxe = wave_max_f(mxe);
@@ -897,10 +931,6 @@ __global__ __launch_bounds__(256) void k_sample_forward(Dev D, float* __restrict
   }
 }
 
-// backward moments of a sample tile: lanes own kernels of the list (64 per
-// wave, 256 per round), the tile's samples are staged in LDS with their G,
-// and each lane sums T0 = sum g, T1 = sum g D, T2 = sum g D D^T over them in
-// order (g = G exp(-D^T A D)), stored at the entry's kernel-major index
 __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restrict__ Gsrc) {
   constexpr int kStage = 1024;
   __shared__ float4 sp[kStage];
@@ -914,18 +944,21 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   for (int si = s0 + tid; si < s1; si += 256) nz |= Gsrc[L.pt_base + __float_as_int(L.spos[si].w)] != 0.f ? 1 : 0;
   if (!__syncthreads_or(nz)) {
     if (tid == 0) {
-      D.tile_nz[slot] = 0;
-      D.tile_pbwd[slot] = 0;
+      if (blockIdx.y == 0) D.tile_nz[slot] = 0;
+      D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = 0;
     }
     return;
   }
-  if (tid == 0) D.tile_nz[slot] = 1;
+  if (tid == 0 && blockIdx.y == 0) D.tile_nz[slot] = 1;
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  // parts of whole rounds of 256 kernels, so that every lane has one
+  const int64_t part = (((end - beg + kSampSplit - 1) / kSampSplit + 255) / 256) * 256;
+  const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
   int64_t pb = 0;
-  for (int64_t c0 = beg; c0 < end; c0 += 256) {
-    const int64_t e = c0 + 64 * wv + lane;
-    const bool have = e < end;
+  for (int64_t c0 = rb; c0 < re; c0 += 256) {
+    const int64_t e = c0 + tid;
+    const bool have = e < re;
     float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
            r2 = make_float4(0.f, 0.f, 0.f, 0.f);
     int e_out = 0;
@@ -979,7 +1012,16 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   pb = wave_sum(pb);
   if (lane == 0) spb[wv] = pb;
   __syncthreads();
-  if (tid == 0) D.tile_pbwd[slot] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
+  if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
+}
+
+// per sample tile: in-ball pairs with G != 0 of its kSampSplit waves
+__global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= D.n_samp_slots) return;
+  int64_t t = 0;
+  for (int y = 0; y < kSampSplit; ++y) t += D.samp_pb[(int64_t)i * kSampSplit + y];
+  D.tile_pbwd[D.samp_slots[i]] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -1728,10 +1770,11 @@ hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, fl
     launch_timed(k_forward<false>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
   }
   if (D.n_samp_slots > 0) {
+    hipLaunchKernelGGL(k_sample_forward, dim3(D.n_samp_slots, kSampSplit), dim3(256), 0, s, D);
     if (loss)
-      hipLaunchKernelGGL(k_sample_forward<true>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+      hipLaunchKernelGGL(k_sample_fwd_final<true>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
     else
-      hipLaunchKernelGGL(k_sample_forward<false>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
+      hipLaunchKernelGGL(k_sample_fwd_final<false>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
   }
   return hipGetLastError();
 }
@@ -1745,7 +1788,10 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
   } else if (n_slots > 0) {
     launch_timed(k_bwd_tiles, dim3(n_slots), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G);
   }
-  if (D.n_samp_slots > 0) hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots), dim3(256), 0, s, D, G);
+  if (D.n_samp_slots > 0) {
+    hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, kSampSplit), dim3(256), 0, s, D, G);
+    hipLaunchKernelGGL(k_sample_bwd_sum, dim3(nblk(D.n_samp_slots, 64)), dim3(64), 0, s, D);
+  }
   launch_timed(k_bwd_reduce, dim3(D.cap_total), dim3(64), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
                grad);
   return hipGetLastError();

@@ -31,15 +31,19 @@ def estimate_pair_cap(level_ns: Sequence[int], s_min: np.ndarray, cull_k: float,
 
 
 class ShapeInput:
-    """Host inputs of one shape: level resolutions, axes, raw SDFs, bands, and
-    which levels are octree layers below the previous one."""
+    """Host inputs of one shape: level resolutions, axes, raw SDFs, bands,
+    which levels are octree layers below the previous one, and which are
+    surface-sample levels (samples[i]: float32 (K, 3) points, sample_caps[i]
+    their index slots; axes/sdfs/bands entries of such a level are None)."""
 
-    def __init__(self, level_ns, axes, sdfs, bands, params, m, cap, octree=None):
+    def __init__(self, level_ns, axes, sdfs, bands, params, m, cap, octree=None, samples=None, sample_caps=None):
         self.level_ns = list(level_ns)
         self.axes = list(axes)
         self.sdfs = list(sdfs)
         self.bands = list(bands)
         self.octree = list(octree) if octree is not None else [False] * len(self.level_ns)
+        self.samples = list(samples) if samples is not None else [None] * len(self.level_ns)
+        self.sample_caps = list(sample_caps) if sample_caps is not None else [0] * len(self.level_ns)
         self.params = np.asarray(params, np.float32)
         self.m = int(m)
         self.cap = int(cap)
@@ -48,7 +52,8 @@ class ShapeInput:
     def from_problem(cls, prob):
         return cls([lv.n for lv in prob.levels], [lv.axis for lv in prob.levels],
                    [lv.S for lv in prob.levels], [lv.band for lv in prob.levels], prob.params, prob.m,
-                   prob.cap, [lv.octree for lv in prob.levels])
+                   prob.cap, [lv.octree for lv in prob.levels], [lv.samples for lv in prob.levels],
+                   [lv.sample_cap if lv.samples is not None else 0 for lv in prob.levels])
 
     def s_min(self):
         seg = self.params.reshape(11, self.cap)[:, :self.m]
@@ -66,17 +71,22 @@ class Fitter:
         self.dev = torch.device("cuda", device)
         if pair_cap is None:
             pair_cap = sum(estimate_pair_cap(s.level_ns, s.s_min(), cull_k) for s in shapes)
-        self.ctx = core.Context([(s.level_ns, s.cap) for s in shapes], pair_cap, cull_k, weight_map, device,
-                                orientation, batch_cap)
+        self.ctx = core.Context([(s.level_ns, s.cap, s.sample_caps) for s in shapes], pair_cap, cull_k, weight_map,
+                                device, orientation, batch_cap)
         self._levels = []
         # eq. 3-10's m: minimum over every level of a shape, computed on the device
         self.m_sdf = torch.zeros(len(shapes), dtype=torch.float32, device=self.dev)
         self.S_dev = []
         for b, s in enumerate(shapes):
             row = []
+            first = True
             for li, S in enumerate(s.sdfs):
+                if s.samples[li] is not None:   # surface samples: no grid SDF
+                    row.append(torch.from_numpy(np.ascontiguousarray(s.samples[li], np.float32)).to(self.dev))
+                    continue
                 Sd = torch.from_numpy(np.ascontiguousarray(S, np.float32)).to(self.dev)
-                core.erbf_sdf_min(Sd, self.m_sdf[b:b + 1], accumulate=li > 0)
+                core.erbf_sdf_min(Sd, self.m_sdf[b:b + 1], accumulate=not first)
+                first = False
                 row.append(Sd)
             self.S_dev.append(row)
         m_host = self.m_sdf.cpu().numpy()
@@ -105,6 +115,12 @@ class Fitter:
         s = self.shapes[b]
         li = self.next_level[b]
         Sd = self.S_dev[b][li]
+        if s.samples[li] is not None:
+            self.ctx.erbf_refine_samples(b, Sd)
+            self._bits[b].append(None)
+            self._levels.append((Sd,))
+            self.next_level[b] += 1
+            return
         ax = torch.from_numpy(np.ascontiguousarray(s.axes[li], np.float32)).to(self.dev)
         t = core.erbf_targets_from_sdf(Sd, float(self._m_host[b]))
         if s.octree[li]:
@@ -195,6 +211,9 @@ class Fitter:
         s = self.shapes[b]
         out = []
         for li in range(self.next_level[b]):
+            if s.samples[li] is not None:
+                out.append(self.ctx.pt_base[b][li] + np.arange(len(s.samples[li])))
+                continue
             S = np.asarray(s.sdfs[li], np.float32).reshape(-1)
             if self._bits[b][li] is not None:
                 words = self._bits[b][li].cpu().numpy().view(np.uint32)

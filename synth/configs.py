@@ -138,14 +138,24 @@ def make_large(seed: int = 2, ns=(64, 128, 256), m0: int = 1024, cap: int = 1638
                    lr=1e-2, steps=1000, extra={"prims": prims})
 
 
-def make_large_snapshot(seed: int = 2, ns=(64, 128, 256), m: int = 16384) -> Problem:
+def make_large_snapshot(seed: int = 2, ns=(64, 128, 256), m: int = 16384, octree: bool = False,
+                        samples: int = 0, sample_bins: int = 64) -> Problem:
     """Timing snapshot of the large hierarchy: all three levels active and
-    ``m`` kernels drawn with the init rule over the union of their points."""
+    ``m`` kernels drawn with the init rule over the union of their points.
+    ``octree`` makes the finer levels octree layers (in place of the band of
+    the finest); ``samples`` > 0 appends that many surface samples binned on
+    ``sample_bins`` cells per axis."""
     rng = _rng(seed)
     prims = _large_shape(rng)
-    levels = _levels(prims, ns, [None] * (len(ns) - 1) + [0.1])
+    if octree:
+        levels = _levels(prims, ns, [None] * len(ns), [False] + [True] * (len(ns) - 1))
+    else:
+        levels = _levels(prims, ns, [None] * (len(ns) - 1) + [0.1])
     pts, sd = _union_points(levels)
     w, c, s, q = init_params_from_points(pts, sd, m, (LN(16), LN(64)), rng)
+    if samples > 0:
+        P = surface_samples(prims, samples, _rng(seed + 7919))
+        levels.append(LevelData(int(sample_bins), None, None, None, False, P, int(samples)))
     return Problem("large_snapshot", levels, pack_params(w, c, s, q), m, m, cull_k=3.0,
                    lr=1e-2, steps=1000, extra={"prims": prims})
 
