@@ -18,3 +18,4 @@ their docstring.
 
 from .erbf import *  # noqa: F401,F403
 from . import schedule  # noqa: F401,E402
+from . import metrics  # noqa: F401,E402
