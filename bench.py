@@ -265,6 +265,59 @@ def variant_bench(kind, steps, warmup):
             "P_fwd_per_step": st.P_fwd_total / steps, "P_bwd_per_step": st.P_bwd_total / steps}
 
 
+def surface_bench(n_samples=100000, with_cpu=True):
+    """Surface evaluation of Section 4 at the paper's sample count: the zero
+    set of the large workload's 256^3 signed distance against that of a
+    stand-in reconstruction (the field sent through eq. 3-10 and back, moved
+    by 0.004), each extracted by marching tetrahedra, 10^5 area-uniform
+    samples each (seeded uniforms), then HD / CD / CS."""
+    import torch
+    import synth
+    from paper_2505_02350_amd import core
+    prob = synth.make_large()
+    lv = prob.levels[2]
+    n = lv.n
+    dev = torch.device("cuda")
+    ax = torch.from_numpy(np.asarray(lv.axis, np.float32)).to(dev)
+    S = torch.from_numpy(np.asarray(lv.S, np.float32)).to(dev)
+    m = float(np.float32(min(float(np.min(l.S)) for l in prob.levels)))
+    t = core.erbf_targets_from_sdf(S, m)
+    Sr = core.erbf_sdf_from_targets(t, m) + 0.004
+    rng = np.random.default_rng(17)
+    ut = torch.from_numpy(rng.random((n_samples, 3)).astype(np.float32)).to(dev)
+    ur = torch.from_numpy(rng.random((n_samples, 3)).astype(np.float32)).to(dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, 1e3 * (time.perf_counter() - t0)
+
+    core.erbf_surface_extract(S, n, ax, 0.0)   # warm-up (module load, allocator)
+    Tt, ms_et = timed(lambda: core.erbf_surface_extract(S, n, ax, 0.0, tri_cap=4 * n * n * 6))
+    Tr, ms_er = timed(lambda: core.erbf_surface_extract(Sr, n, ax, 0.0, tri_cap=4 * n * n * 6))
+    (Pt, Nt, _), ms_st = timed(lambda: core.erbf_surface_sample(Tt, ut))
+    (Pr, Nr, _), ms_sr = timed(lambda: core.erbf_surface_sample(Tr, ur))
+    (hd, cd, cs), ms_m = timed(lambda: core.erbf_surface_metrics(Pt, Nt, Pr, Nr))
+    log(f"surface: {Tt.shape[0]} / {Tr.shape[0]} triangles, extract {ms_et:.1f} ms, sample {ms_st:.1f} ms, "
+        f"metrics {ms_m:.1f} ms; HD {hd:.4g} CD {cd:.4g} CS {cs:.6f}")
+    out = {"workload": "large (seed 2) 256^3 signed distance vs the same through eq. 3-10 and back, moved by 0.004; "
+                       f"{n_samples} samples per surface",
+           "triangles": [int(Tt.shape[0]), int(Tr.shape[0])], "extract_ms": [ms_et, ms_er],
+           "sample_ms": [ms_st, ms_sr], "metrics_ms": ms_m, "pairs_per_s_metrics": 2.0 * n_samples * n_samples /
+           (ms_m * 1e-3), "HD": hd, "CD": cd, "CS": cs}
+    if with_cpu:
+        from oracle import metrics as Mx
+        a = [x.cpu().numpy() for x in (Pt, Nt, Pr, Nr)]
+        t0 = time.perf_counter()
+        ref = Mx.surface_metrics(*a)
+        out["cpu_baseline"] = {"value": 1e3 * (time.perf_counter() - t0), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": "the metrics stage on the same point sets (k-d trees)",
+                               "metrics": list(ref)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +331,7 @@ def main():
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
     ap.add_argument("--samples", action="store_true", help="add the step with 40000 surface samples")
+    ap.add_argument("--surface", action="store_true", help="add the surface evaluation (HD / CD / CS) timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help=f"copy {COPY_CAL_BYTES} bytes device-to-device before the warm-up (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -420,6 +474,8 @@ def main():
         out["octree"] = variant_bench("octree", args.steps, args.warmup)
     if args.samples:
         out["samples"] = variant_bench("samples", args.steps, args.warmup)
+    if args.surface:
+        out["surface"] = surface_bench(with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)

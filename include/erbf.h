@@ -314,6 +314,52 @@ int erbf_init_inscribed(erbf_ctx* ctx, const erbf_params* params, int32_t shape,
                         int32_t max_centres, float* m1, float* m2, int32_t* n_centres,
                         int64_t* n_left, hipStream_t stream);
 
+/* ---- surface evaluation (Section 4, Evaluation Metric) -------------------- */
+
+/* S[i] = m + sqrt(ln(2 / t[i]) / h), h = ln 2 / m^2: eq. 3-10 inverted on
+ * its branch S >= m (t >= 2 gives m; t <= 0 gives +inf), in double, rounded
+ * once.  Takes the network's normalised output back to a signed distance
+ * before its zero-level surface is extracted.  m < 0. */
+int erbf_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t stream);
+
+/* Device scratch bytes of erbf_surface_extract for a grid of n points per
+ * axis, 2 <= n <= 1024. */
+int erbf_surface_scratch_size(int32_t n, size_t* bytes);
+
+/* The iso-surface of the grid field F (device [n^3], x fastest, on the
+ * cell-centred axis, device [n]) by marching tetrahedra: each cube of eight
+ * neighbouring points is split into six tetrahedra around its main diagonal;
+ * a tetrahedron whose corners straddle iso (inside: F < iso) gives one or two
+ * triangles with vertices interpolated linearly along its straddling edges.
+ * Triangles come out in cube order (x fastest), then tetrahedron and case
+ * order: tris device [tri_cap * 9] (x, y, z of three vertices each).
+ * Synchronous; *n_tris receives the count.  ERBF_ERR_CAPACITY (nothing
+ * written, *n_tris the count needed) when it exceeds tri_cap. */
+int erbf_surface_extract(const float* F, int32_t n, const float* axis, float iso, void* scratch,
+                         size_t scratch_bytes, float* tris, int64_t tri_cap, int64_t* n_tris,
+                         hipStream_t stream);
+
+/* Points uniform by area on the triangles (the paper samples 10^5 per
+ * surface): u device [n_samples * 3] uniforms in [0, 1) chosen by the
+ * caller; sample s takes the first triangle whose running area sum (double,
+ * a blocked scan in a fixed order) exceeds u0 times the total, and the point
+ * (1 - sqrt(u1)) A + sqrt(u1) (1 - u2) B + sqrt(u1) u2 C.  area_scratch:
+ * device [n_tris + ceil(n_tris / 1024)] doubles; pts, normals: device
+ * [n_samples * 3] (unit triangle normals);
+ * tri_index: device [n_samples] or NULL. */
+int erbf_surface_sample(const float* tris, int64_t n_tris, const float* u, int64_t n_samples,
+                        double* area_scratch, float* pts, float* normals, int32_t* tri_index,
+                        hipStream_t stream);
+
+/* HD, CD and CS between the point set Pt (normals Nt) of the ground-truth
+ * surface and Pr (Nr) of the reconstructed one, each point's closest point
+ * in the other set by Euclidean distance (ties to the lower index):
+ * out[0] = HD, the largest closest distance either way; out[1] = CD, half
+ * the mean closest distance each way; out[2] = CS, half the mean |n . n'|
+ * each way.  scratch: device [2 (nt + nr)] doubles; out: device [3]. */
+int erbf_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
+                         int64_t nr, double* scratch, double* out, hipStream_t stream);
+
 /* ---- training control (Algorithm 3) -------------------------------------- */
 
 /* Constants of Algorithm 3 (paper values in parentheses). */

@@ -15,7 +15,7 @@ Readings (the paper's extraction method is an external one):
   inverting eq. 3-10 on its branch S >= m, and its surface is that field's
   zero set;
 - points are sampled uniformly by area: a triangle chosen with probability
-  proportional to its area (cumulative areas in float64, summed in order),
+  proportional to its area (cumulative areas in float64),
   then a uniform point on it; the normal is the triangle's unit normal (the
   metric uses |cos|, so orientation does not matter);
 - HD, CD and CS as printed, with closest points by Euclidean distance.

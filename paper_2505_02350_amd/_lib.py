@@ -130,6 +130,12 @@ _SIGS = [
     ("erbf_init_inscribed", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_float,
                                            ctypes.c_int32, _V, _V, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int64), _V]),
+    ("erbf_sdf_from_targets", ctypes.c_int, [_V, ctypes.c_int64, ctypes.c_float, _V, _V]),
+    ("erbf_surface_scratch_size", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("erbf_surface_extract", ctypes.c_int, [_V, ctypes.c_int32, _V, ctypes.c_float, _V, ctypes.c_size_t, _V,
+                                            ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _V]),
+    ("erbf_surface_sample", ctypes.c_int, [_V, ctypes.c_int64, _V, ctypes.c_int64, _V, _V, _V, _V, _V]),
+    ("erbf_surface_metrics", ctypes.c_int, [_V, _V, ctypes.c_int64, _V, _V, ctypes.c_int64, _V, _V, _V]),
     ("erbf_sched_init", ctypes.c_int, [_V, ctypes.POINTER(SchedCfg), ctypes.POINTER(SchedState), _V]),
     ("erbf_sched_step", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(SchedCfg),
                                        ctypes.POINTER(SchedState), _V, _V, _V, _V]),

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "liberbf.so")
 
-SOURCES = ["erbf_kernels.hip", "erbf_seed.hip", "erbf_sched.hip", "erbf_init.hip", "erbf_api.hip"]
+SOURCES = ["erbf_kernels.hip", "erbf_seed.hip", "erbf_sched.hip", "erbf_init.hip", "erbf_surface.hip", "erbf_api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17",

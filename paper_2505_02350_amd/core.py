@@ -328,6 +328,60 @@ def erbf_octree_bits(S_parent: torch.Tensor, n_parent: int, parent_bits: torch.T
     return bits
 
 
+# ---- surface evaluation (Section 4) ---------------------------------------------
+
+def erbf_sdf_from_targets(t: torch.Tensor, m: float, out: torch.Tensor = None, stream=None):
+    """Signed distance from the normalised field (eq. 3-10 inverted on S >= m)."""
+    if out is None:
+        out = torch.empty_like(t)
+    L.check(L.load().erbf_sdf_from_targets(_ptr(t), t.numel(), float(m), _ptr(out), _stream(stream)))
+    return out
+
+
+def erbf_surface_extract(F: torch.Tensor, n: int, axis: torch.Tensor, iso: float = 0.0, tri_cap: int = None,
+                         stream=None):
+    """Triangles [T, 3, 3] of the iso-surface of a grid field (marching
+    tetrahedra)."""
+    lib = L.load()
+    nb = ctypes.c_size_t()
+    L.check(lib.erbf_surface_scratch_size(int(n), ctypes.byref(nb)))
+    scratch = torch.empty(nb.value, dtype=torch.uint8, device=F.device)
+    cap = int(tri_cap) if tri_cap is not None else 8 * n * n
+    while True:
+        tris = torch.empty((max(cap, 1), 3, 3), dtype=torch.float32, device=F.device)
+        nt = ctypes.c_int64()
+        rc = lib.erbf_surface_extract(_ptr(F), int(n), _ptr(axis), float(iso), _ptr(scratch), nb.value, _ptr(tris),
+                                      cap, ctypes.byref(nt), _stream(stream))
+        if rc == L.ERBF_ERR_CAPACITY and tri_cap is None:
+            cap = nt.value
+            continue
+        L.check(rc)
+        return tris[:nt.value]
+
+
+def erbf_surface_sample(tris: torch.Tensor, u: torch.Tensor, stream=None):
+    """Points, unit normals and triangle indices of area-uniform samples
+    (u: float32 [S, 3] uniforms)."""
+    nt, ns = tris.shape[0], u.shape[0]
+    area = torch.empty(nt + (nt + 1023) // 1024, dtype=torch.float64, device=tris.device)
+    pts = torch.empty((ns, 3), dtype=torch.float32, device=tris.device)
+    nrm = torch.empty_like(pts)
+    which = torch.empty(ns, dtype=torch.int32, device=tris.device)
+    L.check(L.load().erbf_surface_sample(_ptr(tris), nt, _ptr(u), ns, _ptr(area), _ptr(pts), _ptr(nrm), _ptr(which),
+                                         _stream(stream)))
+    return pts, nrm, which
+
+
+def erbf_surface_metrics(Pt, Nt, Pr, Nr, stream=None):
+    """(HD, CD, CS) between two sampled surfaces."""
+    scratch = torch.empty(2 * (Pt.shape[0] + Pr.shape[0]), dtype=torch.float64, device=Pt.device)
+    out = torch.empty(3, dtype=torch.float64, device=Pt.device)
+    L.check(L.load().erbf_surface_metrics(_ptr(Pt), _ptr(Nt), Pt.shape[0], _ptr(Pr), _ptr(Nr), Pr.shape[0],
+                                          _ptr(scratch), _ptr(out), _stream(stream)))
+    hd, cd, cs = out.cpu().tolist()
+    return hd, cd, cs
+
+
 def sched_cfg(k_l2=10, tau_l2=0.5, k_l1=50, tau_l1=5.0, tau_d=0.01, T_e=1600, M_e=2000, lr0=0.01,
               lr_final=1e-3, lr_min=1e-5, refine_epochs=(400, 800)):
     """Algorithm 3's constants (defaults: the paper's values)."""

@@ -943,4 +943,79 @@ int erbf_init_inscribed(erbf_ctx* ctx, const erbf_params* params, int32_t shape,
   return ERBF_OK;
 }
 
+/* ---- surface evaluation (Section 4) ---- */
+
+int erbf_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t stream) {
+  if (!t || !S || n < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_sdf_from_targets: bad arguments");
+  if (!(m < 0.f)) return fail(ERBF_ERR_INVALID_ARG, "eq. 3-10 needs a negative minimum signed distance");
+  HIP_TRY(launch_sdf_from_targets(t, n, m, S, stream), "erbf_sdf_from_targets");
+  return ERBF_OK;
+}
+
+namespace {
+struct SurfScratch {
+  size_t cnt, off, blocks, total, bytes;
+};
+SurfScratch surf_scratch(int64_t m3) {
+  SurfScratch L{};
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = align256(o + b); return r; };
+  L.cnt = take(sizeof(int32_t) * (size_t)m3);
+  L.off = take(sizeof(int32_t) * (size_t)(m3 + 1));
+  L.blocks = take(sizeof(int32_t) * (size_t)(m3 / 1024 + 2));
+  L.total = take(sizeof(int64_t));
+  L.bytes = o;
+  return L;
+}
+}  // namespace
+
+int erbf_surface_scratch_size(int32_t n, size_t* bytes) {
+  if (!bytes || n < 2 || n > 1024) return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_scratch_size: n must be in [2, 1024]");
+  const int64_t m = n - 1;
+  *bytes = surf_scratch(m * m * m).bytes;
+  return ERBF_OK;
+}
+
+int erbf_surface_extract(const float* F, int32_t n, const float* axis, float iso, void* scratch, size_t scratch_bytes,
+                         float* tris, int64_t tri_cap, int64_t* n_tris, hipStream_t stream) {
+  if (!F || !axis || !scratch || !n_tris || n < 2 || n > 1024 || tri_cap < 0 || (tri_cap > 0 && !tris))
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_extract: bad arguments");
+  *n_tris = 0;
+  const int64_t m = n - 1, m3 = m * m * m;
+  const SurfScratch L = surf_scratch(m3);
+  if (scratch_bytes < L.bytes) return fail(ERBF_ERR_WORKSPACE, "erbf_surface_extract: scratch too small");
+  char* w = static_cast<char*>(scratch);
+  int32_t* cnt = reinterpret_cast<int32_t*>(w + L.cnt);
+  int32_t* off = reinterpret_cast<int32_t*>(w + L.off);
+  int32_t* blocks = reinterpret_cast<int32_t*>(w + L.blocks);
+  int64_t* total = reinterpret_cast<int64_t*>(w + L.total);
+  HIP_TRY(launch_mt_count(F, axis, n, iso, cnt, stream), "surface: count");
+  HIP_TRY(launch_scan(cnt, (int)m3, blocks, off, total, stream), "surface: scan");
+  int64_t nt = 0;
+  HIP_TRY(hipMemcpyAsync(&nt, total, sizeof(int64_t), hipMemcpyDeviceToHost, stream), "surface: count read");
+  HIP_TRY(hipStreamSynchronize(stream), "surface: sync");
+  *n_tris = nt;
+  if (nt > tri_cap) return fail(ERBF_ERR_CAPACITY, "erbf_surface_extract: " + std::to_string(nt) + " triangles exceed tri_cap");
+  if (nt > 0) HIP_TRY(launch_mt_emit(F, axis, n, iso, off, tris, tri_cap, stream), "surface: emit");
+  HIP_TRY(hipStreamSynchronize(stream), "surface: sync");
+  return ERBF_OK;
+}
+
+int erbf_surface_sample(const float* tris, int64_t n_tris, const float* u, int64_t n_samples, double* area_scratch,
+                        float* pts, float* normals, int32_t* tri_index, hipStream_t stream) {
+  if (!tris || n_tris < 1 || !u || n_samples < 1 || !area_scratch || !pts || !normals)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_sample: bad arguments");
+  HIP_TRY(launch_surface_sample(tris, n_tris, u, n_samples, area_scratch, pts, normals, tri_index, stream),
+          "erbf_surface_sample");
+  return ERBF_OK;
+}
+
+int erbf_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr, int64_t nr,
+                         double* scratch, double* out, hipStream_t stream) {
+  if (!Pt || !Nt || !Pr || !Nr || nt < 1 || nr < 1 || !scratch || !out)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_metrics: bad arguments");
+  HIP_TRY(launch_surface_metrics(Pt, Nt, nt, Pr, Nr, nr, scratch, out, stream), "erbf_surface_metrics");
+  return ERBF_OK;
+}
+
 }  // extern "C"

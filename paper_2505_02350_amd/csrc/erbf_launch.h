@@ -61,6 +61,14 @@ hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, bool sa
                                  float* p, int32_t* m_dev, float* m1, float* m2, hipStream_t s);
 // (centres, uncovered candidates) left by launch_init_inscribed (synchronises the stream); 0 on success
 int init_results(const Dev& D, int32_t* n_centres, int64_t* n_left, hipStream_t s);
+hipError_t launch_mt_count(const float* F, const float* ax, int n, float iso, int32_t* cnt, hipStream_t s);
+hipError_t launch_mt_emit(const float* F, const float* ax, int n, float iso, const int32_t* off, float* tris,
+                          int64_t cap, hipStream_t s);
+hipError_t launch_surface_sample(const float* tris, int64_t nt, const float* u, int64_t ns, double* area, float* pts,
+                                 float* nrm, int32_t* which, hipStream_t s);
+hipError_t launch_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
+                                  int64_t nr, double* scratch, double* out, hipStream_t s);
+hipError_t launch_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t s);
 hipError_t launch_sched_init(const Dev& D, const erbf_sched_state& st, const erbf_sched_cfg& a, hipStream_t s);
 hipError_t launch_sched_step(const Dev& D, const float* p_const, float* p, int32_t* m_dev, float* m1, float* m2,
                              const erbf_sched_state& st, const erbf_sched_cfg& a, const erbf_stats* stats,
