@@ -18,7 +18,10 @@ TAU1 = float(np.float32(0.9))
 TAU2 = float(np.float32(1.1))
 TAU_M = float(np.float32(0.02))
 
-RESULTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out", "parity")
+# measured errors of the parity tests go here (a folder of the caller's
+# choice, else parity_records/ at the repository root)
+RESULTS = os.environ.get("ERBF_PARITY_DIR") or os.path.join(
+    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "parity_records")
 
 
 def record(name, **vals):
