@@ -989,12 +989,15 @@ int erbf_surface_extract(const float* F, int32_t n, const float* axis, float iso
   int32_t* off = reinterpret_cast<int32_t*>(w + L.off);
   int32_t* blocks = reinterpret_cast<int32_t*>(w + L.blocks);
   int64_t* total = reinterpret_cast<int64_t*>(w + L.total);
-  HIP_TRY(launch_mt_count(F, axis, n, iso, cnt, stream), "surface: count");
-  HIP_TRY(launch_scan(cnt, (int)m3, blocks, off, total, stream), "surface: scan");
+  HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(total), 2, 0, stream), "surface: clear");
+  HIP_TRY(launch_mt_count(F, axis, n, iso, cnt, total, stream), "surface: count");
   int64_t nt = 0;
   HIP_TRY(hipMemcpyAsync(&nt, total, sizeof(int64_t), hipMemcpyDeviceToHost, stream), "surface: count read");
   HIP_TRY(hipStreamSynchronize(stream), "surface: sync");
   *n_tris = nt;
+  // the scan and the per-cube offsets are 32-bit
+  if (nt >= (int64_t)INT32_MAX) return fail(ERBF_ERR_UNSUPPORTED, "erbf_surface_extract: more than 2^31 triangles");
+  HIP_TRY(launch_scan(cnt, (int)m3, blocks, off, nullptr, stream), "surface: scan");
   if (nt > tri_cap) return fail(ERBF_ERR_CAPACITY, "erbf_surface_extract: " + std::to_string(nt) + " triangles exceed tri_cap");
   if (nt > 0) HIP_TRY(launch_mt_emit(F, axis, n, iso, off, tris, tri_cap, stream), "surface: emit");
   HIP_TRY(hipStreamSynchronize(stream), "surface: sync");

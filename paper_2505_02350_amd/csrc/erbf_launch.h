@@ -61,7 +61,9 @@ hipError_t launch_init_inscribed(const Dev& D, int shape, uint32_t npts, bool sa
                                  float* p, int32_t* m_dev, float* m1, float* m2, hipStream_t s);
 // (centres, uncovered candidates) left by launch_init_inscribed (synchronises the stream); 0 on success
 int init_results(const Dev& D, int32_t* n_centres, int64_t* n_left, hipStream_t s);
-hipError_t launch_mt_count(const float* F, const float* ax, int n, float iso, int32_t* cnt, hipStream_t s);
+// counts per cube and their 64-bit total (*total64 must start at 0)
+hipError_t launch_mt_count(const float* F, const float* ax, int n, float iso, int32_t* cnt, int64_t* total64,
+                           hipStream_t s);
 hipError_t launch_mt_emit(const float* F, const float* ax, int n, float iso, const int32_t* off, float* tris,
                           int64_t cap, hipStream_t s);
 hipError_t launch_surface_sample(const float* tris, int64_t nt, const float* u, int64_t ns, double* area, float* pts,

@@ -77,6 +77,17 @@ __global__ __launch_bounds__(256) void k_mt_count(const float* __restrict__ F, c
   }
 }
 
+// 64-bit total of the per-cube counts (integer atomics: the sum does not
+// depend on their order)
+__global__ __launch_bounds__(256) void k_count_total(const int32_t* __restrict__ cnt, int64_t m3,
+                                                     unsigned long long* __restrict__ total) {
+  unsigned long long acc = 0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m3; c += (int64_t)gridDim.x * blockDim.x)
+    acc += (unsigned long long)cnt[c];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(total, acc);
+}
+
 __device__ __forceinline__ void edge_point(const float cp[8][3], const float cv[8], int a, int b, float iso,
                                            float* out) {
   const float t = (iso - cv[a]) / (cv[b] - cv[a]);
@@ -318,9 +329,12 @@ inline unsigned gsz(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<
 
 }  // namespace
 
-hipError_t launch_mt_count(const float* F, const float* ax, int n, float iso, int32_t* cnt, hipStream_t s) {
+hipError_t launch_mt_count(const float* F, const float* ax, int n, float iso, int32_t* cnt, int64_t* total64,
+                           hipStream_t s) {
   const int64_t m3 = (int64_t)(n - 1) * (n - 1) * (n - 1);
   hipLaunchKernelGGL(k_mt_count, dim3(gsz(m3)), dim3(256), 0, s, F, ax, n, iso, cnt);
+  hipLaunchKernelGGL(k_count_total, dim3(gsz(m3)), dim3(256), 0, s, cnt, m3,
+                     reinterpret_cast<unsigned long long*>(total64));
   return hipGetLastError();
 }
 

@@ -142,3 +142,55 @@ def test_init_with_samples_uses_the_nearest_sample_depth():
     err_s = float(np.abs(P[4:7].T - ref.s).max())
     record("init_samples", centres=nc, left=left, err_s=err_s)
     assert err_s <= 1e-6 * max(1.0, float(np.abs(ref.s).max()))
+
+
+def test_sample_level_edges():
+    torch = _torch()
+    from paper_2505_02350_amd import core, _lib as L
+    prob = synth.make_custom(87, [16, 24], 40, (1.6, 2.6), kinds=("ellipsoid", "torus"))
+    olv, t32, _ = oracle_levels(prob)
+    dev = torch.device("cuda")
+
+    def ctx_with(samples):
+        ctx = core.Context([([16, 8, 24], prob.cap, [0, 64, 0])], 1 << 22, prob.cull_k)
+        for li, lv in ((0, prob.levels[0]), (1, None), (2, prob.levels[1])):
+            if lv is None:
+                ctx.erbf_refine_samples(0, torch.from_numpy(samples).to(dev))
+            else:
+                ctx.erbf_refine_level(0, torch.from_numpy(lv.axis).to(dev), torch.from_numpy(t32[0 if li == 0 else 1]).to(dev),
+                                      torch.from_numpy(lv.S).to(dev))
+        return ctx
+
+    p = torch.from_numpy(prob.params).to(dev)
+    m = torch.tensor([prob.m], dtype=torch.int32, device=dev)
+    # no samples registered: the grid results equal a context without the level
+    ctx0 = ctx_with(np.zeros((0, 3), np.float32))
+    g0 = ctx0.erbf_loss_grad(p, m, mode=O.MODE_FIXED, lam=1e-4)
+    plain = core.Context([([16, 24], prob.cap)], 1 << 22, prob.cull_k)
+    for li in range(2):
+        lv = prob.levels[li]
+        plain.erbf_refine_level(0, torch.from_numpy(lv.axis).to(dev), torch.from_numpy(t32[li]).to(dev),
+                                torch.from_numpy(lv.S).to(dev))
+    g1 = plain.erbf_loss_grad(p, m, mode=O.MODE_FIXED, lam=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1)
+    # samples on the corners and faces of the domain
+    corners = np.array([[1, 1, 1], [-1, -1, -1], [1, -1, 0.5], [0, 0, 1], [-1, 0.25, 0]], np.float32)
+    ctx1 = ctx_with(corners)
+    f = torch.zeros(ctx1.n_points, device=dev)
+    ctx1.erbf_loss_grad(p, m, mode=O.MODE_FIXED, lam=1e-4, f_out=f)
+    torch.cuda.synchronize()
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    ref = O.forward([O.make_samples(corners, 64)], K)[0]
+    base = ctx1.pt_base[0][1]
+    got = f[base:base + 64].cpu().numpy()
+    allow, _ = O.boundary_allowance([O.make_samples(corners, 64)], K)
+    assert np.all(np.abs(got - ref) <= 1e-5 * max(1.0, np.abs(ref).max()) + allow[0])
+    # invalid samples are rejected before anything is registered
+    bad = core.Context([([16, 8], prob.cap, [0, 4])], 1 << 20, prob.cull_k)
+    bad.erbf_refine_level(0, torch.from_numpy(prob.levels[0].axis).to(dev), torch.from_numpy(t32[0]).to(dev),
+                          torch.from_numpy(prob.levels[0].S).to(dev))
+    with pytest.raises(L.ErbfError):
+        bad.erbf_refine_samples(0, torch.tensor([[0.0, 1.5, 0.0]], device=dev))
+    with pytest.raises(L.ErbfError):
+        bad.erbf_refine_samples(0, torch.zeros((5, 3), device=dev))
