@@ -9,7 +9,8 @@ Readings (the paper's extraction method is an external one):
   tetrahedra around its main diagonal (corner 0 to corner 7, corner c at
   offsets (c & 1, c >> 1 & 1, c >> 2)); a tetrahedron whose corners straddle
   the iso value gives one triangle (one corner apart) or two (two and two),
-  with vertices interpolated linearly along the straddling edges; cubes in
+  with vertices interpolated linearly along the straddling edges (on the
+  finite corner when the other corner's value is infinite); cubes in
   point order (x fastest), tetrahedra and triangles in a fixed order;
 - the network's normalised output is taken back to a signed distance by
   inverting eq. 3-10 on its branch S >= m, and its surface is that field's
@@ -61,7 +62,15 @@ def marching_tets(F: np.ndarray, axis: np.ndarray, iso: float = 0.0) -> np.ndarr
 
 
 def _edge(p, v, a, b, iso):
-    t = (iso - v[a]) / (v[b] - v[a])
+    # an infinite corner value (the inverse of eq. 3-10 where the network
+    # gives t <= 0) is infinitely far outside: the vertex sits on the other
+    # corner
+    if math.isinf(v[b]):
+        t = 0.0
+    elif math.isinf(v[a]):
+        t = 1.0
+    else:
+        t = (iso - v[a]) / (v[b] - v[a])
     return p[a] + t * (p[b] - p[a])
 
 

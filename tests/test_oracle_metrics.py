@@ -101,3 +101,15 @@ def test_sdf_from_targets_inverts_eq_3_10():
     assert np.allclose(Mx.sdf_from_targets(t, m), S, atol=1e-9)
     assert Mx.sdf_from_targets(np.array([2.5]), m)[0] == m
     assert Mx.sdf_from_targets(np.array([1.0]), m)[0] == pytest.approx(0.0, abs=1e-15)
+
+
+def test_infinite_corner_puts_the_vertex_on_the_finite_corner():
+    # eq. 3-10 inverted gives +inf where the network output is <= 0; such a
+    # corner is infinitely far outside, so the surface passes through the
+    # finite (inside) corner
+    ax = np.array([-0.5, 0.5], np.float32)
+    F = np.full(8, np.inf, np.float32)
+    F[0] = -1.0
+    T = Mx.marching_tets(F, ax)
+    assert T.shape[0] > 0 and np.all(np.isfinite(T))
+    assert np.allclose(T.reshape(-1, 3), [-0.5, -0.5, -0.5])
