@@ -330,7 +330,8 @@ int erbf_surface_scratch_size(int32_t n, size_t* bytes);
  * cell-centred axis, device [n]) by marching tetrahedra: each cube of eight
  * neighbouring points is split into six tetrahedra around its main diagonal;
  * a tetrahedron whose corners straddle iso (inside: F < iso) gives one or two
- * triangles with vertices interpolated linearly along its straddling edges.
+ * triangles with vertices interpolated linearly along its straddling edges
+ * (on the finite corner when the other corner's value is infinite).
  * Triangles come out in cube order (x fastest), then tetrahedron and case
  * order: tris device [tri_cap * 9] (x, y, z of three vertices each).
  * Synchronous; *n_tris receives the count.  ERBF_ERR_CAPACITY (nothing

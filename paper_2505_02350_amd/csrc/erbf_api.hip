@@ -53,7 +53,7 @@ struct Layout {
       off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
       off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init, off_samp_pos, off_samp_start, off_samp_slot,
-      off_samp_slots, off_samp_f, off_samp_c, off_samp_pb;
+      off_samp_slots, off_samp_f, off_samp_c, off_samp_pb, off_sel;
   int64_t samp_total = 0, samp_start_total = 0, samp_tiles = 0;
   size_t bytes = 0;
 };
@@ -177,6 +177,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_samp_start = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_start_total, 1));
   L.off_samp_slot = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_total, 1));
   L.off_samp_slots = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_tiles, 1));
+  L.off_sel = take(sizeof(int32_t) * (size_t)std::max(L.tiles_total, 1));
   L.off_samp_f = take(sizeof(float) * kSampSplit * (size_t)std::max<int64_t>(L.samp_total, 1));
   L.off_samp_c = take(sizeof(int32_t) * kSampSplit * (size_t)std::max<int64_t>(L.samp_total, 1));
   L.off_samp_pb = take(sizeof(int64_t) * kSampSplit * (size_t)std::max<int64_t>(L.samp_tiles, 1));
@@ -328,6 +329,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.samp_slots = reinterpret_cast<int32_t*>(w + lay.off_samp_slots);
   D.n_samp_slots = 0;
   D.samp_f = reinterpret_cast<float*>(w + lay.off_samp_f);
+  D.sel_buf = reinterpret_cast<int32_t*>(w + lay.off_sel);
+  D.tile_sel = nullptr;
   D.samp_c = reinterpret_cast<int32_t*>(w + lay.off_samp_c);
   D.samp_pb = reinterpret_cast<int64_t*>(w + lay.off_samp_pb);
   D.init_words = lay.init_words;
@@ -657,7 +660,11 @@ int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_lo
       if (ctx->lv[s.lvl0 + l].kind == kLevelGrid && !ctx->lv[s.lvl0 + l].target)
         return fail(ERBF_ERR_INVALID_ARG, "a registered grid level has no target");
   DeviceGuard guard(ctx->device);
-  const Dev& D = ctx->D;
+  // bucket lists only for the tiles holding batch points: the other tiles'
+  // entries would carry zero moments
+  Dev D = ctx->D;
+  D.tile_sel = D.sel_buf;
+  HIP_TRY(launch_batch_tiles(D, ctx->slots_used, pts, n_pts, D.sel_buf, stream), "batch: tiles");
   // G is zero outside the batch, so the tile backward sees the batch only
   HIP_TRY(launch_fill_f32(D.G, ctx->lay.pts_total, 0.f, stream), "batch: clear G");
   HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "batch: prologue");

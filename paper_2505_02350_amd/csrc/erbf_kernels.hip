@@ -235,6 +235,12 @@ __device__ __forceinline__ bool ball_box_hit(const LevelDev& L, const float4& r0
   return fmaf(ex, ex, e2) < rc2;
 }
 
+// a slot the bucket lists cover: an active tile, selected when a selection
+// is given (mini-batches list only the tiles holding batch points)
+__device__ __forceinline__ bool tile_listed(const Dev& D, int slot) {
+  return slot >= 0 && (D.tile_sel == nullptr || D.tile_sel[slot] != 0);
+}
+
 struct BallBox {
   float rc2;
   int tx0, tx1, ty0, nty, tz0, ntz;
@@ -278,7 +284,7 @@ __device__ __forceinline__ int bucket_count_walk(const Dev& D, const int j, cons
         if (e2 < B.rc2) {
           const int row0 = L.tmap0 + (tz * L.nt + ty) * L.nt;
           for (int tx = B.tx0; tx <= B.tx1; ++tx)
-            if (ball_box_hit(L, r0, e2, tx, B.rc2) && D.tile_map[row0 + tx] >= 0) ++cnt;
+            if (ball_box_hit(L, r0, e2, tx, B.rc2) && tile_listed(D, D.tile_map[row0 + tx])) ++cnt;
         }
       }
       total += (int)wave_sum(cnt);
@@ -325,8 +331,10 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
           }
           const int tx = B.tx0 + qx, ty = B.ty0 + qy, tz = B.tz0 + qz;
           const float e2 = ball_box_e2(L, r0, ty, tz);
-          if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2))
-            slot = D.tile_map[L.tmap0 + (tz * L.nt + ty) * L.nt + tx];
+          if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2)) {
+            const int sl = D.tile_map[L.tmap0 + (tz * L.nt + ty) * L.nt + tx];
+            slot = tile_listed(D, sl) ? sl : -1;
+          }
         }
         const bool hit = slot >= 0;
         const unsigned long long bal = __ballot(hit);
@@ -811,6 +819,28 @@ __global__ __launch_bounds__(256) void k_batch_forward(Dev D, const int64_t* __r
   D.b_id[k] = id ? 1 : 0;
   D.b_pf[k] = valid ? pf : 0;
   D.b_shape[k] = valid ? L.shape : -1;
+}
+
+// tiles holding batch points (the mini-batch's bucket selection)
+__global__ __launch_bounds__(256) void k_batch_tiles(Dev D, const int64_t* __restrict__ pts, int n_pts,
+                                                     int32_t* __restrict__ sel) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n_pts) return;
+  const int64_t gi = pts[k];
+  int li = 0;
+  for (int a = 1; a < D.n_levels_total; ++a)
+    if (D.levels[a].pt_base <= gi) li = a;
+  const LevelDev& L = D.levels[li];
+  const int64_t local = gi - L.pt_base;
+  int slot = -1;
+  if (L.kind == kLevelSamples) {
+    if (gi >= 0 && L.sxyz != nullptr && local >= 0 && local < (int64_t)L.n_samples) slot = L.sslot[local];
+  } else if (gi >= 0 && L.axis != nullptr && local >= 0 && local < (int64_t)L.n * L.n * L.n) {
+    const int n = L.n, nt = L.nt;
+    const int xi = (int)(local % n), yi = (int)((local / n) % n), zi = (int)(local / ((int64_t)n * n));
+    slot = D.tile_map[L.tmap0 + ((zi / kTile) * nt + yi / kTile) * nt + xi / kTile];
+  }
+  if (slot >= 0) sel[slot] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1811,6 +1841,13 @@ hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m
     hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
     hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tiles(const Dev& D, int n_slots, const int64_t* pts, int n_pts, int32_t* sel, hipStream_t s) {
+  hipError_t e = launch_fill_i32(sel, std::max(n_slots, 1), 0, s);
+  if (e != hipSuccess) return e;
+  if (n_pts > 0) hipLaunchKernelGGL(k_batch_tiles, dim3(nblk(n_pts, 256)), dim3(256), 0, s, D, pts, n_pts, sel);
   return hipGetLastError();
 }
 

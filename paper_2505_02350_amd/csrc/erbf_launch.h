@@ -54,6 +54,8 @@ hipError_t launch_seed_select(const Dev& D, int shape, int64_t npts, const float
 int seed_misc_counts(const Dev& D, int32_t* n_cand, int32_t* n_kept, hipStream_t s);
 hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32_t* m_dev, const float* resid,
                              float scale, float* m1, float* m2, float eps, int w_rule, float h_fine, hipStream_t s);
+// marks (1) the slots holding the batch's points in sel, after clearing it
+hipError_t launch_batch_tiles(const Dev& D, int n_slots, const int64_t* pts, int n_pts, int32_t* sel, hipStream_t s);
 hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int n_pts, const float* p,
                              const int32_t* m_dev, float* grad, float* f_out, erbf_stats* out, float tau1, float tau2,
                              const StatsArgs& a, hipStream_t s);

@@ -90,7 +90,9 @@ __global__ __launch_bounds__(256) void k_count_total(const int32_t* __restrict__
 
 __device__ __forceinline__ void edge_point(const float cp[8][3], const float cv[8], int a, int b, float iso,
                                            float* out) {
-  const float t = (iso - cv[a]) / (cv[b] - cv[a]);
+  // an infinite corner value (eq. 3-10 inverted where the network gives
+  // t <= 0) is infinitely far outside: the vertex sits on the other corner
+  const float t = isinf(cv[b]) ? 0.f : (isinf(cv[a]) ? 1.f : (iso - cv[a]) / (cv[b] - cv[a]));
 #pragma unroll
   for (int d = 0; d < 3; ++d) out[d] = cp[a][d] + t * (cp[b][d] - cp[a][d]);
 }

@@ -205,6 +205,40 @@ class Fitter:
             log.append(row)
         return st, log
 
+    def init_inscribed(self, b: int = 0, gamma: float = 1e-3, max_centres: int = 0, stream=None):
+        """Replace shape b's kernels by the inscribed-sphere initialisation
+        (Algorithm 1, eq. 3-12) over its registered levels (with its surface
+        samples, if registered, giving the depth); restarts its Adam state.
+        Returns (centres, candidates left uncovered)."""
+        nc, left = self.ctx.erbf_init_inscribed(self.p, self.m_dev, b, gamma=gamma, max_centres=max_centres,
+                                                m1=self.m1, m2=self.m2, stream=stream)
+        self.step_dev[b:b + 1].zero_()
+        return nc, left
+
+    def surface_metrics(self, b: int, li: int, n_samples: int = 100000, seed: int = 0, stream=None):
+        """Section 4's HD / CD / CS between the zero set of grid level li's
+        signed distance and that of the fitted field on the same grid (the
+        network's output taken back through eq. 3-10), each sampled at
+        n_samples area-uniform points from seeded uniforms."""
+        s = self.shapes[b]
+        if s.samples[li] is not None:
+            raise ValueError("level li must be a grid level")
+        n = s.level_ns[li]
+        f = self.ctx.erbf_eval(self.p, self.m_dev, stream=stream)
+        base = self.ctx.pt_base[b][li]
+        Sr = core.erbf_sdf_from_targets(f[base:base + n ** 3], float(self._m_host[b]), stream=stream)
+        ax = torch.from_numpy(np.ascontiguousarray(s.axes[li], np.float32)).to(self.dev)
+        rng = np.random.default_rng(seed)
+        out = []
+        for field in (self.S_dev[b][li], Sr):
+            tris = core.erbf_surface_extract(field, n, ax, 0.0, stream=stream)
+            if tris.shape[0] == 0:
+                return float("inf"), float("inf"), 0.0
+            u = torch.from_numpy(rng.random((n_samples, 3)).astype(np.float32)).to(self.dev)
+            pts, nrm, _ = core.erbf_surface_sample(tris, u, stream=stream)
+            out.append((pts, nrm))
+        return core.erbf_surface_metrics(out[0][0], out[0][1], out[1][0], out[1][1], stream=stream)
+
     def training_points(self, b: int) -> np.ndarray:
         """Indices (into the context's per-point arrays) of shape b's training
         points: every point of its registered levels inside the level's band."""

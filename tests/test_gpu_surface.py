@@ -128,3 +128,21 @@ def test_pipeline_offset_surface():
     record("surface_pipeline", got=got, ref=ref, err=err)
     assert max(err) <= 1e-4
     assert 0.005 < got[1] < 0.02 and got[2] > 0.95
+
+
+def test_extraction_with_infinite_values_matches_oracle():
+    # the network's output taken back through eq. 3-10 is +inf where it is
+    # <= 0: a field mixing finite and infinite values, as extracted by the oracle
+    torch = _torch()
+    from paper_2505_02350_amd import core
+    ax, S = _shape_field(97, 20)
+    F = S.copy()
+    F[np.random.default_rng(2).random(F.size) < 0.2] = np.inf
+    F[F > 0.3] = np.inf
+    dev = torch.device("cuda")
+    T = core.erbf_surface_extract(torch.from_numpy(F).to(dev), 20, torch.from_numpy(ax).to(dev), 0.0)
+    torch.cuda.synchronize()
+    ref = Mx.marching_tets(F, ax, 0.0)
+    got = T.cpu().numpy().astype(np.float64)
+    assert got.shape == ref.shape and np.all(np.isfinite(got))
+    assert float(np.abs(got - ref).max()) <= 2e-6
