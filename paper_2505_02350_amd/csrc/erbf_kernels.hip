@@ -1078,8 +1078,17 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
   if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_bwd
+  const int tid = threadIdx.x;
+  if (min((int64_t)D.tile_start[slot], D.pair_cap) == min((int64_t)D.tile_start[slot + 1], D.pair_cap)) {
+    // no kernel reaches the tile (or, in a mini-batch, no batch point is in it)
+    if (tid == 0) {
+      D.tile_nz[slot] = 0;
+      D.tile_pbwd[slot] = 0;
+    }
+    return;
+  }
   const int n = L.n, nt = L.nt;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
   const float* __restrict__ G = Gsrc + L.pt_base;
 
