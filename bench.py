@@ -412,17 +412,24 @@ def main():
     log(f"timed {K} steps: {ms_per_step:.3f} ms/step; forward {fwd_avg:.3f} ms, backward tiles "
         f"{bt_avg:.3f} ms, reduce {br_avg:.3f} ms")
 
-    graph_ms = None
+    graph_ms = graph10_ms = None
     if args.graph:
-        fit.capture(**kw)
-        for _ in range(3):
-            fit.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(K):
-            fit.replay()
-        torch.cuda.synchronize()
-        graph_ms = 1e3 * (time.perf_counter() - t0) / K
+        for per in (1, 10):
+            fit.capture(steps_per_graph=per, **kw)
+            for _ in range(2):
+                fit.replay()
+            torch.cuda.synchronize()
+            reps = max(1, K // per)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fit.replay()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / (reps * per)
+            if per == 1:
+                graph_ms = ms
+            else:
+                graph10_ms = ms
+        log(f"graph replay: {graph_ms:.3f} ms per step (one step per graph), {graph10_ms:.3f} ms (ten per graph)")
 
     out = {
         "metric": "fwd+bwd ERBF point-kernel pairs/s",
@@ -462,6 +469,7 @@ def main():
         "fwd_bwd_pairs_per_s": (P_fwd + P_bwd) / ((fwd_ms + bt_ms + br_ms) * 1e-3),
         "bucket_entries": st.n_bucket_pairs,
         "graph_ms_per_step": graph_ms,
+        "graph10_ms_per_step": graph10_ms,
         "per_level_refine_ms": refine_ms,
     }
     if args.batching:

@@ -140,8 +140,9 @@ class Fitter:
         self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr=lr,
                                 lr_dev=lr_dev, stream=stream)
 
-    def capture(self, **kw):
-        """Capture one step into a HIP graph (replay with :meth:`replay`)."""
+    def capture(self, steps_per_graph: int = 1, **kw):
+        """Capture `steps_per_graph` consecutive steps into one HIP graph
+        (replay with :meth:`replay`)."""
         s = torch.cuda.Stream(device=self.dev)
         s.wait_stream(torch.cuda.current_stream(self.dev))
         with torch.cuda.stream(s):
@@ -150,8 +151,10 @@ class Fitter:
         torch.cuda.synchronize(self.dev)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            self.step(stream=s, **kw)
+            for _ in range(int(steps_per_graph)):
+                self.step(stream=s, **kw)
         self.graph = g
+        self.graph_steps = int(steps_per_graph)
         return g
 
     def replay(self):
