@@ -23,12 +23,13 @@
  *  - All pointers named *_dev or documented as "device" point to device
  *    memory of the context's device, owned by the caller.  The library never
  *    allocates device memory: every scratch buffer lives in the caller's
- *    workspace (erbf_workspace_size / erbf_ctx_create).
+ *    workspace (erbf_workspace_size / erbf_ctx_create) or, for the
+ *    context-free surface calls, in scratch arguments.
  *  - Calls that take a hipStream_t only enqueue work on that stream; they do
  *    not synchronise and are safe to capture into a hipGraph, except the
  *    calls documented as "synchronous" (erbf_ctx_create,
  *    erbf_refine_level, erbf_seed_from_error, erbf_init_inscribed,
- *    erbf_autotune).
+ *    erbf_surface_extract, erbf_autotune).
  *  - A context holds one or more independent shapes (the batched extension);
  *    a plain fit is a context with one shape.  Kernels of all shapes share
  *    one global index space: shape b owns slots [kbase_b, kbase_b + cap_b),
