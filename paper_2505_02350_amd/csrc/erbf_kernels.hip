@@ -563,16 +563,66 @@ __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __res
 // ---------------------------------------------------------------------------
 // forward: one workgroup (4 waves) per active tile of 8^3 points
 //   wave w covers x in [0,8), y in 4*(w&1)+[0,4), z in 4*(w>>1)+[0,4);
-//   lane l covers points x = 2*(l&3)+{0,1}, y += (l>>2)&3, z += l>>4.
+//   lane l covers points x = 2*(l&3)+{0,1}, y += (l>>2)&3, z += l>>4,
+//   so the four lanes of a quad share one row (y, z).
+// A wave walks its kernel list four kernels at a time: lane l of a quad forms
+// the row terms (|dyz|^2 and the y/z parts of the quadric) of kernel k + (l&3)
+// for the quad's row, and each of the four kernels then takes its row terms
+// from the quad lane that formed them (DPP quad broadcast).  The row work is
+// done once per (row, kernel) instead of once per lane, and every value is the
+// same float expression as in a one-kernel-at-a-time walk.
 // ---------------------------------------------------------------------------
 
 constexpr int kFwdChunk = 256;
 
+// v broadcast from lane I of each quad to the four lanes of the quad
+template <int I>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), I * 0x55, 0xf, 0xf, false));
+}
+
+// staged kernel record (LDS): U = {cx, A00, r^2, a} is read by the whole wave
+// for one kernel, V0 = {cy, cz, A11, A22} and V1 = {2 A01, 2 A02, 2 A12, 0} by
+// the quad lane that forms that kernel's row terms
+struct FwdRowTerms {
+  float syz, bl, cc;
+};
+
+__device__ __forceinline__ FwdRowTerms fwd_row_terms(const float4 V0, const float4 V1, float py, float pz) {
+  const float dy = py - V0.x, dz = pz - V0.y;
+  FwdRowTerms t;
+  t.syz = fmaf(dy, dy, dz * dz);
+  t.bl = fmaf(V1.x, dy, V1.y * dz);
+  t.cc = fmaf(dy, fmaf(V0.z, dy, V1.z * dz), V0.w * dz * dz);
+  return t;
+}
+
+// one kernel of a group of four at the lane's two points; its row terms come
+// from quad lane I
+template <int I>
+__device__ __forceinline__ void fwd_eval_pair(const float4 U, const FwdRowTerms& t, float px0, float px1,
+                                              unsigned long long act_mask0, unsigned long long act_mask1,
+                                              float& acc0, float& acc1, uint32_t& pf) {
+  const float syz = quad_bcast<I>(t.syz), bl = quad_bcast<I>(t.bl), cc = quad_bcast<I>(t.cc);
+  const float dx0 = px0 - U.x, dx1 = px1 - U.x;
+  float q0 = fmaf(dx0, fmaf(U.y, dx0, bl), cc);
+  float q1 = fmaf(dx1, fmaf(U.y, dx1, bl), cc);
+  const bool in0 = fmaf(dx0, dx0, syz) < U.z;
+  const bool in1 = fmaf(dx1, dx1, syz) < U.z;
+  q0 = in0 ? q0 : INFINITY;
+  q1 = in1 ? q1 : INFINITY;
+  acc0 = fmaf(U.w, fast_exp2(-q0), acc0);
+  acc1 = fmaf(U.w, fast_exp2(-q1), acc1);
+  pf += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
+}
+
 template <bool LOSS>
 __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float* __restrict__ f_out,
                                              float tau1, float tau2) {
-  __shared__ float4 srec[kFwdChunk * 3];
-  __shared__ uint16_t slist[4][kFwdChunk];
+  // records of the chunk, plus an inert record (r^2 < 0, a = 0) at index
+  // kFwdChunk that pads each wave's list to a multiple of four
+  __shared__ float4 srec[kFwdChunk * 3 + 3];
+  __shared__ uint32_t slist[4][kFwdChunk + 4];
   __shared__ int scnt[4][4];
   __shared__ double red_d[4];
   __shared__ float red_f[4];
@@ -617,6 +667,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   float acc0 = 0.f, acc1 = 0.f;
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  if (tid < 3) srec[3 * kFwdChunk + tid] = make_float4(0.f, 0.f, tid == 0 ? -1.f : 0.f, 0.f);
 
   for (int64_t c0 = beg; c0 < end; c0 += kFwdChunk) {
     const int cnt = (int)min((int64_t)kFwdChunk, end - c0);
@@ -624,9 +675,9 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
     if (tid < cnt) {
       const int j = D.items[c0 + tid];
       const float4 a0 = D.rec[3 * j], a1 = D.rec[3 * j + 1], a2 = D.rec[3 * j + 2];
-      srec[3 * tid] = a0;
-      srec[3 * tid + 1] = a1;
-      srec[3 * tid + 2] = a2;
+      srec[3 * tid] = make_float4(a0.x, a1.x, a0.w, a2.z);
+      srec[3 * tid + 1] = make_float4(a0.y, a0.z, a1.y, a1.z);
+      srec[3 * tid + 2] = make_float4(a1.w, a2.x, a2.y, 0.f);
       const float rr = sqrtf(a0.w) * (1.0f + 1e-5f) + 1e-6f;
       const float rc2 = rr * rr;
       const float ex = fmaxf(fmaxf(bx0 - a0.x, a0.x - bx1), 0.f);
@@ -653,30 +704,27 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       if ((mybits >> w) & 1u) {
         int off = prefix[w];
         for (int v = 0; v < wv; ++v) off += scnt[w][v];
-        slist[w][off] = (uint16_t)(tid * (int)sizeof(float4) * 3);   // byte offset of the record
+        slist[w][off] = (uint32_t)(tid * (int)sizeof(float4) * 3);   // byte offset of the record
       }
     }
-    __syncthreads();
     const int len = __builtin_amdgcn_readfirstlane(scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3]);
+    const int len4 = (len + 3) & ~3;
+    // the wave pads its own list (entries [len, len4), written by no other wave)
+    if (lane < len4 - len) slist[wv][len + lane] = (uint32_t)(kFwdChunk * (int)sizeof(float4) * 3);
+    __syncthreads();
     const char* srec_b = reinterpret_cast<const char*>(srec);
     uint32_t pf = 0;
-    for (int k = 0; k < len; ++k) {
-      const float4* rp = reinterpret_cast<const float4*>(srec_b + slist[wv][k]);
-      const float4 a0 = rp[0], a1 = rp[1], a2 = rp[2];
-      const float dy = py - a0.y, dz = pz - a0.z;
-      const float syz = fmaf(dy, dy, dz * dz);
-      const float bl = fmaf(a1.w, dy, a2.x * dz);
-      const float cc = fmaf(dy, fmaf(a1.y, dy, a2.y * dz), a1.z * dz * dz);
-      const float dx0 = px0 - a0.x, dx1 = px1 - a0.x;
-      float q0 = fmaf(dx0, fmaf(a1.x, dx0, bl), cc);
-      float q1 = fmaf(dx1, fmaf(a1.x, dx1, bl), cc);
-      const bool in0 = fmaf(dx0, dx0, syz) < a0.w;
-      const bool in1 = fmaf(dx1, dx1, syz) < a0.w;
-      q0 = in0 ? q0 : INFINITY;
-      q1 = in1 ? q1 : INFINITY;
-      acc0 = fmaf(a2.z, fast_exp2(-q0), acc0);
-      acc1 = fmaf(a2.z, fast_exp2(-q1), acc1);
-      pf += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
+    for (int k = 0; k < len4; k += 4) {
+      const float4* own = reinterpret_cast<const float4*>(srec_b + slist[wv][k + (lane & 3)]);
+      const FwdRowTerms t = fwd_row_terms(own[1], own[2], py, pz);
+      const float4 U0 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k]);
+      const float4 U1 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 1]);
+      const float4 U2 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 2]);
+      const float4 U3 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 3]);
+      fwd_eval_pair<0>(U0, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair<1>(U1, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair<2>(U2, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair<3>(U3, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
     }
     pfw += pf;
     __syncthreads();
@@ -725,9 +773,10 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   }
 }
 
-// one workgroup per tile (grid launch) ...
+// one workgroup per tile (grid launch) ...  Eight waves per SIMD (at most 64
+// VGPRs) keep the exp / LDS latencies of the walk hidden.
 template <bool LOSS>
-__global__ __launch_bounds__(256) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
   forward_tile<LOSS>(D, blockIdx.x, f_out, tau1, tau2);
 }
 
