@@ -565,6 +565,8 @@ __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __res
 //   wave w covers x in [0,8), y in 4*(w&1)+[0,4), z in 4*(w>>1)+[0,4);
 //   lane l covers points x = 2*(l&3)+{0,1}, y += (l>>2)&3, z += l>>4,
 //   so the four lanes of a quad share one row (y, z).
+// Each wave's list holds the kernels of the tile's list whose (padded) ball
+// meets the bounding box of the wave's training points.
 // A wave walks its kernel list four kernels at a time: lane l of a quad forms
 // the row terms (|dyz|^2 and the y/z parts of the quadric) of kernel k + (l&3)
 // for the quad's row, and each of the four kernels then takes its row terms
@@ -624,6 +626,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   __shared__ float4 srec[kFwdChunk * 3 + 3];
   __shared__ uint32_t slist[4][kFwdChunk + 4];
   __shared__ int scnt[4][4];
+  __shared__ float sbox[4][6];
   __shared__ double red_d[4];
   __shared__ float red_f[4];
   __shared__ int red_i[4];
@@ -644,18 +647,6 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   const float py = L.axis[min(yi, n - 1)];
   const float pz = L.axis[min(zi, n - 1)];
 
-  // bounding boxes of the four wave sub-tiles (each thread computes all four)
-  float bx0, bx1, by0[2], by1[2], bz0[2], bz1[2];
-  bx0 = L.axis[tx * kTile];
-  bx1 = L.axis[min(tx * kTile + kTile - 1, n - 1)];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    by0[h] = L.axis[min(ty * kTile + 4 * h, n - 1)];
-    by1[h] = L.axis[min(ty * kTile + 4 * h + 3, n - 1)];
-    bz0[h] = L.axis[min(tz * kTile + 4 * h, n - 1)];
-    bz1[h] = L.axis[min(tz * kTile + 4 * h + 3, n - 1)];
-  }
-
   // training points of this lane (inside the grid and the level's mask)
   const bool vyz = yi < n && zi < n;
   const int64_t local0 = ((int64_t)min(zi, n - 1) * n + min(yi, n - 1)) * n + min(xi0, n - 1);
@@ -663,6 +654,27 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   const bool act1 = vyz && xi0 + 1 < n && point_active(L.bits, local0 + 1);
   const unsigned long long act_mask0 = __ballot(act0), act_mask1 = __ballot(act1);
   int64_t pfw = 0;   // in-ball pairs at this wave's training points (wave-uniform)
+
+  // bounding box of each wave's training points (its list holds the kernels
+  // whose ball meets it; a wave without training points walks nothing)
+  {
+    const bool any = act0 || act1;
+    const int xlo = act0 ? xi0 : (act1 ? xi0 + 1 : INT_MAX), xhi = act1 ? xi0 + 1 : (act0 ? xi0 : -1);
+    const int bxlo = -wave_max_i(-xlo), bxhi = wave_max_i(xhi);
+    const int bylo = -wave_max_i(any ? -yi : -INT_MAX), byhi = wave_max_i(any ? yi : -1);
+    const int bzlo = -wave_max_i(any ? -zi : -INT_MAX), bzhi = wave_max_i(any ? zi : -1);
+    if (lane == 0 && (act_mask0 | act_mask1) != 0ull) {
+      sbox[wv][0] = L.axis[bxlo]; sbox[wv][1] = L.axis[bxhi];
+      sbox[wv][2] = L.axis[bylo]; sbox[wv][3] = L.axis[byhi];
+      sbox[wv][4] = L.axis[bzlo]; sbox[wv][5] = L.axis[bzhi];
+    } else if (lane == 0) {
+      // no training point: an empty box (every distance test fails)
+      sbox[wv][0] = INFINITY; sbox[wv][1] = -INFINITY;
+      sbox[wv][2] = INFINITY; sbox[wv][3] = -INFINITY;
+      sbox[wv][4] = INFINITY; sbox[wv][5] = -INFINITY;
+    }
+  }
+  __syncthreads();
 
   float acc0 = 0.f, acc1 = 0.f;
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
@@ -680,12 +692,11 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       srec[3 * tid + 2] = make_float4(a1.w, a2.x, a2.y, 0.f);
       const float rr = sqrtf(a0.w) * (1.0f + 1e-5f) + 1e-6f;
       const float rc2 = rr * rr;
-      const float ex = fmaxf(fmaxf(bx0 - a0.x, a0.x - bx1), 0.f);
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const int hy = w & 1, hz = w >> 1;
-        const float ey = fmaxf(fmaxf(by0[hy] - a0.y, a0.y - by1[hy]), 0.f);
-        const float ez = fmaxf(fmaxf(bz0[hz] - a0.z, a0.z - bz1[hz]), 0.f);
+        const float ex = fmaxf(fmaxf(sbox[w][0] - a0.x, a0.x - sbox[w][1]), 0.f);
+        const float ey = fmaxf(fmaxf(sbox[w][2] - a0.y, a0.y - sbox[w][3]), 0.f);
+        const float ez = fmaxf(fmaxf(sbox[w][4] - a0.z, a0.z - sbox[w][5]), 0.f);
         if (ex * ex + ey * ey + ez * ez < rc2) mybits |= 1u << w;
       }
     }
