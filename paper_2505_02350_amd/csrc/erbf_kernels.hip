@@ -1122,18 +1122,21 @@ __global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
 // row the lane keeps three sums over x (sum g, sum g dx, sum g dx^2) and folds
 // them into the ten moments with the row's dy, dz:
 //   T0 = sum g, T1 = sum g D, T2 = sum g D D^T,  g = G exp(-D^T A D)
+// A point is staged with G, G x' and G x'^2, x' its offset from the tile's
+// first x, so the row sums cost three FMAs per point: with c' the kernel's
+// offset from that x, sum g dx = sum G e x' - c' sum G e and
+// sum g dx^2 = sum G e x'^2 - 2 c' sum G e x' + c'^2 sum G e (e = exp(...)).
 // The moments of each (tile, kernel) entry go to `partials`.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc) {
-  // non-zero points, row by row: row r's points sit at spx[8 r ...], padded
-  // to an even count with inert points (far away, G = 0) so that they are
-  // read two at a time
-  __shared__ float4 spx4[kTile * kTile * kTile / 2];
+  // non-zero points (x, G, G x', G x'^2), row by row: row r's points sit at
+  // spx[8 r ...], padded to an even count with an inert point (far away,
+  // G = 0) so that they are read two at a time
+  __shared__ float4 spx[kTile * kTile * kTile];
   __shared__ float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
   __shared__ int swr[2][4];
   __shared__ int64_t spb[4];
-  float2* spx = reinterpret_cast<float2*>(spx4);
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
@@ -1156,6 +1159,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   // of the tile: eight consecutive lanes hold one row
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const int rl = lane & ~7;                       // first lane of this lane's row
+  const float xref = L.axis[tx * kTile];         // x' = x - xref
   bool row_used[2];
   int row_cnt[2], row_pos[2];
 #pragma unroll
@@ -1168,11 +1172,14 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     const unsigned long long bal = __ballot(nz);
     const unsigned row_bits = (unsigned)(bal >> rl) & 0xffu;
     const int r = p >> 3;
-    if (nz) spx[8 * r + __popc(row_bits & ((1u << (lane & 7)) - 1u))] = make_float2(L.axis[xi], g);
+    if (nz) {
+      const float px = L.axis[xi], xo = px - xref, gx = g * xo;
+      spx[8 * r + __popc(row_bits & ((1u << (lane & 7)) - 1u))] = make_float4(px, g, gx, gx * xo);
+    }
     const int c = __popc(row_bits);
     row_cnt[h] = c;
     row_used[h] = c > 0;
-    if ((lane & 7) == 0 && (c & 1)) spx[8 * r + c] = make_float2(1e30f, 0.f);
+    if ((lane & 7) == 0 && (c & 1)) spx[8 * r + c] = make_float4(1e30f, 0.f, 0.f, 0.f);
     const unsigned long long rb = __ballot((lane & 7) == 0 && c > 0);
     row_pos[h] = __popcll(rb & lt_mask);
     if (lane == 0) swr[h][wv] = __popcll(rb);
@@ -1228,37 +1235,40 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     }
     const float cx = r0.x, cy = r0.y, cz = r0.z, rad2 = r0.w;
     const float A00 = r1.x, A11 = r1.y, A22 = r1.z, A01x2 = r1.w, A02x2 = r2.x, A12x2 = r2.y;
+    const float co = cx - xref, m2co = -2.f * co, co2 = co * co;
     float T[10];
 #pragma unroll
     for (int i = 0; i < 10; ++i) T[i] = 0.f;
     uint32_t pbg = 0;
     for (int r = 0; r < R; ++r) {
       const float4 RW = srow[r];
-      const int k0 = __builtin_amdgcn_readfirstlane(__float_as_int(RW.z)) >> 1;
+      const int k0 = __builtin_amdgcn_readfirstlane(__float_as_int(RW.z));
       const int kn = __builtin_amdgcn_readfirstlane(__float_as_int(RW.w)) >> 1;
       const float dy = RW.x - cy;
       const float dz = RW.y - cz;
       const float syz = fmaf(dy, dy, dz * dz);
       const float bl = fmaf(A01x2, dy, A02x2 * dz);
       const float cc = fmaf(dy, fmaf(A11, dy, A12x2 * dz), A22 * dz * dz);
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      // sums of G e, G e x', G e x'^2 over the row
+      float s0 = 0.f, t1 = 0.f, t2 = 0.f;
       for (int k = 0; k < kn; ++k) {
-        const float4 PP = spx4[k0 + k];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const float px = u ? PP.z : PP.x, pg = u ? PP.w : PP.y;
-          const float dx = px - cx;
+          const float4 PP = spx[k0 + 2 * k + u];
+          const float dx = PP.x - cx;
           const bool in = fmaf(dx, dx, syz) < rad2;
           float q = fmaf(dx, fmaf(A00, dx, bl), cc);
           q = in ? q : INFINITY;
-          const float g = pg * fast_exp2(-q);
-          s0 += g;
-          const float gx = g * dx;
-          s1 += gx;
-          s2 = fmaf(gx, dx, s2);
+          const float e = fast_exp2(-q);
+          s0 = fmaf(PP.y, e, s0);
+          t1 = fmaf(PP.z, e, t1);
+          t2 = fmaf(PP.w, e, t2);
           pbg += __popcll(__ballot(in));
         }
       }
+      // sum g dx and sum g dx^2 about the kernel's centre
+      const float s1 = fmaf(-co, s0, t1);
+      const float s2 = fmaf(co2, s0, fmaf(m2co, t1, t2));
       T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
       T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
       T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
