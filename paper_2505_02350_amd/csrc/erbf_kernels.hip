@@ -1129,14 +1129,20 @@ __global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
 // The moments of each (tile, kernel) entry go to `partials`.
 // ---------------------------------------------------------------------------
 
+// Four waves per workgroup share a tile's kernel groups of 64 (two or eight
+// waves measured slower on the 256^3 snapshot).
+constexpr int kBwdThreads = 256;
+constexpr int kBwdWaves = kBwdThreads / 64;
+constexpr int kBwdRounds = kTile * kTile * kTile / kBwdThreads;   // points per thread
+
 __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc) {
   // non-zero points (x, G, G x', G x'^2), row by row: row r's points sit at
   // spx[8 r ...], padded to an even count with an inert point (far away,
   // G = 0) so that they are read two at a time
   __shared__ float4 spx[kTile * kTile * kTile];
   __shared__ float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
-  __shared__ int swr[2][4];
-  __shared__ int64_t spb[4];
+  __shared__ int swr[kBwdRounds][kBwdWaves];
+  __shared__ int64_t spb[kBwdWaves];
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
@@ -1155,16 +1161,16 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
   const float* __restrict__ G = Gsrc + L.pt_base;
 
-  // thread p = tid + 256 h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
+  // thread p = tid + kBwdThreads h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
   // of the tile: eight consecutive lanes hold one row
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const int rl = lane & ~7;                       // first lane of this lane's row
   const float xref = L.axis[tx * kTile];         // x' = x - xref
-  bool row_used[2];
-  int row_cnt[2], row_pos[2];
+  bool row_used[kBwdRounds];
+  int row_cnt[kBwdRounds], row_pos[kBwdRounds];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int p = tid + 256 * h;
+  for (int h = 0; h < kBwdRounds; ++h) {
+    const int p = tid + kBwdThreads * h;
     const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
     float g = 0.f;
     if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
@@ -1186,18 +1192,18 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   }
   __syncthreads();
   int tot = 0;
-  int base_h[2];
+  int base_h[kBwdRounds];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    for (int v = 0; v < 4; ++v) {
+  for (int h = 0; h < kBwdRounds; ++h) {
+    for (int v = 0; v < kBwdWaves; ++v) {
       if (v == wv) base_h[h] = tot;
       tot += swr[h][v];
     }
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < kBwdRounds; ++h) {
     if ((lane & 7) == 0 && row_used[h]) {
-      const int p = tid + 256 * h;
+      const int p = tid + kBwdThreads * h;
       const int yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
       srow[base_h[h] + row_pos[h]] =
           make_float4(L.axis[yi], L.axis[zi], __int_as_float(8 * (p >> 3)), __int_as_float((row_cnt[h] + 1) & ~1));
@@ -1221,7 +1227,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   int64_t pb = 0;   // in-ball pairs at non-zero points (wave-uniform)
   // each wave takes its own groups of 64 kernels, so waves past the end of
   // the list do no work
-  for (int64_t c0 = beg + 64 * wv; c0 < end; c0 += 256) {
+  for (int64_t c0 = beg + 64 * wv; c0 < end; c0 += 64 * kBwdWaves) {
     const bool have = c0 + lane < end;
     float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
            r2 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1282,14 +1288,19 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   }
   if (lane == 0) spb[wv] = pb;
   __syncthreads();
-  if (tid == 0) D.tile_pbwd[slot] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
+  if (tid == 0) {
+    int64_t t = 0;
+    for (int v = 0; v < kBwdWaves; ++v) t += spb[v];
+    D.tile_pbwd[slot] = t;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
+__global__ __launch_bounds__(kBwdThreads) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
   bwd_tile(D, blockIdx.x, Gsrc);
 }
 
-__global__ __launch_bounds__(256) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc, int n_slots) {
+__global__ __launch_bounds__(kBwdThreads) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc,
+                                                                       int n_slots) {
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     bwd_tile(D, slot, Gsrc);
     __syncthreads();
@@ -1892,10 +1903,11 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
                            const hipEvent_t* ev, hipStream_t s) {
   if (n_slots > 0 && (D.variant & kVariantBwdPersistent)) {
     const int grid = std::min(n_slots, D.persistent_wgs);
-    launch_timed(k_bwd_tiles_persistent, dim3(grid), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D,
-                 G, n_slots);
+    launch_timed(k_bwd_tiles_persistent, dim3(grid), dim3(kBwdThreads), s, ev ? ev[0] : nullptr,
+                 ev ? ev[1] : nullptr, D, G, n_slots);
   } else if (n_slots > 0) {
-    launch_timed(k_bwd_tiles, dim3(n_slots), dim3(256), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G);
+    launch_timed(k_bwd_tiles, dim3(n_slots), dim3(kBwdThreads), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D,
+                 G);
   }
   if (D.n_samp_slots > 0) {
     hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, kSampSplit), dim3(256), 0, s, D, G);
