@@ -597,8 +597,7 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
       const LevelDev& L = ctx->lv[s.lvl0 + l];
       if (L.bits || L.kind == kLevelSamples) HIP_TRY(launch_fill_f32(f_out + L.pt_base, L.npts, 0.f, stream), "eval: clear");
     }
-  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "eval: prologue");
-  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "eval: buckets");
+  HIP_TRY(launch_buckets(D, params->p, params->m_dev, ctx->slots_used, stream), "eval: buckets");
   HIP_TRY(launch_forward(D, ctx->slots_used, false, f_out, 0.f, 0.f, nullptr, stream), "eval: forward");
   if (stats_dev) {
     StatsArgs a{};
@@ -626,8 +625,7 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
         if (L.bits || L.kind == kLevelSamples)
           HIP_TRY(launch_fill_f32(f_out + L.pt_base, L.npts, 0.f, stream), "loss: clear");
       }
-  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "loss: prologue");
-  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "loss: buckets");
+  HIP_TRY(launch_buckets(D, params->p, params->m_dev, ctx->slots_used, stream), "loss: buckets");
   const hipEvent_t* ev = tev_call(ctx);
   HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, ev, stream), "loss: forward");
   HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
@@ -667,8 +665,7 @@ int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_lo
   HIP_TRY(launch_batch_tiles(D, ctx->slots_used, pts, n_pts, D.sel_buf, stream), "batch: tiles");
   // G is zero outside the batch, so the tile backward sees the batch only
   HIP_TRY(launch_fill_f32(D.G, ctx->lay.pts_total, 0.f, stream), "batch: clear G");
-  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "batch: prologue");
-  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "batch: buckets");
+  HIP_TRY(launch_buckets(D, params->p, params->m_dev, ctx->slots_used, stream), "batch: buckets");
   StatsArgs a{};
   a.mode = cfg->mode;
   a.lambda = cfg->lambda;
@@ -689,8 +686,7 @@ int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, floa
   if (!grad_f || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "grad_f and grad_out must be non-NULL");
   DeviceGuard guard(ctx->device);
   const Dev& D = ctx->D;
-  HIP_TRY(launch_prologue(D, params->p, params->m_dev, stream), "vjp: prologue");
-  HIP_TRY(launch_buckets(D, ctx->slots_used, stream), "vjp: buckets");
+  HIP_TRY(launch_buckets(D, params->p, params->m_dev, ctx->slots_used, stream), "vjp: buckets");
   for (const ShapeDev& s : ctx->sh)
     for (int l = 0; l < s.n_active; ++l) {
       const LevelDev& L = ctx->lv[s.lvl0 + l];

@@ -1,7 +1,8 @@
 // HIP kernels of the ERBF-fit step for gfx950 (CDNA4, wave64).
 //
-//   prologue   per-kernel record: centre, squared cull radius, log2(e)-scaled
-//              quadric A = R^T diag(d^2) R, amplitude (eq. 3-7, 3-26, 3-15)
+//   record     per-kernel record: centre, squared cull radius, log2(e)-scaled
+//              quadric A = R^T diag(d^2) R, amplitude (eq. 3-7, 3-26, 3-15),
+//              formed by the bucket count pass
 //   bucket     tile -> kernel lists: per-kernel count, scan, kernel-major emit,
 //              stable radix sort by tile slot (no atomics)
 //   forward    point-centric gather over the tile's kernel list staged in LDS,
@@ -71,15 +72,14 @@ __device__ __forceinline__ int popcount_range(const uint32_t* bits, int64_t b0, 
 }
 
 // ---------------------------------------------------------------------------
-// prologue: one thread per kernel slot
+// per-kernel record (formed by the bucket count pass, one wave per kernel slot)
 // record: r0 = {cx, cy, cz, r^2}  (r^2 < 0 marks a dead slot)
 //         r1 = {A00, A11, A22, 2 A01}  r2 = {2 A02, 2 A12, a, 0}, A scaled by log2(e)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
-                                                  const int32_t* __restrict__ m_dev, Dev D) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= D.cap_total) return;
+__device__ __forceinline__ void kernel_record(const float* __restrict__ p, const int32_t* __restrict__ m_dev,
+                                              const Dev& D, const int j, float4& r0_out, float4& r1_out,
+                                              float4& r2_out) {
   const int b = D.kshape[j];
   const ShapeDev S = D.shapes[b];
   const int m = min(max(m_dev[b], 0), S.cap);
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(256) void k_prologue(const float* __restrict__ p,
     r1 = make_float4(A[0][0] * kLog2e, A[1][1] * kLog2e, A[2][2] * kLog2e, 2.f * A[0][1] * kLog2e);
     r2 = make_float4(2.f * A[0][2] * kLog2e, 2.f * A[1][2] * kLog2e, amp, 0.f);
   }
-  D.rec[3 * j + 0] = r0;
-  D.rec[3 * j + 1] = r1;
-  D.rec[3 * j + 2] = r2;
+  r0_out = r0;
+  r1_out = r1;
+  r2_out = r2;
 }
 
 // ---------------------------------------------------------------------------
@@ -265,8 +265,7 @@ __device__ __forceinline__ bool ball_box(const LevelDev& L, const float4& r0, Ba
 
 // Count walk: lanes own rows of tiles (y, z) and step along x, so a row's
 // y and z distances are formed once.
-__device__ __forceinline__ int bucket_count_walk(const Dev& D, const int j, const int lane) {
-  const float4 r0 = D.rec[3 * j];
+__device__ __forceinline__ int bucket_count_walk(const Dev& D, const float4 r0, const int j, const int lane) {
   if (r0.w < 0.f) return 0;
   const ShapeDev S = D.shapes[D.kshape[j]];
   int total = 0;
@@ -357,17 +356,32 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
     if (at < D.pair_cap) {
       D.kslot[at] = D.tiles_total;
       D.kj[at] = j;
+      float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
+#pragma unroll
+      for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
     }
   }
 }
 
-// Count pass: kcnt per kernel (one wave each) and the sum of each block's
+// Count pass: the kernel's record (every lane forms the same one, lane 0
+// stores it), kcnt per kernel (one wave each) and the sum of each block's
 // four kernels.
-__global__ __launch_bounds__(256) void k_bucket_count(Dev D) {
+__global__ __launch_bounds__(256) void k_bucket_count(Dev D, const float* __restrict__ p,
+                                                      const int32_t* __restrict__ m_dev) {
   __shared__ int wc[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
-  const int c = j < D.cap_total ? bucket_count_walk(D, j, lane) : 0;
+  int c = 0;
+  if (j < D.cap_total) {
+    float4 r0, r1, r2;
+    kernel_record(p, m_dev, D, j, r0, r1, r2);
+    if (lane == 0) {
+      D.rec[3 * j + 0] = r0;
+      D.rec[3 * j + 1] = r1;
+      D.rec[3 * j + 2] = r2;
+    }
+    c = bucket_count_walk(D, r0, j, lane);
+  }
   if (lane == 0) {
     if (j < D.cap_total) D.kcnt[j] = c;
     wc[w] = c;
@@ -903,6 +917,17 @@ __global__ __launch_bounds__(256) void k_batch_tiles(Dev D, const int64_t* __res
   if (slot >= 0) sel[slot] = 1;
 }
 
+// Zero moments for entries [c_lo, c_hi) of the tile-major lists (tiles whose
+// points all have G = 0), so that every entry's partial is written each step
+// and the reduce reads them without checks.
+__device__ __forceinline__ void zero_partials(const Dev& D, int64_t c_lo, int64_t c_hi, int tid, int nthreads) {
+  for (int64_t c = c_lo + tid; c < c_hi; c += nthreads) {
+    float2* o = D.partials + 5 * (int64_t)D.tile_e[c];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // surface samples (label 1, eq. 3-10 on the surface).  A sample level bins
 // its samples into the 8^3-cell tiles of an n^3-cell grid; a tile's box is
@@ -1030,9 +1055,15 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   const LevelDev L = D.levels[lt.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  // parts of whole rounds of 256 kernels, so that every lane has one
+  const int64_t part = (((end - beg + kSampSplit - 1) / kSampSplit + 255) / 256) * 256;
+  const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
   int nz = 0;
   for (int si = s0 + tid; si < s1; si += 256) nz |= Gsrc[L.pt_base + __float_as_int(L.spos[si].w)] != 0.f ? 1 : 0;
   if (!__syncthreads_or(nz)) {
+    zero_partials(D, rb, re, tid, 256);
     if (tid == 0) {
       if (blockIdx.y == 0) D.tile_nz[slot] = 0;
       D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = 0;
@@ -1040,11 +1071,6 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
     return;
   }
   if (tid == 0 && blockIdx.y == 0) D.tile_nz[slot] = 1;
-  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
-  // parts of whole rounds of 256 kernels, so that every lane has one
-  const int64_t part = (((end - beg + kSampSplit - 1) / kSampSplit + 255) / 256) * 256;
-  const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
   int64_t pb = 0;
   for (int64_t c0 = rb; c0 < re; c0 += 256) {
     const int64_t e = c0 + tid;
@@ -1213,6 +1239,8 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   // makes that visible, so the early exit below is a scalar branch
   const int R = __builtin_amdgcn_readfirstlane(tot);
   if (R == 0) {
+    zero_partials(D, min((int64_t)D.tile_start[slot], D.pair_cap), min((int64_t)D.tile_start[slot + 1], D.pair_cap),
+                  tid, kBwdThreads);
     if (tid == 0) {
       D.tile_nz[slot] = 0;
       D.tile_pbwd[slot] = 0;
@@ -1355,10 +1383,10 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
   for (int i = 0; i < 10; ++i) v[i] = 0.0;
   const int64_t base = D.kstart[j];
   const int c = D.kcnt[j];
-  for (int e = lane; e < c; e += 64) {
-    if (base + e >= D.pair_cap) break;
-    const int sl = D.kslot[base + e];
-    if (sl < 0 || sl >= D.tiles_total || !D.tile_nz[sl]) continue;
+  // every entry's moments are written each step (zero for tiles without a
+  // non-zero G, and for the filler entries of the emit pass)
+  const int cc = (int)min((int64_t)c, max((int64_t)0, D.pair_cap - base));
+  for (int e = lane; e < cc; e += 64) {
     const float2* q = D.partials + 5 * (base + e);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -1796,11 +1824,6 @@ __global__ __launch_bounds__(256) void k_tile_assign(Dev D, int li, const int32_
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 static inline unsigned gridstride(int64_t n) { return (unsigned)std::min<int64_t>(nblk(n, 256), 4096); }
 
-hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_prologue, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, p, m_dev, D);
-  return hipGetLastError();
-}
-
 hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
                        hipStream_t s) {
   const int nb = (int)nblk(n + 1, 1024);
@@ -1821,10 +1844,12 @@ hipError_t launch_scan_any(const int32_t* in, int n, int32_t* blocks, int32_t* o
   return hipGetLastError();
 }
 
-hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s) {
-  if (n_slots <= 0) return hipSuccess;
+hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, int n_slots, hipStream_t s) {
   const int nkb = (int)nblk(D.cap_total, 4);   // count/emit blocks, four kernels each
-  hipLaunchKernelGGL(k_bucket_count, dim3(nkb), dim3(256), 0, s, D);
+  // the count pass also forms every kernel's record, which the forward and
+  // backward read even when no tile is active
+  hipLaunchKernelGGL(k_bucket_count, dim3(nkb), dim3(256), 0, s, D, p, m_dev);
+  if (n_slots <= 0) return hipGetLastError();
   {
     const hipError_t e = launch_scan_any(D.kblock, nkb, D.scan_blocks, D.kblock_ex, D.counters, s);
     if (e != hipSuccess) return e;

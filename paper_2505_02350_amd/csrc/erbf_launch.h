@@ -23,10 +23,10 @@ struct AdamArgs {
 };
 
 
-hipError_t launch_prologue(const Dev& D, const float* p, const int32_t* m_dev, hipStream_t s);
 hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
                        hipStream_t s);
-hipError_t launch_buckets(const Dev& D, int n_slots, hipStream_t s);
+// kernel records, then the tile -> kernel lists
+hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, int n_slots, hipStream_t s);
 // `ev` (optional): start/stop events of each launched kernel, recorded at
 // the kernel's own start and end (forward: 2 events; backward: 4).
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
