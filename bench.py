@@ -4,7 +4,7 @@
 Workload (timing snapshot of the large hierarchy): smooth union of 12 boxes,
 6 capsules and 4 tori sampled on 64^3 + 128^3 + 256^3 grid levels (the finest
 restricted to |S| < 0.1), 16384 ERBFs drawn with the kernel init rule.  One
-step = prologue, tile buckets, forward + masked loss, backward, eq. 3-21
+step = kernel records and tile buckets, forward + masked loss, backward, eq. 3-21
 weights and Adam, all on the device; inputs are resident in HBM before the
 timed region.
 
