@@ -50,7 +50,7 @@ struct Layout {
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_kslot, off_sort_keys[2],
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
-      off_tile_nz, off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
+      off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
       off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init, off_samp_pos, off_samp_start, off_samp_slot,
       off_samp_slots, off_samp_f, off_samp_c, off_samp_pb, off_sel;
@@ -141,7 +141,6 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_kblock = take(sizeof(int32_t) * (L.cap_total / 4 + 1));
   L.off_kblock_ex = take(sizeof(int32_t) * (L.cap_total / 4 + 2));
   L.off_partials = take(sizeof(float2) * 5 * cfg->pair_cap);
-  L.off_tile_nz = take(sizeof(int32_t) * L.tiles_total);
   L.off_scan = take(sizeof(int32_t) * L.scan_blocks);
   L.off_rflags = take(sizeof(int32_t) * (L.max_level_tiles + 1));
   L.off_rexcl = take(sizeof(int32_t) * (L.max_level_tiles + 1));
@@ -299,7 +298,6 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.kblock = reinterpret_cast<int32_t*>(w + lay.off_kblock);
   D.kblock_ex = reinterpret_cast<int32_t*>(w + lay.off_kblock_ex);
   D.partials = reinterpret_cast<float2*>(w + lay.off_partials);
-  D.tile_nz = reinterpret_cast<int32_t*>(w + lay.off_tile_nz);
   D.scan_blocks = reinterpret_cast<int32_t*>(w + lay.off_scan);
   c->rflags = reinterpret_cast<int32_t*>(w + lay.off_rflags);
   c->rexcl = reinterpret_cast<int32_t*>(w + lay.off_rexcl);

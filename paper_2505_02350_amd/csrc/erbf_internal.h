@@ -95,7 +95,6 @@ struct Dev {
   int32_t* kblock;          // [cap_total / 4 + 1] kcnt summed over each count block (four kernels)
   int32_t* kblock_ex;       // [cap_total / 4 + 2] exclusive scan of kblock
   float2* partials;         // [5 * pair_cap] the 10 backward moments of each entry, kernel-major
-  int32_t* tile_nz;         // [tiles_total] tile has a non-zero upstream gradient
   int32_t* sel_buf;         // [tiles_total] scratch of the tile selection below
   const int32_t* tile_sel;  // null, or [tiles_total]: bucket lists only for slots with a non-zero entry
   int32_t* scan_blocks;     // [scan block sums]

@@ -1064,13 +1064,9 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   for (int si = s0 + tid; si < s1; si += 256) nz |= Gsrc[L.pt_base + __float_as_int(L.spos[si].w)] != 0.f ? 1 : 0;
   if (!__syncthreads_or(nz)) {
     zero_partials(D, rb, re, tid, 256);
-    if (tid == 0) {
-      if (blockIdx.y == 0) D.tile_nz[slot] = 0;
-      D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = 0;
-    }
+    if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = 0;
     return;
   }
-  if (tid == 0 && blockIdx.y == 0) D.tile_nz[slot] = 1;
   int64_t pb = 0;
   for (int64_t c0 = rb; c0 < re; c0 += 256) {
     const int64_t e = c0 + tid;
@@ -1176,10 +1172,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const int tid = threadIdx.x;
   if (min((int64_t)D.tile_start[slot], D.pair_cap) == min((int64_t)D.tile_start[slot + 1], D.pair_cap)) {
     // no kernel reaches the tile (or, in a mini-batch, no batch point is in it)
-    if (tid == 0) {
-      D.tile_nz[slot] = 0;
-      D.tile_pbwd[slot] = 0;
-    }
+    if (tid == 0) D.tile_pbwd[slot] = 0;
     return;
   }
   const int n = L.n, nt = L.nt;
@@ -1241,13 +1234,9 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   if (R == 0) {
     zero_partials(D, min((int64_t)D.tile_start[slot], D.pair_cap), min((int64_t)D.tile_start[slot + 1], D.pair_cap),
                   tid, kBwdThreads);
-    if (tid == 0) {
-      D.tile_nz[slot] = 0;
-      D.tile_pbwd[slot] = 0;
-    }
+    if (tid == 0) D.tile_pbwd[slot] = 0;
     return;
   }
-  if (tid == 0) D.tile_nz[slot] = 1;
   __syncthreads();
 
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
