@@ -1185,6 +1185,16 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const int rl = lane & ~7;                       // first lane of this lane's row
   const float xref = L.axis[tx * kTile];         // x' = x - xref
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  // the kernel this lane owns in its wave's first group is read while the
+  // points are staged
+  const int64_t cf = beg + 64 * wv;
+  int jf = 0, ef = 0;
+  if (cf + lane < end) {
+    jf = D.items[cf + lane];
+    ef = D.tile_e[cf + lane];
+  }
   bool row_used[kBwdRounds];
   int row_cnt[kBwdRounds], row_pos[kBwdRounds];
 #pragma unroll
@@ -1208,6 +1218,13 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     const unsigned long long rb = __ballot((lane & 7) == 0 && c > 0);
     row_pos[h] = __popcll(rb & lt_mask);
     if (lane == 0) swr[h][wv] = __popcll(rb);
+  }
+  float4 f0 = make_float4(0.f, 0.f, 0.f, -1.f), f1 = make_float4(0.f, 0.f, 0.f, 0.f),
+         f2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (cf + lane < end) {
+    f0 = D.rec[3 * jf];
+    f1 = D.rec[3 * jf + 1];
+    f2 = D.rec[3 * jf + 2];
   }
   __syncthreads();
   int tot = 0;
@@ -1239,22 +1256,24 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   }
   __syncthreads();
 
-  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
   int64_t pb = 0;   // in-ball pairs at non-zero points (wave-uniform)
   // each wave takes its own groups of 64 kernels, so waves past the end of
   // the list do no work
-  for (int64_t c0 = beg + 64 * wv; c0 < end; c0 += 64 * kBwdWaves) {
+  for (int64_t c0 = cf; c0 < end; c0 += 64 * kBwdWaves) {
     const bool have = c0 + lane < end;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, -1.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
-           r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    int e_out = 0;
-    if (have) {
-      const int j = D.items[c0 + lane];
-      e_out = D.tile_e[c0 + lane];
-      r0 = D.rec[3 * j];
-      r1 = D.rec[3 * j + 1];
-      r2 = D.rec[3 * j + 2];
+    float4 r0 = f0, r1 = f1, r2 = f2;   // the first group's, read above
+    int e_out = ef;
+    if (c0 != cf) {
+      r0 = make_float4(0.f, 0.f, 0.f, -1.f);
+      r1 = r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      e_out = 0;
+      if (have) {
+        const int j = D.items[c0 + lane];
+        e_out = D.tile_e[c0 + lane];
+        r0 = D.rec[3 * j];
+        r1 = D.rec[3 * j + 1];
+        r2 = D.rec[3 * j + 2];
+      }
     }
     const float cx = r0.x, cy = r0.y, cz = r0.z, rad2 = r0.w;
     const float A00 = r1.x, A11 = r1.y, A22 = r1.z, A01x2 = r1.w, A02x2 = r2.x, A12x2 = r2.y;
@@ -1312,7 +1331,8 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   }
 }
 
-__global__ __launch_bounds__(kBwdThreads) void k_bwd_tiles(Dev D, const float* __restrict__ Gsrc) {
+__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_tiles(
+    Dev D, const float* __restrict__ Gsrc) {
   bwd_tile(D, blockIdx.x, Gsrc);
 }
 
