@@ -71,6 +71,25 @@ def test_sampling_is_on_triangles_and_uniform_by_area():
     assert np.allclose(np.abs(N[:, 2]), 1.0)
 
 
+def test_sampling_is_uniform_within_a_triangle():
+    # a uniform density on a triangle has the centroid as its mean, and each
+    # of the four half-scale sub-triangles (three corners, the middle one)
+    # holds a quarter of the samples
+    rng = np.random.default_rng(11)
+    A, B, C = np.array([0.2, -0.1, 0.3]), np.array([1.4, 0.2, 0.1]), np.array([0.5, 1.3, -0.4])
+    T = np.array([[A, B, C]], np.float64)
+    n = 200000
+    P, _, _ = Mx.sample_surface(T, rng.random((n, 3)))
+    side = max(np.linalg.norm(B - A), np.linalg.norm(C - A), np.linalg.norm(C - B))
+    assert np.linalg.norm(P.mean(0) - (A + B + C) / 3.0) < 5e-3 * side
+    # barycentric coordinates of the samples
+    M = np.stack([B - A, C - A], 1)
+    lb, lc = np.linalg.lstsq(M, (P - A).T, rcond=None)[0]
+    la = 1.0 - lb - lc
+    for frac in ((la > 0.5).mean(), (lb > 0.5).mean(), (lc > 0.5).mean()):
+        assert abs(frac - 0.25) < 0.005
+
+
 def test_metrics_brute_force_and_concentric_spheres():
     rng = np.random.default_rng(5)
     A = rng.normal(size=(300, 3))
