@@ -310,6 +310,27 @@ def test_euler_isotropic_kernels_have_zero_angle_gradient():
     assert np.all(gr.q[:, 3] == 0.0)
 
 
+def test_batch_step_over_two_levels_is_additive():
+    # batch indices run over the concatenation of the levels' points: a
+    # partition of both levels' points into three batches adds up to the
+    # full step, and a batch of the second level's points alone sees only them
+    p = synth.make_custom(17, [8, 12], 6, (1.3, 2.1), kinds=("ellipsoid", "torus"))
+    K = O.kernels_from_packed(p.params, p.m, p.cap, 3.0)
+    mS = O.sdf_min([lv.S for lv in p.levels])
+    levels = [O.make_level(lv.n, lv.axis, t=O.targets_from_sdf(lv.S, mS).astype(np.float32), S=lv.S)
+              for lv in p.levels]
+    n0, n1 = levels[0].npts, levels[1].npts
+    full = O.step(levels, K)
+    perm = np.random.default_rng(5).permutation(n0 + n1)
+    parts = [O.step_batch(levels, K, perm[i::3]) for i in range(3)]
+    assert abs(sum(b.loss.L2 for b in parts) - full.loss.L2) <= 1e-12 * full.loss.L2
+    assert sum(b.loss.n_idall for b in parts) == full.loss.n_idall
+    assert sum(b.P_fwd for b in parts) == full.P_fwd
+    second = O.step_batch(levels, K, n0 + np.arange(n1))
+    only = O.step([levels[1]], K)
+    assert second.P_fwd == only.P_fwd and second.loss.n_idall == only.loss.n_idall
+
+
 def test_batch_step_reduces_to_the_full_step_and_is_additive():
     lv, K, p = _problem(seed=16, n=12, m=6, lo=1.3, hi=2.1)
     full = O.step([lv], K)

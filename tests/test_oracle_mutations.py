@@ -66,6 +66,14 @@ MUTATIONS = [
      ["tests/test_oracle_schedule.py"]),
     ("final-phase cosine with the wrong sign", "oracle/schedule.py",
      "(1.0 + math.cos(math.pi * frac))", "(1.0 - math.cos(math.pi * frac))", ["tests/test_oracle_schedule.py"]),
+    ("Euler angles composed in the reverse order (eq. 3-6)", "oracle/erbf.py",
+     "    return Rz @ Ry @ Rx\n", "    return Rx @ Ry @ Rz\n", FWD_BWD),
+    ("seeding keeps points that are not local maxima (Algorithm 2)", "oracle/erbf.py",
+     "if sel.any() and absE[g] < absE[gl[sel]].max():", "if sel.any() and absE[g] < absE[gl[sel]].max() and False:",
+     FWD_BWD),
+    ("mini-batch mask offset by one level's base", "oracle/erbf.py",
+     "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base",
+     "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base // 2", FWD_BWD),
 ]
 
 
