@@ -376,3 +376,22 @@ def test_octree_mask_covers_the_surface_and_nests():
             assert not np.any(child & ~par)
         assert child.sum() < child.size
         prev, S_prev = child, lv.S
+
+
+def test_targets_over_several_levels_keep_eq_3_10_on_its_branch():
+    # eq. 3-10 uses the branch S >= m: with m the minimum over every level's
+    # grid, each point of each level has S - m >= 0, the targets are a
+    # non-increasing function of S over the union of the levels, and the
+    # deepest point of any level gets t = 2.  A finer cell-centred grid comes
+    # closer to a sphere's centre, so here the minimum lies on the second level.
+    from synth.grid import axis_coords
+    from synth.sdf import sample_sdf, sphere
+    S = [sample_sdf([sphere(0.5)], axis_coords(n)).astype(np.float64) for n in (8, 16)]
+    assert S[1].min() < S[0].min()
+    m = O.sdf_min(S)
+    allS = np.concatenate(S)
+    assert np.all(allS - m >= 0.0)
+    t = np.concatenate([O.targets_from_sdf(s, m) for s in S])
+    order = np.argsort(allS, kind="stable")
+    assert np.all(np.diff(t[order]) <= 1e-15)
+    assert t.max() == pytest.approx(2.0, abs=1e-15)

@@ -71,6 +71,19 @@ MUTATIONS = [
     ("seeding keeps points that are not local maxima (Algorithm 2)", "oracle/erbf.py",
      "if sel.any() and absE[g] < absE[gl[sel]].max():", "if sel.any() and absE[g] < absE[gl[sel]].max() and False:",
      FWD_BWD),
+    ("m taken over the first level only (eq. 3-10)", "oracle/erbf.py",
+     "return float(min(np.min(np.asarray(S, dtype=np.float64)) for S in S_levels))",
+     "return float(np.min(np.asarray(S_levels[0], dtype=np.float64)))", FWD_BWD),
+    ("targets lose their factor 2 (eq. 3-10)", "oracle/erbf.py",
+     "return 2.0 * np.exp(-h * (S - m) ** 2)", "return np.exp(-h * (S - m) ** 2)", FWD_BWD),
+    ("L1 of signed weights (eq. 3-14_2)", "oracle/erbf.py",
+     "L1 = float(np.sum(np.abs(K.w)))", "L1 = float(np.sum(K.w))", FWD_BWD),
+    ("Adam bias correction off by one step", "oracle/erbf.py",
+     "mhat = m1 / (1 - b1 ** t)", "mhat = m1 / (1 - b1 ** (t + 1))", FWD_BWD),
+    ("quaternion gradient without the tangent projection", "oracle/erbf.py",
+     "proj = gqhat - K.qhat * np.sum(K.qhat * gqhat, axis=1, keepdims=True)", "proj = gqhat", FWD_BWD),
+    ("a tetrahedron of the cube split replaced", "oracle/metrics.py",
+     "(0, 4, 5, 7), (0, 5, 1, 7))", "(0, 4, 5, 7), (0, 5, 4, 7))", ["tests/test_oracle_metrics.py"]),
     ("mini-batch mask offset by one level's base", "oracle/erbf.py",
      "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base",
      "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base // 2", FWD_BWD),
