@@ -720,32 +720,57 @@ class SeedOut:
 def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
          top_frac: float = 0.01, k_new: int = 256, r_nms: Optional[float] = None,
          eps: float = 1e-7, min_abs_err: float = 0.0, w_rule: int = 0,
-         orientation: int = ORIENT_QUATERNION) -> SeedOut:
+         orientation: int = ORIENT_QUATERNION, n_idall: Optional[int] = None) -> SeedOut:
     """New kernels at local extrema of |E| (Algorithm 2).
 
-    1. candidates: the ceil(top_frac * n_idall) id_all points of largest |E|
-       (ties to the lower global index), keeping |E| > max(min_abs_err, eps);
+    The training set V is the grid levels plus, when registered, the surface
+    samples P (OSamples entries of `levels`; Section 3.4.2, V = {G, P}).
+
+    1. candidates: the ceil(top_frac * n_idall) grid points of id_all with the
+       largest |E| (ties to the lower global index), keeping
+       |E| > max(min_abs_err, eps).  n_idall counts every id_all point of V
+       (default) or is given.  Samples are never candidates: a centre placed
+       on a sample has distance 0 to P, and eq. 3-24 has no scale there;
     2. extreme points: a candidate survives if |E_i| >= |E_k| for every id_all
-       point k of any level with ||x_k - x_i|| <= r_nms (default: twice the
-       finest spacing);
+       point k of V (grid points of every level and samples) with
+       ||x_k - x_i|| <= r_nms (default: twice the finest grid spacing);
     3. the first k_new survivors by (|E| desc, index asc);
     4. eq. 3-24: c = x_i; w = -sign(E)|E| (w_rule 0) or -sign(E) sqrt|E|
-       (w_rule 1); d = sqrt(ln(|E| / eps)) / dbar on all axes with
-       dbar = max(|S_i|, h_finest) standing in for the distance to the
-       nearest surface sample; orientation zero (identity quaternion, or zero
-       Euler angles).
-    Global indices run over the levels in order, x fastest inside a level."""
+       (w_rule 1); d = sqrt(ln(|E| / eps)) / dbar on all axes, dbar the
+       distance from x_i to the nearest registered sample of P, or |S_i|
+       (the distance to the surface that P samples) when no sample is
+       registered, in both cases at least the finest grid spacing h;
+       orientation zero (identity quaternion, or zero Euler angles).
+    Global indices run over the levels in order, x fastest inside a grid
+    level, sample slots in their order inside a sample level."""
     offs = np.cumsum([0] + [lv.npts for lv in levels])
     absE = np.concatenate([np.abs(np.asarray(e, np.float64)) for e in E])
     ida = np.concatenate([np.asarray(i, bool) for i in idall])
-    h_fine = min(float(lv.axis[1] - lv.axis[0]) for lv in levels)
+    is_grid = np.concatenate([np.full(lv.npts, not isinstance(lv, OSamples)) for lv in levels])
+    grids = [lv for lv in levels if not isinstance(lv, OSamples)]
+    h_fine = min(float(lv.axis[1] - lv.axis[0]) for lv in grids)
     if r_nms is None:
         r_nms = 2.0 * h_fine
+    # every registered sample (for dbar) and the id_all samples with their |E|
+    # (for the extreme-point test)
+    P_all, P_ida, P_absE = [], [], []
+    for li, lv in enumerate(levels):
+        if isinstance(lv, OSamples):
+            k = lv.pts.shape[0]
+            P_all.append(lv.pts)
+            sel = np.flatnonzero(ida[offs[li]:offs[li] + k])
+            P_ida.append(lv.pts[sel])
+            P_absE.append(absE[offs[li] + sel])
+    P_all = np.concatenate(P_all) if P_all else np.zeros((0, 3))
+    P_ida = np.concatenate(P_ida) if P_ida else np.zeros((0, 3))
+    P_absE = np.concatenate(P_absE) if P_absE else np.zeros(0)
     gid = np.flatnonzero(ida)
-    n_idall = gid.size
+    if n_idall is None:
+        n_idall = gid.size
     K = int(math.ceil(top_frac * n_idall))
-    order = np.lexsort((gid, -absE[gid]))
-    cand = gid[order[:K]]
+    gcand = gid[is_grid[gid]]
+    order = np.lexsort((gcand, -absE[gcand]))
+    cand = gcand[order[:K]]
     cand = cand[absE[cand] > max(min_abs_err, eps)]
 
     def locate(g):
@@ -765,6 +790,8 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
         x = coords(g)
         ok = True
         for li, lv in enumerate(levels):
+            if isinstance(lv, OSamples):
+                continue
             a = lv.axis
             rng = [_box(a, x[k] - r_nms, x[k] + r_nms) for k in range(3)]
             (x0, x1), (y0, y1), (z0, z1) = rng
@@ -780,6 +807,11 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
             if sel.any() and absE[g] < absE[gl[sel]].max():
                 ok = False
                 break
+        if ok and P_ida.shape[0]:
+            d = P_ida - x[None, :]
+            near = np.sum(d * d, axis=1) <= r2
+            if near.any() and absE[g] < P_absE[near].max():
+                ok = False
         if ok:
             kept.append(g)
     kept = np.asarray(kept, dtype=np.int64)
@@ -787,7 +819,6 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
         o2 = np.lexsort((kept, -absE[kept]))
         kept = kept[o2][:k_new]
     Eall = np.concatenate([np.asarray(e, np.float64) for e in E])
-    Sall = np.concatenate([np.asarray(lv.S, np.float64) for lv in levels]) if kept.size else None
     ev = Eall[kept]
     c = np.array([coords(g) for g in kept]).reshape(-1, 3)
     if w_rule == 0:
@@ -795,7 +826,13 @@ def seed(levels: List[OLevel], E: List[np.ndarray], idall: List[np.ndarray],
     else:
         w = -np.sign(ev) * np.sqrt(np.abs(ev))
     if kept.size:
-        dbar = np.maximum(np.abs(Sall[kept]), h_fine)
+        if P_all.shape[0]:
+            dist = np.array([np.sqrt(np.min(np.sum((P_all - ci[None, :]) ** 2, axis=1))) for ci in c])
+        else:
+            Sall = np.concatenate([np.asarray(lv.S, np.float64) if not isinstance(lv, OSamples)
+                                   else np.zeros(lv.npts) for lv in levels])
+            dist = np.abs(Sall[kept])
+        dbar = np.maximum(dist, h_fine)
         d = np.sqrt(np.log(np.abs(ev) / eps)) / dbar
         s = np.repeat(np.log(d)[:, None], 3, axis=1)
     else:

@@ -99,6 +99,66 @@ def test_gradients_match_central_differences(wm, orientation):
         assert err < 1e-6, (name, err)
 
 
+def _fd_combined(lv, K, idall, alpha, beta, h=1e-6, kernels=(0, 1, 2)):
+    """Central differences of alpha * L2 + beta * L1 (eq. 3-14_2: L1 = sum |w|)
+    with the mask and the weights (alpha, beta) frozen."""
+    out = {}
+    base = dict(w=K.w.copy(), c=K.c.copy(), s=K.s.copy(), q=K.q.copy())
+
+    def J(fields):
+        Kp = O.make_kernels(fields["w"], fields["c"], fields["s"], fields["q"], 3.0, K.weight_map, K.orientation)
+        return alpha * O.l2_frozen([lv], Kp, idall, culled=False) + beta * float(np.sum(np.abs(fields["w"])))
+
+    for name, width in (("w", 1), ("c", 3), ("s", 3), ("q", 4)):
+        g = np.zeros((len(kernels), width))
+        for a, j in enumerate(kernels):
+            for k in range(width):
+                fp = {kk: vv.copy() for kk, vv in base.items()}
+                fm = {kk: vv.copy() for kk, vv in base.items()}
+                if name == "w":
+                    fp["w"][j] += h
+                    fm["w"][j] -= h
+                else:
+                    fp[name][j, k] += h
+                    fm[name][j, k] -= h
+                g[a, k] = (J(fp) - J(fm)) / (2 * h)
+        out[name] = g
+    return out
+
+
+@pytest.mark.parametrize("mode", ["fixed", "dynamic"])
+def test_combined_gradient_matches_central_differences(mode):
+    """eq. 3-15-2 / eq. 3-21: the step's gradient is alpha dL2 + beta dL1, the
+    L1 term acting on w alone.  Pinned by central differences of
+    alpha L2 + beta sum|w| itself, with |w| away from 0 so that |w| is
+    differentiable; in the dynamic case alpha comes from eq. 3-21 and lies
+    strictly inside (0, 1), so a dropped alpha or beta shows."""
+    lv, K, _ = _problem(seed=15, n=12, m=5)
+    assert np.all(np.abs(K.w) > 1e-4) and np.all(np.abs(np.abs(K.w) - 1.0) > 1e-3)
+    f = O.forward([lv], K, culled=False)
+    lo = O.loss([lv], f, K)
+    G = [2.0 * e for e in lo.E]
+    gr = O.backward([lv], K, G, culled=False)
+    if mode == "fixed":
+        al, be = O.loss_weights(O.MODE_FIXED, 0.37, False, lo.max_abs_E, 0.02, gr.w, K.w)
+        assert (al, be) == (1.0, 0.37)
+    else:
+        # the gate of eq. l1_activate2 is opened with a tau_m above max|E|
+        al, be = O.loss_weights(O.MODE_DYNAMIC, 0.0, True, lo.max_abs_E, lo.max_abs_E * 2 + 1.0, gr.w, K.w)
+        assert 0.05 < al < 0.95 and be == pytest.approx(1.0 - al)
+    comb = O.combine(gr, K.w, al, be)
+    kern = (0, 2, 4)
+    fd = _fd_combined(lv, K, lo.idall, al, be, kernels=kern)
+    ana = {"w": comb.w[list(kern)][:, None], "c": comb.c[list(kern)], "s": comb.s[list(kern)],
+           "q": comb.q[list(kern)]}
+    # the quotient's rounding error is about 1e-16 |J| / h, up to 1e-6 of the
+    # small orientation gradients here; a lost alpha or beta is an error of
+    # at least 5 %
+    for name in ana:
+        err = np.abs(ana[name] - fd[name]).max() / max(np.abs(fd[name]).max(), 1e-30)
+        assert err < 1e-5, (mode, name, err)
+
+
 def test_culled_gradients_within_truncation_bounds():
     lv, K, _ = _problem(seed=12, n=16, m=8, lo=1.6, hi=2.4)
     f = O.forward([lv], K, culled=True)

@@ -87,6 +87,17 @@ MUTATIONS = [
     ("mini-batch mask offset by one level's base", "oracle/erbf.py",
      "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base",
      "sel = batch[(batch >= base) & (batch < base + lv.npts)] - base // 2", FWD_BWD),
+    ("L1 gradient beta * w in place of beta * sign(w) (eq. 3-15-2)", "oracle/erbf.py",
+     "alpha * gr.w + beta * sign(w)", "alpha * gr.w + beta * w", FWD_BWD),
+    ("centre gradient without alpha (eq. 3-15-2)", "oracle/erbf.py",
+     "alpha * gr.c, alpha * gr.s", "gr.c, alpha * gr.s", FWD_BWD),
+    ("samples do not suppress in the extreme-point test (Algorithm 2)", "oracle/erbf.py",
+     "if ok and P_ida.shape[0]:", "if ok and P_ida.shape[0] and False:", ["tests/test_oracle_samples.py"]),
+    ("dbar from |S| although samples are registered (eq. 3-24)", "oracle/erbf.py",
+     "        if P_all.shape[0]:\n            dist =", "        if False:\n            dist =",
+     ["tests/test_oracle_samples.py"]),
+    ("samples taken as seeding candidates (Algorithm 2)", "oracle/erbf.py",
+     "gcand = gid[is_grid[gid]]", "gcand = gid", ["tests/test_oracle_samples.py"]),
 ]
 
 

@@ -123,3 +123,76 @@ def test_init_depth_from_samples_is_the_nearest_sample_distance():
         top = max(key[i] for i in free)
         assert k == min(i for i in free if key[i] == top)
     assert out.n_left == 0 and out.index.size > 5
+
+
+def _sphere_level_and_samples(n=16, k=400, cap=410, seed=11):
+    ax = (-1.0 + (2.0 * np.arange(n) + 1.0) / n).astype(np.float32)
+    z, y, x = np.meshgrid(ax.astype(np.float64), ax, ax, indexing="ij")
+    S = (np.sqrt(x * x + y * y + z * z) - 0.6).astype(np.float32).reshape(-1)
+    lv = O.make_level(n, ax, S=S)
+    v = np.random.default_rng(seed).normal(size=(k, 3))
+    sp = (0.6 * v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    return lv, O.make_samples(sp, cap=cap)
+
+
+def test_seed_with_samples_matches_all_pairs_and_eq_3_24():
+    """Algorithm 2 on V = {G, P}: the neighbourhoods hold the id_all samples
+    as well as the grid points, samples are not candidates, and eq. 3-24's
+    dbar is the distance to the nearest sample (a k-d tree here), floored at
+    the grid spacing.  Restated by all pairs over V."""
+    lv, P = _sphere_level_and_samples()
+    rng = np.random.default_rng(12)
+    Eg = np.round(rng.normal(size=lv.npts), 2) * (np.abs(lv.S) < 0.3)
+    Es = np.zeros(P.cap)
+    Es[:P.pts.shape[0]] = np.round(rng.normal(size=P.pts.shape[0]), 2)
+    ida_g, ida_s = Eg != 0.0, P.act() & (Es != 0.0)
+    r_nms = 0.3
+    out = O.seed([lv, P], [Eg, Es], [ida_g, ida_s], top_frac=0.05, k_new=30, r_nms=r_nms, eps=1e-7)
+    # all pairs over V
+    X = np.concatenate([O.level_points(lv), O.level_points(P)])
+    absE = np.abs(np.concatenate([Eg, Es]))
+    ida = np.concatenate([ida_g, ida_s])
+    grid = np.arange(X.shape[0]) < lv.npts
+    K = int(np.ceil(0.05 * ida.sum()))
+    ranked = sorted(np.flatnonzero(ida & grid), key=lambda g: (-absE[g], g))[:K]
+    kept = []
+    for g in ranked:
+        if absE[g] <= 1e-7:
+            continue
+        nb = np.flatnonzero(ida & (np.nansum((X - X[g]) ** 2, axis=1) <= r_nms * r_nms))
+        if absE[g] >= absE[nb].max():
+            kept.append(g)
+    kept = sorted(kept, key=lambda g: (-absE[g], g))[:30]
+    assert list(out.index) == kept and len(kept) >= 5
+    # the samples did suppress: without them more grid candidates survive
+    alone = O.seed([lv], [Eg], [ida_g], top_frac=0.05, k_new=30, r_nms=r_nms, eps=1e-7,
+                   n_idall=int(ida.sum()))
+    assert alone.n_extreme > out.n_extreme
+    # eq. 3-24: |E| exp(-d^2 dbar^2) = eps with dbar the nearest-sample distance
+    dist, _ = cKDTree(P.pts).query(out.c)
+    dbar = np.maximum(dist, 2.0 / lv.n)
+    d = np.exp(out.s[:, 0])
+    assert np.allclose(absE[out.index] * np.exp(-(d * dbar) ** 2), 1e-7, rtol=1e-10)
+    assert np.array_equal(out.w, -np.concatenate([Eg, Es])[out.index])
+
+
+def test_seed_samples_suppress_but_are_not_chosen():
+    lv, P = _sphere_level_and_samples(k=50, cap=50)
+    pts = O.level_points(lv)
+    Eg = np.zeros(lv.npts)
+    Es = np.zeros(P.cap)
+    # grid peak next to a sample with a larger |E| (suppressed), a second grid
+    # peak with no sample near it (kept), and the largest |E| of all on a
+    # sample (never a candidate)
+    s0 = P.pts[0]
+    g_near = int(np.argmin(np.sum((pts - s0) ** 2, axis=1)))
+    far = np.sum((P.pts[:, None, :] - pts[None, :, :]) ** 2, axis=2).min(axis=0)
+    g_far = int(np.argmax(np.where(np.abs(lv.S) < 0.2, far, -1.0)))
+    Eg[g_near], Eg[g_far] = 0.5, -0.4
+    Es[0], Es[1] = 0.7, 0.9
+    r = float(np.sqrt(np.sum((pts[g_near] - s0) ** 2))) * 1.01
+    assert r < np.sqrt(far[g_far])
+    ida_g, ida_s = Eg != 0, Es != 0
+    out = O.seed([lv, P], [Eg, Es], [ida_g, ida_s], top_frac=1.0, k_new=10, r_nms=r)
+    assert list(out.index) == [g_far]
+    assert out.n_candidates == 2 and out.n_extreme == 1
