@@ -35,55 +35,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, budget_s=15.0, seed=0):
-    """The FP64 oracle's culled forward + loss + backward on a sample of the
-    workload's kernels (all three levels, every point), timed on the host."""
-    import oracle as O
+def under_profiler() -> bool:
+    """True when a profiler's tool library is preloaded into this process: then
+    nothing here forks (children would inherit the profiler's session)."""
+    env = os.environ
+    return "rocprof" in env.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF") for k in env)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, n_proc):
+    """The FP64 oracle's culled forward + loss + backward + eq. 3-21 weights
+    over the whole workload (every kernel, every point of the three levels),
+    its kernels split over `n_proc` worker processes, timed on the host."""
+    from oracle import erbf as O
+    from oracle import pool
     S_all = [lv.S for lv in prob.levels]
     m = O.sdf_min(S_all)
     olv = [O.make_level(lv.n, lv.axis, active=(O.band_mask(lv.S, lv.band) if lv.band else None),
                         t=O.targets_from_sdf(lv.S, m).astype(np.float32), S=lv.S) for lv in prob.levels]
-    Kall = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
-    order = np.random.default_rng(seed).permutation(prob.m)
-
-    def sub(idx):
-        return O.make_kernels(Kall.w[idx], Kall.c[idx], Kall.s[idx], Kall.q[idx], prob.cull_k)
-
-    def run(idx):
-        K = sub(idx)
-        t0 = time.perf_counter()
-        f = O.forward(olv, K)
-        lo = O.loss(olv, f, K, tau1=float(np.float32(0.9)), tau2=float(np.float32(1.1)))
-        G = [2.0 * e for e in lo.E]
-        O.backward(olv, K, G)
-        dt = time.perf_counter() - t0
-        pf, pb = O.pair_counts(olv, K, G)
-        return dt, pf, pb
-
-    # calibrate a fixed + per-kernel cost model, then size the sample to the budget
-    d1, _, _ = run(order[:16])
-    d2, _, _ = run(order[:64])
-    per = max((d2 - d1) / 48.0, 1e-4)
-    fixed = max(d1 - 16 * per, 0.0)
-    n = int(min(prob.m, max(64, (budget_s - fixed) / per)))
-    dt, pf, pb = run(order[:n])
-    return {"value": (pf + pb) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} of {prob.m} kernels (seeded random), all 3 levels, one culled "
-                      f"fwd+loss+bwd in float64 numpy, {dt:.1f} s, {pf + pb} pairs"}
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
+    t0 = time.perf_counter()
+    ref = pool.step(olv, K, mode=O.MODE_DYNAMIC, l1_active=True, tau1=float(np.float32(0.9)),
+                    tau2=float(np.float32(1.1)), tau_m=float(np.float32(0.02)), n_proc=n_proc)
+    dt = time.perf_counter() - t0
+    pairs = ref.P_fwd + ref.P_bwd
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": n_proc, "kind": "oracle",
+            "sample": f"the whole first step of the workload ({prob.m} kernels, all 3 levels): culled fwd + loss + "
+                      f"bwd + eq. 3-21 in float64 numpy over {n_proc} worker processes, {dt:.1f} s, {pairs} pairs",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def batching_bench(steps, warmup):
+def batching_bench(probs, steps, warmup):
     """64 shapes (grids 32^3..128^3, 256..4096 kernels, per-shape lambda):
     one batched context with a HIP-graph step vs 64 plain contexts, each with
     its own graph, replayed one after another.  Aggregate pair throughput."""
     import torch
-    import synth
     from paper_2505_02350_amd import _lib as L
     from paper_2505_02350_amd.fit import Fitter, ShapeInput
 
-    t0 = time.perf_counter()
-    probs = synth.make_batching()
-    log(f"batching workload generated in {time.perf_counter() - t0:.1f} s")
     shapes = [ShapeInput.from_problem(p) for p in probs]
     lams = [p.lam for p in probs]
     kw = dict(mode=L.MODE_FIXED, lr=1e-3)
@@ -92,7 +91,7 @@ def batching_bench(steps, warmup):
     lam_dev = torch.tensor(lams, dtype=torch.float32, device=fb.dev)
     var_b, times_b = fb.ctx.erbf_autotune(fb.p, fb.m_dev, reps=1, lambda_dev=lam_dev)
     # equal accuracy: the first step's gradients are bitwise those of the plain fits
-    gb = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lambda_dev=lam_dev).clone()
+    gb = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lam_dev).clone()
     plains = []
     for b, s in enumerate(shapes):
         f = Fitter([s], cull_k=3.0)
@@ -206,7 +205,7 @@ def minibatch_bench(steps, warmup, batch=10000):
 
     def one(i):
         idx = order[(i % nb) * batch:(i % nb + 1) * batch]
-        fit.ctx.erbf_loss_grad_batch(fit.p, fit.m_dev, idx, mode=L.MODE_DYNAMIC, l1_active=True, grad_out=fit.grad)
+        fit.ctx.erbf_loss_grad_minibatch(fit.p, fit.m_dev, idx, mode=L.MODE_DYNAMIC, l1_active=True, grad_out=fit.grad)
         fit.ctx.erbf_adam_step(fit.p, fit.m_dev, fit.grad, fit.m1, fit.m2, fit.step_dev, lr=prob.lr)
 
     for i in range(warmup):
@@ -324,9 +323,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle worker processes of the CPU baseline (0: every host CPU, at most 16)")
     ap.add_argument("--graph", action="store_true", help="also time HIP-graph replays of the step")
-    ap.add_argument("--batching", action="store_true", help="add the 64-shape batched-vs-plain comparison")
+    ap.add_argument("--no-batching", action="store_true", help="leave out the 64-shape batched-vs-plain comparison")
+    ap.add_argument("--batching-steps", type=int, default=5)
+    ap.add_argument("--workload-cache", default="",
+                    help="npz file of the generated timing workload: read if present, else written")
+    ap.add_argument("--gen-only", action="store_true", help="generate (and cache) the workload, then exit")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
@@ -340,14 +344,43 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
-    import torch
     import synth
+    from synth import sdf as synth_sdf
+
+    # Everything that forks runs here, before anything touches the GPU, and
+    # not at all under a profiler: the SDF sampling pool, and the fork server
+    # of the oracle's workers (the CPU baseline).
+    profiled = under_profiler()
+    if profiled:
+        synth_sdf.DEFAULT_WORKERS = 1
+        if not args.no_cpu_baseline:
+            log("under a profiler: no CPU baseline (its workers would fork)")
+            args.no_cpu_baseline = True
+    t_setup = time.perf_counter()
+    if args.workload_cache and os.path.exists(args.workload_cache):
+        prob = synth.load_problem(args.workload_cache)
+        log(f"workload read from {args.workload_cache}")
+    else:
+        prob = synth.make_large_snapshot()
+        log(f"workload generated in {time.perf_counter() - t_setup:.1f} s")
+        if args.workload_cache:
+            synth.save_problem(prob, args.workload_cache)
+    if args.gen_only:
+        return
+    bprobs = None
+    if not args.no_batching:
+        t0 = time.perf_counter()
+        bprobs = synth.make_batching()
+        log(f"batching workload generated in {time.perf_counter() - t0:.1f} s")
+    n_cpu = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
+    if not args.no_cpu_baseline and n_cpu > 1:
+        from oracle import pool
+        pool.start_server()
+
+    import torch
     from paper_2505_02350_amd import _lib as L
     from paper_2505_02350_amd.fit import Fitter, ShapeInput
 
-    t_setup = time.perf_counter()
-    prob = synth.make_large_snapshot()
-    log(f"workload generated in {time.perf_counter() - t_setup:.1f} s")
     shape = ShapeInput.from_problem(prob)
     t0 = time.perf_counter()
     fit = Fitter([shape], cull_k=prob.cull_k, all_levels=False)
@@ -472,8 +505,8 @@ def main():
         "graph10_ms_per_step": graph10_ms,
         "per_level_refine_ms": refine_ms,
     }
-    if args.batching:
-        out["batching"] = batching_bench(max(2, min(args.steps, 10)), 2)
+    if bprobs is not None:
+        out["batching"] = batching_bench(bprobs, args.batching_steps, 2)
     if args.init:
         out["init"] = init_bench(with_cpu=not args.no_cpu_baseline)
     if args.minibatch:
@@ -486,7 +519,7 @@ def main():
         out["surface"] = surface_bench(with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(prob, n_cpu)
     print(json.dumps(out), flush=True)
 
 

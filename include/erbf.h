@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 3
+#define ERBF_ABI_VERSION 4
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -117,7 +117,7 @@ typedef struct {
   int32_t weight_map; /* ERBF_WEIGHT_SIGNED_SQUARE (eq. 3-26) or ERBF_WEIGHT_LINEAR */
   int32_t orientation; /* ERBF_ORIENT_QUATERNION or ERBF_ORIENT_EULER (eq. 3-6); also
                           decides the identity rotation that seeding writes */
-  int32_t batch_cap;   /* largest point count of an erbf_loss_grad_batch call, >= 0 */
+  int32_t batch_cap;   /* largest point count of an erbf_loss_grad_minibatch call, >= 0 */
 } erbf_config;
 
 /* A level (eq. 3-16: the training set is the union of the levels
@@ -256,6 +256,18 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
                    float* grad_out, erbf_stats* stats_dev, float* f_out, float* G_out,
                    hipStream_t stream);
 
+/* Batched fitting (many independent shapes in one context): the loss and
+ * gradient of every shape of the context, each stage one launch over all
+ * shapes' tiles and kernels, with per-shape statistics and loss weights
+ * (per-shape lambda through cfg->lambda_dev, per-shape L1 flags through
+ * cfg->l1_active_dev).  The same call as erbf_loss_grad, which treats a
+ * multi-shape context this way; results of each shape equal those of a
+ * one-shape context holding that shape alone.  stats_dev: device
+ * [n_shapes]. */
+int erbf_loss_grad_batched(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+                           float* grad_out, erbf_stats* stats_dev, float* f_out, float* G_out,
+                           hipStream_t stream);
+
 /* One mini-batch step's loss and gradient (Algorithm 3, the inner loop over
  * batches of B_s shuffled points): as erbf_loss_grad, but f, the id_all mask,
  * E, L2, max|E| (hence the gate of eq. 3-21), the pair counts and the
@@ -265,7 +277,7 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
  * levels' active points contribute nothing.  f_out: optional device
  * [n_pts], f at the batch points in batch order.  The bucket lists are
  * rebuilt from the current parameters as in erbf_loss_grad. */
-int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+int erbf_loss_grad_minibatch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
                          const int64_t* pts, int32_t n_pts, float* grad_out, erbf_stats* stats_dev,
                          float* f_out, hipStream_t stream);
 
@@ -283,11 +295,21 @@ int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, 
 
 /* Append new kernels at local maxima of the residual (Algorithm 2, eq. 3-22,
  * 3-24, 3-25) to `shape`.  resid: device [n_points] residual E (or G with
- * resid_scale = 0.5), 0 outside id_all; n_idall: its id_all count.  New
- * kernels get zero Adam moments in m1/m2 (either may be NULL).  Every
- * active level of the shape needs `sdf`.  Synchronous; *n_added receives
- * the number appended.  ERBF_ERR_CAPACITY (nothing appended) if the shape
- * cannot hold them. */
+ * resid_scale = 0.5), 0 outside id_all; n_idall: its id_all count.
+ * Candidates are the ceil(top_frac * n_idall) grid points of largest |E|
+ * (ties to the lower index) with |E| > max(min_abs_err, eps); surface
+ * samples are never candidates.  A candidate is kept when no point of the
+ * training set V within r_nms -- grid points of the shape's active levels
+ * and its registered surface samples -- has a larger |E|; the first k_new
+ * kept by the same order become kernels: centre at the point, weight
+ * -sign(E)|E| (w_rule 0) or -sign(E) sqrt|E| (w_rule 1), the three scales
+ * d = sqrt(ln(|E| / eps)) / dbar, identity rotation.  dbar is the distance
+ * to the nearest registered surface sample of the shape (eq. 3-24), or,
+ * when the shape has none, |S| at the point; in both cases at least the
+ * finest grid spacing.  New kernels get zero Adam moments in m1/m2 (either
+ * may be NULL).  Every active grid level of the shape needs `sdf`.
+ * Synchronous; *n_added receives the number appended.  ERBF_ERR_CAPACITY
+ * (nothing appended) if the shape cannot hold them. */
 int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape,
                          const float* resid, float resid_scale, int64_t n_idall,
                          const erbf_seed_cfg* cfg, float* m1, float* m2, int32_t* n_added,

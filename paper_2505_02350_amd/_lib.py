@@ -26,7 +26,7 @@ FLAG_BUCKET_OVERFLOW = 1
 MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
 ORIENT_QUATERNION, ORIENT_EULER = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class ErbfError(RuntimeError):
@@ -114,8 +114,10 @@ _SIGS = [
     ("erbf_refine_level", ctypes.c_int, [_V, ctypes.c_int32, ctypes.POINTER(Level), _V]),
     ("erbf_eval", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V]),
     ("erbf_loss_grad", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, _V, _V, _V, _V]),
-    ("erbf_loss_grad_batch", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, ctypes.c_int32,
-                                            _V, _V, _V, _V]),
+    ("erbf_loss_grad_batched", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, _V, _V, _V,
+                                              _V]),
+    ("erbf_loss_grad_minibatch", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V,
+                                                ctypes.c_int32, _V, _V, _V, _V]),
     ("erbf_vjp", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V]),
     ("erbf_adam_step", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V, ctypes.POINTER(AdamCfg), _V]),
     ("erbf_timing_enable", ctypes.c_int, [_V, ctypes.c_int32]),

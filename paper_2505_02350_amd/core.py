@@ -191,9 +191,22 @@ class Context:
                                         _ptr(self.stats_buf), _ptr(f_out), _ptr(G_out), _stream(stream)))
         return grad_out
 
-    def erbf_loss_grad_batch(self, p, m_dev, pts, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
-                             tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None, l1_active_dev=None,
-                             stream=None):
+    def erbf_loss_grad_batched(self, p, m_dev, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
+                               tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None, G_out=None,
+                               l1_active_dev=None, stream=None):
+        """Loss + gradient of every shape of the context (one launch per stage)."""
+        if grad_out is None:
+            grad_out = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
+        pr = self._params(p, m_dev)
+        cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
+                        float(tau2), float(tau_m), _ptr(l1_active_dev))
+        L.check(self.lib.erbf_loss_grad_batched(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(grad_out),
+                                                _ptr(self.stats_buf), _ptr(f_out), _ptr(G_out), _stream(stream)))
+        return grad_out
+
+    def erbf_loss_grad_minibatch(self, p, m_dev, pts, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None,
+                                 l1_active=False, tau1=0.9, tau2=1.1, tau_m=0.02, grad_out=None, f_out=None,
+                                 l1_active_dev=None, stream=None):
         """One mini-batch loss + gradient; pts: int64 device tensor of point indices."""
         if pts.dtype != torch.int64:
             raise ValueError("pts must be int64")
@@ -202,9 +215,9 @@ class Context:
         pr = self._params(p, m_dev)
         cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
                         float(tau2), float(tau_m), _ptr(l1_active_dev))
-        L.check(self.lib.erbf_loss_grad_batch(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(pts),
-                                              int(pts.numel()), _ptr(grad_out), _ptr(self.stats_buf), _ptr(f_out),
-                                              _stream(stream)))
+        L.check(self.lib.erbf_loss_grad_minibatch(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(pts),
+                                                  int(pts.numel()), _ptr(grad_out), _ptr(self.stats_buf),
+                                                  _ptr(f_out), _stream(stream)))
         return grad_out
 
     def erbf_vjp(self, p, m_dev, grad_f, grad_out=None, stats=False, stream=None):

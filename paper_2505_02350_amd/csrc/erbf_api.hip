@@ -137,11 +137,11 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 256));
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
-  L.off_kstart = take(sizeof(int32_t) * (L.cap_total + 1));
+  L.off_kstart = take(sizeof(int64_t) * (L.cap_total + 1));
   L.off_kblock = take(sizeof(int32_t) * (L.cap_total / 4 + 1));
-  L.off_kblock_ex = take(sizeof(int32_t) * (L.cap_total / 4 + 2));
+  L.off_kblock_ex = take(sizeof(int64_t) * (L.cap_total / 4 + 2));
   L.off_partials = take(sizeof(float2) * 5 * cfg->pair_cap);
-  L.off_scan = take(sizeof(int32_t) * L.scan_blocks);
+  L.off_scan = take(sizeof(int64_t) * L.scan_blocks);
   L.off_rflags = take(sizeof(int32_t) * (L.max_level_tiles + 1));
   L.off_rexcl = take(sizeof(int32_t) * (L.max_level_tiles + 1));
   L.off_rec = take(sizeof(float4) * 3 * L.cap_total);
@@ -294,9 +294,9 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.rhist_ex = reinterpret_cast<int32_t*>(w + lay.off_rhist_ex);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
-  D.kstart = reinterpret_cast<int32_t*>(w + lay.off_kstart);
+  D.kstart = reinterpret_cast<int64_t*>(w + lay.off_kstart);
   D.kblock = reinterpret_cast<int32_t*>(w + lay.off_kblock);
-  D.kblock_ex = reinterpret_cast<int32_t*>(w + lay.off_kblock_ex);
+  D.kblock_ex = reinterpret_cast<int64_t*>(w + lay.off_kblock_ex);
   D.partials = reinterpret_cast<float2*>(w + lay.off_partials);
   D.scan_blocks = reinterpret_cast<int32_t*>(w + lay.off_scan);
   c->rflags = reinterpret_cast<int32_t*>(w + lay.off_rflags);
@@ -643,7 +643,14 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   return ERBF_OK;
 }
 
-int erbf_loss_grad_batch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, const int64_t* pts,
+int erbf_loss_grad_batched(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
+                           erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
+  // a context's shapes share every launch of the step already; this entry
+  // point names that use
+  return erbf_loss_grad(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream);
+}
+
+int erbf_loss_grad_minibatch(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, const int64_t* pts,
                          int32_t n_pts, float* grad_out, erbf_stats* stats_dev, float* f_out, hipStream_t stream) {
   int rc = check_params(ctx, params);
   if (rc) return rc;
@@ -868,10 +875,17 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
   if (sd.n_active < 1) return fail(ERBF_ERR_STATE, "shape has no registered level");
   int64_t npts = 0;
   int finest = -1;
+  int samp_levels[ERBF_MAX_LEVELS];
+  int64_t samp_counts[ERBF_MAX_LEVELS];
+  int n_samp_levels = 0;
   for (int l = 0; l < sd.n_active; ++l) {
     const LevelDev& L = ctx->lv[sd.lvl0 + l];
     npts += L.npts;
-    if (L.kind != kLevelGrid) continue;   // surface samples are not seeded
+    if (L.kind != kLevelGrid) {   // surface samples: neighbours and dbar, never candidates
+      samp_levels[n_samp_levels] = sd.lvl0 + l;
+      samp_counts[n_samp_levels++] = L.n_samples;
+      continue;
+    }
     if (!L.sdf) return fail(ERBF_ERR_INVALID_ARG, "seeding needs the raw SDF of every registered grid level");
     if (finest < 0 || L.n > ctx->lv[finest].n) finest = sd.lvl0 + l;
   }
@@ -903,7 +917,7 @@ int erbf_seed_from_error(erbf_ctx* ctx, const erbf_params* params, int32_t shape
   if (m_now < 0 || m_now + n_add > sd.cap)
     return fail(ERBF_ERR_CAPACITY, "seeding " + std::to_string(n_add) + " kernels exceeds the shape capacity");
   HIP_TRY(launch_seed_write(D, shape, n_add, params->p, params->m_dev, resid, resid_scale, m1, m2, cfg->eps,
-                            cfg->w_rule, h_fine, stream),
+                            cfg->w_rule, h_fine, samp_levels, samp_counts, n_samp_levels, stream),
           "seed: write");
   HIP_TRY(hipStreamSynchronize(stream), "seed: sync");
   *n_added = n_add;

@@ -25,30 +25,32 @@ __device__ __forceinline__ float wave_max_f(float v) {
 }
 
 // exclusive scan over a 1024-thread block (16 waves); also returns the total
-__device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int& total) {
+// (T = int or int64_t; sh holds 32 values of T)
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_1024(T v, T* sh, T& total) {
   // 1024 threads, 16 waves
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int x = v;
+  T x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
+    const T y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   if (lane == 63) sh[wv] = x;
   __syncthreads();
   if (wv == 0) {
-    int s = lane < 16 ? sh[lane] : 0;
+    T s = lane < 16 ? sh[lane] : (T)0;
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) {
-      const int y = __shfl_up(s, o, 64);
+      const T y = __shfl_up(s, o, 64);
       if (lane >= o) s += y;
     }
     if (lane < 16) sh[16 + lane] = s;
   }
   __syncthreads();
   total = sh[31];
-  const int wbase = wv > 0 ? sh[16 + wv - 1] : 0;
-  const int r = wbase + x - v;
+  const T wbase = wv > 0 ? sh[16 + wv - 1] : (T)0;
+  const T r = wbase + x - v;
   __syncthreads();
   return r;
 }

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_init_greedy(Dev D, int shape, uint32_t
     const uint32_t w = w0 + (uint32_t)tid;
     const uint32_t bits = w < nw ? mask[w] : 0u;
     int total;
-    const int ex = block_excl_scan_1024(__popc(bits), scan_sh, total);
+    const int ex = block_excl_scan_1024<int>(__popc(bits), scan_sh, total);
     uint32_t at = n_in + (uint32_t)ex, rest = bits;
     while (rest) {
       const int b = __builtin_ctz(rest);

@@ -91,13 +91,13 @@ struct Dev {
   int32_t* tile_e;          // [pair_cap] kernel-major index of each tile-major entry
   int32_t* items;           // [pair_cap] kernel of each tile-major entry: ascending within a tile
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
-  int32_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
+  int64_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
   int32_t* kblock;          // [cap_total / 4 + 1] kcnt summed over each count block (four kernels)
-  int32_t* kblock_ex;       // [cap_total / 4 + 2] exclusive scan of kblock
+  int64_t* kblock_ex;       // [cap_total / 4 + 2] exclusive scan of kblock
   float2* partials;         // [5 * pair_cap] the 10 backward moments of each entry, kernel-major
   int32_t* sel_buf;         // [tiles_total] scratch of the tile selection below
   const int32_t* tile_sel;  // null, or [tiles_total]: bucket lists only for slots with a non-zero entry
-  int32_t* scan_blocks;     // [scan block sums]
+  int32_t* scan_blocks;     // [scan block sums] (int64 when a 64-bit scan uses it)
   // per step
   float4* rec;              // [3 * cap_total]
   float* G;                 // [pts_total]

@@ -145,57 +145,60 @@ __device__ __forceinline__ void kernel_record(const float* __restrict__ p, const
 // ---------------------------------------------------------------------------
 
 
-__global__ __launch_bounds__(1024) void k_scan_reduce(const int32_t* __restrict__ in, int n,
-                                                      int32_t* __restrict__ blocks) {
-  __shared__ int sh[32];
+// T: the type of the block sums and of the output (int32 when every prefix
+// fits, int64 for the bucket-entry offsets, whose total may pass 2^31 before
+// it is compared with the list capacity)
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_reduce(const int32_t* __restrict__ in, int n, T* __restrict__ blocks) {
+  __shared__ T sh[32];
   const int i = blockIdx.x * 1024 + threadIdx.x;
-  int total;
-  block_excl_scan_1024(i < n ? in[i] : 0, sh, total);
+  T total;
+  block_excl_scan_1024<T>(i < n ? (T)in[i] : (T)0, sh, total);
   if (threadIdx.x == 0) blocks[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ blocks, int nb,
-                                                      int64_t* __restrict__ total_out) {
-  __shared__ int sh[32];
-  int carry = 0;
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_blocks(T* __restrict__ blocks, int nb, int64_t* __restrict__ total_out) {
+  __shared__ T sh[32];
+  T carry = 0;
   for (int base = 0; base < nb; base += 1024) {
     const int i = base + threadIdx.x;
-    const int v = i < nb ? blocks[i] : 0;
-    int total;
-    const int e = block_excl_scan_1024(v, sh, total);
+    const T v = i < nb ? blocks[i] : (T)0;
+    T total;
+    const T e = block_excl_scan_1024<T>(v, sh, total);
     if (i < nb) blocks[i] = carry + e;
     carry += total;
   }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
+  if (threadIdx.x == 0 && total_out) *total_out = (int64_t)carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ in, int n,
-                                                    const int32_t* __restrict__ blocks,
-                                                    int32_t* __restrict__ out) {
-  __shared__ int sh[32];
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_down(const int32_t* __restrict__ in, int n, const T* __restrict__ blocks,
+                                                    T* __restrict__ out) {
+  __shared__ T sh[32];
   const int i = blockIdx.x * 1024 + threadIdx.x;
-  int total;
-  const int e = block_excl_scan_1024(i < n ? in[i] : 0, sh, total);
+  T total;
+  const T e = block_excl_scan_1024<T>(i < n ? (T)in[i] : (T)0, sh, total);
   if (i <= n) out[i] = blocks[blockIdx.x] + e;  // out has n + 1 entries
 }
 
 // Single-block exclusive scan of n <= 1024 * PER values; out[n] = total.
 // Each thread owns PER consecutive values, read with independent loads.
-template <int PER>
-__global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict__ in, int n,
-                                                      int32_t* __restrict__ out, int64_t* __restrict__ total_out) {
-  __shared__ int sh[32];
+template <int PER, typename T>
+__global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict__ in, int n, T* __restrict__ out,
+                                                      int64_t* __restrict__ total_out) {
+  __shared__ T sh[32];
   const int t = threadIdx.x;
   const int lo = t * PER;
-  int v[PER];
-  int sum = 0;
+  T v[PER];
+  T sum = 0;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    v[u] = lo + u < n ? in[lo + u] : 0;
+    v[u] = lo + u < n ? (T)in[lo + u] : (T)0;
     sum += v[u];
   }
-  int total;
-  int run = block_excl_scan_1024(sum, sh, total);
+  T total;
+  T run = block_excl_scan_1024<T>(sum, sh, total);
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     if (lo + u < n) out[lo + u] = run;
@@ -203,13 +206,13 @@ __global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict_
   }
   if (t == 0) {
     out[n] = total;
-    if (total_out) *total_out = total;
+    if (total_out) *total_out = (int64_t)total;
   }
 }
 
 // exclusive scan of n values into out[0..n], the total also to *total_out
-hipError_t launch_scan_any(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
-                           hipStream_t s);
+template <typename T>
+hipError_t launch_scan_any(const int32_t* in, int n, T* blocks, T* out, int64_t* total, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Tile buckets.  One wave per kernel slot; lanes test the tiles of the
@@ -340,7 +343,7 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
         if (hit) {
           const int v = vbase + __popcll(bal & lt_mask);
           const int64_t at = e0 + v;
-          if (v < cnt_j && at < D.pair_cap) {
+          if (v < cnt_j && at >= 0 && at < D.pair_cap) {
             D.kslot[at] = slot;
             D.kj[at] = j;
           }
@@ -353,7 +356,7 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
   // counted range is still filled, with a slot past every real tile
   for (int v = vbase + lane; v < cnt_j; v += 64) {
     const int64_t at = e0 + v;
-    if (at < D.pair_cap) {
+    if (at >= 0 && at < D.pair_cap) {
       D.kslot[at] = D.tiles_total;
       D.kj[at] = j;
       float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void k_bucket_emit(Dev D) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (j >= D.cap_total) return;
-  int e0 = D.kblock_ex[blockIdx.x];
+  int64_t e0 = D.kblock_ex[blockIdx.x];
   for (int k = 0; k < w; ++k) e0 += D.kcnt[4 * blockIdx.x + k];
   if (lane == 0) D.kstart[j] = e0;
   bucket_emit_walk(D, j, lane, e0, D.kcnt[j]);
@@ -1833,23 +1836,28 @@ __global__ __launch_bounds__(256) void k_tile_assign(Dev D, int li, const int32_
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 static inline unsigned gridstride(int64_t n) { return (unsigned)std::min<int64_t>(nblk(n, 256), 4096); }
 
-hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
-                       hipStream_t s) {
+template <typename T>
+hipError_t launch_scan_t(const int32_t* in, int n, T* blocks, T* out, int64_t* total, hipStream_t s) {
   const int nb = (int)nblk(n + 1, 1024);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, s, in, n, blocks);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blocks, nb, total);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(1024), 0, s, in, n, blocks, out);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(1024), 0, s, in, n, blocks);
+  hipLaunchKernelGGL(k_scan_blocks<T>, dim3(1), dim3(1024), 0, s, blocks, nb, total);
+  hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(1024), 0, s, in, n, blocks, out);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_any(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
-                           hipStream_t s) {
+hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, int64_t* total,
+                       hipStream_t s) {
+  return launch_scan_t<int32_t>(in, n, blocks, out, total, s);
+}
+
+template <typename T>
+hipError_t launch_scan_any(const int32_t* in, int n, T* blocks, T* out, int64_t* total, hipStream_t s) {
   if (n <= 1024 * 4)
-    hipLaunchKernelGGL(k_scan_single<4>, dim3(1), dim3(1024), 0, s, in, n, out, total);
+    hipLaunchKernelGGL((k_scan_single<4, T>), dim3(1), dim3(1024), 0, s, in, n, out, total);
   else if (n <= 1024 * 16)
-    hipLaunchKernelGGL(k_scan_single<16>, dim3(1), dim3(1024), 0, s, in, n, out, total);
+    hipLaunchKernelGGL((k_scan_single<16, T>), dim3(1), dim3(1024), 0, s, in, n, out, total);
   else
-    return launch_scan(in, n, blocks, out, total, s);
+    return launch_scan_t<T>(in, n, blocks, out, total, s);
   return hipGetLastError();
 }
 
@@ -1860,7 +1868,11 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
   hipLaunchKernelGGL(k_bucket_count, dim3(nkb), dim3(256), 0, s, D, p, m_dev);
   if (n_slots <= 0) return hipGetLastError();
   {
-    const hipError_t e = launch_scan_any(D.kblock, nkb, D.scan_blocks, D.kblock_ex, D.counters, s);
+    // 64-bit offsets: the entry total may pass 2^31 (then it exceeds the
+    // list capacity, no entry past it is written, and the overflow flag is
+    // raised from counters[0])
+    const hipError_t e = launch_scan_any<int64_t>(D.kblock, nkb, reinterpret_cast<int64_t*>(D.scan_blocks),
+                                                  D.kblock_ex, D.counters, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);

@@ -52,8 +52,11 @@ hipError_t launch_seed_select(const Dev& D, int shape, int64_t npts, const float
                               float floor_abs, float r_nms, int64_t k_cand, hipStream_t s);
 // counts left by launch_seed_select (synchronises the stream); 0 on success
 int seed_misc_counts(const Dev& D, int32_t* n_cand, int32_t* n_kept, hipStream_t s);
+// dbar (eq. 3-24) from the nearest sample of the listed sample levels (level
+// table index and registered count each) when any holds a sample, else |S|
 hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32_t* m_dev, const float* resid,
-                             float scale, float* m1, float* m2, float eps, int w_rule, float h_fine, hipStream_t s);
+                             float scale, float* m1, float* m2, float eps, int w_rule, float h_fine,
+                             const int* samp_levels, const int64_t* samp_counts, int n_samp_levels, hipStream_t s);
 // marks (1) the slots holding the batch's points in sel, after clearing it
 hipError_t launch_batch_tiles(const Dev& D, int n_slots, const int64_t* pts, int n_pts, int32_t* sel, hipStream_t s);
 hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int n_pts, const float* p,

@@ -6,18 +6,27 @@
 //      ((~bits|E|) << 32 | index), so "largest |E|, then lowest index" is
 //      "smallest key"; a four-digit radix select finds the K-th smallest key
 //      without sorting.  Candidates also need |E| > max(min_abs_err, eps).
-//   2. extreme points: a candidate survives if no point within r_nms (any
-//      active level of the shape) has a larger |E|.  Points outside id_all
-//      have E = 0 and cannot suppress anything.
+//      Surface samples are not candidates (a centre on a sample has
+//      distance 0 to P, where eq. 3-24 gives no scale).
+//   2. extreme points: a candidate survives if no point of V within r_nms
+//      (grid points of any active level of the shape, and its registered
+//      surface samples) has a larger |E|.  Points outside id_all have E = 0
+//      and cannot suppress anything.
 //   3. the first k_new survivors by key (a second radix select, then one
 //      sorted block).
 //   4. eq. 3-24 parameters, appended after the shape's live kernels; their
-//      Adam moments are cleared.
+//      Adam moments are cleared.  dbar is the distance from the centre to
+//      the nearest registered sample (the minimum of the squared distances
+//      is exact whatever the order, so atomics give the same result), or
+//      |S| at the centre when the shape has no sample registered; in both
+//      cases at least the finest grid spacing.
 // Lists are built with atomics but every result is defined by the keys, so
 // the outcome does not depend on the order of the atomics.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "erbf_internal.h"
@@ -191,6 +200,34 @@ __device__ __forceinline__ int locate(const Dev& D, const ShapeDev& S, int64_t g
   return 0;
 }
 
+// Does a registered sample of sample level L within r_nms of (xi, yi, zi)
+// have a larger |E| than ei?  The samples are binned into the 8^3-cell tiles
+// of the level's n^3-cell grid; the tiles meeting the neighbourhood's box
+// (widened by a cell) are searched.
+__device__ bool sample_suppresses(const Dev& D, const LevelDev& L, const float* __restrict__ resid, float xi,
+                                  float yi, float zi, float r_nms, float r2, float ei) {
+  if (L.n_samples <= 0) return false;
+  const int n = L.n, nt = L.nt;
+  const float inv = 1.0f / L.h;
+  const int cx0 = max(0, (int)floorf((xi - r_nms + 1.f) * inv) - 1), cx1 = min(n - 1, (int)floorf((xi + r_nms + 1.f) * inv) + 1);
+  const int cy0 = max(0, (int)floorf((yi - r_nms + 1.f) * inv) - 1), cy1 = min(n - 1, (int)floorf((yi + r_nms + 1.f) * inv) + 1);
+  const int cz0 = max(0, (int)floorf((zi - r_nms + 1.f) * inv) - 1), cz1 = min(n - 1, (int)floorf((zi + r_nms + 1.f) * inv) + 1);
+  for (int tz = cz0 / kTile; tz <= cz1 / kTile; ++tz)
+    for (int ty = cy0 / kTile; ty <= cy1 / kTile; ++ty)
+      for (int tx = cx0 / kTile; tx <= cx1 / kTile; ++tx) {
+        const int slot = D.tile_map[L.tmap0 + (tz * nt + ty) * nt + tx];
+        if (slot < 0) continue;
+        const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
+        for (int q = s0; q < s1; ++q) {
+          const float4 P = L.spos[q];
+          const float dx = P.x - xi, dy = P.y - yi, dz = P.z - zi;
+          if (dx * dx + dy * dy + dz * dz > r2) continue;
+          if (fabsf(resid[L.pt_base + __float_as_int(P.w)]) > ei) return true;
+        }
+      }
+  return false;
+}
+
 // extreme-point test of each candidate; survivors' keys go to the keep list
 __global__ __launch_bounds__(256) void k_nms(Dev D, int shape, const float* __restrict__ resid, float r_nms) {
   const ShapeDev S = D.shapes[shape];
@@ -209,9 +246,13 @@ __global__ __launch_bounds__(256) void k_nms(Dev D, int shape, const float* __re
     for (int l = 0; l < S.n_active && ok; ++l) {
       const LevelDev L = D.levels[S.lvl0 + l];
       const int n = L.n;
-      if (L.kind != kLevelGrid) {   // samples do not suppress
-        off += L.npts;
-        continue;
+      if (L.kind != kLevelGrid) {
+        if (!sample_suppresses(D, L, resid, xi, yi, zi, r_nms, r2, ei)) {
+          off += L.npts;
+          continue;
+        }
+        ok = false;
+        break;
       }
       // conservative index ranges, then the exact distance test
       int x0 = max(0, (int)floorf((xi - r_nms - L.lo) / L.h) - 1), x1 = min(n - 1, (int)ceilf((xi + r_nms - L.lo) / L.h) + 1);
@@ -255,14 +296,13 @@ __global__ __launch_bounds__(256) void k_collect_sel(Dev D) {
   }
 }
 
-// one workgroup: sort the selection by key and write eq. 3-24 parameters
-__global__ __launch_bounds__(1024) void k_seed_write(Dev D, int shape, float* __restrict__ p,
-                                                     int32_t* __restrict__ m_dev, const float* __restrict__ resid,
-                                                     float scale, float* __restrict__ m1, float* __restrict__ m2,
-                                                     float eps, int w_rule, float h_fine, int n_add) {
+// one workgroup: sort the selection by key (ascending: largest |E| first,
+// ties to the lower index) in place, and clear the squared nearest-sample
+// distances
+__global__ __launch_bounds__(1024) void k_seed_sort(Dev D, int n_add) {
   __shared__ uint64_t buf[4096];
-  const ShapeDev S = D.shapes[shape];
-  const uint64_t* sel = reinterpret_cast<const uint64_t*>(D.seed_cand);
+  uint64_t* sel = reinterpret_cast<uint64_t*>(D.seed_cand);
+  uint32_t* dmin2 = reinterpret_cast<uint32_t*>(D.seed_keep);
   const int tid = threadIdx.x;
   int pw = 1;
   while (pw < n_add) pw <<= 1;
@@ -281,41 +321,89 @@ __global__ __launch_bounds__(1024) void k_seed_write(Dev D, int shape, float* __
       __syncthreads();
     }
   }
-  const int m = m_dev[shape];
-  const int C = D.cap_total;
-  for (int r = tid; r < n_add; r += 1024) {
-    const int64_t g = (int64_t)(uint32_t)(buf[r] & 0xffffffffull);
-    int li, i, j, k;
-    locate(D, S, g, li, i, j, k);
-    const LevelDev L = D.levels[li];
-    const float E = resid[S.pt_base + g] * scale;
-    const float aE = fabsf(E);
-    const float sg = E > 0.f ? 1.f : (E < 0.f ? -1.f : 0.f);
-    const float w = w_rule == 0 ? -sg * aE : -sg * sqrtf(aE);
-    const float Sv = L.sdf[((int64_t)k * L.n + j) * L.n + i];
-    const float dbar = fmaxf(fabsf(Sv), h_fine);
-    const float dd = sqrtf(logf(aE / eps)) / dbar;
-    const float s = logf(dd);
-    const int slot = S.kbase + m + r;
-    p[slot] = w;
-    p[C + slot] = L.axis[i];
-    p[2 * C + slot] = L.axis[j];
-    p[3 * C + slot] = L.axis[k];
-    p[4 * C + slot] = s;
-    p[5 * C + slot] = s;
-    p[6 * C + slot] = s;
-    p[7 * C + slot] = D.orientation == ERBF_ORIENT_EULER ? 0.f : 1.f;   // identity rotation
-    p[8 * C + slot] = 0.f;
-    p[9 * C + slot] = 0.f;
-    p[10 * C + slot] = 0.f;
-    for (int seg = 0; seg < 11; ++seg) {
-      if (m1) m1[seg * C + slot] = 0.f;
-      if (m2) m2[seg * C + slot] = 0.f;
+  for (int i = tid; i < n_add; i += 1024) {
+    sel[i] = buf[i];
+    dmin2[i] = __float_as_uint(INFINITY);
+  }
+}
+
+// squared distance from each new centre to its nearest registered sample of
+// the shape: blocks take slices of a sample level's samples (staged in LDS)
+// and the centres; the minimum goes through an unsigned atomic min on the
+// float bits (non-negative floats order as their bits), exact in any order
+__global__ __launch_bounds__(256) void k_seed_dbar(Dev D, int shape, int li, int n_add) {
+  __shared__ float4 sp[256];
+  const ShapeDev S = D.shapes[shape];
+  const LevelDev L = D.levels[li];
+  const uint64_t* sel = reinterpret_cast<const uint64_t*>(D.seed_cand);
+  uint32_t* dmin2 = reinterpret_cast<uint32_t*>(D.seed_keep);
+  const int tid = threadIdx.x;
+  const int64_t ns = L.n_samples;
+  for (int64_t q0 = (int64_t)blockIdx.x * 256; q0 < ns; q0 += (int64_t)gridDim.x * 256) {
+    const int nq = (int)min((int64_t)256, ns - q0);
+    __syncthreads();   // the previous slice is no longer read
+    if (tid < nq) sp[tid] = L.spos[q0 + tid];
+    __syncthreads();
+    for (int r = blockIdx.y * 256 + tid; r < n_add; r += gridDim.y * 256) {
+      const int64_t g = (int64_t)(uint32_t)(sel[r] & 0xffffffffull);
+      int lc, i, j, k;
+      if (!locate(D, S, g, lc, i, j, k)) continue;
+      const LevelDev Lc = D.levels[lc];
+      const float cx = Lc.axis[i], cy = Lc.axis[j], cz = Lc.axis[k];
+      float best = INFINITY;
+      for (int q = 0; q < nq; ++q) {
+        const float dx = sp[q].x - cx, dy = sp[q].y - cy, dz = sp[q].z - cz;
+        best = fminf(best, dx * dx + dy * dy + dz * dz);
+      }
+      atomicMin(&dmin2[r], __float_as_uint(best));
     }
   }
-  __syncthreads();
-  if (tid == 0) m_dev[shape] = m + n_add;
 }
+
+// eq. 3-24 parameters of the sorted selection, appended after the live kernels
+__global__ __launch_bounds__(256) void k_seed_write(Dev D, int shape, float* __restrict__ p,
+                                                    const int32_t* __restrict__ m_dev, const float* __restrict__ resid,
+                                                    float scale, float* __restrict__ m1, float* __restrict__ m2,
+                                                    float eps, int w_rule, float h_fine, int n_add, int use_samples) {
+  const ShapeDev S = D.shapes[shape];
+  const uint64_t* sel = reinterpret_cast<const uint64_t*>(D.seed_cand);
+  const uint32_t* dmin2 = reinterpret_cast<const uint32_t*>(D.seed_keep);
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n_add) return;
+  const int m = m_dev[shape];
+  const int C = D.cap_total;
+  const int64_t g = (int64_t)(uint32_t)(sel[r] & 0xffffffffull);
+  int li, i, j, k;
+  locate(D, S, g, li, i, j, k);
+  const LevelDev L = D.levels[li];
+  const float E = resid[S.pt_base + g] * scale;
+  const float aE = fabsf(E);
+  const float sg = E > 0.f ? 1.f : (E < 0.f ? -1.f : 0.f);
+  const float w = w_rule == 0 ? -sg * aE : -sg * sqrtf(aE);
+  const float dist = use_samples ? sqrtf(__uint_as_float(dmin2[r])) : fabsf(L.sdf[((int64_t)k * L.n + j) * L.n + i]);
+  const float dbar = fmaxf(dist, h_fine);
+  const float dd = sqrtf(logf(aE / eps)) / dbar;
+  const float s = logf(dd);
+  const int slot = S.kbase + m + r;
+  p[slot] = w;
+  p[C + slot] = L.axis[i];
+  p[2 * C + slot] = L.axis[j];
+  p[3 * C + slot] = L.axis[k];
+  p[4 * C + slot] = s;
+  p[5 * C + slot] = s;
+  p[6 * C + slot] = s;
+  p[7 * C + slot] = D.orientation == ERBF_ORIENT_EULER ? 0.f : 1.f;   // identity rotation
+  p[8 * C + slot] = 0.f;
+  p[9 * C + slot] = 0.f;
+  p[10 * C + slot] = 0.f;
+  for (int seg = 0; seg < 11; ++seg) {
+    if (m1) m1[seg * C + slot] = 0.f;
+    if (m2) m2[seg * C + slot] = 0.f;
+  }
+}
+
+// the shape's live count grows by the appended kernels
+__global__ void k_seed_count(int32_t* m_dev, int shape, int n_add) { m_dev[shape] += n_add; }
 
 __global__ __launch_bounds__(1024) void k_fill_u32_hist(Dev D) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kHist; i += gridDim.x * blockDim.x) D.seed_hist[i] = 0u;
@@ -366,7 +454,8 @@ hipError_t launch_seed_select(const Dev& D, int shape, int64_t npts, const float
 
 // Stage 3-4: the first n_add survivors by key, written as new kernels.
 hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32_t* m_dev, const float* resid,
-                             float scale, float* m1, float* m2, float eps, int w_rule, float h_fine, hipStream_t s) {
+                             float scale, float* m1, float* m2, float eps, int w_rule, float h_fine,
+                             const int* samp_levels, const int64_t* samp_counts, int n_samp_levels, hipStream_t s) {
   hipLaunchKernelGGL(k_seed_reset_select, dim3(1), dim3(1), 0, s, D, (int64_t)n_add);
   const uint64_t* keys = reinterpret_cast<const uint64_t*>(D.seed_keep);
   for (int d = 0; d < 4; ++d) {
@@ -374,8 +463,18 @@ hipError_t launch_seed_write(const Dev& D, int shape, int n_add, float* p, int32
     hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, s, D, d);
   }
   hipLaunchKernelGGL(k_collect_sel, dim3(gs(D.cand_cap)), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_seed_write, dim3(1), dim3(1024), 0, s, D, shape, p, m_dev, resid, scale, m1, m2, eps, w_rule,
-                     h_fine, n_add);
+  hipLaunchKernelGGL(k_seed_sort, dim3(1), dim3(1024), 0, s, D, n_add);
+  int use_samples = 0;
+  for (int a = 0; a < n_samp_levels; ++a) {
+    if (samp_counts[a] <= 0) continue;
+    use_samples = 1;
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((samp_counts[a] + 255) / 256, 2048));
+    const unsigned gy = (unsigned)((n_add + 255) / 256);
+    hipLaunchKernelGGL(k_seed_dbar, dim3(gx, gy), dim3(256), 0, s, D, shape, samp_levels[a], n_add);
+  }
+  hipLaunchKernelGGL(k_seed_write, dim3((n_add + 255) / 256), dim3(256), 0, s, D, shape, p, m_dev, resid, scale, m1,
+                     m2, eps, w_rule, h_fine, n_add, use_samples);
+  hipLaunchKernelGGL(k_seed_count, dim3(1), dim3(1), 0, s, m_dev, shape, n_add);
   return hipGetLastError();
 }
 

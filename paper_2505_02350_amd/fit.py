@@ -275,7 +275,7 @@ class Fitter:
             order = torch.from_numpy(pts[perm]).to(self.dev)
             for i in range(0, pts.size, batch_size):
                 idx = order[i:i + batch_size]
-                self.ctx.erbf_loss_grad_batch(self.p, self.m_dev, idx, mode=mode, lam=lam, l1_active=l1_active,
+                self.ctx.erbf_loss_grad_minibatch(self.p, self.m_dev, idx, mode=mode, lam=lam, l1_active=l1_active,
                                               tau1=tau1, tau2=tau2, tau_m=tau_m, grad_out=self.grad, stream=stream)
                 self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr=lr,
                                         stream=stream)

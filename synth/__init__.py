@@ -38,4 +38,6 @@ from .configs import (  # noqa: F401
     make_batching,
     make_diff,
     make_custom,
+    save_problem,
+    load_problem,
 )

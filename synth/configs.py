@@ -24,6 +24,8 @@ Workloads (seed in brackets):
 from dataclasses import dataclass, field
 from typing import List, Optional
 
+import os
+
 import numpy as np
 
 from .grid import axis_coords, grid_points
@@ -218,3 +220,38 @@ def make_custom(seed: int, ns, m: int, log_scale_range, kinds=("ellipsoid",) * 4
     cap = m if cap is None else cap
     return Problem(f"custom{seed}", levels, pack_params(w, c, s, q, cap), m, cap,
                    cull_k=cull_k, weight_map=weight_map, orientation=orientation, extra={"prims": prims})
+
+
+def save_problem(prob: Problem, path: str) -> None:
+    """Write a problem's arrays and settings to an npz file (no pickles; the
+    primitives in `extra` are not kept)."""
+    arrs = {"params": prob.params,
+            "meta": np.array([prob.m, prob.cap, prob.weight_map, prob.orientation, prob.steps, len(prob.levels)],
+                             np.int64),
+            "fmeta": np.array([prob.cull_k, prob.lr, prob.lam], np.float64),
+            "name": np.array(prob.name)}
+    for i, lv in enumerate(prob.levels):
+        if lv.axis is not None:
+            arrs[f"l{i}_axis"] = lv.axis
+            arrs[f"l{i}_S"] = lv.S
+        arrs[f"l{i}_meta"] = np.array([lv.n, lv.band is not None, lv.band or 0.0, lv.octree,
+                                       lv.samples is not None, lv.sample_cap], np.float64)
+        if lv.samples is not None:
+            arrs[f"l{i}_samples"] = lv.samples
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arrs)
+    os.replace(tmp, path)
+
+
+def load_problem(path: str) -> Problem:
+    with np.load(path, allow_pickle=False) as z:
+        m, cap, wm, orient, steps, nl = (int(v) for v in z["meta"])
+        cull_k, lr, lam = (float(v) for v in z["fmeta"])
+        levels = []
+        for i in range(nl):
+            n, has_band, band, octree, has_samples, scap = z[f"l{i}_meta"]
+            grid = f"l{i}_axis" in z.files
+            levels.append(LevelData(int(n), z[f"l{i}_axis"] if grid else None, z[f"l{i}_S"] if grid else None,
+                                    float(band) if has_band else None,
+                                    bool(octree), z[f"l{i}_samples"] if has_samples else None, int(scap)))
+        return Problem(str(z["name"]), levels, z["params"], m, cap, cull_k, wm, orient, lr, lam, steps)

@@ -171,6 +171,10 @@ def _eval_slabs(prims, a, k, z0, z1):
 
 _POOL_ARGS = None
 
+# worker processes of sample_sdf on large grids when the caller names none
+# (None: up to 16, one per host CPU); 1 keeps the sampling in this process
+DEFAULT_WORKERS = None
+
 
 def _pool_job(span):
     prims, a, k = _POOL_ARGS
@@ -188,6 +192,8 @@ def sample_sdf(prims: Sequence[Primitive], axis: np.ndarray, k: float = 0.05,
     global _POOL_ARGS
     a = np.asarray(axis, dtype=np.float64)
     n = a.size
+    if workers is None:
+        workers = DEFAULT_WORKERS
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if n ** 3 >= (1 << 21) else 1
     if workers <= 1:

@@ -11,6 +11,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    # the oracle's worker pool forks from a server started here, before any
+    # test touches the GPU
+    from oracle import pool
+    pool.start_server()
 
 
 def _gpu_available():

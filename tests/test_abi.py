@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 def test_abi_version(lib):
     from paper_2505_02350_amd import _lib as L
-    assert lib.erbf_abi_version() == L.ABI_VERSION == 3
+    assert lib.erbf_abi_version() == L.ABI_VERSION == 4
 
 
 def _struct_sizes_from_c():

@@ -47,7 +47,7 @@ def test_batched_equals_plain_bitwise_and_variants():
     for v in (0, 1, 2, 3):
         print(f"batched loss_grad, 4 shapes, launch variant {v}", flush=True)
         fb.ctx.erbf_set_variant(v)
-        g = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lambda_dev=lams, tau1=TAU1, tau2=TAU2)
+        g = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lams, tau1=TAU1, tau2=TAU2)
         torch.cuda.synchronize()
         outs[v] = (g.clone(), fb.ctx.stats())
     for v in (1, 2, 3):

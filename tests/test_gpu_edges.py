@@ -154,3 +154,35 @@ def test_unnormalised_quaternions():
     K3 = O.kernels_from_packed(prob3.params, prob3.m, prob3.cap, prob3.cull_k)
     ref = O.step(olv, K3, mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2)
     assert rel_inf(g3["q"], ref.grads.q) <= 1e-4
+
+
+def test_bucket_total_past_2_31_is_flagged_and_counted():
+    """The bucket-entry offsets are 64-bit: 70 000 kernels whose balls
+    (radius 6) reach all 32^3 tiles of a 256^3 grid need 70 000 * 32 768 =
+    2 293 760 000 entries, more than 2^31.  The count comes back exactly,
+    the overflow flag is raised, and nothing past the small list capacity is
+    written."""
+    torch = _torch()
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd import core
+    n, m = 256, 70000
+    ctx = core.Context([([n], m)], pair_cap=1 << 20, cull_k=3.0)
+    dev = ctx.device
+    ax = torch.from_numpy(synth.axis_coords(n)).to(dev)
+    ctx.erbf_refine_level(0, ax)
+    rng = np.random.default_rng(56)
+    p = np.zeros((11, m), np.float32)
+    p[0] = rng.uniform(0.1, 0.2, m)
+    p[1:4] = rng.uniform(-1.0, 1.0, (3, m))
+    p[4:7] = np.float32(np.log(0.5))
+    p[7] = 1.0
+    pt = torch.from_numpy(p.reshape(-1)).to(dev)
+    mdev = torch.tensor([m], dtype=torch.int32, device=dev)
+    print("256^3 grid, 70000 kernels of radius 6, pair_cap 2^20", flush=True)
+    ctx.erbf_eval(pt, mdev, stats=True)
+    torch.cuda.synchronize()
+    st = ctx.stats()[0]
+    record("edge_offsets_64bit", needed=st.n_bucket_pairs, cap=1 << 20)
+    assert st.n_bucket_pairs == m * (n // 8) ** 3 > 2 ** 31
+    assert st.flags & L.FLAG_BUCKET_OVERFLOW
+    ctx.close()

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-import oracle_pool
+from oracle import pool as oracle_pool
 import synth
 from gpu_helpers import TAU1, TAU2, TAU_M, GpuProblem, oracle_grads_dict, oracle_levels, record, rel_inf
 

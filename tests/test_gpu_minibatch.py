@@ -48,7 +48,7 @@ def test_minibatch_step_matches_oracle(mode):
     gp = GpuProblem(prob, t32, batch_cap=batch.size)
     f = torch.zeros(batch.size, device=gp.ctx.device)
     kw = dict(mode=mode, lam=1e-4, l1_active=True, tau1=TAU1, tau2=TAU2, tau_m=10.0)
-    g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
+    g = gp.ctx.erbf_loss_grad_minibatch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
     torch.cuda.synchronize()
     st = gp.ctx.stats()[0]
     K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
@@ -89,7 +89,7 @@ def test_minibatch_partition_adds_up_to_the_full_batch():
     L2 = 0.0
     cnt = np.zeros(3, np.int64)
     for part in parts:
-        g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(part).to(dev), **kw)
+        g = gp.ctx.erbf_loss_grad_minibatch(gp.p, gp.m_dev, torch.from_numpy(part).to(dev), **kw)
         torch.cuda.synchronize()
         s = gp.ctx.stats()[0]
         acc += g.cpu().numpy().astype(np.float64)

@@ -1,7 +1,7 @@
 """Surface samples P (label 1; the training set V = {G, P} of Section 3.4.2)
 on the device against the oracle: the full step with a sample level between
 two grid levels, one crowded sample tile, the VJP, a mini-batch mixing grid
-points and samples, seeding next to samples, and the inscribed-sphere
+points and samples, seeding with samples in the neighbourhoods and dbar, and the inscribed-sphere
 initialisation with the nearest-sample depth of Algorithm 1."""
 
 import numpy as np
@@ -75,7 +75,7 @@ def test_minibatch_mixing_grid_points_and_samples():
     gp = GpuProblem(prob, t32, batch_cap=batch.size)
     f = torch.zeros(batch.size, device=gp.ctx.device)
     kw = dict(mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2)
-    g = gp.ctx.erbf_loss_grad_batch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
+    g = gp.ctx.erbf_loss_grad_minibatch(gp.p, gp.m_dev, torch.from_numpy(batch).to(gp.ctx.device), f_out=f, **kw)
     torch.cuda.synchronize()
     st = gp.ctx.stats()[0]
     K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k)
@@ -95,34 +95,48 @@ def test_minibatch_mixing_grid_points_and_samples():
         assert errs[k] <= 1e-4, (k, errs[k])
 
 
-def test_seeding_next_to_samples_ignores_them():
-    # the same grid residual seeds the same kernels with and without a
-    # sample level registered, whatever the residual at the samples
+def test_seeding_with_samples_matches_oracle():
+    # Algorithm 2 on V = {G, P}: registered samples sit in the extreme-point
+    # neighbourhoods and give eq. 3-24's dbar (nearest-sample distance);
+    # they are never candidates
     torch = _torch()
-    prob = _problem(85, kcap=200)
-    plain = synth.make_custom(85, [16, 24], 40, (1.6, 2.6), kinds=("ellipsoid", "torus", "capsule"), cap=200)
-    _, t32, _ = oracle_levels(prob)
-    _, t32p, _ = oracle_levels(plain)
+    prob = _problem(85, kcap=400)
+    olv, t32, _ = oracle_levels(prob)
+    gp = GpuProblem(prob, t32)
     rng = np.random.default_rng(7)
-    out = []
-    for pr, tt in ((prob, t32), (plain, t32p)):
-        gp = GpuProblem(pr, tt)
-        parts, gi = [], 0
-        for lv in pr.levels:
-            if lv.samples is not None:
-                parts.append(rng.normal(size=lv.npts).astype(np.float32) * 5.0)
-            else:
-                parts.append(np.random.default_rng(100 + gi).normal(size=lv.npts).astype(np.float32))
-                gi += 1
-        resid = torch.from_numpy(np.concatenate(parts)).to(gp.ctx.device)
-        n_grid = sum(lv.npts for lv in pr.levels if lv.samples is None)
-        n = gp.ctx.erbf_seed_from_error(gp.p, gp.m_dev, 0, resid, 1.0, n_grid, top_frac=0.01, k_new=32,
-                                        r_nms=0.0, eps=1e-7)
-        torch.cuda.synchronize()
-        P = gp.p.cpu().numpy().reshape(11, pr.cap)
-        out.append((n, P[:, pr.m:pr.m + n].copy()))
-    assert out[0][0] == out[1][0] > 0
-    assert np.array_equal(out[0][1], out[1][1])
+    E, ida = [], []
+    for lv in olv:
+        if isinstance(lv, O.OSamples):
+            e = np.zeros(lv.npts, np.float32)
+            e[:lv.pts.shape[0]] = np.round(rng.normal(size=lv.pts.shape[0]) * 0.6, 2)
+        else:
+            e = np.round(rng.normal(size=lv.npts) * 0.3, 2).astype(np.float32)
+            e[rng.random(lv.npts) < 0.3] = 0.0
+        E.append(e.astype(np.float32))
+        ida.append(e != 0.0)
+    n_id = int(sum(i.sum() for i in ida))
+    tf = float(np.float32(0.02))
+    out = O.seed(olv, [e.astype(np.float64) for e in E], ida, top_frac=tf, k_new=1024, eps=1e-7,
+                 n_idall=n_id)
+    grid_only = O.seed([lv for lv in olv if not isinstance(lv, O.OSamples)],
+                       [e.astype(np.float64) for e, lv in zip(E, olv) if not isinstance(lv, O.OSamples)],
+                       [i for i, lv in zip(ida, olv) if not isinstance(lv, O.OSamples)], top_frac=tf, k_new=1024,
+                       eps=1e-7, n_idall=n_id)
+    # the samples change the result: fewer extreme points, other scales
+    assert out.n_extreme < grid_only.n_extreme
+    resid = torch.from_numpy(np.concatenate(E)).to(gp.ctx.device)
+    n = gp.ctx.erbf_seed_from_error(gp.p, gp.m_dev, 0, resid, 1.0, n_id, top_frac=tf, k_new=1024, eps=1e-7)
+    torch.cuda.synchronize()
+    assert n == out.index.size > 10
+    P = gp.p.cpu().numpy().reshape(11, prob.cap)
+    new = P[:, prob.m:prob.m + n]
+    assert np.array_equal(new[0], out.w.astype(np.float32))
+    assert np.array_equal(new[1:4].T, out.c.astype(np.float32))
+    assert np.array_equal(new[7:11].T, out.q.astype(np.float32))
+    s_err = float(np.abs(new[4:7].T.astype(np.float64) - out.s).max() / max(1.0, np.abs(out.s).max()))
+    record("seed_with_samples", n_added=n, n_candidates=out.n_candidates, n_extreme=out.n_extreme,
+           n_extreme_grid_only=grid_only.n_extreme, s_rel_err=s_err)
+    assert s_err <= 1e-6
 
 
 def test_init_with_samples_uses_the_nearest_sample_depth():

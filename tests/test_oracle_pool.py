@@ -4,7 +4,7 @@ step (sums over kernels regrouped, so equal to rounding)."""
 import numpy as np
 
 import oracle as O
-import oracle_pool
+from oracle import pool as oracle_pool
 import synth
 
 
