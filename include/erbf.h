@@ -384,6 +384,17 @@ int erbf_surface_sample(const float* tris, int64_t n_tris, const float* u, int64
 int erbf_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
                          int64_t nr, double* scratch, double* out, hipStream_t stream);
 
+/* erbf_surface_metrics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and result, with the per-point scratch
+ * taken from a buffer built into the library (16 MiB per GPU, held until the
+ * process ends) instead of a scratch argument.  nt + nr <= 2^20, else
+ * ERBF_ERR_INVALID_ARG.  Allocates nothing.  Every call on one GPU shares
+ * that buffer: calls that overlap on one GPU (different streams or threads)
+ * race and must be serialised by the caller. */
+int erbf_surface_metrics_noalloc(const float* Pt, const float* Nt, int64_t nt, const float* Pr,
+                                 const float* Nr, int64_t nr, double* out, hipStream_t stream);
+
 /* ---- training control (Algorithm 3) -------------------------------------- */
 
 /* Constants of Algorithm 3 (paper values in parentheses). */

@@ -138,6 +138,7 @@ _SIGS = [
                                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _V]),
     ("erbf_surface_sample", ctypes.c_int, [_V, ctypes.c_int64, _V, ctypes.c_int64, _V, _V, _V, _V, _V]),
     ("erbf_surface_metrics", ctypes.c_int, [_V, _V, ctypes.c_int64, _V, _V, ctypes.c_int64, _V, _V, _V]),
+    ("erbf_surface_metrics_noalloc", ctypes.c_int, [_V, _V, ctypes.c_int64, _V, _V, ctypes.c_int64, _V, _V]),
     ("erbf_sched_init", ctypes.c_int, [_V, ctypes.POINTER(SchedCfg), ctypes.POINTER(SchedState), _V]),
     ("erbf_sched_step", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(SchedCfg),
                                        ctypes.POINTER(SchedState), _V, _V, _V, _V]),

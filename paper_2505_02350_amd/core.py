@@ -395,6 +395,17 @@ def erbf_surface_metrics(Pt, Nt, Pr, Nr, stream=None):
     return hd, cd, cs
 
 
+def erbf_surface_metrics_noalloc(Pt, Nt, Pr, Nr, out=None, stream=None):
+    """(HD, CD, CS) as erbf_surface_metrics, with the library's built-in
+    scratch (nothing allocated on the device but `out` when not given)."""
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=Pt.device)
+    L.check(L.load().erbf_surface_metrics_noalloc(_ptr(Pt), _ptr(Nt), Pt.shape[0], _ptr(Pr), _ptr(Nr), Pr.shape[0],
+                                                  _ptr(out), _stream(stream)))
+    hd, cd, cs = out.cpu().tolist()
+    return hd, cd, cs
+
+
 def sched_cfg(k_l2=10, tau_l2=0.5, k_l1=50, tau_l1=5.0, tau_d=0.01, T_e=1600, M_e=2000, lr0=0.01,
               lr_final=1e-3, lr_min=1e-5, refine_epochs=(400, 800)):
     """Algorithm 3's constants (defaults: the paper's values)."""

@@ -1036,4 +1036,18 @@ int erbf_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const flo
   return ERBF_OK;
 }
 
+int erbf_surface_metrics_noalloc(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
+                                 int64_t nr, double* out, hipStream_t stream) {
+  if (!Pt || !Nt || !Pr || !Nr || nt < 1 || nr < 1 || !out)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_metrics_noalloc: bad arguments");
+  if (nt > kNoallocMetricsPoints - nr)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_surface_metrics_noalloc: nt + nr = " + std::to_string(nt + nr) +
+                                          " exceeds the built-in scratch limit of " +
+                                          std::to_string(kNoallocMetricsPoints) + " points");
+  double* scr = nullptr;
+  HIP_TRY(noalloc_metrics_scratch(&scr), "erbf_surface_metrics_noalloc: scratch address");
+  HIP_TRY(launch_surface_metrics(Pt, Nt, nt, Pr, Nr, nr, scr, out, stream), "erbf_surface_metrics_noalloc");
+  return ERBF_OK;
+}
+
 }  // extern "C"

@@ -76,6 +76,11 @@ hipError_t launch_surface_sample(const float* tris, int64_t nt, const float* u, 
 hipError_t launch_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
                                   int64_t nr, double* scratch, double* out, hipStream_t s);
 hipError_t launch_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t s);
+// erbf_surface_metrics_noalloc: at most this many points over both sets
+constexpr int64_t kNoallocMetricsPoints = (int64_t)1 << 20;
+// device address of the metrics scratch on the current device (looked up on
+// the first call on each device)
+hipError_t noalloc_metrics_scratch(double** out);
 hipError_t launch_sched_init(const Dev& D, const erbf_sched_state& st, const erbf_sched_cfg& a, hipStream_t s);
 hipError_t launch_sched_step(const Dev& D, const float* p_const, float* p, int32_t* m_dev, float* m1, float* m2,
                              const erbf_sched_state& st, const erbf_sched_cfg& a, const erbf_stats* stats,

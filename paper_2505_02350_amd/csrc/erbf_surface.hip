@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "erbf_device.h"
 #include "erbf_internal.h"
@@ -370,6 +371,35 @@ hipError_t launch_surface_metrics(const float* Pt, const float* Nt, int64_t nt, 
   hipLaunchKernelGGL(k_closest, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, Pr, Nr, nr, Pt, Nt, nt, d_rt, c_rt);
   hipLaunchKernelGGL(k_metrics, dim3(1), dim3(1024), 0, s, d_tr, c_tr, nt, d_rt, c_rt, nr, out);
   return hipGetLastError();
+}
+
+// Device scratch of the metrics variant that allocates nothing: one copy per
+// GPU, held until the process ends.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is handed to kernels.
+static __device__ __align__(256) double scratch[2 * kNoallocMetricsPoints];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_metrics_scratch(double** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t s) {
