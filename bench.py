@@ -331,6 +331,10 @@ def main():
     ap.add_argument("--workload-cache", default="",
                     help="npz file of the generated timing workload: read if present, else written")
     ap.add_argument("--gen-only", action="store_true", help="generate (and cache) the workload, then exit")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="launch variant of the tile kernels (erbf_set_variant); default: the library's")
+    ap.add_argument("--slot-chunk", type=int, default=-1,
+                    help="XCD runs of tiles of the grid launches (erbf_set_launch); default: the library's")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
@@ -401,6 +405,11 @@ def main():
         del src, dst
         log(f"copy calibration: 3 device copies of {COPY_CAL_BYTES} bytes")
 
+    if args.variant >= 0 or args.slot_chunk >= 0:
+        v0, c0, s0 = fit.ctx.erbf_get_launch()
+        fit.ctx.erbf_set_launch(args.variant if args.variant >= 0 else v0,
+                                args.slot_chunk if args.slot_chunk >= 0 else c0, s0)
+    variant, slot_chunk, _ = fit.ctx.erbf_get_launch()
     kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
     for _ in range(args.warmup):
         fit.step(**kw)
@@ -427,14 +436,21 @@ def main():
     pairs_per_step = (P_fwd + P_bwd) / K
     value = (P_fwd + P_bwd) / wall
     fwd_avg, bt_avg, br_avg = fwd_ms / K, bt_ms / K, br_ms / K
-    fwd_rate = FWD_FLOP_PER_PAIR * P_fwd / K / (fwd_avg * 1e-3)
-    # the backward's per-pair arithmetic runs in the tile kernel; the reduce
-    # kernel only sums per-tile moments
-    bwd_rate = BWD_FLOP_PER_PAIR * P_bwd / K / (bt_avg * 1e-3)
-    if bt_avg >= fwd_avg:
-        dom, dom_short, ach, t_dom = "k_bwd_tiles (backward moments)", "k_bwd_tiles", bwd_rate, bt_avg
+    fused = (variant & L.VARIANT_FUSED) != 0
+    if fused:
+        # one kernel forms f, the loss and the backward moments of every tile
+        # (the reduce kernel only sums per-tile moments)
+        fwd_rate = bwd_rate = None
+        ach = (FWD_FLOP_PER_PAIR * P_fwd + BWD_FLOP_PER_PAIR * P_bwd) / K / (fwd_avg * 1e-3)
+        dom, dom_short, t_dom = "k_step_tiles (forward + loss + backward moments)", "k_step_tiles", fwd_avg
     else:
-        dom, dom_short, ach, t_dom = "k_forward (forward + loss)", "k_forward", fwd_rate, fwd_avg
+        fwd_rate = FWD_FLOP_PER_PAIR * P_fwd / K / (fwd_avg * 1e-3)
+        # the backward's per-pair arithmetic runs in the tile kernel
+        bwd_rate = BWD_FLOP_PER_PAIR * P_bwd / K / (bt_avg * 1e-3)
+        if bt_avg >= fwd_avg:
+            dom, dom_short, ach, t_dom = "k_bwd_tiles (backward moments)", "k_bwd_tiles", bwd_rate, bt_avg
+        else:
+            dom, dom_short, ach, t_dom = "k_forward (forward + loss)", "k_forward", fwd_rate, fwd_avg
     # HBM bytes per launch from the committed counter summary, if it was
     # taken on the current kernel source
     from paper_2505_02350_amd.prof_summary import read_traffic
@@ -442,8 +458,12 @@ def main():
     traffic = None
     if tb is not None and dom_short in tb.get("kernels", {}):
         traffic = tb["kernels"][dom_short]["traffic_bytes_per_launch"]
-    log(f"timed {K} steps: {ms_per_step:.3f} ms/step; forward {fwd_avg:.3f} ms, backward tiles "
-        f"{bt_avg:.3f} ms, reduce {br_avg:.3f} ms")
+    if fused:
+        log(f"timed {K} steps: {ms_per_step:.3f} ms/step; step tiles (forward + backward) {fwd_avg:.3f} ms, "
+            f"reduce {br_avg:.3f} ms")
+    else:
+        log(f"timed {K} steps: {ms_per_step:.3f} ms/step; forward {fwd_avg:.3f} ms, backward tiles "
+            f"{bt_avg:.3f} ms, reduce {br_avg:.3f} ms")
 
     graph_ms = graph10_ms = None
     if args.graph:
@@ -497,8 +517,10 @@ def main():
             "frac": ach / FP32_VECTOR_PEAK,
             "traffic": traffic,
         },
-        "kernels_ms": {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
-                       "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12},
+        "kernels_ms": ({"step_tiles": fwd_avg, "backward_reduce": br_avg} if fused else
+                       {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
+                        "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12}),
+        "launch": {"variant": variant, "slot_chunk": slot_chunk},
         "fwd_bwd_pairs_per_s": (P_fwd + P_bwd) / ((fwd_ms + bt_ms + br_ms) * 1e-3),
         "bucket_entries": st.n_bucket_pairs,
         "graph_ms_per_step": graph_ms,

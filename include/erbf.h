@@ -454,6 +454,15 @@ int erbf_sched_step(erbf_ctx* ctx, const erbf_params* params, const erbf_sched_c
                     const erbf_sched_state* state, const erbf_stats* stats_dev, float* m1, float* m2,
                     hipStream_t stream);
 
+/* One optimisation step (Algorithm 3's inner step): erbf_loss_grad followed
+ * by erbf_adam_step on its gradient, with the same arguments and results
+ * (grad_out receives the combined gradient alpha dL2 + beta dL1, step_dev is
+ * incremented, stats_dev, f_out and G_out as for erbf_loss_grad), in fewer
+ * launches: the combination of eq. 3-21 is applied inside the Adam pass. */
+int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+                    const erbf_adam_cfg* adam, float* grad_out, float* m1, float* m2, int32_t* step_dev,
+                    erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream);
+
 /* ---- measurement --------------------------------------------------------- */
 
 /* Time the hot kernels of the next `max_calls` erbf_loss_grad / erbf_vjp
@@ -470,22 +479,51 @@ int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls);
 
 /* ---- launch variants and the autotuner ------------------------------------ */
 
-/* Launch variants of the two per-tile kernels (bit flags; results do not
- * depend on the variant, only the time does):
- *   1  forward tiles walked round-robin by a persistent grid
- *   2  backward tiles walked round-robin by a persistent grid
- * 0 launches one workgroup per tile for both. */
+/* Launch variants of the per-tile kernels (bit flags; results do not depend
+ * on the variant, only the time does):
+ *   1  forward tiles (with 4: forward + backward tiles) walked round-robin by
+ *      a persistent grid
+ *   2  backward tiles walked round-robin by a persistent grid (without 4)
+ *   4  the loss call takes each tile through the forward, the loss and the
+ *      backward moments in one kernel, instead of a forward kernel and a
+ *      backward kernel
+ * 0 (the default) launches one workgroup per tile for both kernels. */
 #define ERBF_VARIANT_FWD_PERSISTENT 1
 #define ERBF_VARIANT_BWD_PERSISTENT 2
+#define ERBF_VARIANT_FUSED 4
+#define ERBF_N_VARIANTS 8
 
 int erbf_set_variant(erbf_ctx* ctx, int32_t variant);
 int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
 
-/* Time erbf_loss_grad under every launch variant (one warm-up and `reps`
- * timed calls each, HIP events on `stream`), keep the fastest in the context
- * and return it in *chosen; times_ms (optional) receives the mean time of
- * each variant [4].  grad_scratch: device [11 * cap_total].  The parameters
- * are read, not modified.  Synchronous. */
+/* The launch choices of a context (results do not depend on them, except
+ * that samp_split regroups the sums of f at surface samples, within float32
+ * rounding):
+ *   variant     ERBF_VARIANT_* bits above (default 0)
+ *   slot_chunk  0: workgroup b of a one-workgroup-per-tile launch takes
+ *               active tile b; C in 1 .. 256: runs of C consecutive tiles are
+ *               dealt to the GPU's eight XCDs round-robin (neighbouring tiles
+ *               share kernel records in one XCD's L2) (default 8)
+ *   samp_split  workgroups per active surface-sample tile, 1 .. 32 (default 16) */
+typedef struct {
+  int32_t variant;
+  int32_t slot_chunk;
+  int32_t samp_split;
+} erbf_launch_cfg;
+
+int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg);
+int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg);
+
+/* Tune the context's launch choices for erbf_loss_grad by timing it (one
+ * warm-up and `reps` timed calls per candidate, HIP events on `stream`), one
+ * choice after the other: the variant (every ERBF_N_VARIANTS entry), then
+ * slot_chunk (0, 2, 8, 32), then samp_split (8, 16, 32; only when a surface
+ * sample level is registered), each with the best of the choices before it.
+ * The fastest set stays in the context (erbf_get_launch); *chosen receives
+ * its variant and times_ms (optional) the mean time of each variant
+ * [ERBF_N_VARIANTS] (a negative entry for a variant that is the same launch
+ * as a lower one and is not timed).  grad_scratch: device [11 * cap_total].
+ * The parameters are read, not modified.  Synchronous. */
 int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_scratch,
                   int32_t reps, int32_t* chosen, float* times_ms, hipStream_t stream);
 

@@ -26,6 +26,7 @@ FLAG_BUCKET_OVERFLOW = 1
 MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
 ORIENT_QUATERNION, ORIENT_EULER = 0, 1
+VARIANT_FWD_PERSISTENT, VARIANT_BWD_PERSISTENT, VARIANT_FUSED, N_VARIANTS = 1, 2, 4, 8
 ABI_VERSION = 4
 
 
@@ -97,6 +98,10 @@ class SchedState(ctypes.Structure):
 STATS_BYTES = ctypes.sizeof(Stats)
 
 # (name, restype, argtypes) of every exported symbol of include/erbf.h
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("slot_chunk", ctypes.c_int32), ("samp_split", ctypes.c_int32)]
+
+
 _V = ctypes.c_void_p
 _SIGS = [
     ("erbf_abi_version", ctypes.c_int32, []),
@@ -120,10 +125,14 @@ _SIGS = [
                                                 ctypes.c_int32, _V, _V, _V, _V]),
     ("erbf_vjp", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V]),
     ("erbf_adam_step", ctypes.c_int, [_V, ctypes.POINTER(Params), _V, _V, _V, _V, ctypes.POINTER(AdamCfg), _V]),
+    ("erbf_train_step", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), ctypes.POINTER(AdamCfg),
+                                       _V, _V, _V, _V, _V, _V, _V, _V]),
     ("erbf_timing_enable", ctypes.c_int, [_V, ctypes.c_int32]),
     ("erbf_timing_read", ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     ("erbf_set_variant", ctypes.c_int, [_V, ctypes.c_int32]),
     ("erbf_get_variant", ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_int32)]),
+    ("erbf_set_launch", ctypes.c_int, [_V, ctypes.POINTER(LaunchCfg)]),
+    ("erbf_get_launch", ctypes.c_int, [_V, ctypes.POINTER(LaunchCfg)]),
     ("erbf_autotune", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.POINTER(LossCfg), _V, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), _V, _V]),
     ("erbf_seed_from_error", ctypes.c_int, [_V, ctypes.POINTER(Params), ctypes.c_int32, _V, ctypes.c_float,

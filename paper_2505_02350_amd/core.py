@@ -237,6 +237,19 @@ class Context:
         L.check(self.lib.erbf_adam_step(self.handle, ctypes.byref(pr), _ptr(grad), _ptr(m1), _ptr(m2),
                                         _ptr(step_dev), ctypes.byref(cfg), _stream(stream)))
 
+    def erbf_train_step(self, p, m_dev, grad_out, m1, m2, step_dev, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None,
+                        l1_active=False, tau1=0.9, tau2=1.1, tau_m=0.02, l1_active_dev=None, lr=1e-3, lr_dev=None,
+                        beta1=0.9, beta2=0.999, eps=1e-8, f_out=None, G_out=None, stream=None):
+        """Loss, gradient and Adam update in one call (erbf_train_step)."""
+        pr = self._params(p, m_dev)
+        cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
+                        float(tau2), float(tau_m), _ptr(l1_active_dev))
+        acfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps))
+        L.check(self.lib.erbf_train_step(self.handle, ctypes.byref(pr), ctypes.byref(cfg), ctypes.byref(acfg),
+                                         _ptr(grad_out), _ptr(m1), _ptr(m2), _ptr(step_dev), _ptr(self.stats_buf),
+                                         _ptr(f_out), _ptr(G_out), _stream(stream)))
+        return grad_out
+
     def erbf_seed_from_error(self, p, m_dev, shape, resid, resid_scale, n_idall, top_frac=0.01,
                              k_new=256, r_nms=0.0, eps=1e-7, min_abs_err=0.0, w_rule=0, m1=None, m2=None,
                              stream=None):
@@ -288,6 +301,16 @@ class Context:
         L.check(self.lib.erbf_get_variant(self.handle, ctypes.byref(v)))
         return v.value
 
+    def erbf_set_launch(self, variant: int, slot_chunk: int, samp_split: int):
+        c = L.LaunchCfg(int(variant), int(slot_chunk), int(samp_split))
+        L.check(self.lib.erbf_set_launch(self.handle, ctypes.byref(c)))
+
+    def erbf_get_launch(self):
+        """(variant, slot_chunk, samp_split) of the context."""
+        c = L.LaunchCfg()
+        L.check(self.lib.erbf_get_launch(self.handle, ctypes.byref(c)))
+        return c.variant, c.slot_chunk, c.samp_split
+
     def erbf_autotune(self, p, m_dev, reps=3, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
                       tau1=0.9, tau2=1.1, tau_m=0.02, stream=None):
         """Choose the fastest launch variant for these parameters; returns
@@ -297,7 +320,7 @@ class Context:
                         float(tau2), float(tau_m))
         scratch = torch.empty(11 * self.cap_total, dtype=torch.float32, device=self.device)
         chosen = ctypes.c_int32()
-        times = (ctypes.c_float * 4)()
+        times = (ctypes.c_float * 8)()
         L.check(self.lib.erbf_autotune(self.handle, ctypes.byref(pr), ctypes.byref(cfg), _ptr(scratch), int(reps),
                                        ctypes.byref(chosen), times, _stream(stream)))
         return chosen.value, list(times)

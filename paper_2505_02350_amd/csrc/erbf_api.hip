@@ -51,7 +51,7 @@ struct Layout {
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
-      off_counters, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
+      off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
       off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init, off_samp_pos, off_samp_start, off_samp_slot,
       off_samp_slots, off_samp_f, off_samp_c, off_samp_pb, off_sel;
   int64_t samp_total = 0, samp_start_total = 0, samp_tiles = 0;
@@ -149,6 +149,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_tstat = take(sizeof(TileStat) * L.tiles_total);
   L.off_tile_pbwd = take(sizeof(int64_t) * L.tiles_total);
   L.off_counters = take(sizeof(int64_t) * 8);
+  L.off_tickets = take(sizeof(uint32_t) * (cfg->n_shapes + 1));
   L.off_stat_part = take(sizeof(StatPart) * kStatParts * cfg->n_shapes);
   L.off_stat_ab = take(sizeof(double2) * cfg->n_shapes);
   L.off_prune_flag = take(sizeof(int32_t) * cfg->n_shapes);
@@ -177,9 +178,9 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_samp_slot = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_total, 1));
   L.off_samp_slots = take(sizeof(int32_t) * (size_t)std::max<int64_t>(L.samp_tiles, 1));
   L.off_sel = take(sizeof(int32_t) * (size_t)std::max(L.tiles_total, 1));
-  L.off_samp_f = take(sizeof(float) * kSampSplit * (size_t)std::max<int64_t>(L.samp_total, 1));
-  L.off_samp_c = take(sizeof(int32_t) * kSampSplit * (size_t)std::max<int64_t>(L.samp_total, 1));
-  L.off_samp_pb = take(sizeof(int64_t) * kSampSplit * (size_t)std::max<int64_t>(L.samp_tiles, 1));
+  L.off_samp_f = take(sizeof(float) * kSampSplitMax * (size_t)std::max<int64_t>(L.samp_total, 1));
+  L.off_samp_c = take(sizeof(int32_t) * kSampSplitMax * (size_t)std::max<int64_t>(L.samp_total, 1));
+  L.off_samp_pb = take(sizeof(int64_t) * kSampSplitMax * (size_t)std::max<int64_t>(L.samp_tiles, 1));
   L.bytes = o;
   return L;
 }
@@ -306,6 +307,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.tstat = reinterpret_cast<TileStat*>(w + lay.off_tstat);
   D.tile_pbwd = reinterpret_cast<int64_t*>(w + lay.off_tile_pbwd);
   D.counters = reinterpret_cast<int64_t*>(w + lay.off_counters);
+  D.tickets = reinterpret_cast<uint32_t*>(w + lay.off_tickets);
   D.stat_part = reinterpret_cast<StatPart*>(w + lay.off_stat_part);
   D.stat_ab = reinterpret_cast<double2*>(w + lay.off_stat_ab);
   D.prune_flag = reinterpret_cast<int32_t*>(w + lay.off_prune_flag);
@@ -343,6 +345,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.weight_map = cfg->weight_map;
   D.orientation = cfg->orientation;
   D.variant = 0;
+  D.slot_chunk = 8;
+  D.samp_split = 16;
   {
     hipDeviceProp_t prop;
     const hipError_t pe = hipGetDeviceProperties(&prop, device);
@@ -393,6 +397,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   if (e == hipSuccess) e = launch_fill_i32(D.tile_map, lay.tiles_total, -1, nullptr);
   if (e == hipSuccess) e = launch_fill_f32(D.G, lay.pts_total, 0.f, nullptr);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(D.counters), 16, 0, nullptr);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(D.tickets), cfg->n_shapes + 1, 0, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete c;
@@ -604,8 +609,35 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
   return ERBF_OK;
 }
 
+namespace {
+// the loss call; apply = false leaves the L2 gradient in grad_out and the
+// weights of eq. 3-21 in the workspace (erbf_train_step combines them in Adam)
+int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, bool apply);
+}  // namespace
+
 int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
                    erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
+  return loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, true);
+}
+
+int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
+                    const erbf_adam_cfg* adam, float* grad_out, float* m1, float* m2, int32_t* step_dev,
+                    erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
+  if (!adam || !m1 || !m2 || !step_dev) return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: NULL argument");
+  if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f && adam->eps > 0.f))
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: bad Adam hyper-parameters");
+  int rc = loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, false);
+  if (rc) return rc;
+  DeviceGuard guard(ctx->device);
+  AdamArgs a{adam->lr, adam->lr_dev, adam->beta1, adam->beta2, adam->eps};
+  HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad_out, m1, m2, step_dev, a, true, stream), "train: adam");
+  return ERBF_OK;
+}
+
+namespace {
+int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, bool apply) {
   int rc = check_params(ctx, params);
   if (rc) return rc;
   if (!cfg || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "cfg and grad_out must be non-NULL");
@@ -625,8 +657,9 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
       }
   HIP_TRY(launch_buckets(D, params->p, params->m_dev, ctx->slots_used, stream), "loss: buckets");
   const hipEvent_t* ev = tev_call(ctx);
-  HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, ev, stream), "loss: forward");
-  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
+  const bool fused = (D.variant & kVariantFused) != 0;
+  HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, ev, stream, fused), "loss: forward");
+  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream, fused),
           "loss: backward");
   if (ev) ctx->t_used += 1;
   StatsArgs a{};
@@ -636,12 +669,13 @@ int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   a.l1_active = cfg->l1_active;
   a.l1_active_dev = cfg->l1_active_dev;
   a.tau_m = cfg->tau_m;
-  HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream), "loss: stats");
+  HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream, apply), "loss: stats");
   if (G_out)
     HIP_TRY(hipMemcpyAsync(G_out, D.G, sizeof(float) * ctx->lay.pts_total, hipMemcpyDeviceToDevice, stream),
             "loss: copy G");
   return ERBF_OK;
 }
+}  // namespace
 
 int erbf_loss_grad_batched(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
                            erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
@@ -721,12 +755,13 @@ int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, 
     return fail(ERBF_ERR_INVALID_ARG, "erbf_adam_step: bad hyper-parameters");
   DeviceGuard guard(ctx->device);
   AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps};
-  HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad, m1, m2, step_dev, a, stream), "adam");
+  HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, const_cast<float*>(grad), m1, m2, step_dev, a, false, stream),
+          "adam");
   return ERBF_OK;
 }
 
 int erbf_set_variant(erbf_ctx* ctx, int32_t variant) {
-  if (!ctx || variant < 0 || variant > (kVariantFwdPersistent | kVariantBwdPersistent))
+  if (!ctx || variant < 0 || variant > kVariantAll)
     return fail(ERBF_ERR_INVALID_ARG, "erbf_set_variant: bad arguments");
   ctx->D.variant = variant;
   return ERBF_OK;
@@ -738,13 +773,30 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant) {
   return ERBF_OK;
 }
 
+int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg) {
+  if (!ctx || !cfg || cfg->variant < 0 || cfg->variant > kVariantAll || cfg->slot_chunk < 0 ||
+      cfg->slot_chunk > 256 || cfg->samp_split < 1 || cfg->samp_split > kSampSplitMax)
+    return fail(ERBF_ERR_INVALID_ARG, "erbf_set_launch: bad arguments");
+  ctx->D.variant = cfg->variant;
+  ctx->D.slot_chunk = cfg->slot_chunk;
+  ctx->D.samp_split = cfg->samp_split;
+  return ERBF_OK;
+}
+
+int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg) {
+  if (!ctx || !cfg) return fail(ERBF_ERR_INVALID_ARG, "erbf_get_launch: bad arguments");
+  cfg->variant = ctx->D.variant;
+  cfg->slot_chunk = ctx->D.slot_chunk;
+  cfg->samp_split = ctx->D.samp_split;
+  return ERBF_OK;
+}
+
 int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_scratch,
                   int32_t reps, int32_t* chosen, float* times_ms, hipStream_t stream) {
   int rc = check_params(ctx, params);
   if (rc) return rc;
   if (!cfg || !grad_scratch || reps < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_autotune: bad arguments");
   DeviceGuard guard(ctx->device);
-  const int n_var = (kVariantFwdPersistent | kVariantBwdPersistent) + 1;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "autotune: event");
   hipError_t ce = hipEventCreate(&e1);
@@ -754,36 +806,77 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
   }
   const int saved_tmax = ctx->t_max;
   ctx->t_max = 0;  // no per-kernel timing while tuning
-  int best = 0;
-  float best_ms = 0.f;
+  const Dev saved = ctx->D;
   int status = ERBF_OK;
-  for (int v = 0; v < n_var && status == ERBF_OK; ++v) {
-    ctx->D.variant = v;
-    status = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);  // warm-up
-    if (status != ERBF_OK) break;
+  // mean time of one erbf_loss_grad under the context's current choices
+  auto time_it = [&](float* ms_out) -> int {
+    int st = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);  // warm-up
+    if (st != ERBF_OK) return st;
     hipError_t e = hipEventRecord(e0, stream);
-    for (int r = 0; r < reps && e == hipSuccess && status == ERBF_OK; ++r)
-      status = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);
+    for (int r = 0; r < reps && e == hipSuccess && st == ERBF_OK; ++r)
+      st = erbf_loss_grad(ctx, params, cfg, grad_scratch, nullptr, nullptr, nullptr, stream);
+    if (st != ERBF_OK) return st;
     if (e == hipSuccess) e = hipEventRecord(e1, stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      status = hip_fail(e, "autotune: timing");
-      break;
-    }
-    ms /= (float)reps;
-    if (times_ms) times_ms[v] = ms;
-    if (v == 0 || ms < best_ms) {
-      best = v;
+    if (e != hipSuccess) return hip_fail(e, "autotune: timing");
+    *ms_out = ms / (float)reps;
+    return ERBF_OK;
+  };
+  erbf_launch_cfg best{0, 0, saved.samp_split};
+  float best_ms = 0.f;
+  bool have = false;
+  auto consider = [&](const erbf_launch_cfg& c, float* ms_slot) -> int {
+    ctx->D.variant = c.variant;
+    ctx->D.slot_chunk = c.slot_chunk;
+    ctx->D.samp_split = c.samp_split;
+    float ms = 0.f;
+    const int st = time_it(&ms);
+    if (st != ERBF_OK) return st;
+    if (ms_slot) *ms_slot = ms;
+    if (!have || ms < best_ms) {
+      best = c;
       best_ms = ms;
+      have = true;
     }
+    return ERBF_OK;
+  };
+  // 1. the launch variant
+  for (int v = 0; v <= kVariantAll && status == ERBF_OK; ++v) {
+    if ((v & kVariantBwdPersistent) && (v & kVariantFused)) {
+      // the fused kernel has no separate backward launch: same as v - 2
+      if (times_ms) times_ms[v] = -1.f;
+      continue;
+    }
+    status = consider(erbf_launch_cfg{v, 0, best.samp_split}, times_ms ? times_ms + v : nullptr);
+  }
+  // 2. the XCD runs of the grid launches
+  const int chunks[] = {2, 8, 32};
+  const erbf_launch_cfg after_variant = best;
+  for (int k = 0; k < 3 && status == ERBF_OK; ++k)
+    status = consider(erbf_launch_cfg{after_variant.variant, chunks[k], after_variant.samp_split}, nullptr);
+  // 3. the sample tiles' split
+  if (status == ERBF_OK && ctx->D.n_samp_slots > 0) {
+    const int splits[] = {8, 16, 32};
+    const erbf_launch_cfg after_chunk = best;
+    for (int k = 0; k < 3 && status == ERBF_OK; ++k)
+      if (splits[k] != after_chunk.samp_split)
+        status = consider(erbf_launch_cfg{after_chunk.variant, after_chunk.slot_chunk, splits[k]}, nullptr);
   }
   ctx->t_max = saved_tmax;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->D.variant = status == ERBF_OK ? best : 0;
-  if (status == ERBF_OK && chosen) *chosen = best;
+  if (status == ERBF_OK) {
+    ctx->D.variant = best.variant;
+    ctx->D.slot_chunk = best.slot_chunk;
+    ctx->D.samp_split = best.samp_split;
+    if (chosen) *chosen = best.variant;
+  } else {
+    ctx->D.variant = saved.variant;
+    ctx->D.slot_chunk = saved.slot_chunk;
+    ctx->D.samp_split = saved.samp_split;
+  }
   return status;
 }
 

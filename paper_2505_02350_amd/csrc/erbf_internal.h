@@ -14,9 +14,11 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 // launch variants chosen by the autotuner (bit flags)
 constexpr int kVariantFwdPersistent = 1;   // forward tiles walked by a persistent grid
-constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persistent grid
+constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persistent grid (separate kernels)
+constexpr int kVariantFused = 4;           // the loss call's forward and backward tiles in one kernel
+constexpr int kVariantAll = 7;
 
-constexpr int kSampSplit = 16;     // workgroups per active sample tile (parts of its kernel list)
+constexpr int kSampSplitMax = 32;  // most workgroups per active sample tile (parts of its kernel list)
 constexpr int kLevelGrid = 0;      // cell-centred grid of n^3 points
 constexpr int kLevelSamples = 1;   // surface samples binned into the tiles of an n^3-cell grid
 
@@ -104,6 +106,7 @@ struct Dev {
   TileStat* tstat;          // [tiles_total]
   int64_t* tile_pbwd;       // [tiles_total] in-ball pairs at non-zero-G points of each tile
   int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
+  uint32_t* tickets;        // [n_shapes + 1] last-block tickets: statistics per shape, then Adam (0 between calls)
   StatPart* stat_part;      // [n_shapes * kStatParts]
   int32_t* prune_flag;      // [n_shapes] eq. 3-27 due after this step (training control)
   // mini-batch records, one per batch point (batch order)
@@ -124,9 +127,9 @@ struct Dev {
   int32_t* samp_slot;       // [total sample capacity]
   int32_t* samp_slots;      // [sample-level tiles] slots of every active sample tile
   int32_t n_samp_slots;     // entries of samp_slots in use
-  float* samp_f;            // [total sample capacity * kSampSplit] forward sum of each (sample, list part)
-  int32_t* samp_c;          // [total sample capacity * kSampSplit] its in-ball pair count
-  int64_t* samp_pb;         // [sample-level tiles * kSampSplit] backward pair counts of each list part
+  float* samp_f;            // [total sample capacity * kSampSplitMax] forward sum of each (sample, list part)
+  int32_t* samp_c;          // [total sample capacity * kSampSplitMax] its in-ball pair count
+  int64_t* samp_pb;         // [sample-level tiles * kSampSplitMax] backward pair counts of each list part
   // inscribed-sphere initialisation scratch: nearest-sample squared
   // distances (double, init_cand_cap), candidate mask (init_words), two
   // candidate lists (init_cand_cap each) and 8 result words
@@ -142,6 +145,8 @@ struct Dev {
   int32_t weight_map;
   int32_t orientation;      // ERBF_ORIENT_*
   int32_t variant;          // kVariant* flags
+  int32_t slot_chunk;       // tile runs per XCD of the grid launches (0: workgroup b takes slot b)
+  int32_t samp_split;       // parts of each sample tile's kernel list (workgroups), 1 .. kSampSplitMax
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass
   int32_t n_levels_total;   // entries of `levels` (ordered by pt_base)

@@ -635,19 +635,69 @@ __device__ __forceinline__ void fwd_eval_pair(const float4 U, const FwdRowTerms&
   pf += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
 }
 
-template <bool LOSS>
-__device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float* __restrict__ f_out,
-                                             float tau1, float tau2) {
+// LDS of the forward tile body
+struct FwdLds {
   // records of the chunk, plus an inert record (r^2 < 0, a = 0) at index
   // kFwdChunk that pads each wave's list to a multiple of four
-  __shared__ float4 srec[kFwdChunk * 3 + 3];
-  __shared__ uint32_t slist[4][kFwdChunk + 4];
-  __shared__ int scnt[4][4];
-  __shared__ float sbox[4][6];
-  __shared__ double red_d[4];
-  __shared__ float red_f[4];
-  __shared__ int red_i[4];
-  __shared__ int64_t red_p[4];
+  float4 srec[kFwdChunk * 3 + 3];
+  uint32_t slist[4][kFwdChunk + 4];
+  int scnt[4][4];
+  float sbox[4][6];
+  double red_d[4];
+  float red_f[4];
+  int red_i[4];
+  int64_t red_p[4];
+};
+
+// backward tile: a workgroup of four waves, 512 points (two per thread)
+constexpr int kBwdThreads = 256;
+constexpr int kBwdWaves = kBwdThreads / 64;
+constexpr int kBwdRounds = kTile * kTile * kTile / kBwdThreads;   // points per thread
+
+// LDS of the backward tile body: the tile's points with a non-zero upstream
+// gradient (x, G, G x', G x'^2), row r's points at spx[8 r ...], padded to an
+// even count with an inert point (far away, G = 0), and the rows in use
+struct BwdLds {
+  float4 spx[kTile * kTile * kTile];
+  float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
+  int swr[kBwdRounds][kBwdWaves];
+  int64_t spb[kBwdWaves];
+  uint32_t wrows[kBwdWaves];    // fused staging: rows in use of each wave's 16 rows
+};
+
+template <int N>
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kTileLdsBytes = cmax<0>((int)sizeof(FwdLds), (int)sizeof(BwdLds));
+
+// The active slot handled by workgroup b of a grid launch over n slots.
+// chunk 0: slot b.  chunk C > 0: the slots are cut into runs of C
+// consecutive slots (neighbouring tiles, sharing most of their kernels),
+// dealt to the eight XCDs round-robin, since workgroup b runs on XCD b % 8;
+// each XCD then works on a few runs at a time and finds their kernel records
+// in its own L2.  The grid is padded to a multiple of 8 C; padding
+// workgroups get -1.  A bijection of [0, padded grid) onto the slots and -1.
+__device__ __forceinline__ int tile_slot(int b, int n, int chunk) {
+  if (chunk <= 0) return b;
+  const int x = b & 7, k = b >> 3;
+  const int slot = ((k / chunk) * 8 + x) * chunk + (k % chunk);
+  return slot < n ? slot : -1;
+}
+
+__device__ void bwd_stage_from_registers(const Dev& D, const LevelDev& L, int slot, int tx, int ty, int tz,
+                                         const float g[2], BwdLds& B, int64_t beg, int64_t end);
+
+template <bool LOSS, bool BWD>
+__device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float* __restrict__ f_out,
+                                             float tau1, float tau2, char* lds) {
+  FwdLds& F = *reinterpret_cast<FwdLds*>(lds);
+  float4* srec = F.srec;
+  auto& slist = F.slist;
+  auto& scnt = F.scnt;
+  auto& sbox = F.sbox;
+  double* red_d = F.red_d;
+  float* red_f = F.red_f;
+  int* red_i = F.red_i;
+  int64_t* red_p = F.red_p;
 
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
@@ -762,6 +812,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   double l2 = 0.0;
   float mxe = 0.f;
   int cnt_id = 0;
+  float gv[2] = {0.f, 0.f};   // G = 2E at the lane's two points (0 outside id_all or the grid)
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int xi = xi0 + h;
@@ -778,7 +829,8 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       const bool id2 = t >= tau2 && f < tau2;
       const bool in = act && (id0 || id1 || id2);
       const float E = in ? f - t : 0.f;
-      D.G[idx] = 2.f * E;
+      gv[h] = 2.f * E;
+      D.G[idx] = gv[h];
       l2 += (double)E * (double)E;
       mxe = fmaxf(mxe, fabsf(E));
       cnt_id += in ? 1 : 0;
@@ -799,13 +851,22 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
     ts.p_fwd = (red_p[0] + red_p[1]) + (red_p[2] + red_p[3]);
     D.tstat[slot] = ts;
   }
+  if (BWD) {
+    // the backward of the same tile: G of its points is in registers, and
+    // the list's records were just read (L2)
+    __syncthreads();   // the forward's LDS is no longer read
+    bwd_stage_from_registers(D, L, slot, tx, ty, tz, gv, *reinterpret_cast<BwdLds*>(lds), beg, end);
+  }
 }
 
 // one workgroup per tile (grid launch) ...  Eight waves per SIMD (at most 64
 // VGPRs) keep the exp / LDS latencies of the walk hidden.
 template <bool LOSS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2) {
-  forward_tile<LOSS>(D, blockIdx.x, f_out, tau1, tau2);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
+  __shared__ __align__(16) char lds[sizeof(FwdLds)];
+  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  if (slot < 0) return;
+  forward_tile<LOSS, false>(D, slot, f_out, tau1, tau2, lds);
 }
 
 // ... or a persistent grid: each workgroup walks the tiles round-robin
@@ -815,8 +876,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 template <bool LOSS>
 __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __restrict__ f_out, float tau1,
                                                             float tau2, int n_slots) {
+  __shared__ __align__(16) char lds[sizeof(FwdLds)];
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    forward_tile<LOSS>(D, slot, f_out, tau1, tau2);
+    forward_tile<LOSS, false>(D, slot, f_out, tau1, tau2, lds);
+    __syncthreads();
+  }
+}
+
+// The step's tile kernel: forward and loss, then the backward moments of the
+// same tile (the two bodies of k_forward<true> and k_bwd_tiles, with the
+// backward's points staged from the forward's registers; results equal those
+// of the two kernels bit for bit).  The LDS of the two bodies overlaps.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step_tiles(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
+  __shared__ __align__(16) char lds[kTileLdsBytes];
+  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  if (slot < 0) return;
+  forward_tile<true, true>(D, slot, f_out, tau1, tau2, lds);
+}
+
+__global__ __launch_bounds__(256) void k_step_tiles_persistent(Dev D, float* __restrict__ f_out, float tau1,
+                                                               float tau2, int n_slots) {
+  __shared__ __align__(16) char lds[kTileLdsBytes];
+  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+    forward_tile<true, true>(D, slot, f_out, tau1, tau2, lds);
     __syncthreads();
   }
 }
@@ -940,7 +1022,7 @@ __device__ __forceinline__ void zero_partials(const Dev& D, int64_t c_lo, int64_
 // the pair arithmetic is the grid kernels' expression for expression.
 // ---------------------------------------------------------------------------
 
-// Each active sample tile's kernel list is cut into kSampSplit contiguous
+// Each active sample tile's kernel list is cut into samp_split contiguous
 // parts (in the backward, whole rounds of 256 kernels), one workgroup each.  Forward: the part's kernel records are staged
 // in LDS and every lane takes one sample of the tile, so a record serves
 // 256 samples; each (sample, part) sum goes to a scratch slot, and a second
@@ -956,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_sample_forward(Dev D) {
   const int s0 = L.sstart[slot - L.slot0], s1 = L.sstart[slot - L.slot0 + 1];
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
-  const int64_t part = (end - beg + kSampSplit - 1) / kSampSplit;
+  const int64_t part = (end - beg + D.samp_split - 1) / D.samp_split;
   const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
   const int64_t gbase = L.spos - D.samp_pos;   // this level's first entry of the sorted sample arrays
   for (int sb = s0; sb < s1; sb += 256) {
@@ -986,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_sample_forward(Dev D) {
       }
     }
     if (valid) {
-      const int64_t o = (gbase + si) * kSampSplit + blockIdx.y;
+      const int64_t o = (gbase + si) * kSampSplitMax + blockIdx.y;
       D.samp_f[o] = acc;
       D.samp_c[o] = cnt;
     }
@@ -1014,9 +1096,8 @@ __global__ __launch_bounds__(256) void k_sample_fwd_final(Dev D, float* __restri
   for (int si = s0 + tid; si < s1; si += 256) {
     float f = 0.f;
     int pf = 0;
-    const int64_t o = (gbase + si) * kSampSplit;
-#pragma unroll
-    for (int y = 0; y < kSampSplit; ++y) {
+    const int64_t o = (gbase + si) * kSampSplitMax;
+    for (int y = 0; y < D.samp_split; ++y) {
       f += D.samp_f[o + y];
       pf += D.samp_c[o + y];
     }
@@ -1061,13 +1142,13 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
   // parts of whole rounds of 256 kernels, so that every lane has one
-  const int64_t part = (((end - beg + kSampSplit - 1) / kSampSplit + 255) / 256) * 256;
+  const int64_t part = (((end - beg + D.samp_split - 1) / D.samp_split + 255) / 256) * 256;
   const int64_t rb = min(end, beg + part * blockIdx.y), re = min(end, rb + part);
   int nz = 0;
   for (int si = s0 + tid; si < s1; si += 256) nz |= Gsrc[L.pt_base + __float_as_int(L.spos[si].w)] != 0.f ? 1 : 0;
   if (!__syncthreads_or(nz)) {
     zero_partials(D, rb, re, tid, 256);
-    if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = 0;
+    if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplitMax + blockIdx.y] = 0;
     return;
   }
   int64_t pb = 0;
@@ -1127,15 +1208,15 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
   pb = wave_sum(pb);
   if (lane == 0) spb[wv] = pb;
   __syncthreads();
-  if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplit + blockIdx.y] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
+  if (tid == 0) D.samp_pb[(int64_t)blockIdx.x * kSampSplitMax + blockIdx.y] = (spb[0] + spb[1]) + (spb[2] + spb[3]);
 }
 
-// per sample tile: in-ball pairs with G != 0 of its kSampSplit waves
+// per sample tile: in-ball pairs with G != 0 of its samp_split workgroups
 __global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= D.n_samp_slots) return;
   int64_t t = 0;
-  for (int y = 0; y < kSampSplit; ++y) t += D.samp_pb[(int64_t)i * kSampSplit + y];
+  for (int y = 0; y < D.samp_split; ++y) t += D.samp_pb[(int64_t)i * kSampSplitMax + y];
   D.tile_pbwd[D.samp_slots[i]] = t;
 }
 
@@ -1154,117 +1235,22 @@ __global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
 // The moments of each (tile, kernel) entry go to `partials`.
 // ---------------------------------------------------------------------------
 
-// Four waves per workgroup share a tile's kernel groups of 64 (two or eight
-// waves measured slower on the 256^3 snapshot).
-constexpr int kBwdThreads = 256;
-constexpr int kBwdWaves = kBwdThreads / 64;
-constexpr int kBwdRounds = kTile * kTile * kTile / kBwdThreads;   // points per thread
+// (Four waves per workgroup share a tile's kernel groups of 64; two or eight
+// waves measured slower on the 256^3 snapshot.)
 
-__device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc) {
-  // non-zero points (x, G, G x', G x'^2), row by row: row r's points sit at
-  // spx[8 r ...], padded to an even count with an inert point (far away,
-  // G = 0) so that they are read two at a time
-  __shared__ float4 spx[kTile * kTile * kTile];
-  __shared__ float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
-  __shared__ int swr[kBwdRounds][kBwdWaves];
-  __shared__ int64_t spb[kBwdWaves];
-
-  const int2 lt = D.slot_tile[slot];
-  const LevelDev L = D.levels[lt.x];
-  if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_bwd
+// The walk over the staged rows, once the tile's R rows are in B: each wave
+// takes its own groups of 64 kernels of the list [beg, end) (waves past the
+// end of the list do no work); the first group's kernel of each lane (jf, ef,
+// record f0..f2) was read while the points were staged.
+__device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLds& B, const int R, const float xref,
+                                         const int64_t end, const int64_t cf, const int ef, const float4 f0,
+                                         const float4 f1, const float4 f2) {
   const int tid = threadIdx.x;
-  if (min((int64_t)D.tile_start[slot], D.pair_cap) == min((int64_t)D.tile_start[slot + 1], D.pair_cap)) {
-    // no kernel reaches the tile (or, in a mini-batch, no batch point is in it)
-    if (tid == 0) D.tile_pbwd[slot] = 0;
-    return;
-  }
-  const int n = L.n, nt = L.nt;
   const int lane = tid & 63, wv = tid >> 6;
-  const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
-  const float* __restrict__ G = Gsrc + L.pt_base;
-
-  // thread p = tid + kBwdThreads h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
-  // of the tile: eight consecutive lanes hold one row
-  const unsigned long long lt_mask = (1ull << lane) - 1ull;
-  const int rl = lane & ~7;                       // first lane of this lane's row
-  const float xref = L.axis[tx * kTile];         // x' = x - xref
-  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
-  // the kernel this lane owns in its wave's first group is read while the
-  // points are staged
-  const int64_t cf = beg + 64 * wv;
-  int jf = 0, ef = 0;
-  if (cf + lane < end) {
-    jf = D.items[cf + lane];
-    ef = D.tile_e[cf + lane];
-  }
-  bool row_used[kBwdRounds];
-  int row_cnt[kBwdRounds], row_pos[kBwdRounds];
-#pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
-    const int p = tid + kBwdThreads * h;
-    const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
-    float g = 0.f;
-    if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
-    const bool nz = g != 0.f;
-    const unsigned long long bal = __ballot(nz);
-    const unsigned row_bits = (unsigned)(bal >> rl) & 0xffu;
-    const int r = p >> 3;
-    if (nz) {
-      const float px = L.axis[xi], xo = px - xref, gx = g * xo;
-      spx[8 * r + __popc(row_bits & ((1u << (lane & 7)) - 1u))] = make_float4(px, g, gx, gx * xo);
-    }
-    const int c = __popc(row_bits);
-    row_cnt[h] = c;
-    row_used[h] = c > 0;
-    if ((lane & 7) == 0 && (c & 1)) spx[8 * r + c] = make_float4(1e30f, 0.f, 0.f, 0.f);
-    const unsigned long long rb = __ballot((lane & 7) == 0 && c > 0);
-    row_pos[h] = __popcll(rb & lt_mask);
-    if (lane == 0) swr[h][wv] = __popcll(rb);
-  }
-  float4 f0 = make_float4(0.f, 0.f, 0.f, -1.f), f1 = make_float4(0.f, 0.f, 0.f, 0.f),
-         f2 = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (cf + lane < end) {
-    f0 = D.rec[3 * jf];
-    f1 = D.rec[3 * jf + 1];
-    f2 = D.rec[3 * jf + 2];
-  }
-  __syncthreads();
-  int tot = 0;
-  int base_h[kBwdRounds];
-#pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
-    for (int v = 0; v < kBwdWaves; ++v) {
-      if (v == wv) base_h[h] = tot;
-      tot += swr[h][v];
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
-    if ((lane & 7) == 0 && row_used[h]) {
-      const int p = tid + kBwdThreads * h;
-      const int yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
-      srow[base_h[h] + row_pos[h]] =
-          make_float4(L.axis[yi], L.axis[zi], __int_as_float(8 * (p >> 3)), __int_as_float((row_cnt[h] + 1) & ~1));
-    }
-  }
-  // workgroup-uniform (all threads read the same LDS counts); readfirstlane
-  // makes that visible, so the early exit below is a scalar branch
-  const int R = __builtin_amdgcn_readfirstlane(tot);
-  if (R == 0) {
-    zero_partials(D, min((int64_t)D.tile_start[slot], D.pair_cap), min((int64_t)D.tile_start[slot + 1], D.pair_cap),
-                  tid, kBwdThreads);
-    if (tid == 0) D.tile_pbwd[slot] = 0;
-    return;
-  }
-  __syncthreads();
-
   int64_t pb = 0;   // in-ball pairs at non-zero points (wave-uniform)
-  // each wave takes its own groups of 64 kernels, so waves past the end of
-  // the list do no work
   for (int64_t c0 = cf; c0 < end; c0 += 64 * kBwdWaves) {
     const bool have = c0 + lane < end;
-    float4 r0 = f0, r1 = f1, r2 = f2;   // the first group's, read above
+    float4 r0 = f0, r1 = f1, r2 = f2;   // the first group's, read during staging
     int e_out = ef;
     if (c0 != cf) {
       r0 = make_float4(0.f, 0.f, 0.f, -1.f);
@@ -1286,7 +1272,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
     for (int i = 0; i < 10; ++i) T[i] = 0.f;
     uint32_t pbg = 0;
     for (int r = 0; r < R; ++r) {
-      const float4 RW = srow[r];
+      const float4 RW = B.srow[r];
       const int k0 = __builtin_amdgcn_readfirstlane(__float_as_int(RW.z));
       const int kn = __builtin_amdgcn_readfirstlane(__float_as_int(RW.w)) >> 1;
       const float dy = RW.x - cy;
@@ -1299,7 +1285,7 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
       for (int k = 0; k < kn; ++k) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const float4 PP = spx[k0 + 2 * k + u];
+          const float4 PP = B.spx[k0 + 2 * k + u];
           const float dx = PP.x - cx;
           const bool in = fmaf(dx, dx, syz) < rad2;
           float q = fmaf(dx, fmaf(A00, dx, bl), cc);
@@ -1325,24 +1311,197 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
       for (int i = 0; i < 5; ++i) o[i] = make_float2(T[2 * i], T[2 * i + 1]);
     }
   }
-  if (lane == 0) spb[wv] = pb;
+  if (lane == 0) B.spb[wv] = pb;
   __syncthreads();
   if (tid == 0) {
     int64_t t = 0;
-    for (int v = 0; v < kBwdWaves; ++v) t += spb[v];
+    for (int v = 0; v < kBwdWaves; ++v) t += B.spb[v];
     D.tile_pbwd[slot] = t;
   }
 }
 
+// The kernel each lane owns in its wave's first group of the list, read
+// while the points are staged.
+struct BwdFirst {
+  int64_t cf;
+  int ef;
+  float4 f0, f1, f2;
+};
+
+__device__ __forceinline__ BwdFirst bwd_first_group(const Dev& D, int64_t beg, int64_t end) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  BwdFirst F;
+  F.cf = beg + 64 * wv;
+  F.ef = 0;
+  F.f0 = make_float4(0.f, 0.f, 0.f, -1.f);
+  F.f1 = F.f2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (F.cf + lane < end) {
+    const int jf = D.items[F.cf + lane];
+    F.ef = D.tile_e[F.cf + lane];
+    F.f0 = D.rec[3 * jf];
+    F.f1 = D.rec[3 * jf + 1];
+    F.f2 = D.rec[3 * jf + 2];
+  }
+  return F;
+}
+
+__device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc, BwdLds& B) {
+  const int2 lt = D.slot_tile[slot];
+  const LevelDev L = D.levels[lt.x];
+  if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_bwd
+  const int tid = threadIdx.x;
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  if (beg == end) {
+    // no kernel reaches the tile (or, in a mini-batch, no batch point is in it)
+    if (tid == 0) D.tile_pbwd[slot] = 0;
+    return;
+  }
+  const int n = L.n, nt = L.nt;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
+  const float* __restrict__ G = Gsrc + L.pt_base;
+
+  // thread p = tid + kBwdThreads h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
+  // of the tile: eight consecutive lanes hold one row
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  const int rl = lane & ~7;                       // first lane of this lane's row
+  const float xref = L.axis[tx * kTile];         // x' = x - xref
+  const BwdFirst F = bwd_first_group(D, beg, end);
+  bool row_used[kBwdRounds];
+  int row_cnt[kBwdRounds], row_pos[kBwdRounds];
+#pragma unroll
+  for (int h = 0; h < kBwdRounds; ++h) {
+    const int p = tid + kBwdThreads * h;
+    const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
+    float g = 0.f;
+    if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
+    const bool nz = g != 0.f;
+    const unsigned long long bal = __ballot(nz);
+    const unsigned row_bits = (unsigned)(bal >> rl) & 0xffu;
+    const int r = p >> 3;
+    if (nz) {
+      const float px = L.axis[xi], xo = px - xref, gx = g * xo;
+      B.spx[8 * r + __popc(row_bits & ((1u << (lane & 7)) - 1u))] = make_float4(px, g, gx, gx * xo);
+    }
+    const int c = __popc(row_bits);
+    row_cnt[h] = c;
+    row_used[h] = c > 0;
+    if ((lane & 7) == 0 && (c & 1)) B.spx[8 * r + c] = make_float4(1e30f, 0.f, 0.f, 0.f);
+    const unsigned long long rb = __ballot((lane & 7) == 0 && c > 0);
+    row_pos[h] = __popcll(rb & lt_mask);
+    if (lane == 0) B.swr[h][wv] = __popcll(rb);
+  }
+  __syncthreads();
+  int tot = 0;
+  int base_h[kBwdRounds];
+#pragma unroll
+  for (int h = 0; h < kBwdRounds; ++h) {
+    for (int v = 0; v < kBwdWaves; ++v) {
+      if (v == wv) base_h[h] = tot;
+      tot += B.swr[h][v];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < kBwdRounds; ++h) {
+    if ((lane & 7) == 0 && row_used[h]) {
+      const int p = tid + kBwdThreads * h;
+      const int yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
+      B.srow[base_h[h] + row_pos[h]] =
+          make_float4(L.axis[yi], L.axis[zi], __int_as_float(8 * (p >> 3)), __int_as_float((row_cnt[h] + 1) & ~1));
+    }
+  }
+  // workgroup-uniform (all threads read the same LDS counts); readfirstlane
+  // makes that visible, so the early exit below is a scalar branch
+  const int R = __builtin_amdgcn_readfirstlane(tot);
+  if (R == 0) {
+    zero_partials(D, beg, end, tid, kBwdThreads);
+    if (tid == 0) D.tile_pbwd[slot] = 0;
+    return;
+  }
+  __syncthreads();
+  bwd_walk(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
+}
+
+// Staging from the forward's registers (the fused step kernel): thread
+// (wave w, lane l) holds the points x = 2 (l & 3) + {0, 1}, y = 4 (w & 1) +
+// ((l >> 2) & 3), z = 4 (w >> 1) + (l >> 4) of the tile, so the four lanes of
+// a quad hold one row (y, z).  Rows are numbered r = 8 z + y and placed in
+// ascending r, points in ascending x, exactly as bwd_tile places them.
+__device__ void bwd_stage_from_registers(const Dev& D, const LevelDev& L, int slot, int tx, int ty, int tz,
+                                         const float g[2], BwdLds& B, int64_t beg, int64_t end) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (beg == end) {
+    if (tid == 0) D.tile_pbwd[slot] = 0;
+    return;
+  }
+  const int n = L.n;
+  const float xref = L.axis[tx * kTile];
+  const BwdFirst F = bwd_first_group(D, beg, end);
+  const int q = lane & 3, qb = lane & ~3;
+  const int yl = 4 * (wv & 1) + ((lane >> 2) & 3), zl = 4 * (wv >> 1) + (lane >> 4);
+  const int r = 8 * zl + yl;
+  const bool nz0 = g[0] != 0.f, nz1 = g[1] != 0.f;
+  const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
+  const unsigned long long below = ((1ull << q) - 1ull) << qb, quad = 0xfull << qb;
+  const int pos0 = __popcll(b0 & below) + __popcll(b1 & below);
+  const int c = __popcll(b0 & quad) + __popcll(b1 & quad);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h ? nz1 : nz0) {
+      const int xi = tx * kTile + 2 * q + h;
+      const float px = L.axis[min(xi, n - 1)], xo = px - xref, gx = g[h] * xo;
+      B.spx[8 * r + pos0 + (h ? (nz0 ? 1 : 0) : 0)] = make_float4(px, g[h], gx, gx * xo);
+    }
+  }
+  if (q == 0 && (c & 1)) B.spx[8 * r + c] = make_float4(1e30f, 0.f, 0.f, 0.f);
+  // this wave's 16 rows in use (quad i of the wave is row bit i)
+  const unsigned long long lead = __ballot(q == 0 && c > 0);
+  if (lane == 0) {
+    uint32_t m = 0;
+    for (int i = 0; i < 16; ++i) m |= (uint32_t)((lead >> (4 * i)) & 1ull) << i;
+    B.wrows[wv] = m;
+  }
+  __syncthreads();
+  // the 64-bit mask of rows in use, bit r = 8 z + y
+  unsigned long long used = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t m = B.wrows[w];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int rr = 8 * (4 * (w >> 1) + (i >> 2)) + 4 * (w & 1) + (i & 3);
+      used |= (unsigned long long)((m >> i) & 1u) << rr;
+    }
+  }
+  if (q == 0 && c > 0) {
+    const int yi = ty * kTile + yl, zi = tz * kTile + zl;
+    B.srow[__popcll(used & ((1ull << r) - 1ull))] =
+        make_float4(L.axis[min(yi, n - 1)], L.axis[min(zi, n - 1)], __int_as_float(8 * r), __int_as_float((c + 1) & ~1));
+  }
+  const int R = __builtin_amdgcn_readfirstlane(__popcll(used));
+  if (R == 0) {
+    zero_partials(D, beg, end, tid, kBwdThreads);
+    if (tid == 0) D.tile_pbwd[slot] = 0;
+    return;
+  }
+  __syncthreads();
+  bwd_walk(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
+}
+
 __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_tiles(
-    Dev D, const float* __restrict__ Gsrc) {
-  bwd_tile(D, blockIdx.x, Gsrc);
+    Dev D, const float* __restrict__ Gsrc, int n_slots) {
+  __shared__ BwdLds B;
+  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  if (slot < 0) return;
+  bwd_tile(D, slot, Gsrc, B);
 }
 
 __global__ __launch_bounds__(kBwdThreads) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc,
                                                                        int n_slots) {
+  __shared__ BwdLds B;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    bwd_tile(D, slot, Gsrc);
+    bwd_tile(D, slot, Gsrc, B);
     __syncthreads();
   }
 }
@@ -1526,9 +1685,9 @@ __device__ __forceinline__ float block_max_256(float v, float* sh) {
 // BATCH: the forward part comes from the mini-batch records (n_pts of them)
 // instead of the tile statistics.
 template <int MODE, bool BATCH>
-__global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restrict__ p,
-                                                    const int32_t* __restrict__ m_dev,
-                                                    const float* __restrict__ grad, int n_pts) {
+__device__ __forceinline__ void stats_part_body(const Dev& D, const float* __restrict__ p,
+                                                const int32_t* __restrict__ m_dev, const float* __restrict__ grad,
+                                                int n_pts) {
   __shared__ double shd[4];
   __shared__ float shf[4];
   const int part = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
@@ -1595,10 +1754,19 @@ __global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restri
   if (tid == 0) D.stat_part[b * kStatParts + part] = sp;
 }
 
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(256) void k_stats_part(Dev D, const float* __restrict__ p,
+                                                    const int32_t* __restrict__ m_dev,
+                                                    const float* __restrict__ grad, int n_pts) {
+  stats_part_body<MODE, BATCH>(D, p, m_dev, grad, n_pts);
+}
+
+// One wave: the shape's slices in a fixed order, the weights of eq. 3-21 and
+// the statistics.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_stats_final(Dev D, const int32_t* __restrict__ m_dev,
-                                                    erbf_stats* __restrict__ out, StatsArgs a) {
-  const int b = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void stats_final_wave(const Dev& D, const int b, const int lane,
+                                                 const int32_t* __restrict__ m_dev, erbf_stats* __restrict__ out,
+                                                 const StatsArgs& a) {
   const ShapeDev S = D.shapes[b];
   const int m = min(max(m_dev[b], 0), S.cap);
   StatPart sp = {};
@@ -1641,6 +1809,37 @@ __global__ __launch_bounds__(64) void k_stats_final(Dev D, const int32_t* __rest
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(64) void k_stats_final(Dev D, const int32_t* __restrict__ m_dev,
+                                                    erbf_stats* __restrict__ out, StatsArgs a) {
+  stats_final_wave<MODE>(D, blockIdx.x, threadIdx.x, m_dev, out, a);
+}
+
+// The slices and the final in one launch: every block writes its slice,
+// then takes a ticket; the block holding the shape's last ticket has seen
+// every slice written (each block fences its slice before its ticket) and
+// forms the statistics and the weights in the same fixed order as
+// k_stats_final, then resets the ticket for the next call.
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(256) void k_stats_fused(Dev D, const float* __restrict__ p,
+                                                     const int32_t* __restrict__ m_dev,
+                                                     const float* __restrict__ grad, int n_pts,
+                                                     erbf_stats* __restrict__ out, StatsArgs a) {
+  __shared__ int last;
+  stats_part_body<MODE, BATCH>(D, p, m_dev, grad, n_pts);
+  const int b = blockIdx.y;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned t = atomicAdd(&D.tickets[b], 1u);
+    last = t == (unsigned)(kStatParts - 1);
+    if (last) __threadfence();
+  }
+  __syncthreads();
+  if (!last) return;
+  if (threadIdx.x < 64) stats_final_wave<MODE>(D, b, threadIdx.x, m_dev, out, a);
+  if (threadIdx.x == 0) D.tickets[b] = 0u;
+}
+
 // combine: alpha * dL2 + beta * sign(w) on w; alpha * dL2 on the rest
 __global__ __launch_bounds__(256) void k_stats_apply(Dev D, const float* __restrict__ p,
                                                      const int32_t* __restrict__ m_dev, float* __restrict__ grad) {
@@ -1664,33 +1863,60 @@ __global__ __launch_bounds__(256) void k_stats_apply(Dev D, const float* __restr
 // Adam
 // ---------------------------------------------------------------------------
 
-__global__ void k_step_inc(int32_t* step, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) step[i] += 1;
-}
-
+// Bias-corrected Adam over the packed parameters.  Each thread takes its
+// shape's step count t = step[b] + 1; the block holding the launch's last
+// ticket (every other block has read the counts by then) stores the
+// incremented counts and resets the ticket.  COMBINE: the gradient is the
+// L2 gradient as the backward left it, combined here with the step's loss
+// weights (alpha dL2 + beta sign(w) on w, alpha dL2 elsewhere, eq. 3-21) and
+// written back, so the loss call needs no pass of its own for it.
+template <bool COMBINE>
 __global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, const int32_t* __restrict__ m_dev,
-                                              const float* __restrict__ g, float* __restrict__ m1,
-                                              float* __restrict__ m2, const int32_t* __restrict__ step,
-                                              AdamArgs a) {
+                                              float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
+                                              int32_t* __restrict__ step, AdamArgs a) {
+  __shared__ int last;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int C = D.cap_total;
-  if (i >= (int64_t)11 * C) return;
-  const int j = (int)(i % C);
-  const int b = D.kshape[j];
-  const ShapeDev S = D.shapes[b];
-  if (j - S.kbase >= min(max(m_dev[b], 0), S.cap)) return;
-  const float lr = a.lr_dev ? a.lr_dev[b] : a.lr;
-  const int t = step[b];
-  const float gi = g[i];
-  const float mm = a.beta1 * m1[i] + (1.f - a.beta1) * gi;
-  const float vv = a.beta2 * m2[i] + (1.f - a.beta2) * gi * gi;
-  m1[i] = mm;
-  m2[i] = vv;
-  const float bc1 = 1.f - powf(a.beta1, (float)t);
-  const float bc2 = 1.f - powf(a.beta2, (float)t);
-  const float denom = sqrtf(vv) / sqrtf(bc2) + a.eps;
-  p[i] -= (lr / bc1) * mm / denom;
+  if (i < (int64_t)11 * C) {
+    const int j = (int)(i % C);
+    const int b = D.kshape[j];
+    const ShapeDev S = D.shapes[b];
+    if (j - S.kbase < min(max(m_dev[b], 0), S.cap)) {
+      const float lr = a.lr_dev ? a.lr_dev[b] : a.lr;
+      const int t = step[b] + 1;
+      float gi = g[i];
+      if (COMBINE) {
+        const double2 ab = D.stat_ab[b];
+        if (i < C) {
+          const float w = p[i];
+          const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
+          gi = (float)(ab.x * (double)gi + ab.y * sg);
+          g[i] = gi;
+        } else if (ab.x != 1.0) {
+          gi = (float)(ab.x * (double)gi);
+          g[i] = gi;
+        }
+      }
+      const float mm = a.beta1 * m1[i] + (1.f - a.beta1) * gi;
+      const float vv = a.beta2 * m2[i] + (1.f - a.beta2) * gi * gi;
+      m1[i] = mm;
+      m2[i] = vv;
+      const float bc1 = 1.f - powf(a.beta1, (float)t);
+      const float bc2 = 1.f - powf(a.beta2, (float)t);
+      const float denom = sqrtf(vv) / sqrtf(bc2) + a.eps;
+      p[i] -= (lr / bc1) * mm / denom;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned tk = atomicAdd(&D.tickets[D.n_shapes], 1u);
+    last = tk == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  for (int b = threadIdx.x; b < D.n_shapes; b += blockDim.x) step[b] += 1;
+  if (threadIdx.x == 0) D.tickets[D.n_shapes] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1909,6 +2135,13 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
   return hipGetLastError();
 }
 
+// grid of a one-workgroup-per-tile launch (padded for the XCD runs)
+static inline int tile_grid(const Dev& D, int n_slots) {
+  if (D.slot_chunk <= 0) return n_slots;
+  const int per = 8 * D.slot_chunk;
+  return (n_slots + per - 1) / per * per;
+}
+
 // Launch with start/stop events taken at the kernel's own start and end when
 // timing is requested, otherwise as an ordinary launch (graph-capturable).
 template <typename... Args>
@@ -1921,22 +2154,29 @@ inline void launch_timed(void (*kernel)(Args...), dim3 grid, dim3 block, hipStre
 }
 
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
-                          const hipEvent_t* ev, hipStream_t s) {
-  if (n_slots <= 0) return hipSuccess;
-  hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
-  if (D.variant & kVariantFwdPersistent) {
-    const int grid = std::min(n_slots, D.persistent_wgs);
-    if (loss)
-      launch_timed(k_forward_persistent<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
-    else
-      launch_timed(k_forward_persistent<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
-  } else if (loss) {
-    launch_timed(k_forward<true>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
-  } else {
-    launch_timed(k_forward<false>, dim3(n_slots), dim3(256), s, e0, e1, D, f_out, tau1, tau2);
+                          const hipEvent_t* ev, hipStream_t s, bool with_bwd) {
+  if (n_slots > 0) {
+    hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
+    const bool pers = (D.variant & kVariantFwdPersistent) != 0;
+    const int grid = pers ? std::min(n_slots, D.persistent_wgs) : tile_grid(D, n_slots);
+    if (with_bwd) {
+      if (pers)
+        launch_timed(k_step_tiles_persistent, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+      else
+        launch_timed(k_step_tiles, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+    } else if (pers) {
+      if (loss)
+        launch_timed(k_forward_persistent<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+      else
+        launch_timed(k_forward_persistent<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+    } else if (loss) {
+      launch_timed(k_forward<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+    } else {
+      launch_timed(k_forward<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+    }
   }
   if (D.n_samp_slots > 0) {
-    hipLaunchKernelGGL(k_sample_forward, dim3(D.n_samp_slots, kSampSplit), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_sample_forward, dim3(D.n_samp_slots, D.samp_split), dim3(256), 0, s, D);
     if (loss)
       hipLaunchKernelGGL(k_sample_fwd_final<true>, dim3(D.n_samp_slots), dim3(256), 0, s, D, f_out, tau1, tau2);
     else
@@ -1946,17 +2186,28 @@ hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, fl
 }
 
 hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
-                           const hipEvent_t* ev, hipStream_t s) {
-  if (n_slots > 0 && (D.variant & kVariantBwdPersistent)) {
+                           const hipEvent_t* ev, hipStream_t s, bool tiles_done) {
+  if (tiles_done) {
+    // the grid tiles' moments came with the forward (the fused step kernel):
+    // a zero-length interval for the backward-tile events
+    if (ev && ev[0]) {
+      const hipError_t e = hipEventRecord(ev[0], s);
+      if (e != hipSuccess) return e;
+    }
+    if (ev && ev[1]) {
+      const hipError_t e = hipEventRecord(ev[1], s);
+      if (e != hipSuccess) return e;
+    }
+  } else if (n_slots > 0 && (D.variant & kVariantBwdPersistent)) {
     const int grid = std::min(n_slots, D.persistent_wgs);
     launch_timed(k_bwd_tiles_persistent, dim3(grid), dim3(kBwdThreads), s, ev ? ev[0] : nullptr,
                  ev ? ev[1] : nullptr, D, G, n_slots);
   } else if (n_slots > 0) {
-    launch_timed(k_bwd_tiles, dim3(n_slots), dim3(kBwdThreads), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D,
-                 G);
+    launch_timed(k_bwd_tiles, dim3(tile_grid(D, n_slots)), dim3(kBwdThreads), s, ev ? ev[0] : nullptr,
+                 ev ? ev[1] : nullptr, D, G, n_slots);
   }
   if (D.n_samp_slots > 0) {
-    hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, kSampSplit), dim3(256), 0, s, D, G);
+    hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, D.samp_split), dim3(256), 0, s, D, G);
     hipLaunchKernelGGL(k_sample_bwd_sum, dim3(nblk(D.n_samp_slots, 64)), dim3(64), 0, s, D);
   }
   launch_timed(k_bwd_reduce, dim3(D.cap_total), dim3(64), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
@@ -1965,18 +2216,15 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
 }
 
 hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
-                        erbf_stats* out, const StatsArgs& a, hipStream_t s) {
+                        erbf_stats* out, const StatsArgs& a, hipStream_t s, bool apply) {
   const dim3 parts(kStatParts, D.n_shapes);
   if (mode == 0) {
-    hipLaunchKernelGGL((k_stats_part<0, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
-    hipLaunchKernelGGL(k_stats_final<0>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+    hipLaunchKernelGGL((k_stats_fused<0, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0, out, a);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_stats_part<1, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
-    hipLaunchKernelGGL(k_stats_final<1>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+    hipLaunchKernelGGL((k_stats_fused<1, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0, out, a);
   } else {
-    hipLaunchKernelGGL((k_stats_part<2, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0);
-    hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
-    hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
+    hipLaunchKernelGGL((k_stats_fused<2, false>), parts, dim3(256), 0, s, D, p, m_dev, grad, 0, out, a);
+    if (apply) hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
   }
   return hipGetLastError();
 }
@@ -1993,20 +2241,21 @@ hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int 
                              const StatsArgs& a, hipStream_t s) {
   if (n_pts > 0)
     hipLaunchKernelGGL(k_batch_forward, dim3(nblk(n_pts, 4)), dim3(256), 0, s, D, pts, n_pts, f_out, tau1, tau2);
-  hipError_t e = launch_backward(D, n_slots, p, D.G, grad, nullptr, s);
+  hipError_t e = launch_backward(D, n_slots, p, D.G, grad, nullptr, s, false);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stats_part<2, true>), dim3(kStatParts, D.n_shapes), dim3(256), 0, s, D, p, m_dev, grad,
-                     n_pts);
-  hipLaunchKernelGGL(k_stats_final<2>, dim3(D.n_shapes), dim3(64), 0, s, D, m_dev, out, a);
+  hipLaunchKernelGGL((k_stats_fused<2, true>), dim3(kStatParts, D.n_shapes), dim3(256), 0, s, D, p, m_dev, grad,
+                     n_pts, out, a);
   hipLaunchKernelGGL(k_stats_apply, dim3(nblk(D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, grad);
   return hipGetLastError();
 }
 
-hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, const float* g, float* m1, float* m2,
-                       int32_t* step, const AdamArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_inc, dim3(nblk(D.n_shapes, 256)), dim3(256), 0, s, step, D.n_shapes);
-  hipLaunchKernelGGL(k_adam, dim3(nblk((int64_t)11 * D.cap_total, 256)), dim3(256), 0, s, D, p, m_dev, g, m1,
-                     m2, step, a);
+hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, float* g, float* m1, float* m2,
+                       int32_t* step, const AdamArgs& a, bool combine, hipStream_t s) {
+  const dim3 grid(nblk((int64_t)11 * D.cap_total, 256));
+  if (combine)
+    hipLaunchKernelGGL(k_adam<true>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
+  else
+    hipLaunchKernelGGL(k_adam<false>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
   return hipGetLastError();
 }
 

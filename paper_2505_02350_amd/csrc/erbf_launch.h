@@ -29,14 +29,19 @@ hipError_t launch_scan(const int32_t* in, int n, int32_t* blocks, int32_t* out, 
 hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, int n_slots, hipStream_t s);
 // `ev` (optional): start/stop events of each launched kernel, recorded at
 // the kernel's own start and end (forward: 2 events; backward: 4).
+// with_bwd: the grid tiles' backward moments are formed by the same kernel
+// (the fused step kernel, for the loss); launch_backward then skips its tile
+// kernel (tiles_done).
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
-                          const hipEvent_t* ev, hipStream_t s);
+                          const hipEvent_t* ev, hipStream_t s, bool with_bwd = false);
 hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
-                           const hipEvent_t* ev, hipStream_t s);
+                           const hipEvent_t* ev, hipStream_t s, bool tiles_done = false);
+// mode 2 with apply = false leaves the L2 gradient in grad (the combine then
+// runs in launch_adam with combine = true)
 hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
-                        erbf_stats* out, const StatsArgs& a, hipStream_t s);
-hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, const float* g, float* m1, float* m2,
-                       int32_t* step, const AdamArgs& a, hipStream_t s);
+                        erbf_stats* out, const StatsArgs& a, hipStream_t s, bool apply = true);
+hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, float* g, float* m1, float* m2,
+                       int32_t* step, const AdamArgs& a, bool combine, hipStream_t s);
 hipError_t launch_mask_copy(const Dev& D, int li, int64_t npts, const float* src, hipStream_t s);
 hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);

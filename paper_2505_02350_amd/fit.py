@@ -134,11 +134,9 @@ class Fitter:
 
     def step(self, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False, lr=1e-3, lr_dev=None,
              tau1=0.9, tau2=1.1, tau_m=0.02, stream=None):
-        self.ctx.erbf_loss_grad(self.p, self.m_dev, mode=mode, lam=lam, lambda_dev=lambda_dev,
-                                l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m, grad_out=self.grad,
-                                stream=stream)
-        self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr=lr,
-                                lr_dev=lr_dev, stream=stream)
+        self.ctx.erbf_train_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, mode=mode, lam=lam,
+                                 lambda_dev=lambda_dev, l1_active=l1_active, tau1=tau1, tau2=tau2, tau_m=tau_m,
+                                 lr=lr, lr_dev=lr_dev, stream=stream)
 
     def capture(self, steps_per_graph: int = 1, **kw):
         """Capture `steps_per_graph` consecutive steps into one HIP graph

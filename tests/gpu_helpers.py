@@ -129,3 +129,70 @@ def rel_inf(a, b):
 
 def oracle_grads_dict(gr):
     return {"w": gr.w, "c": gr.c, "s": gr.s, "q": gr.q}
+
+
+def fd_check(prob, lv, u3, kk, pp, grad, h=1e-6):
+    """Check gradients of sum_i u_i f_i on grid level `lv` (u3: the upstream
+    as an (n, n, n) array) against FP64 central differences (step h), for the
+    (kernel, parameter) pairs (kk[i], pp[i]); parameter index in the packed
+    order w, cx, cy, cz, sx, sy, sz, q0..q3.  grad: (m, 11) gradients to check.
+
+    Only kernel j's term moves with its parameters, so each quotient is taken
+    on that kernel's own field over its index box with the cull radius doubled
+    (oracle.kernel_field), away from the cull boundary.  The checked gradient
+    sums the culled terms only: the terms between r and 2 r are the truncation
+    allowance, bounded as in the oracle's pins (every dropped pair has
+    |D R Delta| >= k_cull), per kernel from the sum of |u| over that shell.
+    Returns, per group, the largest (|g - fd| - allowance) / (the group's
+    largest |fd|); per group, the largest |g - (fd - shell)| / (that scale),
+    shell the oracle's analytic gradient of the terms between r and 2 r (the
+    allowance's exact value); and the largest allowance relative to |fd|."""
+    import dataclasses
+    from oracle import erbf as OE
+    P = np.asarray(prob.params, np.float64).reshape(11, prob.cap)
+    K = OE.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k, prob.weight_map, prob.orientation)
+    k2 = prob.cull_k ** 2
+    ek = math.exp(-k2)
+    fd, gv, allow, group, shells = [], [], [], [], []
+    shell_of = {}
+    for j, par in zip(kk, pp):
+        def obj(delta):
+            Q = P[:, j].copy()
+            Q[par] += delta
+            Kj = OE.make_kernels(Q[0:1], Q[None, 1:4], Q[None, 4:7], Q[None, 7:11], prob.cull_k, prob.weight_map,
+                                 prob.orientation)
+            (z0, z1, y0, y1, x0, x1), v = OE.kernel_field(lv, Kj, 0, radius_scale=2.0)
+            return float(np.sum(u3[z0:z1, y0:y1, x0:x1] * v))
+        fd.append((obj(h) - obj(-h)) / (2 * h))
+        gv.append(float(grad[j, par]))
+        Kj = OE.subset(K, [j])
+        (z0, z1, y0, y1, x0, x1), dx, dy, dz = OE._kernel_box(lv, Kj, 0, 4.0 * Kj.r2[0])
+        d2 = dx * dx + dy * dy + dz * dz
+        shell = float(np.sum(np.abs(u3[z0:z1, y0:y1, x0:x1]) * ((d2 >= Kj.r2[0]) & (d2 < 4.0 * Kj.r2[0]))))
+        a, dmax, dmin = abs(Kj.a[0]), Kj.d[0].max(), Kj.d[0].min()
+        if par == 0:
+            b = ek * shell * Kj.dadw[0]
+        elif par < 4:
+            b = 2 * a * dmax * prob.cull_k * ek * shell
+        elif par < 7:
+            b = 2 * a * k2 * ek * shell
+        else:
+            J = OE.quat_rot_jacobian(Kj.qhat[0:1])[0].reshape(4, 9)
+            b = np.linalg.norm(J, 2) * 2 * a * (dmax / dmin) * k2 * ek * shell / Kj.qn[0]
+        allow.append(b)
+        group.append(0 if par == 0 else (1 if par < 4 else (2 if par < 7 else 3)))
+        if j not in shell_of:
+            ge = OE.backward([lv], dataclasses.replace(Kj, r2=4.0 * Kj.r2), [u3.reshape(-1)])
+            gc = OE.backward([lv], Kj, [u3.reshape(-1)])
+            shell_of[j] = (np.concatenate([ge.w, ge.c[0], ge.s[0], ge.q[0]]) -
+                           np.concatenate([gc.w, gc.c[0], gc.s[0], gc.q[0]]))
+        shells.append(float(shell_of[j][par]))
+    fd, gv, allow, group, shells = map(np.asarray, (fd, gv, allow, group, shells))
+    worst, exact = {}, {}
+    for gi, name in enumerate(("w", "c", "s", "q")):
+        sel = group == gi
+        if sel.any():
+            scale = np.abs(fd[sel]).max()
+            worst[name] = float(((np.abs(gv[sel] - fd[sel]) - allow[sel]) / scale).max())
+            exact[name] = float((np.abs(gv[sel] - (fd[sel] - shells[sel])) / scale).max())
+    return worst, exact, float((allow / np.maximum(np.abs(fd), 1e-30)).max())

@@ -52,9 +52,10 @@ def _struct_sizes_from_c():
 #include <stddef.h>
 #include "erbf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(erbf_shape_desc), sizeof(erbf_config),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(erbf_shape_desc), sizeof(erbf_config),
          sizeof(erbf_level), sizeof(erbf_params), sizeof(erbf_loss_cfg), sizeof(erbf_stats),
-         sizeof(erbf_adam_cfg), sizeof(erbf_seed_cfg), offsetof(erbf_stats, P_fwd_total));
+         sizeof(erbf_adam_cfg), sizeof(erbf_seed_cfg), offsetof(erbf_stats, P_fwd_total),
+         sizeof(erbf_launch_cfg), offsetof(erbf_launch_cfg, samp_split));
   return 0;
 }
 '''
@@ -76,6 +77,7 @@ def test_struct_layouts_match_binding():
                                         L.SeedCfg)]
     assert sizes[:8] == mine
     assert sizes[8] == L.Stats.P_fwd_total.offset
+    assert sizes[9] == ctypes.sizeof(L.LaunchCfg) and sizes[10] == L.LaunchCfg.samp_split.offset
 
 
 def _cfg(L, shapes, pair_cap=1024, cull_k=3.0, wm=0):

@@ -21,7 +21,7 @@ import pytest
 import oracle as O
 from oracle import pool as oracle_pool
 import synth
-from gpu_helpers import TAU1, TAU2, TAU_M, GpuProblem, oracle_grads_dict, oracle_levels, record, rel_inf
+from gpu_helpers import TAU1, TAU2, TAU_M, GpuProblem, fd_check, oracle_grads_dict, oracle_levels, record, rel_inf
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -160,3 +160,58 @@ def test_diff_512_autograd_sampled_parity():
     assert e_f <= F_TOL
     for k in go:
         assert errs[k] <= G_TOL, (k, errs[k])
+
+    # FP64 central differences of sum_i u_i f_i for 1000 random (kernel,
+    # parameter) pairs (250 kernels, 4 parameters each), each on the kernel's own field with the cull radius
+    # doubled, against the GPU gradient within the truncation allowance of
+    # the terms between r and 2 r (see gpu_helpers.fd_check)
+    _say("diff: finite differences of 1000 parameters")
+    u3 = u.reshape(n, n, n)
+    kk = np.repeat(rng.choice(prob.m, 250, replace=False), 4)
+    pp = np.concatenate([rng.choice(11, 4, replace=False) for _ in range(250)])
+    gpu_all = np.concatenate([gg["w"][:, None], gg["c"], gg["s"], gg["q"]], axis=1)
+    worst, exact, max_allow = fd_check(prob, olv, u3, kk, pp, gpu_all)
+    record("diff_512_finite_differences", n_params=int(kk.size), worst_minus_allowance=worst,
+           worst_with_exact_shell=exact, max_allowance_rel=max_allow)
+    for name, e in exact.items():
+        assert e <= G_TOL, (name, e)
+    for name, e in worst.items():
+        assert e <= G_TOL, (name, e)
+
+
+def test_seed_at_large_snapshot_size():
+    """Algorithm 2 at the 256^3 snapshot's size (64^3 + 128^3 + band(256^3),
+    5.8 M training points, a third of them in id_all with a seeded residual):
+    top 1 % candidates (about 19 000), extreme points, the first 256 kernels,
+    against the oracle."""
+    torch = _torch()
+    prob = synth.make_large_snapshot()
+    prob.cap = prob.m + 256
+    prob.params = np.concatenate([prob.params.reshape(11, prob.m), np.zeros((11, 256), np.float32)],
+                                 axis=1).reshape(-1)
+    olv, t32, _ = oracle_levels(prob)
+    rng = np.random.default_rng(37)
+    E, ida = [], []
+    for lv in olv:
+        e = (np.round(rng.standard_normal(lv.npts) * 0.3, 2)).astype(np.float32)
+        ia = lv.act() & (rng.random(lv.npts) < 0.33)
+        E.append(np.where(ia, e, np.float32(0)).astype(np.float32))
+        ida.append(ia & (E[-1] != 0))
+    n_id = int(sum(i.sum() for i in ida))
+    tf = float(np.float32(0.01))
+    _say(f"seed at full size: {n_id} id_all points, oracle")
+    out = O.seed(olv, [e.astype(np.float64) for e in E], ida, top_frac=tf, k_new=256)
+    gp = GpuProblem(prob, t32, pair_cap=1 << 20)
+    resid = torch.from_numpy(np.concatenate(E)).to(gp.ctx.device)
+    _say("seed at full size: GPU")
+    n = gp.ctx.erbf_seed_from_error(gp.p, gp.m_dev, 0, resid, 1.0, n_id, top_frac=tf, k_new=256)
+    torch.cuda.synchronize()
+    P = gp.p.cpu().numpy().reshape(11, prob.cap)
+    new = P[:, prob.m:prob.m + n]
+    s_err = float(np.abs(new[4:7].T.astype(np.float64) - out.s).max() / max(1.0, np.abs(out.s).max()))
+    record("seed_large_snapshot", n_idall=n_id, n_candidates=out.n_candidates, n_added=n, s_rel_err=s_err)
+    assert n == out.index.size == 256
+    assert np.array_equal(new[0], out.w.astype(np.float32))
+    assert np.array_equal(new[1:4].T, out.c.astype(np.float32))
+    assert np.array_equal(new[7:11].T, out.q.astype(np.float32))
+    assert s_err <= 1e-6
