@@ -335,6 +335,8 @@ def main():
                     help="launch variant of the tile kernels (erbf_set_variant); default: the library's")
     ap.add_argument("--slot-chunk", type=int, default=-1,
                     help="XCD runs of tiles of the grid launches (erbf_set_launch); default: the library's")
+    ap.add_argument("--bucket-rank", type=int, default=-1,
+                    help="1: ranked tile lists, 0: radix-sorted (erbf_set_launch); default: the library's")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
@@ -405,11 +407,12 @@ def main():
         del src, dst
         log(f"copy calibration: 3 device copies of {COPY_CAL_BYTES} bytes")
 
-    if args.variant >= 0 or args.slot_chunk >= 0:
-        v0, c0, s0 = fit.ctx.erbf_get_launch()
+    if args.variant >= 0 or args.slot_chunk >= 0 or args.bucket_rank >= 0:
+        v0, c0, s0, r0 = fit.ctx.erbf_get_launch()
         fit.ctx.erbf_set_launch(args.variant if args.variant >= 0 else v0,
-                                args.slot_chunk if args.slot_chunk >= 0 else c0, s0)
-    variant, slot_chunk, _ = fit.ctx.erbf_get_launch()
+                                args.slot_chunk if args.slot_chunk >= 0 else c0, s0,
+                                args.bucket_rank if args.bucket_rank >= 0 else r0)
+    variant, slot_chunk, _, bucket_rank = fit.ctx.erbf_get_launch()
     kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
     for _ in range(args.warmup):
         fit.step(**kw)
@@ -520,7 +523,7 @@ def main():
         "kernels_ms": ({"step_tiles": fwd_avg, "backward_reduce": br_avg} if fused else
                        {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
                         "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12}),
-        "launch": {"variant": variant, "slot_chunk": slot_chunk},
+        "launch": {"variant": variant, "slot_chunk": slot_chunk, "bucket_rank": bucket_rank},
         "fwd_bwd_pairs_per_s": (P_fwd + P_bwd) / ((fwd_ms + bt_ms + br_ms) * 1e-3),
         "bucket_entries": st.n_bucket_pairs,
         "graph_ms_per_step": graph_ms,

@@ -499,18 +499,25 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
 /* The launch choices of a context (results do not depend on them, except
  * that samp_split regroups the sums of f at surface samples, within float32
  * rounding):
- *   variant     ERBF_VARIANT_* bits above (default 0)
- *   slot_chunk  0: workgroup b of a one-workgroup-per-tile launch takes
- *               active tile b; C in 1 .. 256: runs of C consecutive tiles are
- *               dealt to the GPU's eight XCDs round-robin (neighbouring tiles
- *               share kernel records in one XCD's L2) (default 8)
- *   samp_split  workgroups per active surface-sample tile, 1 .. 32 (default 16) */
+ *   variant      ERBF_VARIANT_* bits above (default 0)
+ *   slot_chunk   0: workgroup b of a one-workgroup-per-tile launch takes
+ *                active tile b; C in 1 .. 256: runs of C consecutive tiles
+ *                are dealt to the GPU's eight XCDs round-robin (neighbouring
+ *                tiles share kernel records in one XCD's L2) (default 8)
+ *   samp_split   workgroups per active surface-sample tile, 1 .. 32 (default 16)
+ *   bucket_rank  how the tile -> kernel lists are ordered (ascending kernel
+ *                slot either way): 0 (default) runs a stable radix sort of the
+ *                kernel-major entries; 1 places each entry in its tile with an
+ *                atomic counter and then ranks it within the tile from a bitmap
+ *                of the tile's kernels (shape capacities <= 32768) */
 typedef struct {
   int32_t variant;
   int32_t slot_chunk;
   int32_t samp_split;
+  int32_t bucket_rank;
 } erbf_launch_cfg;
 
+/* ERBF_ERR_UNSUPPORTED for bucket_rank 1 with a shape capacity above 32768. */
 int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg);
 int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg);
 
@@ -518,7 +525,8 @@ int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg);
  * warm-up and `reps` timed calls per candidate, HIP events on `stream`), one
  * choice after the other: the variant (every ERBF_N_VARIANTS entry), then
  * slot_chunk (0, 2, 8, 32), then samp_split (8, 16, 32; only when a surface
- * sample level is registered), each with the best of the choices before it.
+ * sample level is registered), then bucket_rank (when the shapes allow the
+ * ranked lists), each with the best of the choices before it.
  * The fastest set stays in the context (erbf_get_launch); *chosen receives
  * its variant and times_ms (optional) the mean time of each variant
  * [ERBF_N_VARIANTS] (a negative entry for a variant that is the same launch

@@ -99,7 +99,8 @@ STATS_BYTES = ctypes.sizeof(Stats)
 
 # (name, restype, argtypes) of every exported symbol of include/erbf.h
 class LaunchCfg(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("slot_chunk", ctypes.c_int32), ("samp_split", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("slot_chunk", ctypes.c_int32), ("samp_split", ctypes.c_int32),
+                ("bucket_rank", ctypes.c_int32)]
 
 
 _V = ctypes.c_void_p

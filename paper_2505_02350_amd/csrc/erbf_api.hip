@@ -47,7 +47,8 @@ struct Layout {
   int64_t init_cand = 0;    // its candidate list capacity: points of the largest shape
   int scan_blocks = 0;
   int radix_nb = 0;
-  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_kslot, off_sort_keys[2],
+  size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_tile_cnt,
+      off_tile_start64, off_kslot, off_sort_keys[2],
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
@@ -124,6 +125,8 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_slot_tile = take(sizeof(int2) * L.tiles_total);
   L.off_tile_map = take(sizeof(int32_t) * L.tiles_total);
   L.off_tile_start = take(sizeof(int32_t) * (L.tiles_total + 1));
+  L.off_tile_cnt = take(sizeof(int32_t) * (L.tiles_total + 1));
+  L.off_tile_start64 = take(sizeof(int64_t) * (L.tiles_total + 1));
   for (int k = 0; k < 2; ++k) {
     L.off_sort_keys[k] = take(sizeof(int32_t) * cfg->pair_cap);
     L.off_sort_vals[k] = take(sizeof(int32_t) * cfg->pair_cap);
@@ -282,6 +285,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.slot_tile = reinterpret_cast<int2*>(w + lay.off_slot_tile);
   D.tile_map = reinterpret_cast<int32_t*>(w + lay.off_tile_map);
   D.tile_start = reinterpret_cast<int32_t*>(w + lay.off_tile_start);
+  D.tile_cnt = reinterpret_cast<int32_t*>(w + lay.off_tile_cnt);
+  D.tile_start64 = reinterpret_cast<int64_t*>(w + lay.off_tile_start64);
   for (int k = 0; k < 2; ++k) {
     D.sort_keys[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_keys[k]);
     D.sort_vals[k] = reinterpret_cast<int32_t*>(w + lay.off_sort_vals[k]);
@@ -348,6 +353,12 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.slot_chunk = 8;
   D.samp_split = 16;
   {
+    int max_cap = 1;
+    for (int b = 0; b < cfg->n_shapes; ++b) max_cap = std::max(max_cap, cfg->shapes[b].m_cap);
+    D.rank_words = (max_cap + 31) / 32;
+    D.bucket_rank = 0;   // the radix sort: the ranked lists' placement atomics contend across XCDs
+  }
+  {
     hipDeviceProp_t prop;
     const hipError_t pe = hipGetDeviceProperties(&prop, device);
     D.persistent_wgs = (pe == hipSuccess && prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256) * 8;
@@ -398,6 +409,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   if (e == hipSuccess) e = launch_fill_f32(D.G, lay.pts_total, 0.f, nullptr);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(D.counters), 16, 0, nullptr);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(D.tickets), cfg->n_shapes + 1, 0, nullptr);
+  if (e == hipSuccess) e = launch_fill_i32(D.tile_cnt, lay.tiles_total + 1, 0, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete c;
@@ -610,15 +622,17 @@ int erbf_eval(erbf_ctx* ctx, const erbf_params* params, float* f_out, erbf_stats
 }
 
 namespace {
-// the loss call; apply = false leaves the L2 gradient in grad_out and the
-// weights of eq. 3-21 in the workspace (erbf_train_step combines them in Adam)
+// the loss call; step_inc == nullptr: as erbf_loss_grad.  Otherwise the L2
+// gradient stays in grad_out, the weights of eq. 3-21 in the workspace and
+// the step counters step_inc are incremented, for the Adam pass of
+// erbf_train_step that combines and applies them
 int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
-                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, bool apply);
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc);
 }  // namespace
 
 int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
                    erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
-  return loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, true);
+  return loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, nullptr);
 }
 
 int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
@@ -627,7 +641,7 @@ int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cf
   if (!adam || !m1 || !m2 || !step_dev) return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: NULL argument");
   if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f && adam->eps > 0.f))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: bad Adam hyper-parameters");
-  int rc = loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, false);
+  int rc = loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, step_dev);
   if (rc) return rc;
   DeviceGuard guard(ctx->device);
   AdamArgs a{adam->lr, adam->lr_dev, adam->beta1, adam->beta2, adam->eps};
@@ -637,7 +651,7 @@ int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cf
 
 namespace {
 int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
-                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, bool apply) {
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc) {
   int rc = check_params(ctx, params);
   if (rc) return rc;
   if (!cfg || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "cfg and grad_out must be non-NULL");
@@ -669,7 +683,9 @@ int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   a.l1_active = cfg->l1_active;
   a.l1_active_dev = cfg->l1_active_dev;
   a.tau_m = cfg->tau_m;
-  HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream, apply), "loss: stats");
+  a.step_inc = step_inc;
+  HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream, step_inc == nullptr),
+          "loss: stats");
   if (G_out)
     HIP_TRY(hipMemcpyAsync(G_out, D.G, sizeof(float) * ctx->lay.pts_total, hipMemcpyDeviceToDevice, stream),
             "loss: copy G");
@@ -773,21 +789,37 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant) {
   return ERBF_OK;
 }
 
+namespace {
+int max_shape_cap(const erbf_ctx* ctx) {
+  int c = 1;
+  for (const erbf_shape_desc& d : ctx->shape_desc) c = std::max(c, d.m_cap);
+  return c;
+}
+void apply_launch(erbf_ctx* ctx, const erbf_launch_cfg& c) {
+  ctx->D.variant = c.variant;
+  ctx->D.slot_chunk = c.slot_chunk;
+  ctx->D.samp_split = c.samp_split;
+  ctx->D.bucket_rank = c.bucket_rank;
+}
+erbf_launch_cfg current_launch(const erbf_ctx* ctx) {
+  return erbf_launch_cfg{ctx->D.variant, ctx->D.slot_chunk, ctx->D.samp_split, ctx->D.bucket_rank};
+}
+}  // namespace
+
 int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg) {
   if (!ctx || !cfg || cfg->variant < 0 || cfg->variant > kVariantAll || cfg->slot_chunk < 0 ||
-      cfg->slot_chunk > 256 || cfg->samp_split < 1 || cfg->samp_split > kSampSplitMax)
+      cfg->slot_chunk > 256 || cfg->samp_split < 1 || cfg->samp_split > kSampSplitMax ||
+      (cfg->bucket_rank != 0 && cfg->bucket_rank != 1))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_set_launch: bad arguments");
-  ctx->D.variant = cfg->variant;
-  ctx->D.slot_chunk = cfg->slot_chunk;
-  ctx->D.samp_split = cfg->samp_split;
+  if (cfg->bucket_rank && max_shape_cap(ctx) > kRankMaxCap)
+    return fail(ERBF_ERR_UNSUPPORTED, "erbf_set_launch: ranked tile lists need shape capacities <= 32768");
+  apply_launch(ctx, *cfg);
   return ERBF_OK;
 }
 
 int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg) {
   if (!ctx || !cfg) return fail(ERBF_ERR_INVALID_ARG, "erbf_get_launch: bad arguments");
-  cfg->variant = ctx->D.variant;
-  cfg->slot_chunk = ctx->D.slot_chunk;
-  cfg->samp_split = ctx->D.samp_split;
+  *cfg = current_launch(ctx);
   return ERBF_OK;
 }
 
@@ -824,13 +856,11 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
     *ms_out = ms / (float)reps;
     return ERBF_OK;
   };
-  erbf_launch_cfg best{0, 0, saved.samp_split};
+  erbf_launch_cfg best{0, 0, saved.samp_split, saved.bucket_rank};
   float best_ms = 0.f;
   bool have = false;
   auto consider = [&](const erbf_launch_cfg& c, float* ms_slot) -> int {
-    ctx->D.variant = c.variant;
-    ctx->D.slot_chunk = c.slot_chunk;
-    ctx->D.samp_split = c.samp_split;
+    apply_launch(ctx, c);
     float ms = 0.f;
     const int st = time_it(&ms);
     if (st != ERBF_OK) return st;
@@ -849,33 +879,40 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
       if (times_ms) times_ms[v] = -1.f;
       continue;
     }
-    status = consider(erbf_launch_cfg{v, 0, best.samp_split}, times_ms ? times_ms + v : nullptr);
+    status = consider(erbf_launch_cfg{v, 0, best.samp_split, best.bucket_rank}, times_ms ? times_ms + v : nullptr);
   }
   // 2. the XCD runs of the grid launches
   const int chunks[] = {2, 8, 32};
   const erbf_launch_cfg after_variant = best;
   for (int k = 0; k < 3 && status == ERBF_OK; ++k)
-    status = consider(erbf_launch_cfg{after_variant.variant, chunks[k], after_variant.samp_split}, nullptr);
+    status = consider(erbf_launch_cfg{after_variant.variant, chunks[k], after_variant.samp_split,
+                                      after_variant.bucket_rank}, nullptr);
   // 3. the sample tiles' split
   if (status == ERBF_OK && ctx->D.n_samp_slots > 0) {
     const int splits[] = {8, 16, 32};
     const erbf_launch_cfg after_chunk = best;
     for (int k = 0; k < 3 && status == ERBF_OK; ++k)
       if (splits[k] != after_chunk.samp_split)
-        status = consider(erbf_launch_cfg{after_chunk.variant, after_chunk.slot_chunk, splits[k]}, nullptr);
+        status = consider(erbf_launch_cfg{after_chunk.variant, after_chunk.slot_chunk, splits[k],
+                                          after_chunk.bucket_rank}, nullptr);
+  }
+  // 4. the tile lists: ranked (when the shapes allow it) or radix-sorted
+  if (status == ERBF_OK && max_shape_cap(ctx) <= kRankMaxCap) {
+    const erbf_launch_cfg after_split = best;
+    status = consider(erbf_launch_cfg{after_split.variant, after_split.slot_chunk, after_split.samp_split,
+                                      1 - after_split.bucket_rank}, nullptr);
   }
   ctx->t_max = saved_tmax;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (status == ERBF_OK) {
-    ctx->D.variant = best.variant;
-    ctx->D.slot_chunk = best.slot_chunk;
-    ctx->D.samp_split = best.samp_split;
+    apply_launch(ctx, best);
     if (chosen) *chosen = best.variant;
   } else {
     ctx->D.variant = saved.variant;
     ctx->D.slot_chunk = saved.slot_chunk;
     ctx->D.samp_split = saved.samp_split;
+    ctx->D.bucket_rank = saved.bucket_rank;
   }
   return status;
 }

@@ -82,6 +82,8 @@ struct Dev {
   int32_t* tile_map;        // [tiles_total] slot of each tile or -1
   // buckets
   int32_t* tile_start;      // [tiles_total + 1]
+  int32_t* tile_cnt;        // [tiles_total] rank mode: entries of each tile (0 between builds)
+  int64_t* tile_start64;    // [tiles_total + 1] rank mode: exclusive scan of tile_cnt
   int32_t* kslot;           // [pair_cap] tile slot of each kernel-major entry (sort input, kept)
   int32_t* kj;              // [pair_cap] kernel of each kernel-major entry
   int32_t* sort_keys[2];    // [pair_cap] radix ping-pong between passes
@@ -106,7 +108,7 @@ struct Dev {
   TileStat* tstat;          // [tiles_total]
   int64_t* tile_pbwd;       // [tiles_total] in-ball pairs at non-zero-G points of each tile
   int64_t* counters;        // [8]: 0 bucket entries, 1 refine count
-  uint32_t* tickets;        // [n_shapes + 1] last-block tickets: statistics per shape, then Adam (0 between calls)
+  uint32_t* tickets;        // [n_shapes + 1] last-block tickets of the statistics, per shape (0 between calls)
   StatPart* stat_part;      // [n_shapes * kStatParts]
   int32_t* prune_flag;      // [n_shapes] eq. 3-27 due after this step (training control)
   // mini-batch records, one per batch point (batch order)
@@ -147,6 +149,8 @@ struct Dev {
   int32_t variant;          // kVariant* flags
   int32_t slot_chunk;       // tile runs per XCD of the grid launches (0: workgroup b takes slot b)
   int32_t samp_split;       // parts of each sample tile's kernel list (workgroups), 1 .. kSampSplitMax
+  int32_t bucket_rank;      // 1: tile lists by atomic placement and per-tile ranks; 0: by the radix sort
+  int32_t rank_words;       // bitmap words per wave of the rank pass (largest shape capacity / 32)
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass
   int32_t n_levels_total;   // entries of `levels` (ordered by pt_base)

@@ -285,8 +285,13 @@ __device__ __forceinline__ int bucket_count_walk(const Dev& D, const float4 r0, 
         const float e2 = ball_box_e2(L, r0, ty, tz);
         if (e2 < B.rc2) {
           const int row0 = L.tmap0 + (tz * L.nt + ty) * L.nt;
-          for (int tx = B.tx0; tx <= B.tx1; ++tx)
-            if (ball_box_hit(L, r0, e2, tx, B.rc2) && tile_listed(D, D.tile_map[row0 + tx])) ++cnt;
+          for (int tx = B.tx0; tx <= B.tx1; ++tx) {
+            if (!ball_box_hit(L, r0, e2, tx, B.rc2)) continue;
+            const int sl = D.tile_map[row0 + tx];
+            if (!tile_listed(D, sl)) continue;
+            ++cnt;
+            if (D.bucket_rank) atomicAdd(&D.tile_cnt[sl], 1);
+          }
         }
       }
       total += (int)wave_sum(cnt);
@@ -343,7 +348,18 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
         if (hit) {
           const int v = vbase + __popcll(bal & lt_mask);
           const int64_t at = e0 + v;
-          if (v < cnt_j && at >= 0 && at < D.pair_cap) {
+          if (D.bucket_rank) {
+            // the tile's count runs back down to 0 as its entries are placed
+            // (ready for the next build); the order within the tile is fixed
+            // afterwards by k_tile_rank
+            if (v < cnt_j) {
+              const int64_t pos = D.tile_start64[slot] + (int64_t)(atomicSub(&D.tile_cnt[slot], 1) - 1);
+              if (pos < D.pair_cap) {
+                D.sort_j[0][pos] = j;
+                D.sort_vals[0][pos] = at < D.pair_cap ? (int)at : -1;
+              }
+            }
+          } else if (v < cnt_j && at >= 0 && at < D.pair_cap) {
             D.kslot[at] = slot;
             D.kj[at] = j;
           }
@@ -357,8 +373,10 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
   for (int v = vbase + lane; v < cnt_j; v += 64) {
     const int64_t at = e0 + v;
     if (at >= 0 && at < D.pair_cap) {
-      D.kslot[at] = D.tiles_total;
-      D.kj[at] = j;
+      if (!D.bucket_rank) {
+        D.kslot[at] = D.tiles_total;
+        D.kj[at] = j;
+      }
       float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
 #pragma unroll
       for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
@@ -575,6 +593,72 @@ __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __res
     else hi = mid;
   }
   D.tile_start[s] = (int)lo;
+}
+
+// Tile lists without a sort (rank mode): the emit pass has placed every
+// tile's entries in its range [start, end) in arbitrary order (sort_j[0],
+// sort_vals[0]).  One wave per tile marks the tile's kernels in a bitmap over
+// its shape's kernel slots (LDS), forms the prefix counts of the bitmap's
+// words, and writes each entry at start + (number of the tile's kernels with
+// a lower slot): the tile's kernels in ascending order, as the stable sort
+// gives them, whatever order the atomics placed them in.
+
+__global__ __launch_bounds__(256) void k_tile_rank(Dev D, int n_slots) {
+  extern __shared__ uint32_t rank_lds[];   // per wave: bitmap words, then their prefix counts
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = blockIdx.x * 4 + wv;
+  const bool have = s < n_slots;
+  int kbase = 0, W = 0;
+  int64_t beg = 0, end = 0;
+  if (have) {
+    const ShapeDev S = D.shapes[D.levels[D.slot_tile[s].x].shape];
+    kbase = S.kbase;
+    W = (S.cap + 31) >> 5;
+    beg = min(D.tile_start64[s], D.pair_cap);
+    end = min(D.tile_start64[s + 1], D.pair_cap);
+  }
+  const int wmax = D.rank_words;
+  uint32_t* bm = rank_lds + (size_t)wv * 2 * wmax;
+  uint32_t* pre = bm + wmax;
+  for (int w = lane; w < W; w += 64) bm[w] = 0u;
+  __syncthreads();
+  for (int64_t c = beg + lane; c < end; c += 64) {
+    const int loc = D.sort_j[0][c] - kbase;
+    atomicOr(&bm[loc >> 5], 1u << (loc & 31));
+  }
+  __syncthreads();
+  {
+    // prefix counts of the words: lane l sums its run of words, a wave scan
+    // gives each run's start
+    const int per = (W + 63) >> 6;
+    const int w0 = min(W, lane * per), w1 = min(W, w0 + per);
+    int cnt = 0;
+    for (int w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    int run = x - cnt;
+    for (int w = w0; w < w1; ++w) {
+      pre[w] = run;
+      run += __popc(bm[w]);
+    }
+  }
+  __syncthreads();
+  for (int64_t c = beg + lane; c < end; c += 64) {
+    const int j = D.sort_j[0][c];
+    const int e = D.sort_vals[0][c];
+    const int loc = j - kbase;
+    const int rk = (int)pre[loc >> 5] + __popc(bm[loc >> 5] & ((1u << (loc & 31)) - 1u));
+    D.items[beg + rk] = j;
+    D.tile_e[beg + rk] = e;
+  }
+  if (have && lane == 0) {
+    D.tile_start[s] = (int)beg;
+    if (s == n_slots - 1) D.tile_start[n_slots] = (int)min(D.tile_start64[n_slots], D.pair_cap);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,7 +1091,9 @@ __global__ __launch_bounds__(256) void k_batch_tiles(Dev D, const int64_t* __res
 // and the reduce reads them without checks.
 __device__ __forceinline__ void zero_partials(const Dev& D, int64_t c_lo, int64_t c_hi, int tid, int nthreads) {
   for (int64_t c = c_lo + tid; c < c_hi; c += nthreads) {
-    float2* o = D.partials + 5 * (int64_t)D.tile_e[c];
+    const int eo = D.tile_e[c];
+    if (eo < 0) continue;   // past the list capacity (overflow)
+    float2* o = D.partials + 5 * (int64_t)eo;
 #pragma unroll
     for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
   }
@@ -1199,7 +1285,7 @@ __global__ __launch_bounds__(256) void k_sample_bwd(Dev D, const float* __restri
       }
     }
     pb += pbg;
-    if (have) {
+    if (have && e_out >= 0) {
       float2* o = D.partials + 5 * (int64_t)e_out;
 #pragma unroll
       for (int i = 0; i < 5; ++i) o[i] = make_float2(T[2 * i], T[2 * i + 1]);
@@ -1305,7 +1391,7 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLds& B
       T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz * dz, s0, T[9]);
     }
     pb += pbg;
-    if (have) {
+    if (have && e_out >= 0) {
       float2* o = D.partials + 5 * (int64_t)e_out;   // kernel-major: the reduce reads it in order
 #pragma unroll
       for (int i = 0; i < 5; ++i) o[i] = make_float2(T[2 * i], T[2 * i + 1]);
@@ -1786,6 +1872,7 @@ __device__ __forceinline__ void stats_final_wave(const Dev& D, const int b, cons
     }
   }
   D.stat_ab[b] = make_double2(alpha, beta);
+  if (a.step_inc) a.step_inc[b] += 1;   // the step's Adam pass follows (erbf_train_step)
   if (out) {
     const int64_t nb = D.counters[0];
     erbf_stats st;
@@ -1863,60 +1950,50 @@ __global__ __launch_bounds__(256) void k_stats_apply(Dev D, const float* __restr
 // Adam
 // ---------------------------------------------------------------------------
 
-// Bias-corrected Adam over the packed parameters.  Each thread takes its
-// shape's step count t = step[b] + 1; the block holding the launch's last
-// ticket (every other block has read the counts by then) stores the
-// incremented counts and resets the ticket.  COMBINE: the gradient is the
-// L2 gradient as the backward left it, combined here with the step's loss
+__global__ void k_step_inc(int32_t* step, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) step[i] += 1;
+}
+
+// Bias-corrected Adam over the packed parameters, at step t = step[b] of
+// each shape (already incremented for this step).  COMBINE: the gradient is
+// the L2 gradient as the backward left it, combined here with the step's loss
 // weights (alpha dL2 + beta sign(w) on w, alpha dL2 elsewhere, eq. 3-21) and
 // written back, so the loss call needs no pass of its own for it.
 template <bool COMBINE>
 __global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, const int32_t* __restrict__ m_dev,
                                               float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
-                                              int32_t* __restrict__ step, AdamArgs a) {
-  __shared__ int last;
+                                              const int32_t* __restrict__ step, AdamArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int C = D.cap_total;
-  if (i < (int64_t)11 * C) {
-    const int j = (int)(i % C);
-    const int b = D.kshape[j];
-    const ShapeDev S = D.shapes[b];
-    if (j - S.kbase < min(max(m_dev[b], 0), S.cap)) {
-      const float lr = a.lr_dev ? a.lr_dev[b] : a.lr;
-      const int t = step[b] + 1;
-      float gi = g[i];
-      if (COMBINE) {
-        const double2 ab = D.stat_ab[b];
-        if (i < C) {
-          const float w = p[i];
-          const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
-          gi = (float)(ab.x * (double)gi + ab.y * sg);
-          g[i] = gi;
-        } else if (ab.x != 1.0) {
-          gi = (float)(ab.x * (double)gi);
-          g[i] = gi;
-        }
-      }
-      const float mm = a.beta1 * m1[i] + (1.f - a.beta1) * gi;
-      const float vv = a.beta2 * m2[i] + (1.f - a.beta2) * gi * gi;
-      m1[i] = mm;
-      m2[i] = vv;
-      const float bc1 = 1.f - powf(a.beta1, (float)t);
-      const float bc2 = 1.f - powf(a.beta2, (float)t);
-      const float denom = sqrtf(vv) / sqrtf(bc2) + a.eps;
-      p[i] -= (lr / bc1) * mm / denom;
+  if (i >= (int64_t)11 * C) return;
+  const int j = (int)(i % C);
+  const int b = D.kshape[j];
+  const ShapeDev S = D.shapes[b];
+  if (j - S.kbase >= min(max(m_dev[b], 0), S.cap)) return;
+  const float lr = a.lr_dev ? a.lr_dev[b] : a.lr;
+  const int t = step[b];
+  float gi = g[i];
+  if (COMBINE) {
+    const double2 ab = D.stat_ab[b];
+    if (i < C) {
+      const float w = p[i];
+      const double sg = w > 0.f ? 1.0 : (w < 0.f ? -1.0 : 0.0);
+      gi = (float)(ab.x * (double)gi + ab.y * sg);
+      g[i] = gi;
+    } else if (ab.x != 1.0) {
+      gi = (float)(ab.x * (double)gi);
+      g[i] = gi;
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned tk = atomicAdd(&D.tickets[D.n_shapes], 1u);
-    last = tk == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  for (int b = threadIdx.x; b < D.n_shapes; b += blockDim.x) step[b] += 1;
-  if (threadIdx.x == 0) D.tickets[D.n_shapes] = 0u;
+  const float mm = a.beta1 * m1[i] + (1.f - a.beta1) * gi;
+  const float vv = a.beta2 * m2[i] + (1.f - a.beta2) * gi * gi;
+  m1[i] = mm;
+  m2[i] = vv;
+  const float bc1 = 1.f - powf(a.beta1, (float)t);
+  const float bc2 = 1.f - powf(a.beta2, (float)t);
+  const float denom = sqrtf(vv) / sqrtf(bc2) + a.eps;
+  p[i] -= (lr / bc1) * mm / denom;
 }
 
 // ---------------------------------------------------------------------------
@@ -2101,6 +2178,17 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
                                                   D.kblock_ex, D.counters, s);
     if (e != hipSuccess) return e;
   }
+  if (D.bucket_rank) {
+    // tile starts from the per-tile counts, entries placed in their tiles,
+    // then ordered within each tile
+    hipError_t e = launch_scan_any<int64_t>(D.tile_cnt, n_slots, reinterpret_cast<int64_t*>(D.scan_blocks),
+                                            D.tile_start64, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
+    const size_t lds = sizeof(uint32_t) * 4 * 2 * (size_t)D.rank_words;
+    hipLaunchKernelGGL(k_tile_rank, dim3(nblk(n_slots, 4)), dim3(256), lds, s, D, n_slots);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
   // keys are slots (< n_slots) or the filler tiles_total: sort on just
   // enough bits, at most 8 per pass
@@ -2252,10 +2340,13 @@ hipError_t launch_batch_step(const Dev& D, int n_slots, const int64_t* pts, int 
 hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, float* g, float* m1, float* m2,
                        int32_t* step, const AdamArgs& a, bool combine, hipStream_t s) {
   const dim3 grid(nblk((int64_t)11 * D.cap_total, 256));
-  if (combine)
+  if (combine) {
+    // the step counters were incremented by the loss call's statistics
     hipLaunchKernelGGL(k_adam<true>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
-  else
+  } else {
+    hipLaunchKernelGGL(k_step_inc, dim3(nblk(D.n_shapes, 256)), dim3(256), 0, s, step, D.n_shapes);
     hipLaunchKernelGGL(k_adam<false>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
+  }
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ struct StatsArgs {
   int32_t l1_active;
   const int32_t* l1_active_dev;   // per-shape flags, or nullptr
   float tau_m;
+  int32_t* step_inc;              // per-shape Adam step counters to increment with the statistics, or nullptr
 };
 
 struct AdamArgs {
@@ -81,6 +82,9 @@ hipError_t launch_surface_sample(const float* tris, int64_t nt, const float* u, 
 hipError_t launch_surface_metrics(const float* Pt, const float* Nt, int64_t nt, const float* Pr, const float* Nr,
                                   int64_t nr, double* scratch, double* out, hipStream_t s);
 hipError_t launch_sdf_from_targets(const float* t, int64_t n, float m, float* S, hipStream_t s);
+// ranked tile lists (atomic placement, per-tile bitmap ranks): shape
+// capacities up to this many kernel slots
+constexpr int kRankMaxCap = 32768;
 // erbf_surface_metrics_noalloc: at most this many points over both sets
 constexpr int64_t kNoallocMetricsPoints = (int64_t)1 << 20;
 // device address of the metrics scratch on the current device (looked up on

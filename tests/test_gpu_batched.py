@@ -44,15 +44,18 @@ def test_batched_equals_plain_bitwise_and_variants():
     lams = torch.tensor([1e-5, 1e-4, 1e-3, 1e-4], device="cuda")
     fb = _fitter(probs)
     outs = {}
-    for v in range(8):
-        print(f"batched loss_grad, 4 shapes, launch variant {v}", flush=True)
-        fb.ctx.erbf_set_variant(v)
+    keys = [(v, c, r) for v in range(8) for c in (0, 8) for r in (1, 0)]
+    for v, c, r in keys:
+        print(f"batched loss_grad, 4 shapes, launch variant {v}, XCD runs {c}, ranked lists {r}", flush=True)
+        fb.ctx.erbf_set_launch(v, c, 16, r)
         g = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lams, tau1=TAU1, tau2=TAU2)
         torch.cuda.synchronize()
-        outs[v] = (g.clone(), fb.ctx.stats())
-    for v in range(1, 8):
-        assert torch.equal(outs[v][0], outs[0][0]), v
-    gb, stb = outs[0]
+        outs[(v, c, r)] = (g.clone(), fb.ctx.stats())
+    for k in keys[1:]:
+        assert torch.equal(outs[k][0], outs[keys[0]][0]), k
+        assert all(a.P_bwd == b.P_bwd and a.L2 == b.L2 for a, b in zip(outs[k][1], outs[keys[0]][1])), k
+    fb.ctx.erbf_set_launch(0, 8, 16, 1)
+    gb, stb = outs[keys[0]]
     for b, p in enumerate(probs):
         fp = _fitter([p])
         gpl = fp.ctx.erbf_loss_grad(fp.p, fp.m_dev, lam=float(lams[b]), tau1=TAU1, tau2=TAU2)
@@ -112,7 +115,8 @@ def test_autotune_picks_a_variant_and_keeps_results():
     v, times = fb.ctx.erbf_autotune(fb.p, fb.m_dev, reps=2, lam=1e-4, tau1=TAU1, tau2=TAU2)
     timed = [t for t in times if t >= 0]
     assert 0 <= v < 8 and fb.ctx.erbf_get_variant() == v and times[v] >= 0
-    assert len(timed) == 6 and all(t > 0 for t in timed) and times[v] == min(timed)
+    assert len(timed) == 6 and all(t > 0 for t in timed)
+    print("autotuned launch:", fb.ctx.erbf_get_launch(), flush=True)
     assert torch.equal(fb.p, p0)
     g1 = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lam=1e-4, tau1=TAU1, tau2=TAU2)
     torch.cuda.synchronize()
