@@ -14,6 +14,7 @@ Prints one JSON line.  `value` is whole-step pair throughput,
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -317,6 +318,140 @@ def surface_bench(n_samples=100000, with_cpu=True):
     return out
 
 
+def autograd_steps(fit, steps):
+    """Steps through the differentiable field (forward erbf_eval, backward
+    erbf_vjp recomputing the responses) with a squared-residual loss on the
+    first level's targets and torch's Adam; ms per step."""
+    import torch
+    from paper_2505_02350_amd.autograd import ERBFLayer
+    layer = ERBFLayer(fit.ctx, fit.p, fit.m_dev)
+    t = fit._levels[0][1]
+    opt = torch.optim.Adam(layer.parameters(), lr=1e-4)
+    for i in range(steps + 2):
+        if i == 2:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        opt.zero_grad(set_to_none=False)
+        f = layer()
+        loss = ((f[:t.numel()] - t) ** 2).sum()
+        loss.backward()
+        opt.step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    log(f"autograd layer: {ms:.3f} ms per step, loss {float(loss):.4g}")
+    return {"steps": steps, "ms_per_step": ms, "loss_last": float(loss)}
+
+
+def e2e_bench(name):
+    """One spec configuration run end to end: the whole training loop
+    on the device (the fixed-weight loop of the tiny config; Algorithm 3's
+    control with eq. 3-21, pruning, kernel addition and level appends for
+    mid, large and diff; 200 batched steps against 64 sequential plain fits
+    for batching), then Section 4's HD / CD / CS of the result against the
+    ground-truth zero set on the finest grid level (10^5 samples each)."""
+    import torch
+    import synth
+    from paper_2505_02350_amd import _lib as L
+    from paper_2505_02350_amd import core
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    tau = dict(tau1=float(np.float32(0.9)), tau2=float(np.float32(1.1)), tau_m=float(np.float32(0.02)))
+    t_gen = time.perf_counter()
+    if name == "batching":
+        probs = synth.make_batching()
+        log(f"{name}: workload generated in {time.perf_counter() - t_gen:.1f} s")
+        shapes = [ShapeInput.from_problem(p) for p in probs]
+        lams = torch.tensor([p.lam for p in probs], dtype=torch.float32)
+        fb = Fitter(shapes, cull_k=3.0)
+        kw = dict(mode=L.MODE_FIXED, lr=1e-3, **tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            fb.step(lambda_dev=lams.to(fb.dev), **kw)
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t0
+        L2b = [st.L2 for st in fb.stats()]
+        del fb
+        torch.cuda.empty_cache()
+        wall_p, L2p = 0.0, []
+        for b, sh in enumerate(shapes):
+            f = Fitter([sh], cull_k=3.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(200):
+                f.step(lam=float(lams[b]), **kw)
+            torch.cuda.synchronize()
+            wall_p += time.perf_counter() - t0
+            L2p.append(f.stats()[0].L2)
+            del f
+        rel = max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(L2b, L2p))
+        log(f"{name}: 200 steps batched {wall_b:.2f} s, 64 plain fits {wall_p:.2f} s, final L2 rel diff {rel:.3g}")
+        return {"config": name, "steps": 200, "batched_s": wall_b, "plain_s": wall_p, "speedup": wall_p / wall_b,
+                "final_L2_max_rel_diff": rel}
+    if name == "tiny":
+        prob = synth.make_tiny()
+    elif name == "mid":
+        prob = synth.make_mid()
+    elif name in ("large", "large-growth"):
+        prob = synth.make_large()
+    elif name == "diff":
+        prob = synth.make_diff()
+    else:
+        raise SystemExit(f"unknown e2e config {name}")
+    log(f"{name}: workload generated in {time.perf_counter() - t_gen:.1f} s")
+    shape = ShapeInput.from_problem(prob)
+    hier = name.startswith("large")
+    # list capacity for kernels of any scale the run may add (eq. 3-24 floors
+    # the scale at the finest grid spacing)
+    pair_cap = {"tiny": 1 << 20, "mid": 1 << 26, "diff": 1 << 27}.get(name, 1 << 26)
+    fit = Fitter([shape], cull_k=prob.cull_k, pair_cap=pair_cap, all_levels=not hier)
+    if hier:
+        fit.refine(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if name == "tiny":
+        steps = 100
+        for _ in range(steps):
+            fit.step(mode=L.MODE_FIXED, lam=prob.lam, lr=prob.lr, **tau)
+        torch.cuda.synchronize()
+        n_add = n_prune = 0
+    else:
+        steps = {"mid": 500, "diff": 2000}.get(name, 3000)
+        cfg = {"mid": core.sched_cfg(T_e=400, M_e=500, refine_epochs=()),
+               "diff": core.sched_cfg(T_e=1600, M_e=2000, refine_epochs=())}.get(
+            name, core.sched_cfg(T_e=2600, M_e=3000, refine_epochs=(1000, 2000)))
+        # large-growth: a growth round of 256 kernels from the top-1% residual
+        # points every 40 steps as well (1k -> 16k within the first 2600 steps)
+        add_every = 40 if name == "large-growth" else 0
+        def progress(i, row):
+            if (i + 1) % 250 == 0:
+                r = row[0]
+                log(f"{name}: step {i + 1}, L2 {r['L2']:.4g}, kernels {r['m']}, l1 {r['l1']}, "
+                    f"b_f {r['b_f']}, levels {fit.next_level[0]}")
+        _, lg = fit.fit_schedule(steps, cfg, top_frac=0.01, k_new=256, on_step=progress, add_every=add_every,
+                                 **tau)
+        n_add = sum(r[0]["n_added"] for r in lg)
+        n_prune = sum(r[0]["n_pruned"] for r in lg)
+    wall = time.perf_counter() - t0
+    st = fit.stats()[0]
+    m_final = int(fit.m_dev.item())
+    finest = len(prob.levels) - 1
+    t1 = time.perf_counter()
+    hd, cd, cs = fit.surface_metrics(0, finest, n_samples=100000, seed=1)
+    ms_eval = 1e3 * (time.perf_counter() - t1)
+    finite = math.isfinite(hd)
+    out = {"config": name, "steps": steps, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+           "final_L2": st.L2, "n_idall": st.n_idall, "kernels_initial": prob.m, "kernels_final": m_final,
+           "kernels_added": n_add, "kernels_pruned": n_prune, "overflow": bool(st.flags),
+           "pairs_last_step": st.P_fwd + st.P_bwd, "HD": hd if finite else None, "CD": cd if finite else None,
+           "CS": cs, "surface": "ok" if finite else "fitted field has no zero crossing",
+           "metrics_ms": ms_eval, "levels": [lv.n for lv in prob.levels]}
+    if name == "diff":
+        out["autograd"] = autograd_steps(fit, 20)
+    log(f"{name}: {steps} steps in {wall:.2f} s ({out['ms_per_step']:.3f} ms/step), L2 {st.L2:.4g}, kernels "
+        f"{prob.m} -> {m_final}, HD {hd:.4g} CD {cd:.4g} CS {cs:.4f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +466,8 @@ def main():
     ap.add_argument("--workload-cache", default="",
                     help="npz file of the generated timing workload: read if present, else written")
     ap.add_argument("--gen-only", action="store_true", help="generate (and cache) the workload, then exit")
+    ap.add_argument("--e2e", default="",
+                    help="run one configuration end to end (tiny, mid, large, diff, batching) and print its JSON")
     ap.add_argument("--variant", type=int, default=-1,
                     help="launch variant of the tile kernels (erbf_set_variant); default: the library's")
     ap.add_argument("--slot-chunk", type=int, default=-1,
@@ -350,6 +487,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    if args.e2e:
+        print(json.dumps(e2e_bench(args.e2e)), flush=True)
+        return
     import synth
     from synth import sdf as synth_sdf
 

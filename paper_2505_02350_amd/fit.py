@@ -162,48 +162,63 @@ class Fitter:
         return self.ctx.stats()
 
     def fit_schedule(self, steps: int, cfg=None, tau1: float = 0.9, tau2: float = 1.1, tau_m: float = 0.02,
-                     top_frac: float = 0.01, k_new: int = 256, min_abs_err: float = 0.0, stream=None):
+                     top_frac: float = 0.01, k_new: int = 256, min_abs_err: float = 0.0, stream=None,
+                     on_step=None, add_every: int = 0):
         """Algorithm 3 on every shape for `steps` full-batch steps.
 
         Each step: loss and gradient with eq. 3-21 gated by the device control
-        state, Adam with the state's learning rate, then the control itself
-        (pruning by eq. 3-27 happens there, on the device).  When the control
-        asks for new kernels (eq. add_activate) the shape is seeded from the
-        step's residual (Algorithm 2); when it asks for the next grid level,
-        the level is appended (eq. 3-16).  Returns the control state and a
-        per-step log of (L2, m, b_f, l1_active, n_added, n_pruned) per shape.
+        state and Adam with the state's learning rate (one erbf_train_step),
+        then the control itself (pruning by eq. 3-27 happens there, on the
+        device).  When the control asks for new kernels (eq. add_activate) the
+        shape is seeded from the step's residual (Algorithm 2) before the next
+        step; when it asks for the next grid level, the level is appended
+        (eq. 3-16).  The host waits once per step, for one copy of the
+        requests, counts and statistics.  Returns the control state and a
+        per-step log of (L2, m, b_f, l1_active, n_added, n_pruned) per shape;
+        ``on_step(i, row)``, when given, is called with each step's log row.
+        ``add_every`` > 0 also seeds every shape after each add_every-th step
+        (a fixed growth round, next to the control's own requests) until the
+        final phase.
         """
         cfg = cfg or core.sched_cfg()
         st = core.SchedState(self.ctx, cfg)
         self.ctx.erbf_sched_init(cfg, st, stream=stream)
         G = torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev)
+        n = len(self.shapes)
+        snap_h = torch.empty((7, n), dtype=torch.int32, pin_memory=True)
+        stats_h = torch.empty_like(self.ctx.stats_buf, device="cpu").pin_memory()
+        s_obj = stream if stream is not None else torch.cuda.current_stream(self.dev)
         log = []
         for _ in range(steps):
-            self.ctx.erbf_loss_grad(self.p, self.m_dev, mode=L.MODE_DYNAMIC, l1_active_dev=st.l1_active, tau1=tau1,
-                                    tau2=tau2, tau_m=tau_m, grad_out=self.grad, G_out=G, stream=stream)
-            self.ctx.erbf_adam_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev, lr_dev=st.lr,
-                                    stream=stream)
-            self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, stream=stream)
-            torch.cuda.synchronize(self.dev)
-            stats = self.ctx.stats()
-            add = st.add_request.cpu().tolist()
-            ref = st.refine_request.cpu().tolist()
-            m_now = self.m_dev.cpu().tolist()
+            with torch.cuda.stream(s_obj):
+                self.ctx.erbf_train_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev,
+                                         mode=L.MODE_DYNAMIC, l1_active_dev=st.l1_active, tau1=tau1, tau2=tau2,
+                                         tau_m=tau_m, lr_dev=st.lr, G_out=G, stream=stream)
+                self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, stream=stream)
+                snap = torch.stack([st.add_request, st.refine_request, self.m_dev, st.l1_active, st.b_f,
+                                    st.n_pruned, st.final_phase])
+                snap_h.copy_(snap, non_blocking=True)
+                stats_h.copy_(self.ctx.stats_buf, non_blocking=True)
+            s_obj.synchronize()
+            stats = core.parse_stats(stats_h, n)
+            add, ref, m_now, l1, b_f, n_pr, fin = (snap_h[i].tolist() for i in range(7))
+            grow = add_every > 0 and (len(log) + 1) % add_every == 0
             row = []
             for b, s in enumerate(self.shapes):
                 n_added = 0
                 room = s.cap - m_now[b]
-                if add[b] and room > 0 and stats[b].n_idall > 0:
+                if (add[b] or (grow and not fin[b])) and room > 0 and stats[b].n_idall > 0:
                     n_added = self.ctx.erbf_seed_from_error(self.p, self.m_dev, b, G, 0.5, stats[b].n_idall,
                                                             top_frac=top_frac, k_new=min(k_new, room),
                                                             min_abs_err=min_abs_err, m1=self.m1, m2=self.m2,
                                                             stream=stream)
                 if ref[b] and self.next_level[b] < len(s.level_ns):
                     self.refine(b)
-                row.append(dict(L2=stats[b].L2, m=m_now[b] + n_added, l1=bool(st.l1_active[b].item()),
-                                b_f=int(st.b_f[b].item()), n_added=n_added,
-                                n_pruned=int(st.n_pruned[b].item())))
+                row.append(dict(L2=stats[b].L2, m=m_now[b] + n_added, l1=bool(l1[b]), b_f=int(b_f[b]),
+                                n_added=n_added, n_pruned=int(n_pr[b])))
             log.append(row)
+            if on_step is not None:
+                on_step(len(log) - 1, row)
         return st, log
 
     def init_inscribed(self, b: int = 0, gamma: float = 1e-3, max_centres: int = 0, stream=None):
