@@ -90,13 +90,22 @@ def batching_bench(probs, steps, warmup):
 
     fb = Fitter(shapes, cull_k=3.0)
     lam_dev = torch.tensor(lams, dtype=torch.float32, device=fb.dev)
-    var_b, times_b = fb.ctx.erbf_autotune(fb.p, fb.m_dev, reps=1, lambda_dev=lam_dev)
+    fb.ctx.erbf_autotune(fb.p, fb.m_dev, reps=2, lambda_dev=lam_dev)
+    launch_b = fb.ctx.erbf_get_launch()
     # equal accuracy: the first step's gradients are bitwise those of the plain fits
     gb = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lam_dev).clone()
+    # the plain fits: one launch choice per grid-size class, tuned on the
+    # class's first shape and kept by every context of the class
+    per_class = {}
     plains = []
     for b, s in enumerate(shapes):
         f = Fitter([s], cull_k=3.0)
-        f.ctx.erbf_autotune(f.p, f.m_dev, reps=1, lam=lams[b])
+        cls = str(s.level_ns[0])
+        if cls not in per_class:
+            f.ctx.erbf_autotune(f.p, f.m_dev, reps=2, lam=lams[b])
+            per_class[cls] = f.ctx.erbf_get_launch()
+        else:
+            f.ctx.erbf_set_launch_dict(per_class[cls])
         g = f.ctx.erbf_loss_grad(f.p, f.m_dev, lam=lams[b])
         kb, cap = fb.ctx.kbase[b], s.cap
         same = torch.equal(gb.view(11, -1)[:, kb:kb + cap], g.view(11, -1)[:, :cap])
@@ -145,7 +154,8 @@ def batching_bench(probs, steps, warmup):
         "batched_pairs_per_s": thr_b,
         "plain_pairs_per_s": thr_p,
         "speedup": thr_b / thr_p,
-        "batched_variant": var_b,
+        "launch_batched": launch_b,
+        "launch_plain_per_grid_class": dict(sorted(per_class.items(), key=lambda kv: int(kv[0]))),
         "equal_accuracy": "first-step gradients bitwise equal to the plain fits",
     }
 
@@ -474,6 +484,10 @@ def main():
                     help="XCD runs of tiles of the grid launches (erbf_set_launch); default: the library's")
     ap.add_argument("--bucket-rank", type=int, default=-1,
                     help="1: ranked tile lists, 0: radix-sorted (erbf_set_launch); default: the library's")
+    ap.add_argument("--fwd-chunk", type=int, default=-1,
+                    help="kernel records staged per forward chunk: 64, 128 or 256; default: the library's")
+    ap.add_argument("--bwd-waves", type=int, default=-1,
+                    help="waves per backward tile workgroup: 2, 4 or 8; default: the library's")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
@@ -547,12 +561,15 @@ def main():
         del src, dst
         log(f"copy calibration: 3 device copies of {COPY_CAL_BYTES} bytes")
 
-    if args.variant >= 0 or args.slot_chunk >= 0 or args.bucket_rank >= 0:
-        v0, c0, s0, r0 = fit.ctx.erbf_get_launch()
-        fit.ctx.erbf_set_launch(args.variant if args.variant >= 0 else v0,
-                                args.slot_chunk if args.slot_chunk >= 0 else c0, s0,
-                                args.bucket_rank if args.bucket_rank >= 0 else r0)
-    variant, slot_chunk, _, bucket_rank = fit.ctx.erbf_get_launch()
+    launch = fit.ctx.erbf_get_launch()
+    for key, val in (("variant", args.variant), ("slot_chunk", args.slot_chunk),
+                     ("bucket_rank", args.bucket_rank), ("fwd_chunk", args.fwd_chunk),
+                     ("bwd_waves", args.bwd_waves)):
+        if val >= 0:
+            launch[key] = val
+    fit.ctx.erbf_set_launch_dict(launch)
+    launch = fit.ctx.erbf_get_launch()
+    variant = launch["variant"]
     kw = dict(mode=L.MODE_DYNAMIC, l1_active=True, lr=prob.lr)
     for _ in range(args.warmup):
         fit.step(**kw)
@@ -663,7 +680,7 @@ def main():
         "kernels_ms": ({"step_tiles": fwd_avg, "backward_reduce": br_avg} if fused else
                        {"forward": fwd_avg, "backward_tiles": bt_avg, "backward_reduce": br_avg,
                         "forward_tflops": fwd_rate / 1e12, "backward_tflops": bwd_rate / 1e12}),
-        "launch": {"variant": variant, "slot_chunk": slot_chunk, "bucket_rank": bucket_rank},
+        "launch": launch,
         "fwd_bwd_pairs_per_s": (P_fwd + P_bwd) / ((fwd_ms + bt_ms + br_ms) * 1e-3),
         "bucket_entries": st.n_bucket_pairs,
         "graph_ms_per_step": graph_ms,

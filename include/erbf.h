@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 4
+#define ERBF_ABI_VERSION 5
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -498,7 +498,7 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
 
 /* The launch choices of a context (results do not depend on them, except
  * that samp_split regroups the sums of f at surface samples, within float32
- * rounding):
+ * rounding; every other choice gives bit-identical results):
  *   variant      ERBF_VARIANT_* bits above (default 0)
  *   slot_chunk   0: workgroup b of a one-workgroup-per-tile launch takes
  *                active tile b; C in 1 .. 256: runs of C consecutive tiles
@@ -509,12 +509,20 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
  *                slot either way): 0 (default) runs a stable radix sort of the
  *                kernel-major entries; 1 places each entry in its tile with an
  *                atomic counter and then ranks it within the tile from a bitmap
- *                of the tile's kernels (shape capacities <= 32768) */
+ *                of the tile's kernels (shape capacities <= 32768)
+ *   fwd_chunk    kernel records a forward tile workgroup stages in LDS at a
+ *                time: 64, 128 or 256 (default 256; the fused variant always
+ *                uses 256)
+ *   bwd_waves    waves of a backward tile workgroup, each taking its own
+ *                groups of 64 kernels of the tile's list: 2, 4 or 8 (default
+ *                4; the fused variant always uses 4) */
 typedef struct {
   int32_t variant;
   int32_t slot_chunk;
   int32_t samp_split;
   int32_t bucket_rank;
+  int32_t fwd_chunk;
+  int32_t bwd_waves;
 } erbf_launch_cfg;
 
 /* ERBF_ERR_UNSUPPORTED for bucket_rank 1 with a shape capacity above 32768. */
@@ -524,9 +532,12 @@ int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg);
 /* Tune the context's launch choices for erbf_loss_grad by timing it (one
  * warm-up and `reps` timed calls per candidate, HIP events on `stream`), one
  * choice after the other: the variant (every ERBF_N_VARIANTS entry), then
- * slot_chunk (0, 2, 8, 32), then samp_split (8, 16, 32; only when a surface
- * sample level is registered), then bucket_rank (when the shapes allow the
- * ranked lists), each with the best of the choices before it.
+ * slot_chunk (0, 2, 8, 32), bwd_waves (2, 4, 8) and fwd_chunk (64, 128, 256)
+ * (both unless the fused variant won), samp_split (8, 16, 32; only when a
+ * surface sample level is registered) and
+ * bucket_rank (when the shapes allow the ranked lists), each with the best
+ * of the choices before it.  The choice is kept per context, so contexts
+ * holding shapes of different size classes are tuned apart.
  * The fastest set stays in the context (erbf_get_launch); *chosen receives
  * its variant and times_ms (optional) the mean time of each variant
  * [ERBF_N_VARIANTS] (a negative entry for a variant that is the same launch

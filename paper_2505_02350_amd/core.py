@@ -301,15 +301,21 @@ class Context:
         L.check(self.lib.erbf_get_variant(self.handle, ctypes.byref(v)))
         return v.value
 
-    def erbf_set_launch(self, variant: int, slot_chunk: int, samp_split: int, bucket_rank: int):
-        c = L.LaunchCfg(int(variant), int(slot_chunk), int(samp_split), int(bucket_rank))
+    def erbf_set_launch(self, variant: int, slot_chunk: int, samp_split: int, bucket_rank: int,
+                        fwd_chunk: int = 256, bwd_waves: int = 4):
+        c = L.LaunchCfg(int(variant), int(slot_chunk), int(samp_split), int(bucket_rank), int(fwd_chunk),
+                        int(bwd_waves))
         L.check(self.lib.erbf_set_launch(self.handle, ctypes.byref(c)))
 
     def erbf_get_launch(self):
-        """(variant, slot_chunk, samp_split, bucket_rank) of the context."""
+        """dict of the context's launch choices (erbf_launch_cfg's fields)."""
         c = L.LaunchCfg()
         L.check(self.lib.erbf_get_launch(self.handle, ctypes.byref(c)))
-        return c.variant, c.slot_chunk, c.samp_split, c.bucket_rank
+        return {f: getattr(c, f) for f, _ in L.LaunchCfg._fields_}
+
+    def erbf_set_launch_dict(self, d):
+        """Set the launch choices from a dict like erbf_get_launch's."""
+        self.erbf_set_launch(**d)
 
     def erbf_autotune(self, p, m_dev, reps=3, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None, l1_active=False,
                       tau1=0.9, tau2=1.1, tau_m=0.02, stream=None):

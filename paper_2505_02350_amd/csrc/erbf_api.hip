@@ -352,6 +352,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.variant = 0;
   D.slot_chunk = 8;
   D.samp_split = 16;
+  D.fwd_chunk = 256;
+  D.bwd_waves = 4;
   {
     int max_cap = 1;
     for (int b = 0; b < cfg->n_shapes; ++b) max_cap = std::max(max_cap, cfg->shapes[b].m_cap);
@@ -800,16 +802,30 @@ void apply_launch(erbf_ctx* ctx, const erbf_launch_cfg& c) {
   ctx->D.slot_chunk = c.slot_chunk;
   ctx->D.samp_split = c.samp_split;
   ctx->D.bucket_rank = c.bucket_rank;
+  ctx->D.fwd_chunk = c.fwd_chunk;
+  ctx->D.bwd_waves = c.bwd_waves;
 }
 erbf_launch_cfg current_launch(const erbf_ctx* ctx) {
-  return erbf_launch_cfg{ctx->D.variant, ctx->D.slot_chunk, ctx->D.samp_split, ctx->D.bucket_rank};
+  return erbf_launch_cfg{ctx->D.variant,     ctx->D.slot_chunk, ctx->D.samp_split,
+                         ctx->D.bucket_rank, ctx->D.fwd_chunk,  ctx->D.bwd_waves};
+}
+int32_t current_field(const erbf_launch_cfg& c, int field) {
+  const int32_t f[] = {c.variant, c.slot_chunk, c.samp_split, c.bucket_rank, c.fwd_chunk, c.bwd_waves};
+  return f[field];
+}
+erbf_launch_cfg with(erbf_launch_cfg c, int field, int32_t v) {
+  int32_t* f[] = {&c.variant, &c.slot_chunk, &c.samp_split, &c.bucket_rank, &c.fwd_chunk, &c.bwd_waves};
+  *f[field] = v;
+  return c;
 }
 }  // namespace
 
 int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg) {
   if (!ctx || !cfg || cfg->variant < 0 || cfg->variant > kVariantAll || cfg->slot_chunk < 0 ||
       cfg->slot_chunk > 256 || cfg->samp_split < 1 || cfg->samp_split > kSampSplitMax ||
-      (cfg->bucket_rank != 0 && cfg->bucket_rank != 1))
+      (cfg->bucket_rank != 0 && cfg->bucket_rank != 1) ||
+      (cfg->fwd_chunk != 64 && cfg->fwd_chunk != 128 && cfg->fwd_chunk != 256) ||
+      (cfg->bwd_waves != 2 && cfg->bwd_waves != 4 && cfg->bwd_waves != 8))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_set_launch: bad arguments");
   if (cfg->bucket_rank && max_shape_cap(ctx) > kRankMaxCap)
     return fail(ERBF_ERR_UNSUPPORTED, "erbf_set_launch: ranked tile lists need shape capacities <= 32768");
@@ -856,7 +872,7 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
     *ms_out = ms / (float)reps;
     return ERBF_OK;
   };
-  erbf_launch_cfg best{0, 0, saved.samp_split, saved.bucket_rank};
+  erbf_launch_cfg best{0, 0, saved.samp_split, saved.bucket_rank, saved.fwd_chunk, saved.bwd_waves};
   float best_ms = 0.f;
   bool have = false;
   auto consider = [&](const erbf_launch_cfg& c, float* ms_slot) -> int {
@@ -879,28 +895,30 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
       if (times_ms) times_ms[v] = -1.f;
       continue;
     }
-    status = consider(erbf_launch_cfg{v, 0, best.samp_split, best.bucket_rank}, times_ms ? times_ms + v : nullptr);
+    status = consider(with(best, 0, v), times_ms ? times_ms + v : nullptr);
   }
-  // 2. the XCD runs of the grid launches
-  const int chunks[] = {2, 8, 32};
-  const erbf_launch_cfg after_variant = best;
-  for (int k = 0; k < 3 && status == ERBF_OK; ++k)
-    status = consider(erbf_launch_cfg{after_variant.variant, chunks[k], after_variant.samp_split,
-                                      after_variant.bucket_rank}, nullptr);
-  // 3. the sample tiles' split
-  if (status == ERBF_OK && ctx->D.n_samp_slots > 0) {
-    const int splits[] = {8, 16, 32};
-    const erbf_launch_cfg after_chunk = best;
-    for (int k = 0; k < 3 && status == ERBF_OK; ++k)
-      if (splits[k] != after_chunk.samp_split)
-        status = consider(erbf_launch_cfg{after_chunk.variant, after_chunk.slot_chunk, splits[k],
-                                          after_chunk.bucket_rank}, nullptr);
-  }
-  // 4. the tile lists: ranked (when the shapes allow it) or radix-sorted
-  if (status == ERBF_OK && max_shape_cap(ctx) <= kRankMaxCap) {
-    const erbf_launch_cfg after_split = best;
-    status = consider(erbf_launch_cfg{after_split.variant, after_split.slot_chunk, after_split.samp_split,
-                                      1 - after_split.bucket_rank}, nullptr);
+  // then one choice at a time, each from the best set so far: (field, the
+  // values tried)
+  struct Axis {
+    int field, n, v[3];
+  };
+  const Axis axes[] = {
+      {1, 3, {2, 8, 32}},     // XCD runs of the grid launches
+      {5, 3, {2, 4, 8}},      // backward waves per tile
+      {4, 3, {64, 128, 256}}, // forward records staged per chunk
+      {2, 3, {8, 16, 32}},    // sample tiles' split
+      {3, 2, {0, 1}},         // ranked or radix-sorted tile lists
+  };
+  for (const Axis& a : axes) {
+    if (status != ERBF_OK) break;
+    if (a.field == 2 && ctx->D.n_samp_slots == 0) continue;
+    if (a.field == 3 && max_shape_cap(ctx) > kRankMaxCap) continue;
+    // the fused step kernel has its own chunk and waves
+    if ((a.field == 4 || a.field == 5) && (best.variant & kVariantFused)) continue;
+    const erbf_launch_cfg from = best;
+    const int32_t cur = current_field(from, a.field);
+    for (int k = 0; k < a.n && status == ERBF_OK; ++k)
+      if (a.v[k] != cur) status = consider(with(from, a.field, a.v[k]), nullptr);
   }
   ctx->t_max = saved_tmax;
   (void)hipEventDestroy(e0);
@@ -913,6 +931,8 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
     ctx->D.slot_chunk = saved.slot_chunk;
     ctx->D.samp_split = saved.samp_split;
     ctx->D.bucket_rank = saved.bucket_rank;
+    ctx->D.fwd_chunk = saved.fwd_chunk;
+    ctx->D.bwd_waves = saved.bwd_waves;
   }
   return status;
 }

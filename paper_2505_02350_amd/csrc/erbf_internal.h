@@ -150,6 +150,8 @@ struct Dev {
   int32_t slot_chunk;       // tile runs per XCD of the grid launches (0: workgroup b takes slot b)
   int32_t samp_split;       // parts of each sample tile's kernel list (workgroups), 1 .. kSampSplitMax
   int32_t bucket_rank;      // 1: tile lists by atomic placement and per-tile ranks; 0: by the radix sort
+  int32_t fwd_chunk;        // kernel records a forward tile workgroup stages at a time: 64, 128 or 256
+  int32_t bwd_waves;        // waves of a backward tile workgroup: 2, 4 or 8
   int32_t rank_words;       // bitmap words per wave of the rank pass (largest shape capacity / 32)
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass

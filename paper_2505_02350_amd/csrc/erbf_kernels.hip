@@ -719,12 +719,13 @@ __device__ __forceinline__ void fwd_eval_pair(const float4 U, const FwdRowTerms&
   pf += __popcll(__ballot(in0) & act_mask0) + __popcll(__ballot(in1) & act_mask1);
 }
 
-// LDS of the forward tile body
-struct FwdLds {
+// LDS of the forward tile body for chunks of C kernel records
+template <int C>
+struct FwdLdsT {
   // records of the chunk, plus an inert record (r^2 < 0, a = 0) at index
-  // kFwdChunk that pads each wave's list to a multiple of four
-  float4 srec[kFwdChunk * 3 + 3];
-  uint32_t slist[4][kFwdChunk + 4];
+  // C that pads each wave's list to a multiple of four
+  float4 srec[C * 3 + 3];
+  uint32_t slist[4][C + 4];
   int scnt[4][4];
   float sbox[4][6];
   double red_d[4];
@@ -732,22 +733,24 @@ struct FwdLds {
   int red_i[4];
   int64_t red_p[4];
 };
+using FwdLds = FwdLdsT<kFwdChunk>;
 
-// backward tile: a workgroup of four waves, 512 points (two per thread)
+// backward tile: a workgroup of W waves (2, 4 or 8; four in the fused step
+// kernel), 512 points (512 / (64 W) per thread)
 constexpr int kBwdThreads = 256;
-constexpr int kBwdWaves = kBwdThreads / 64;
-constexpr int kBwdRounds = kTile * kTile * kTile / kBwdThreads;   // points per thread
 
 // LDS of the backward tile body: the tile's points with a non-zero upstream
 // gradient (x, G, G x', G x'^2), row r's points at spx[8 r ...], padded to an
 // even count with an inert point (far away, G = 0), and the rows in use
-struct BwdLds {
+template <int W>
+struct BwdLdsT {
   float4 spx[kTile * kTile * kTile];
   float4 srow[kTile * kTile];   // (y, z, first point, point count) of the rows in use
-  int swr[kBwdRounds][kBwdWaves];
-  int64_t spb[kBwdWaves];
-  uint32_t wrows[kBwdWaves];    // fused staging: rows in use of each wave's 16 rows
+  int swr[kTile * kTile * kTile / (64 * W)][W];
+  int64_t spb[W];
+  uint32_t wrows[4];            // fused staging (four waves): rows in use of each wave's 16 rows
 };
+using BwdLds = BwdLdsT<4>;
 
 template <int N>
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -770,10 +773,10 @@ __device__ __forceinline__ int tile_slot(int b, int n, int chunk) {
 __device__ void bwd_stage_from_registers(const Dev& D, const LevelDev& L, int slot, int tx, int ty, int tz,
                                          const float g[2], BwdLds& B, int64_t beg, int64_t end);
 
-template <bool LOSS, bool BWD>
+template <bool LOSS, bool BWD, int C>
 __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float* __restrict__ f_out,
                                              float tau1, float tau2, char* lds) {
-  FwdLds& F = *reinterpret_cast<FwdLds*>(lds);
+  FwdLdsT<C>& F = *reinterpret_cast<FwdLdsT<C>*>(lds);
   float4* srec = F.srec;
   auto& slist = F.slist;
   auto& scnt = F.scnt;
@@ -830,10 +833,10 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   float acc0 = 0.f, acc1 = 0.f;
   const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
   const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
-  if (tid < 3) srec[3 * kFwdChunk + tid] = make_float4(0.f, 0.f, tid == 0 ? -1.f : 0.f, 0.f);
+  if (tid < 3) srec[3 * C + tid] = make_float4(0.f, 0.f, tid == 0 ? -1.f : 0.f, 0.f);
 
-  for (int64_t c0 = beg; c0 < end; c0 += kFwdChunk) {
-    const int cnt = (int)min((int64_t)kFwdChunk, end - c0);
+  for (int64_t c0 = beg; c0 < end; c0 += C) {
+    const int cnt = (int)min((int64_t)C, end - c0);
     uint32_t mybits = 0;
     if (tid < cnt) {
       const int j = D.items[c0 + tid];
@@ -872,7 +875,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
     const int len = __builtin_amdgcn_readfirstlane(scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3]);
     const int len4 = (len + 3) & ~3;
     // the wave pads its own list (entries [len, len4), written by no other wave)
-    if (lane < len4 - len) slist[wv][len + lane] = (uint32_t)(kFwdChunk * (int)sizeof(float4) * 3);
+    if (lane < len4 - len) slist[wv][len + lane] = (uint32_t)(C * (int)sizeof(float4) * 3);
     __syncthreads();
     const char* srec_b = reinterpret_cast<const char*>(srec);
     uint32_t pf = 0;
@@ -945,24 +948,24 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
 
 // one workgroup per tile (grid launch) ...  Eight waves per SIMD (at most 64
 // VGPRs) keep the exp / LDS latencies of the walk hidden.
-template <bool LOSS>
+template <bool LOSS, int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
-  __shared__ __align__(16) char lds[sizeof(FwdLds)];
+  __shared__ __align__(16) char lds[sizeof(FwdLdsT<C>)];
   const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
   if (slot < 0) return;
-  forward_tile<LOSS, false>(D, slot, f_out, tau1, tau2, lds);
+  forward_tile<LOSS, false, C>(D, slot, f_out, tau1, tau2, lds);
 }
 
 // ... or a persistent grid: each workgroup walks the tiles round-robin
 // (slot = blockIdx.x, blockIdx.x + gridDim.x, ...).  The walk depends only on
 // blockIdx and gridDim, so every branch of the loop is uniform and every
 // barrier inside the tile body is reached by the whole workgroup.
-template <bool LOSS>
+template <bool LOSS, int C>
 __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __restrict__ f_out, float tau1,
                                                             float tau2, int n_slots) {
-  __shared__ __align__(16) char lds[sizeof(FwdLds)];
+  __shared__ __align__(16) char lds[sizeof(FwdLdsT<C>)];
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    forward_tile<LOSS, false>(D, slot, f_out, tau1, tau2, lds);
+    forward_tile<LOSS, false, C>(D, slot, f_out, tau1, tau2, lds);
     __syncthreads();
   }
 }
@@ -975,14 +978,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ __align__(16) char lds[kTileLdsBytes];
   const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
   if (slot < 0) return;
-  forward_tile<true, true>(D, slot, f_out, tau1, tau2, lds);
+  forward_tile<true, true, kFwdChunk>(D, slot, f_out, tau1, tau2, lds);
 }
 
 __global__ __launch_bounds__(256) void k_step_tiles_persistent(Dev D, float* __restrict__ f_out, float tau1,
                                                                float tau2, int n_slots) {
   __shared__ __align__(16) char lds[kTileLdsBytes];
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    forward_tile<true, true>(D, slot, f_out, tau1, tau2, lds);
+    forward_tile<true, true, kFwdChunk>(D, slot, f_out, tau1, tau2, lds);
     __syncthreads();
   }
 }
@@ -1328,13 +1331,14 @@ __global__ __launch_bounds__(64) void k_sample_bwd_sum(Dev D) {
 // takes its own groups of 64 kernels of the list [beg, end) (waves past the
 // end of the list do no work); the first group's kernel of each lane (jf, ef,
 // record f0..f2) was read while the points were staged.
-__device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLds& B, const int R, const float xref,
+template <int W>
+__device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W>& B, const int R, const float xref,
                                          const int64_t end, const int64_t cf, const int ef, const float4 f0,
                                          const float4 f1, const float4 f2) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   int64_t pb = 0;   // in-ball pairs at non-zero points (wave-uniform)
-  for (int64_t c0 = cf; c0 < end; c0 += 64 * kBwdWaves) {
+  for (int64_t c0 = cf; c0 < end; c0 += 64 * W) {
     const bool have = c0 + lane < end;
     float4 r0 = f0, r1 = f1, r2 = f2;   // the first group's, read during staging
     int e_out = ef;
@@ -1401,7 +1405,7 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLds& B
   __syncthreads();
   if (tid == 0) {
     int64_t t = 0;
-    for (int v = 0; v < kBwdWaves; ++v) t += B.spb[v];
+    for (int v = 0; v < W; ++v) t += B.spb[v];
     D.tile_pbwd[slot] = t;
   }
 }
@@ -1431,7 +1435,9 @@ __device__ __forceinline__ BwdFirst bwd_first_group(const Dev& D, int64_t beg, i
   return F;
 }
 
-__device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc, BwdLds& B) {
+template <int W>
+__device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const float* __restrict__ Gsrc, BwdLdsT<W>& B) {
+  constexpr int kThreads = 64 * W, kRounds = kTile * kTile * kTile / kThreads;
   const int2 lt = D.slot_tile[slot];
   const LevelDev L = D.levels[lt.x];
   if (L.kind != kLevelGrid) return;   // sample tiles: k_sample_bwd
@@ -1448,17 +1454,17 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   const int tz = lt.y / (nt * nt), ty = (lt.y / nt) % nt, tx = lt.y % nt;
   const float* __restrict__ G = Gsrc + L.pt_base;
 
-  // thread p = tid + kBwdThreads h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
+  // thread p = tid + kThreads h holds point (x, y, z) = (p & 7, (p >> 3) & 7, p >> 6)
   // of the tile: eight consecutive lanes hold one row
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
   const int rl = lane & ~7;                       // first lane of this lane's row
   const float xref = L.axis[tx * kTile];         // x' = x - xref
   const BwdFirst F = bwd_first_group(D, beg, end);
-  bool row_used[kBwdRounds];
-  int row_cnt[kBwdRounds], row_pos[kBwdRounds];
+  bool row_used[kRounds];
+  int row_cnt[kRounds], row_pos[kRounds];
 #pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
-    const int p = tid + kBwdThreads * h;
+  for (int h = 0; h < kRounds; ++h) {
+    const int p = tid + kThreads * h;
     const int xi = tx * kTile + (p & 7), yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
     float g = 0.f;
     if (xi < n && yi < n && zi < n) g = G[((int64_t)zi * n + yi) * n + xi];
@@ -1480,18 +1486,18 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   }
   __syncthreads();
   int tot = 0;
-  int base_h[kBwdRounds];
+  int base_h[kRounds];
 #pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
-    for (int v = 0; v < kBwdWaves; ++v) {
+  for (int h = 0; h < kRounds; ++h) {
+    for (int v = 0; v < W; ++v) {
       if (v == wv) base_h[h] = tot;
       tot += B.swr[h][v];
     }
   }
 #pragma unroll
-  for (int h = 0; h < kBwdRounds; ++h) {
+  for (int h = 0; h < kRounds; ++h) {
     if ((lane & 7) == 0 && row_used[h]) {
-      const int p = tid + kBwdThreads * h;
+      const int p = tid + kThreads * h;
       const int yi = ty * kTile + ((p >> 3) & 7), zi = tz * kTile + (p >> 6);
       B.srow[base_h[h] + row_pos[h]] =
           make_float4(L.axis[yi], L.axis[zi], __int_as_float(8 * (p >> 3)), __int_as_float((row_cnt[h] + 1) & ~1));
@@ -1501,12 +1507,12 @@ __device__ __forceinline__ void bwd_tile(const Dev& D, const int slot, const flo
   // makes that visible, so the early exit below is a scalar branch
   const int R = __builtin_amdgcn_readfirstlane(tot);
   if (R == 0) {
-    zero_partials(D, beg, end, tid, kBwdThreads);
+    zero_partials(D, beg, end, tid, kThreads);
     if (tid == 0) D.tile_pbwd[slot] = 0;
     return;
   }
   __syncthreads();
-  bwd_walk(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
+  bwd_walk<W>(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
 }
 
 // Staging from the forward's registers (the fused step kernel): thread
@@ -1572,22 +1578,24 @@ __device__ void bwd_stage_from_registers(const Dev& D, const LevelDev& L, int sl
     return;
   }
   __syncthreads();
-  bwd_walk(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
+  bwd_walk<4>(D, slot, B, R, xref, end, F.cf, F.ef, F.f0, F.f1, F.f2);
 }
 
-__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_tiles(
+template <int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_tiles(
     Dev D, const float* __restrict__ Gsrc, int n_slots) {
-  __shared__ BwdLds B;
+  __shared__ BwdLdsT<W> B;
   const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
   if (slot < 0) return;
-  bwd_tile(D, slot, Gsrc, B);
+  bwd_tile<W>(D, slot, Gsrc, B);
 }
 
-__global__ __launch_bounds__(kBwdThreads) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc,
-                                                                       int n_slots) {
-  __shared__ BwdLds B;
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc,
+                                                                  int n_slots) {
+  __shared__ BwdLdsT<W> B;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    bwd_tile(D, slot, Gsrc, B);
+    bwd_tile<W>(D, slot, Gsrc, B);
     __syncthreads();
   }
 }
@@ -2252,15 +2260,17 @@ hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, fl
         launch_timed(k_step_tiles_persistent, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
       else
         launch_timed(k_step_tiles, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
-    } else if (pers) {
-      if (loss)
-        launch_timed(k_forward_persistent<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
-      else
-        launch_timed(k_forward_persistent<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
-    } else if (loss) {
-      launch_timed(k_forward<true>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
     } else {
-      launch_timed(k_forward<false>, dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1, tau2, n_slots);
+      // the chunk of kernel records staged at a time (64, 128 or 256)
+      using FwdKernel = void (*)(Dev, float*, float, float, int);
+      const int ci = D.fwd_chunk == 64 ? 0 : (D.fwd_chunk == 128 ? 1 : 2);
+      static const FwdKernel grid_k[2][3] = {{k_forward<false, 64>, k_forward<false, 128>, k_forward<false, 256>},
+                                             {k_forward<true, 64>, k_forward<true, 128>, k_forward<true, 256>}};
+      static const FwdKernel pers_k[2][3] = {
+          {k_forward_persistent<false, 64>, k_forward_persistent<false, 128>, k_forward_persistent<false, 256>},
+          {k_forward_persistent<true, 64>, k_forward_persistent<true, 128>, k_forward_persistent<true, 256>}};
+      launch_timed((pers ? pers_k : grid_k)[loss ? 1 : 0][ci], dim3(grid), dim3(256), s, e0, e1, D, f_out, tau1,
+                   tau2, n_slots);
     }
   }
   if (D.n_samp_slots > 0) {
@@ -2286,13 +2296,23 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
       const hipError_t e = hipEventRecord(ev[1], s);
       if (e != hipSuccess) return e;
     }
-  } else if (n_slots > 0 && (D.variant & kVariantBwdPersistent)) {
-    const int grid = std::min(n_slots, D.persistent_wgs);
-    launch_timed(k_bwd_tiles_persistent, dim3(grid), dim3(kBwdThreads), s, ev ? ev[0] : nullptr,
-                 ev ? ev[1] : nullptr, D, G, n_slots);
   } else if (n_slots > 0) {
-    launch_timed(k_bwd_tiles, dim3(tile_grid(D, n_slots)), dim3(kBwdThreads), s, ev ? ev[0] : nullptr,
-                 ev ? ev[1] : nullptr, D, G, n_slots);
+    // W waves per tile workgroup (2, 4 or 8)
+    using BwdKernel = void (*)(Dev, const float*, int);
+    const int wi = D.bwd_waves == 2 ? 0 : (D.bwd_waves == 8 ? 2 : 1);
+    static const BwdKernel grid_k[3] = {k_bwd_tiles<2>, k_bwd_tiles<4>, k_bwd_tiles<8>};
+    static const BwdKernel pers_k[3] = {k_bwd_tiles_persistent<2>, k_bwd_tiles_persistent<4>,
+                                        k_bwd_tiles_persistent<8>};
+    const int threads = 64 * (wi == 0 ? 2 : (wi == 2 ? 8 : 4));
+    if (D.variant & kVariantBwdPersistent) {
+      // the same number of resident waves whatever W
+      const int grid = std::min(n_slots, D.persistent_wgs * 256 / threads);
+      launch_timed(pers_k[wi], dim3(grid), dim3(threads), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G,
+                   n_slots);
+    } else {
+      launch_timed(grid_k[wi], dim3(tile_grid(D, n_slots)), dim3(threads), s, ev ? ev[0] : nullptr,
+                   ev ? ev[1] : nullptr, D, G, n_slots);
+    }
   }
   if (D.n_samp_slots > 0) {
     hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, D.samp_split), dim3(256), 0, s, D, G);

@@ -44,16 +44,19 @@ def test_batched_equals_plain_bitwise_and_variants():
     lams = torch.tensor([1e-5, 1e-4, 1e-3, 1e-4], device="cuda")
     fb = _fitter(probs)
     outs = {}
-    keys = [(v, c, r) for v in range(8) for c in (0, 8) for r in (1, 0)]
-    for v, c, r in keys:
-        print(f"batched loss_grad, 4 shapes, launch variant {v}, XCD runs {c}, ranked lists {r}", flush=True)
-        fb.ctx.erbf_set_launch(v, c, 16, r)
+    keys = [(v, c, r, 256, 4) for v in range(8) for c in (0, 8) for r in (1, 0)]
+    keys += [(v, 8, 0, ch, w) for v in (0, 3) for ch in (64, 128, 256) for w in (2, 4, 8)]
+    for v, c, r, ch, w in keys:
+        print(f"batched loss_grad, 4 shapes, launch variant {v}, XCD runs {c}, ranked lists {r}, "
+              f"forward chunk {ch}, backward waves {w}", flush=True)
+        fb.ctx.erbf_set_launch(v, c, 16, r, ch, w)
         g = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lams, tau1=TAU1, tau2=TAU2)
         torch.cuda.synchronize()
-        outs[(v, c, r)] = (g.clone(), fb.ctx.stats())
+        outs[(v, c, r, ch, w)] = (g.clone(), fb.ctx.stats())
     for k in keys[1:]:
         assert torch.equal(outs[k][0], outs[keys[0]][0]), k
-        assert all(a.P_bwd == b.P_bwd and a.L2 == b.L2 for a, b in zip(outs[k][1], outs[keys[0]][1])), k
+        assert all(a.P_bwd == b.P_bwd and a.P_fwd == b.P_fwd and a.L2 == b.L2
+                   for a, b in zip(outs[k][1], outs[keys[0]][1])), k
     fb.ctx.erbf_set_launch(0, 8, 16, 1)
     gb, stb = outs[keys[0]]
     for b, p in enumerate(probs):
@@ -116,7 +119,9 @@ def test_autotune_picks_a_variant_and_keeps_results():
     timed = [t for t in times if t >= 0]
     assert 0 <= v < 8 and fb.ctx.erbf_get_variant() == v and times[v] >= 0
     assert len(timed) == 6 and all(t > 0 for t in timed)
-    print("autotuned launch:", fb.ctx.erbf_get_launch(), flush=True)
+    launch = fb.ctx.erbf_get_launch()
+    print("autotuned launch:", launch, flush=True)
+    assert launch["variant"] == v and launch["fwd_chunk"] in (64, 128, 256) and launch["bwd_waves"] in (2, 4, 8)
     assert torch.equal(fb.p, p0)
     g1 = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lam=1e-4, tau1=TAU1, tau2=TAU2)
     torch.cuda.synchronize()
