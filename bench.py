@@ -455,6 +455,15 @@ def e2e_bench(name):
            "pairs_last_step": st.P_fwd + st.P_bwd, "HD": hd if finite else None, "CD": cd if finite else None,
            "CS": cs, "surface": "ok" if finite else "fitted field has no zero crossing",
            "metrics_ms": ms_eval, "levels": [lv.n for lv in prob.levels]}
+    if name != "tiny":
+        # the same step without the control and its one host wait per step:
+        # 100 plain steps from the final state, after the metrics
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(100):
+            fit.step(mode=L.MODE_DYNAMIC, lr=1e-5, **tau)
+        torch.cuda.synchronize()
+        out["ms_per_step_plain_final_state"] = 1e3 * (time.perf_counter() - t1) / 100
     if name == "diff":
         out["autograd"] = autograd_steps(fit, 20)
     log(f"{name}: {steps} steps in {wall:.2f} s ({out['ms_per_step']:.3f} ms/step), L2 {st.L2:.4g}, kernels "

@@ -447,16 +447,16 @@ class SchedState:
     """Device arrays of the training-control state of every shape of a
     context (see erbf_sched_state in include/erbf.h)."""
 
+    FLAG_ROWS = ("epoch", "l1_active", "final_phase", "add_request", "refine_request", "b_f", "n_pruned")
+
     def __init__(self, ctx: "Context", cfg):
         dev, n = ctx.device, ctx.n_shapes
         i32 = dict(dtype=torch.int32, device=dev)
-        self.epoch = torch.zeros(n, **i32)
-        self.l1_active = torch.zeros(n, **i32)
-        self.final_phase = torch.zeros(n, **i32)
-        self.add_request = torch.zeros(n, **i32)
-        self.refine_request = torch.zeros(n, **i32)
-        self.b_f = torch.zeros(n, **i32)
-        self.n_pruned = torch.zeros(n, **i32)
+        # the integer fields are rows of one block, so that a driver can read
+        # them all with one copy (rows in FLAG_ROWS order)
+        self.flags = torch.zeros((len(self.FLAG_ROWS), n), **i32)
+        for i, f in enumerate(self.FLAG_ROWS):
+            setattr(self, f, self.flags[i])
         self.lr = torch.zeros(n, dtype=torch.float32, device=dev)
         self.l2_ring = torch.zeros(n * cfg.k_l2, dtype=torch.float64, device=dev)
         self.bf_ring = torch.zeros(n * cfg.k_l1, **i32)

@@ -594,6 +594,7 @@ int erbf_refine_level(erbf_ctx* ctx, int32_t shape, const erbf_level* level, hip
   HIP_TRY(hipStreamSynchronize(stream), "refine: sync");
   L.slot0 = ctx->slots_used;
   L.n_slots = (int32_t)n_act;
+  L.dense = n_act == (int64_t)ntt ? 1 : 0;
   ctx->slots_used += (int32_t)n_act;
   sd.n_active += 1;
   if (sd.n_active == 1) sd.slot0 = L.slot0;

@@ -34,6 +34,7 @@ struct LevelDev {
   float lo, h;              // axis[0] and nominal spacing 2/n (used for index ranges only)
   float pad;                // tile boxes reach this far past their outer points (samples: the
                             // half cell, so the boxes tile space)
+  int32_t dense;            // grid levels whose every tile is active: tile t has slot slot0 + t
   int32_t kind;             // kLevelGrid or kLevelSamples
   int32_t n_samples;        // sample levels: samples registered
   const float* axis;

@@ -266,6 +266,12 @@ __device__ __forceinline__ bool ball_box(const LevelDev& L, const float4& r0, Ba
   return true;
 }
 
+// slot of tile t (index in the level's tile grid): arithmetic on a level
+// whose tiles are all active, the tile map otherwise
+__device__ __forceinline__ int tile_slot_of(const Dev& D, const LevelDev& L, int t) {
+  return L.dense ? L.slot0 + t : D.tile_map[L.tmap0 + t];
+}
+
 // Count walk: lanes own rows of tiles (y, z) and step along x, so a row's
 // y and z distances are formed once.
 __device__ __forceinline__ int bucket_count_walk(const Dev& D, const float4 r0, const int j, const int lane) {
@@ -284,10 +290,10 @@ __device__ __forceinline__ int bucket_count_walk(const Dev& D, const float4 r0, 
         const int qz = r / B.nty, ty = B.ty0 + (r - qz * B.nty), tz = B.tz0 + qz;
         const float e2 = ball_box_e2(L, r0, ty, tz);
         if (e2 < B.rc2) {
-          const int row0 = L.tmap0 + (tz * L.nt + ty) * L.nt;
+          const int row0 = (tz * L.nt + ty) * L.nt;
           for (int tx = B.tx0; tx <= B.tx1; ++tx) {
             if (!ball_box_hit(L, r0, e2, tx, B.rc2)) continue;
-            const int sl = D.tile_map[row0 + tx];
+            const int sl = tile_slot_of(D, L, row0 + tx);
             if (!tile_listed(D, sl)) continue;
             ++cnt;
             if (D.bucket_rank) atomicAdd(&D.tile_cnt[sl], 1);
@@ -339,7 +345,7 @@ __device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, cons
           const int tx = B.tx0 + qx, ty = B.ty0 + qy, tz = B.tz0 + qz;
           const float e2 = ball_box_e2(L, r0, ty, tz);
           if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2)) {
-            const int sl = D.tile_map[L.tmap0 + (tz * L.nt + ty) * L.nt + tx];
+            const int sl = tile_slot_of(D, L, (tz * L.nt + ty) * L.nt + tx);
             slot = tile_listed(D, sl) ? sl : -1;
           }
         }

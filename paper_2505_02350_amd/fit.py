@@ -185,9 +185,11 @@ class Fitter:
         self.ctx.erbf_sched_init(cfg, st, stream=stream)
         G = torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev)
         n = len(self.shapes)
-        snap_h = torch.empty((7, n), dtype=torch.int32, pin_memory=True)
+        rows = {f: i for i, f in enumerate(core.SchedState.FLAG_ROWS)}
+        snap_h = torch.empty(tuple(st.flags.shape), dtype=torch.int32, pin_memory=True)
         stats_h = torch.empty_like(self.ctx.stats_buf, device="cpu").pin_memory()
         s_obj = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        m_host = self.m_dev.cpu().tolist()
         log = []
         for _ in range(steps):
             with torch.cuda.stream(s_obj):
@@ -195,13 +197,15 @@ class Fitter:
                                          mode=L.MODE_DYNAMIC, l1_active_dev=st.l1_active, tau1=tau1, tau2=tau2,
                                          tau_m=tau_m, lr_dev=st.lr, G_out=G, stream=stream)
                 self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, stream=stream)
-                snap = torch.stack([st.add_request, st.refine_request, self.m_dev, st.l1_active, st.b_f,
-                                    st.n_pruned, st.final_phase])
-                snap_h.copy_(snap, non_blocking=True)
+                snap_h.copy_(st.flags, non_blocking=True)
                 stats_h.copy_(self.ctx.stats_buf, non_blocking=True)
             s_obj.synchronize()
             stats = core.parse_stats(stats_h, n)
-            add, ref, m_now, l1, b_f, n_pr, fin = (snap_h[i].tolist() for i in range(7))
+            add, ref, l1, b_f, n_pr, fin = (snap_h[rows[f]].tolist() for f in
+                                            ("add_request", "refine_request", "l1_active", "b_f", "n_pruned",
+                                             "final_phase"))
+            # the live counts follow from the pruning counts and the seeding
+            m_now = [m_host[b] - n_pr[b] for b in range(n)]
             grow = add_every > 0 and (len(log) + 1) % add_every == 0
             row = []
             for b, s in enumerate(self.shapes):
@@ -214,7 +218,8 @@ class Fitter:
                                                             stream=stream)
                 if ref[b] and self.next_level[b] < len(s.level_ns):
                     self.refine(b)
-                row.append(dict(L2=stats[b].L2, m=m_now[b] + n_added, l1=bool(l1[b]), b_f=int(b_f[b]),
+                m_host[b] = m_now[b] + n_added
+                row.append(dict(L2=stats[b].L2, m=m_host[b], l1=bool(l1[b]), b_f=int(b_f[b]),
                                 n_added=n_added, n_pruned=int(n_pr[b])))
             log.append(row)
             if on_step is not None:
