@@ -176,6 +176,11 @@ _POOL_ARGS = None
 DEFAULT_WORKERS = None
 
 
+def _pool_init(args):
+    global _POOL_ARGS
+    _POOL_ARGS = args
+
+
 def _pool_job(span):
     prims, a, k = _POOL_ARGS
     return _eval_slabs(prims, a, k, span[0], span[1])
@@ -187,9 +192,9 @@ def sample_sdf(prims: Sequence[Primitive], axis: np.ndarray, k: float = 0.05,
 
     Returns float32 of shape ``(n^3,)`` with x fastest.  Evaluation runs in
     float64 at the float32 grid coordinates, a few z-planes at a time; large
-    grids are split over forked worker processes (the result does not depend
-    on the split)."""
-    global _POOL_ARGS
+    grids are split over worker processes (the result does not depend
+    on the split).  The workers come from multiprocessing's fork server, so
+    none is a copy of a caller that has already used the GPU."""
     a = np.asarray(axis, dtype=np.float64)
     n = a.size
     if workers is None:
@@ -201,10 +206,6 @@ def sample_sdf(prims: Sequence[Primitive], axis: np.ndarray, k: float = 0.05,
     import multiprocessing as mp
     chunk = max(1, -(-n // (4 * workers)))
     spans = [(z, min(n, z + chunk)) for z in range(0, n, chunk)]
-    _POOL_ARGS = (prims, a, k)
-    try:
-        with mp.get_context("fork").Pool(workers) as pool:
-            parts = pool.map(_pool_job, spans)
-    finally:
-        _POOL_ARGS = None
+    with mp.get_context("forkserver").Pool(workers, initializer=_pool_init, initargs=((prims, a, k),)) as pool:
+        parts = pool.map(_pool_job, spans)
     return np.concatenate(parts)
