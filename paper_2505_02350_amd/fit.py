@@ -163,7 +163,7 @@ class Fitter:
 
     def fit_schedule(self, steps: int, cfg=None, tau1: float = 0.9, tau2: float = 1.1, tau_m: float = 0.02,
                      top_frac: float = 0.01, k_new: int = 256, min_abs_err: float = 0.0, stream=None,
-                     on_step=None, add_every: int = 0):
+                     on_step=None, add_every: int = 0, state=None):
         """Algorithm 3 on every shape for `steps` full-batch steps.
 
         Each step: loss and gradient with eq. 3-21 gated by the device control
@@ -178,11 +178,16 @@ class Fitter:
         ``on_step(i, row)``, when given, is called with each step's log row.
         ``add_every`` > 0 also seeds every shape after each add_every-th step
         (a fixed growth round, next to the control's own requests) until the
-        final phase.
+        final phase.  ``state``: a control state to continue from (one made
+        for this context and ``cfg``, e.g. restored by :meth:`load`); by
+        default a fresh one.
         """
         cfg = cfg or core.sched_cfg()
-        st = core.SchedState(self.ctx, cfg)
-        self.ctx.erbf_sched_init(cfg, st, stream=stream)
+        if state is None:
+            st = core.SchedState(self.ctx, cfg)
+            self.ctx.erbf_sched_init(cfg, st, stream=stream)
+        else:
+            st = state
         G = torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev)
         n = len(self.shapes)
         rows = {f: i for i, f in enumerate(core.SchedState.FLAG_ROWS)}
@@ -225,6 +230,46 @@ class Fitter:
             if on_step is not None:
                 on_step(len(log) - 1, row)
         return st, log
+
+    # ---- checkpoint / resume --------------------------------------------------
+    def save(self, path: str, sched: "core.SchedState" = None):
+        """Write the fit's state to an ``.npz`` file (no pickles): parameters,
+        Adam moments and step counters, live counts, registered levels per
+        shape and, when given, the training control's state.  Resuming with
+        :meth:`load` into a Fitter built from the same shapes continues the
+        fit bit for bit."""
+        torch.cuda.synchronize(self.dev)
+        arrs = {"p": self.p.cpu().numpy(), "m1": self.m1.cpu().numpy(), "m2": self.m2.cpu().numpy(),
+                "step": self.step_dev.cpu().numpy(), "m": self.m_dev.cpu().numpy(),
+                "levels": np.asarray(self.next_level, np.int32)}
+        if sched is not None:
+            for f, _ in L.SchedState._fields_:
+                arrs["sched_" + f] = getattr(sched, f).cpu().numpy()
+        np.savez(path, **arrs)
+
+    def load(self, path: str, sched: "core.SchedState" = None):
+        """Restore a state written by :meth:`save` (levels not yet registered
+        here are appended first; the shapes must be the ones it was saved
+        from)."""
+        z = np.load(path, allow_pickle=False)
+        levels = z["levels"].tolist()
+        if len(levels) != len(self.shapes):
+            raise ValueError("checkpoint holds a different number of shapes")
+        for b, want in enumerate(levels):
+            if self.next_level[b] > want:
+                raise ValueError("checkpoint has fewer registered levels than this fitter")
+            while self.next_level[b] < want:
+                self.refine(b)
+        for name, t in (("p", self.p), ("m1", self.m1), ("m2", self.m2), ("step", self.step_dev),
+                        ("m", self.m_dev)):
+            a = z[name]
+            if a.shape != tuple(t.shape):
+                raise ValueError(f"checkpoint field {name} has shape {a.shape}, expected {tuple(t.shape)}")
+            t.copy_(torch.from_numpy(a))
+        if sched is not None:
+            for f, _ in L.SchedState._fields_:
+                getattr(sched, f).copy_(torch.from_numpy(z["sched_" + f]))
+        torch.cuda.synchronize(self.dev)
 
     def init_inscribed(self, b: int = 0, gamma: float = 1e-3, max_centres: int = 0, stream=None):
         """Replace shape b's kernels by the inscribed-sphere initialisation
@@ -299,3 +344,15 @@ class Fitter:
                                         stream=stream)
                 log.append(self.ctx.stats()[0].L2)
         return log
+
+
+def jsonl_logger(path: str):
+    """An ``on_step`` callback for :meth:`Fitter.fit_schedule` that appends
+    each step's per-shape row (L2, kernel count, b_f, L1 flag, kernels added
+    and pruned) to a JSON-lines file."""
+    import json
+
+    def on_step(i, row):
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"step": i, "shapes": row}) + "\n")
+    return on_step

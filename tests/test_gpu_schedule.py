@@ -132,3 +132,46 @@ def test_scheduled_fit_takes_every_branch_and_is_deterministic():
     fit2, _, log2 = _scheduled_fit()
     assert torch.equal(fit.p, fit2.p) and torch.equal(fit.m_dev, fit2.m_dev)
     assert [r[0]["L2"] for r in log2] == [r["L2"] for r in rows]
+
+
+def test_checkpoint_resume_continues_bit_for_bit(tmp_path):
+    """A scheduled fit saved after 25 steps (past a seeding and the level
+    request) and resumed in a fresh context for 25 more steps ends with the
+    same parameters, counts and per-step L2 as one run of 50 steps; the
+    JSON-lines log holds one row per step."""
+    import json
+    torch = _torch()
+    from paper_2505_02350_amd import core
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput, jsonl_logger
+    prob = synth.make_custom(57, [16, 24], 40, (1.6, 2.6), kinds=("ellipsoid", "torus"), bands=[None, 0.15],
+                             cap=200)
+    cfg = core.sched_cfg(k_l2=4, tau_l2=1e6, k_l1=6, tau_l1=3.0, tau_d=0.02, T_e=40, M_e=50, lr0=1e-2,
+                         lr_final=1e-3, lr_min=1e-5, refine_epochs=(10,))
+    kw = dict(tau1=float(np.float32(0.9)), tau2=float(np.float32(1.1)), tau_m=1e3, top_frac=0.05, k_new=16)
+
+    def new_fit():
+        f = Fitter([ShapeInput.from_problem(prob)], cull_k=3.0, all_levels=False)
+        f.refine(0)
+        return f
+
+    print("scheduled fit: 50 steps in one run", flush=True)
+    full = new_fit()
+    _, log_full = full.fit_schedule(50, cfg, **kw)
+    print("scheduled fit: 25 steps, checkpoint, 25 more in a fresh context", flush=True)
+    first = new_fit()
+    st, log_a = first.fit_schedule(25, cfg, on_step=jsonl_logger(str(tmp_path / "log.jsonl")), **kw)
+    ck = str(tmp_path / "ck.npz")
+    first.save(ck, st)
+    del first
+    second = new_fit()
+    st2 = core.SchedState(second.ctx, cfg)
+    second.load(ck, st2)
+    _, log_b = second.fit_schedule(25, cfg, state=st2, **kw)
+    torch.cuda.synchronize()
+    assert second.next_level[0] == 2
+    assert any(r[0]["n_added"] > 0 for r in log_a)
+    assert torch.equal(full.p, second.p) and torch.equal(full.m_dev, second.m_dev)
+    assert torch.equal(full.m1, second.m1) and torch.equal(full.step_dev, second.step_dev)
+    assert [r[0]["L2"] for r in log_full] == [r[0]["L2"] for r in log_a + log_b]
+    rows = [json.loads(x) for x in open(tmp_path / "log.jsonl")]
+    assert [r["step"] for r in rows] == list(range(25)) and rows[-1]["shapes"][0]["L2"] == log_a[-1][0]["L2"]
