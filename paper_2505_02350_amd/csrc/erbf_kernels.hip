@@ -1639,37 +1639,11 @@ __device__ __forceinline__ double mat3_dot(const double A[3][3], const double B[
   return r;
 }
 
-__global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restrict__ p,
-                                                   float* __restrict__ grad) {
-  const int j = blockIdx.x;
+// A kernel's gradients from its ten summed moments (Appendix A; the
+// quaternion or Euler chain rule), written to its slot of grad.
+__device__ void reduce_epilogue(const Dev& D, const float* __restrict__ p, float* __restrict__ grad, const int j,
+                                const double v[10]) {
   const int C = D.cap_total;
-  const int lane = threadIdx.x;
-  const float4 r0 = D.rec[3 * j];
-  if (r0.w < 0.f) {
-    if (lane < 11) grad[lane * C + j] = 0.f;
-    return;
-  }
-  double v[10];
-#pragma unroll
-  for (int i = 0; i < 10; ++i) v[i] = 0.0;
-  const int64_t base = D.kstart[j];
-  const int c = D.kcnt[j];
-  // every entry's moments are written each step (zero for tiles without a
-  // non-zero G, and for the filler entries of the emit pass)
-  const int cc = (int)min((int64_t)c, max((int64_t)0, D.pair_cap - base));
-  for (int e = lane; e < cc; e += 64) {
-    const float2* q = D.partials + 5 * (base + e);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      const float2 a = q[i];
-      v[2 * i] += a.x;
-      v[2 * i + 1] += a.y;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 10; ++i) v[i] = wave_sum(v[i]);
-  if (lane != 0) return;
-
   const double w = p[j];
   const double s[3] = {p[4 * C + j], p[5 * C + j], p[6 * C + j]};
   const double q4[4] = {p[7 * C + j], p[8 * C + j], p[9 * C + j], p[10 * C + j]};
@@ -1751,6 +1725,47 @@ __global__ __launch_bounds__(64) void k_bwd_reduce(Dev D, const float* __restric
                qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
   const double dot = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
   for (int k = 0; k < 4; ++k) grad[(7 + k) * C + j] = (float)((gq[k] - qh[k] * dot) / qn);
+}
+
+// Sixteen lanes per kernel, four kernels per wave, sixteen per block: a
+// lane group sums its kernel's partials (contiguous, entries strided by 16)
+// in float64, folds them over the group in a fixed order, and the group's
+// first lane forms the gradients.
+__global__ __launch_bounds__(256) void k_bwd_reduce(Dev D, const float* __restrict__ p,
+                                                    float* __restrict__ grad) {
+  const int lane = threadIdx.x & 63, sl = lane & 15;
+  const int j = blockIdx.x * 16 + (threadIdx.x >> 6) * 4 + (lane >> 4);
+  const int C = D.cap_total;
+  if (j >= C) return;   // the whole lane group leaves together
+  const float4 r0 = D.rec[3 * j];
+  if (r0.w < 0.f) {
+    if (sl < 11) grad[sl * C + j] = 0.f;
+    return;
+  }
+  double v[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) v[i] = 0.0;
+  const int64_t base = D.kstart[j];
+  const int c = D.kcnt[j];
+  // every entry's moments are written each step (zero for tiles without a
+  // non-zero G, and for the filler entries of the emit pass)
+  const int cc = (int)min((int64_t)c, max((int64_t)0, D.pair_cap - base));
+  for (int e = sl; e < cc; e += 16) {
+    const float2* q = D.partials + 5 * (base + e);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const float2 a = q[i];
+      v[2 * i] += a.x;
+      v[2 * i + 1] += a.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 16);
+  }
+  if (sl != 0) return;
+  reduce_epilogue(D, p, grad, j, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -2324,7 +2339,7 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
     hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, D.samp_split), dim3(256), 0, s, D, G);
     hipLaunchKernelGGL(k_sample_bwd_sum, dim3(nblk(D.n_samp_slots, 64)), dim3(64), 0, s, D);
   }
-  launch_timed(k_bwd_reduce, dim3(D.cap_total), dim3(64), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
+  launch_timed(k_bwd_reduce, dim3(nblk(D.cap_total, 16)), dim3(256), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
                grad);
   return hipGetLastError();
 }
