@@ -353,7 +353,7 @@ def autograd_steps(fit, steps):
 
 
 def e2e_bench(name):
-    """One spec configuration run end to end: the whole training loop
+    """One of the benchmark configurations run end to end: the whole training loop
     on the device (the fixed-weight loop of the tiny config; Algorithm 3's
     control with eq. 3-21, pruning, kernel addition and level appends for
     mid, large and diff; 200 batched steps against 64 sequential plain fits
