@@ -206,6 +206,11 @@ class Fitter:
                 stats_h.copy_(self.ctx.stats_buf, non_blocking=True)
             s_obj.synchronize()
             stats = core.parse_stats(stats_h, n)
+            for b in range(n):
+                if stats[b].flags & L.FLAG_BUCKET_OVERFLOW:
+                    raise RuntimeError(f"tile lists overflowed at step {len(log)} (shape {b}): "
+                                       f"{stats[b].n_bucket_pairs} entries needed; build the Fitter with a "
+                                       f"larger pair_cap")
             add, ref, l1, b_f, n_pr, fin = (snap_h[rows[f]].tolist() for f in
                                             ("add_request", "refine_request", "l1_active", "b_f", "n_pruned",
                                              "final_phase"))
