@@ -1607,9 +1607,10 @@ __global__ __launch_bounds__(64 * W) void k_bwd_tiles_persistent(Dev D, const fl
 }
 
 // ---------------------------------------------------------------------------
-// backward, stage 2: one wave per kernel slot.  Sums the kernel's per-tile
-// moments in its fixed visit order (lane-strided, then a fixed butterfly) in
-// float64 and turns them into gradients (Appendix A; quaternion chain rule).
+// backward, stage 2: sixteen lanes per kernel slot.  Sums the kernel's
+// per-tile moments in a fixed order (lane-strided, then a fixed butterfly)
+// in float64 and turns them into gradients (Appendix A; quaternion or Euler
+// chain rule).
 // ---------------------------------------------------------------------------
 
 // Rotation about axis k (0 = x, 1 = y, 2 = z) by angle t and its derivative
