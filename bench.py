@@ -352,7 +352,7 @@ def autograd_steps(fit, steps):
     return {"steps": steps, "ms_per_step": ms, "loss_last": float(loss)}
 
 
-def e2e_bench(name):
+def e2e_bench(name, prob=None):
     """One of the benchmark configurations run end to end: the whole training loop
     on the device (the fixed-weight loop of the tiny config; Algorithm 3's
     control with eq. 3-21, pruning, kernel addition and level appends for
@@ -397,7 +397,9 @@ def e2e_bench(name):
         log(f"{name}: 200 steps batched {wall_b:.2f} s, 64 plain fits {wall_p:.2f} s, final L2 rel diff {rel:.3g}")
         return {"config": name, "steps": 200, "batched_s": wall_b, "plain_s": wall_p, "speedup": wall_p / wall_b,
                 "final_L2_max_rel_diff": rel}
-    if name == "tiny":
+    if prob is not None:
+        pass
+    elif name == "tiny":
         prob = synth.make_tiny()
     elif name == "mid":
         prob = synth.make_mid()
@@ -485,6 +487,8 @@ def main():
     ap.add_argument("--workload-cache", default="",
                     help="npz file of the generated timing workload: read if present, else written")
     ap.add_argument("--gen-only", action="store_true", help="generate (and cache) the workload, then exit")
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="leave the 128^3 scheduled fit (500 steps) out of the default line")
     ap.add_argument("--e2e", default="",
                     help="run one configuration end to end (tiny, mid, large, diff, batching) and print its JSON")
     ap.add_argument("--variant", type=int, default=-1,
@@ -525,6 +529,8 @@ def main():
         if not args.no_cpu_baseline:
             log("under a profiler: no CPU baseline (its workers would fork)")
             args.no_cpu_baseline = True
+        # the profile covers the benchmark step alone
+        args.no_e2e = True
     t_setup = time.perf_counter()
     if args.workload_cache and os.path.exists(args.workload_cache):
         prob = synth.load_problem(args.workload_cache)
@@ -541,8 +547,13 @@ def main():
         t0 = time.perf_counter()
         bprobs = synth.make_batching()
         log(f"batching workload generated in {time.perf_counter() - t0:.1f} s")
+    mid_prob = None
+    if not args.no_e2e:
+        mid_prob = synth.make_mid()
     n_cpu = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
-    if not args.no_cpu_baseline and n_cpu > 1:
+    if not profiled:
+        # the fork server of the oracle's and the SDF sampler's workers,
+        # started while nothing here has touched the GPU
         from oracle import pool
         pool.start_server()
 
@@ -698,6 +709,8 @@ def main():
     }
     if bprobs is not None:
         out["batching"] = batching_bench(bprobs, args.batching_steps, 2)
+    if mid_prob is not None:
+        out["end_to_end"] = e2e_bench("mid", mid_prob)
     if args.init:
         out["init"] = init_bench(with_cpu=not args.no_cpu_baseline)
     if args.minibatch:
