@@ -47,9 +47,10 @@ struct Layout {
   int64_t init_cand = 0;    // its candidate list capacity: points of the largest shape
   int scan_blocks = 0;
   int radix_nb = 0;
+  int hit_cap = 0;   // tile slots kept per kernel by the count pass (0: the emit pass walks)
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_tile_cnt,
       off_tile_start64, off_kslot, off_sort_keys[2],
-      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
+      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
@@ -140,6 +141,12 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 256));
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
+  // the count pass keeps each kernel's first hit_cap tile slots, so the emit
+  // pass copies them instead of walking the box again; sized to at most
+  // twice the list capacity
+  L.hit_cap = (int)std::min<int64_t>(kHitCapMax, 2 * cfg->pair_cap / std::max(L.cap_total, 1));
+  if (L.hit_cap < 16) L.hit_cap = 0;
+  L.off_hits = take(sizeof(int32_t) * (size_t)L.cap_total * (size_t)L.hit_cap + 4);
   L.off_kstart = take(sizeof(int64_t) * (L.cap_total + 1));
   L.off_kblock = take(sizeof(int32_t) * (L.cap_total / 4 + 1));
   L.off_kblock_ex = take(sizeof(int64_t) * (L.cap_total / 4 + 2));
@@ -300,6 +307,8 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.rhist_ex = reinterpret_cast<int32_t*>(w + lay.off_rhist_ex);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
+  D.hits = reinterpret_cast<int32_t*>(w + lay.off_hits);
+  D.hit_cap = lay.hit_cap;
   D.kstart = reinterpret_cast<int64_t*>(w + lay.off_kstart);
   D.kblock = reinterpret_cast<int32_t*>(w + lay.off_kblock);
   D.kblock_ex = reinterpret_cast<int64_t*>(w + lay.off_kblock_ex);
@@ -847,8 +856,8 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
   if (!cfg || !grad_scratch || reps < 1) return fail(ERBF_ERR_INVALID_ARG, "erbf_autotune: bad arguments");
   DeviceGuard guard(ctx->device);
   hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0), "autotune: event");
-  hipError_t ce = hipEventCreate(&e1);
+  HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence), "autotune: event");
+  hipError_t ce = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
   if (ce != hipSuccess) {
     (void)hipEventDestroy(e0);
     return hip_fail(ce, "autotune: event");
@@ -944,7 +953,9 @@ int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls) {
   const size_t need = kEvPerCall * (size_t)max_calls;
   while (ctx->tev.size() < need) {
     hipEvent_t e;
-    HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    // timing only: without the system-scope fence, recording an event does
+    // not write back and invalidate the caches around the timed kernels
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
     ctx->tev.push_back(e);
   }
   ctx->t_max = max_calls;

@@ -18,6 +18,7 @@ constexpr int kVariantBwdPersistent = 2;   // backward tiles walked by a persist
 constexpr int kVariantFused = 4;           // the loss call's forward and backward tiles in one kernel
 constexpr int kVariantAll = 7;
 
+constexpr int kHitCapMax = 512;   // most tile slots the count pass keeps per kernel
 constexpr int kSampSplitMax = 32;  // most workgroups per active sample tile (parts of its kernel list)
 constexpr int kLevelGrid = 0;      // cell-centred grid of n^3 points
 constexpr int kLevelSamples = 1;   // surface samples binned into the tiles of an n^3-cell grid
@@ -96,6 +97,7 @@ struct Dev {
   int32_t* tile_e;          // [pair_cap] kernel-major index of each tile-major entry
   int32_t* items;           // [pair_cap] kernel of each tile-major entry: ascending within a tile
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
+  int32_t* hits;            // [cap_total * hit_cap] tile slots a kernel hits, in visit order (count pass)
   int64_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
   int32_t* kblock;          // [cap_total / 4 + 1] kcnt summed over each count block (four kernels)
   int64_t* kblock_ex;       // [cap_total / 4 + 2] exclusive scan of kblock
@@ -156,6 +158,7 @@ struct Dev {
   int32_t rank_words;       // bitmap words per wave of the rank pass (largest shape capacity / 32)
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass
+  int32_t hit_cap;          // columns of hits (0: none kept)
   int32_t n_levels_total;   // entries of `levels` (ordered by pt_base)
   int32_t batch_cap;        // largest mini-batch
 };

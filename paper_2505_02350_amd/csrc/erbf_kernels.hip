@@ -217,17 +217,18 @@ hipError_t launch_scan_any(const int32_t* in, int n, T* blocks, T* out, int64_t*
 // ---------------------------------------------------------------------------
 // Tile buckets.  One wave per kernel slot; lanes test the tiles of the
 // ball's tile box.  A kernel's tiles are numbered in a fixed order (level,
-// z, y, x): the visit index.  The count pass counts each kernel's tiles; the
-// emit pass writes the entries kernel-major, entry e = kstart[j] + visit,
-// with the tile slot as the sort key.  A stable sort of the kernel-major
+// z, y, x): the visit index.  The count pass counts each kernel's tiles and
+// keeps their slots (up to hit_cap per kernel); the emit pass writes the
+// entries kernel-major, entry e = kstart[j] + visit, with the tile slot as
+// the sort key, copying the kept slots (walking again only for a kernel
+// with more tiles than were kept).  A stable sort of the kernel-major
 // list by slot then gives every tile's kernels in ascending order, with no
 // atomics and the same result on every run.
 // ---------------------------------------------------------------------------
 
-// Walks kernel j's tile boxes (j wave-uniform) in visit order (level, z, y,
-// x) and returns the number of tiles hit.  A tile is hit when the ball,
-// widened slightly, reaches the tile's point box (fixed expression, so both
-// walks below take the same decisions) and the tile is in use.
+// A tile is hit when the ball, widened slightly, reaches the tile's point box
+// (a fixed expression, so a walk in the count pass and one in the emit pass
+// take the same decisions) and the tile is in use.
 __device__ __forceinline__ float ball_box_e2(const LevelDev& L, const float4& r0, int ty, int tz) {
   const float ey = fmaxf(fmaxf(tile_lo(L, ty) - r0.y, r0.y - tile_hi(L, ty)), 0.f);
   const float ez = fmaxf(fmaxf(tile_lo(L, tz) - r0.z, r0.z - tile_hi(L, tz)), 0.f);
@@ -272,127 +273,79 @@ __device__ __forceinline__ int tile_slot_of(const Dev& D, const LevelDev& L, int
   return L.dense ? L.slot0 + t : D.tile_map[L.tmap0 + t];
 }
 
-// Count walk: lanes own rows of tiles (y, z) and step along x, so a row's
-// y and z distances are formed once.
-__device__ __forceinline__ int bucket_count_walk(const Dev& D, const float4 r0, const int j, const int lane) {
+// Box walk: lanes own consecutive tiles of the ball's tile box, so a ballot
+// numbers the hits in visit order; hit(v, slot) is called for the tile of
+// visit index v.  Returns the kernel's tile count.
+template <class F>
+__device__ __forceinline__ int bucket_box_walk(const Dev& D, const float4 r0, const int j, const int lane, F&& hit) {
   if (r0.w < 0.f) return 0;
+  int vbase = 0;
   const ShapeDev S = D.shapes[D.kshape[j]];
-  int total = 0;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
   for (int li = 0; li < S.n_active; ++li) {
     const LevelDev L = D.levels[S.lvl0 + li];
     BallBox B;
     if (!ball_box(L, r0, B)) continue;
-    const int nrows = B.nty * B.ntz;
-    for (int rb = 0; rb < nrows; rb += 64) {
-      const int r = rb + lane;
-      int cnt = 0;
-      if (r < nrows) {
-        const int qz = r / B.nty, ty = B.ty0 + (r - qz * B.nty), tz = B.tz0 + qz;
+    const int ntx = B.tx1 - B.tx0 + 1, nxy = ntx * B.nty, total = nxy * B.ntz;
+    // box index -> (x, y, z) by a float reciprocal: exact while
+    // (quotient + 1) * divisor < 2^21, which keeps the rounding error
+    // below the 0.5 / divisor gap to the next integer; larger boxes take
+    // the integer division
+    const bool small_box = total + nxy < (1 << 21);
+    const float inv_x = 1.0f / (float)ntx, inv_xy = 1.0f / (float)nxy;
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      int slot = -1;
+      if (idx < total) {
+        int qz, qy, qx;
+        if (small_box) {
+          qz = (int)(((float)idx + 0.5f) * inv_xy);
+          const int rem = idx - qz * nxy;
+          qy = (int)(((float)rem + 0.5f) * inv_x);
+          qx = rem - qy * ntx;
+        } else {
+          qz = idx / nxy;
+          qy = (idx % nxy) / ntx;
+          qx = idx % ntx;
+        }
+        const int tx = B.tx0 + qx, ty = B.ty0 + qy, tz = B.tz0 + qz;
         const float e2 = ball_box_e2(L, r0, ty, tz);
-        if (e2 < B.rc2) {
-          const int row0 = (tz * L.nt + ty) * L.nt;
-          for (int tx = B.tx0; tx <= B.tx1; ++tx) {
-            if (!ball_box_hit(L, r0, e2, tx, B.rc2)) continue;
-            const int sl = tile_slot_of(D, L, row0 + tx);
-            if (!tile_listed(D, sl)) continue;
-            ++cnt;
-            if (D.bucket_rank) atomicAdd(&D.tile_cnt[sl], 1);
-          }
+        if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2)) {
+          const int sl = tile_slot_of(D, L, (tz * L.nt + ty) * L.nt + tx);
+          slot = tile_listed(D, sl) ? sl : -1;
         }
       }
-      total += (int)wave_sum(cnt);
+      const unsigned long long bal = __ballot(slot >= 0);
+      if (slot >= 0) hit(vbase + __popcll(bal & lt_mask), slot);
+      vbase += __popcll(bal);
     }
   }
-  return total;
+  return vbase;
 }
 
-// Emit walk: lanes own consecutive box tiles, so consecutive entries are
-// written by consecutive lanes.  Writes entries e0 + visit for visits
-// below cnt_j.
-__device__ __forceinline__ void bucket_emit_walk(const Dev& D, const int j, const int lane, const int64_t e0,
-                                                 const int cnt_j) {
-  const float4 r0 = D.rec[3 * j];
-  int vbase = 0;
-  if (r0.w >= 0.f) {
-    const ShapeDev S = D.shapes[D.kshape[j]];
-    const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    for (int li = 0; li < S.n_active; ++li) {
-      const LevelDev L = D.levels[S.lvl0 + li];
-      BallBox B;
-      if (!ball_box(L, r0, B)) continue;
-      const int ntx = B.tx1 - B.tx0 + 1, nxy = ntx * B.nty, total = nxy * B.ntz;
-      // box index -> (x, y, z) by a float reciprocal: exact while
-      // (quotient + 1) * divisor < 2^21, which keeps the rounding error
-      // below the 0.5 / divisor gap to the next integer; larger boxes take
-      // the integer division
-      const bool small_box = total + nxy < (1 << 21);
-      const float inv_x = 1.0f / (float)ntx, inv_xy = 1.0f / (float)nxy;
-      for (int base = 0; base < total; base += 64) {
-        const int idx = base + lane;
-        int slot = -1;
-        if (idx < total) {
-          int qz, qy, qx;
-          if (small_box) {
-            qz = (int)(((float)idx + 0.5f) * inv_xy);
-            const int rem = idx - qz * nxy;
-            qy = (int)(((float)rem + 0.5f) * inv_x);
-            qx = rem - qy * ntx;
-          } else {
-            qz = idx / nxy;
-            qy = (idx % nxy) / ntx;
-            qx = idx % ntx;
-          }
-          const int tx = B.tx0 + qx, ty = B.ty0 + qy, tz = B.tz0 + qz;
-          const float e2 = ball_box_e2(L, r0, ty, tz);
-          if (e2 < B.rc2 && ball_box_hit(L, r0, e2, tx, B.rc2)) {
-            const int sl = tile_slot_of(D, L, (tz * L.nt + ty) * L.nt + tx);
-            slot = tile_listed(D, sl) ? sl : -1;
-          }
-        }
-        const bool hit = slot >= 0;
-        const unsigned long long bal = __ballot(hit);
-        if (hit) {
-          const int v = vbase + __popcll(bal & lt_mask);
-          const int64_t at = e0 + v;
-          if (D.bucket_rank) {
-            // the tile's count runs back down to 0 as its entries are placed
-            // (ready for the next build); the order within the tile is fixed
-            // afterwards by k_tile_rank
-            if (v < cnt_j) {
-              const int64_t pos = D.tile_start64[slot] + (int64_t)(atomicSub(&D.tile_cnt[slot], 1) - 1);
-              if (pos < D.pair_cap) {
-                D.sort_j[0][pos] = j;
-                D.sort_vals[0][pos] = at < D.pair_cap ? (int)at : -1;
-              }
-            }
-          } else if (v < cnt_j && at >= 0 && at < D.pair_cap) {
-            D.kslot[at] = slot;
-            D.kj[at] = j;
-          }
-        }
-        vbase += __popcll(bal);
-      }
+// Entry v of kernel j (of cnt_j, starting at e0), for tile slot `slot`.
+__device__ __forceinline__ void bucket_place(const Dev& D, const int j, const int64_t e0, const int v, const int cnt_j,
+                                             const int slot) {
+  if (v >= cnt_j) return;
+  const int64_t at = e0 + v;
+  if (D.bucket_rank) {
+    // the tile's count runs back down to 0 as its entries are placed (ready
+    // for the next build); the order within the tile is fixed afterwards by
+    // k_tile_rank
+    const int64_t pos = D.tile_start64[slot] + (int64_t)(atomicSub(&D.tile_cnt[slot], 1) - 1);
+    if (pos < D.pair_cap) {
+      D.sort_j[0][pos] = j;
+      D.sort_vals[0][pos] = at < D.pair_cap ? (int)at : -1;
     }
-  }
-  // both walks take the same decisions; should they ever differ, the
-  // counted range is still filled, with a slot past every real tile
-  for (int v = vbase + lane; v < cnt_j; v += 64) {
-    const int64_t at = e0 + v;
-    if (at >= 0 && at < D.pair_cap) {
-      if (!D.bucket_rank) {
-        D.kslot[at] = D.tiles_total;
-        D.kj[at] = j;
-      }
-      float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
-#pragma unroll
-      for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
-    }
+  } else if (at >= 0 && at < D.pair_cap) {
+    D.kslot[at] = slot;
+    D.kj[at] = j;
   }
 }
 
 // Count pass: the kernel's record (every lane forms the same one, lane 0
-// stores it), kcnt per kernel (one wave each) and the sum of each block's
-// four kernels.
+// stores it), kcnt per kernel (one wave each), its first hit_cap tile slots
+// in visit order, and the sum of each block's four kernels.
 __global__ __launch_bounds__(256) void k_bucket_count(Dev D, const float* __restrict__ p,
                                                       const int32_t* __restrict__ m_dev) {
   __shared__ int wc[4];
@@ -407,7 +360,11 @@ __global__ __launch_bounds__(256) void k_bucket_count(Dev D, const float* __rest
       D.rec[3 * j + 1] = r1;
       D.rec[3 * j + 2] = r2;
     }
-    c = bucket_count_walk(D, r0, j, lane);
+    int32_t* hj = D.hits + (int64_t)j * D.hit_cap;
+    c = bucket_box_walk(D, r0, j, lane, [&](int v, int sl) {
+      if (v < D.hit_cap) hj[v] = sl;
+      if (D.bucket_rank) atomicAdd(&D.tile_cnt[sl], 1);
+    });
   }
   if (lane == 0) {
     if (j < D.cap_total) D.kcnt[j] = c;
@@ -417,7 +374,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(Dev D, const float* __rest
   if (threadIdx.x == 0) D.kblock[blockIdx.x] = (wc[0] + wc[1]) + (wc[2] + wc[3]);
 }
 
-// Emit pass: kstart from the scanned block sums, then the entries.
+// Emit pass: kstart from the scanned block sums, then the entries, copied
+// from the count pass's slots when they were all kept, else by the same walk.
 __global__ __launch_bounds__(256) void k_bucket_emit(Dev D) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
@@ -425,7 +383,37 @@ __global__ __launch_bounds__(256) void k_bucket_emit(Dev D) {
   int64_t e0 = D.kblock_ex[blockIdx.x];
   for (int k = 0; k < w; ++k) e0 += D.kcnt[4 * blockIdx.x + k];
   if (lane == 0) D.kstart[j] = e0;
-  bucket_emit_walk(D, j, lane, e0, D.kcnt[j]);
+  const int cnt_j = D.kcnt[j];
+  int done;
+  if (cnt_j <= D.hit_cap) {
+    const int32_t* hj = D.hits + (int64_t)j * D.hit_cap;
+    for (int v0 = 0; v0 < cnt_j; v0 += 256) {
+      // four loads in flight per lane (indices clamped into the kept slots)
+      int sl[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sl[i] = hj[min(v0 + 64 * i + lane, cnt_j - 1)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bucket_place(D, j, e0, v0 + 64 * i + lane, cnt_j, sl[i]);
+    }
+    done = cnt_j;
+  } else {
+    done = bucket_box_walk(D, D.rec[3 * j], j, lane,
+                           [&](int v, int sl) { bucket_place(D, j, e0, v, cnt_j, sl); });
+  }
+  // both walks take the same decisions; should they ever differ, the
+  // counted range is still filled, with a slot past every real tile
+  for (int v = done + lane; v < cnt_j; v += 64) {
+    const int64_t at = e0 + v;
+    if (at >= 0 && at < D.pair_cap) {
+      if (!D.bucket_rank) {
+        D.kslot[at] = D.tiles_total;
+        D.kj[at] = j;
+      }
+      float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
+#pragma unroll
+      for (int i = 0; i < 5; ++i) o[i] = make_float2(0.f, 0.f);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -445,6 +433,8 @@ __device__ __forceinline__ void radix_segment(int64_t n, int nb, int b, int64_t&
   hi = min(n, lo + per);
 }
 
+constexpr int kRadixHistPer = 8;   // keys per thread per block iteration of the count
+
 __global__ __launch_bounds__(256) void k_radix_hist(Dev D, const int32_t* __restrict__ keys, int shift, int mask) {
   __shared__ int cnt[256];
   const int t = threadIdx.x;
@@ -452,7 +442,18 @@ __global__ __launch_bounds__(256) void k_radix_hist(Dev D, const int32_t* __rest
   __syncthreads();
   int64_t lo, hi;
   radix_segment(bucket_entries(D), D.radix_nb, blockIdx.x, lo, hi);
-  for (int64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
+  for (int64_t base = lo; base < hi; base += 256 * kRadixHistPer) {
+    // all loads first (indices clamped into the segment), then the counts
+    int k[kRadixHistPer];
+#pragma unroll
+    for (int i = 0; i < kRadixHistPer; ++i) {
+      const int64_t idx = base + 256 * i + t;
+      k[i] = keys[idx < hi ? idx : lo];
+    }
+#pragma unroll
+    for (int i = 0; i < kRadixHistPer; ++i)
+      if (base + 256 * i + t < hi) atomicAdd(&cnt[(k[i] >> shift) & mask], 1);
+  }
   __syncthreads();
   D.rhist[t * D.radix_nb + blockIdx.x] = cnt[t];
 }
@@ -503,8 +504,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
   __shared__ int run[256];
   __shared__ int wcnt[4][256];   // per-wave digit counts, then global starts
   __shared__ int lcnt[4][256];   // starts within this iteration's staged run
+  __shared__ int run_off[STAGE ? 256 : 1];   // output index minus stage index, per digit
   __shared__ int sws[4];
-  __shared__ int4 stage[STAGE ? kRadixSpan : 1];
+  // staged (key, entry, kernel); an entry's destination is its digit's
+  // global start plus its place in the digit's staged run
+  __shared__ int stage_k[STAGE ? kRadixSpan : 1], stage_v[STAGE ? kRadixSpan : 1], stage_j[STAGE ? kRadixSpan : 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
   int64_t lo, hi;
@@ -518,13 +522,27 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
     __syncthreads();
     int key[kRadixPerLane], val[kRadixPerLane], kid[kRadixPerLane], rank[kRadixPerLane];
     bool ok[kRadixPerLane];
+    // all loads first, from indices clamped into the segment (lo < hi), so
+    // that they are in flight together; entries past the segment are
+    // masked by ok
 #pragma unroll
     for (int i = 0; i < kRadixPerLane; ++i) {
       const int64_t idx = base + w * kRadixWaveSpan + i * 64 + lane;
       ok[i] = idx < hi;
-      key[i] = ok[i] ? kin[idx] : 0;
-      val[i] = ok[i] ? (vin ? vin[idx] : (int)idx) : 0;
-      kid[i] = ok[i] ? jin[idx] : 0;
+      const int64_t ci = ok[i] ? idx : lo;
+      key[i] = kin[ci];
+      kid[i] = jin[ci];
+      val[i] = (int)idx;
+    }
+    if (vin) {
+#pragma unroll
+      for (int i = 0; i < kRadixPerLane; ++i) {
+        const int64_t idx = base + w * kRadixWaveSpan + i * 64 + lane;
+        val[i] = vin[idx < hi ? idx : lo];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kRadixPerLane; ++i) {
       const int d = (key[i] >> shift) & mask;
       // lanes of this wave holding the same digit
       unsigned long long same = __ballot(ok[i]);
@@ -547,6 +565,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
       }
       int l = STAGE ? block_excl_scan_256(tot, sws) : 0;
       int g = run[t];
+      // the waves' runs of digit t are consecutive both in the stage and in
+      // the output, so a stage index maps to the output by one offset
+      if (STAGE) run_off[t] = g - l;
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) {
         wcnt[ww][t] = g;
@@ -562,16 +583,20 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
       for (int i = 0; i < kRadixPerLane; ++i) {
         if (ok[i]) {
           const int d = (key[i] >> shift) & mask;
-          stage[lcnt[w][d] + rank[i]] = make_int4(key[i], val[i], kid[i], wcnt[w][d] + rank[i]);
+          const int q = lcnt[w][d] + rank[i];
+          stage_k[q] = key[i];
+          stage_v[q] = val[i];
+          stage_j[q] = kid[i];
         }
       }
       __syncthreads();
       const int nit = (int)min((int64_t)kRadixSpan, hi - base);
       for (int q = t; q < nit; q += 256) {
-        const int4 e = stage[q];
-        kout[e.w] = e.x;
-        vout[e.w] = e.y;
-        jout[e.w] = e.z;
+        const int k = stage_k[q];
+        const int pos = run_off[(k >> shift) & mask] + q;
+        kout[pos] = k;
+        vout[pos] = stage_v[q];
+        jout[pos] = stage_j[q];
       }
     } else {
 #pragma unroll
