@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 5
+#define ERBF_ABI_VERSION 6
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -177,6 +177,10 @@ typedef struct {
   float lr;            /* used when lr_dev is NULL */
   const float* lr_dev; /* device [n_shapes] per-shape learning rate, or NULL */
   float beta1, beta2, eps;  /* Adam hyper-parameters (0.9, 0.999, 1e-8) */
+  /* device [1] or NULL: while the word is non-zero the call leaves the
+   * parameters, the moments and the step counters as they are (the hold
+   * word of erbf_sched_state) */
+  const int32_t* hold_dev;
 } erbf_adam_cfg;
 
 typedef struct {
@@ -419,7 +423,18 @@ typedef struct {
  * add_request asks the caller to add kernels (erbf_seed_from_error,
  * Algorithm 2); refine_request asks for the next grid level
  * (erbf_refine_level); b_f is the effective basis count and n_pruned the
- * kernels removed by eq. 3-27 in this call. */
+ * kernels removed by eq. 3-27 in this call.
+ *
+ * hold (device [1], or NULL for none) lets a caller enqueue the next step
+ * before it has read this call's requests: a call that leaves a request to
+ * act on -- add_request for a shape with fewer live kernels than its m_cap
+ * (after this call's pruning) and a non-empty id_all in stats_dev, or
+ * refine_request -- sets the word to 1, and a call that finds it non-zero
+ * changes no field (n_pruned aside, which it sets to 0).  Passed as
+ * the next step's erbf_adam_cfg.hold_dev, the word makes that step leave the
+ * parameters, moments and step counters unchanged too, so the caller can
+ * handle the requests, clear the word (to 0) and repeat the step, on exactly
+ * the trajectory of a caller that waits for every call. */
 typedef struct {
   int32_t* epoch;
   int32_t* l1_active;
@@ -431,6 +446,7 @@ typedef struct {
   float* lr;
   double* l2_ring;
   int32_t* bf_ring;
+  int32_t* hold;
 } erbf_sched_state;
 
 /* Reset the control state (epoch 0, L1 off, lr = lr0).  INVALID_ARG for a

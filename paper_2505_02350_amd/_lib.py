@@ -27,7 +27,7 @@ MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
 ORIENT_QUATERNION, ORIENT_EULER = 0, 1
 VARIANT_FWD_PERSISTENT, VARIANT_BWD_PERSISTENT, VARIANT_FUSED, N_VARIANTS = 1, 2, 4, 8
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class ErbfError(RuntimeError):
@@ -74,7 +74,7 @@ class Stats(ctypes.Structure):
 
 class AdamCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("lr_dev", ctypes.c_void_p), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("hold_dev", ctypes.c_void_p)]
 
 
 class SeedCfg(ctypes.Structure):
@@ -92,7 +92,7 @@ class SchedCfg(ctypes.Structure):
 class SchedState(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
                 ("epoch", "l1_active", "final_phase", "add_request", "refine_request", "b_f", "n_pruned", "lr",
-                 "l2_ring", "bf_ring")]
+                 "l2_ring", "bf_ring", "hold")]
 
 
 STATS_BYTES = ctypes.sizeof(Stats)

@@ -231,20 +231,20 @@ class Context:
         return grad_out
 
     def erbf_adam_step(self, p, m_dev, grad, m1, m2, step_dev, lr=1e-3, lr_dev=None, beta1=0.9,
-                       beta2=0.999, eps=1e-8, stream=None):
+                       beta2=0.999, eps=1e-8, hold_dev=None, stream=None):
         pr = self._params(p, m_dev)
-        cfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps))
+        cfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps), _ptr(hold_dev))
         L.check(self.lib.erbf_adam_step(self.handle, ctypes.byref(pr), _ptr(grad), _ptr(m1), _ptr(m2),
                                         _ptr(step_dev), ctypes.byref(cfg), _stream(stream)))
 
     def erbf_train_step(self, p, m_dev, grad_out, m1, m2, step_dev, mode=L.MODE_FIXED, lam=0.0, lambda_dev=None,
                         l1_active=False, tau1=0.9, tau2=1.1, tau_m=0.02, l1_active_dev=None, lr=1e-3, lr_dev=None,
-                        beta1=0.9, beta2=0.999, eps=1e-8, f_out=None, G_out=None, stream=None):
+                        beta1=0.9, beta2=0.999, eps=1e-8, f_out=None, G_out=None, hold_dev=None, stream=None):
         """Loss, gradient and Adam update in one call (erbf_train_step)."""
         pr = self._params(p, m_dev)
         cfg = L.LossCfg(int(mode), float(lam), _ptr(lambda_dev), int(bool(l1_active)), float(tau1),
                         float(tau2), float(tau_m), _ptr(l1_active_dev))
-        acfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps))
+        acfg = L.AdamCfg(float(lr), _ptr(lr_dev), float(beta1), float(beta2), float(eps), _ptr(hold_dev))
         L.check(self.lib.erbf_train_step(self.handle, ctypes.byref(pr), ctypes.byref(cfg), ctypes.byref(acfg),
                                          _ptr(grad_out), _ptr(m1), _ptr(m2), _ptr(step_dev), _ptr(self.stats_buf),
                                          _ptr(f_out), _ptr(G_out), _stream(stream)))
@@ -274,13 +274,16 @@ class Context:
 
     # ---- training control (Algorithm 3) ----------------------------------------
     def erbf_sched_init(self, cfg, state: "SchedState", stream=None):
-        L.check(self.lib.erbf_sched_init(self.handle, ctypes.byref(cfg), ctypes.byref(state.c), _stream(stream)))
+        L.check(self.lib.erbf_sched_init(self.handle, ctypes.byref(cfg), ctypes.byref(state.c_hold),
+                                         _stream(stream)))
 
-    def erbf_sched_step(self, p, m_dev, cfg, state: "SchedState", m1=None, m2=None, stream=None):
+    def erbf_sched_step(self, p, m_dev, cfg, state: "SchedState", m1=None, m2=None, hold=False, stream=None):
         """Control after a step; reads this context's stats of the last
-        erbf_loss_grad call."""
+        erbf_loss_grad call.  hold: pass the state's hold word (a requesting
+        call then holds the calls after it until the word is cleared)."""
         pr = self._params(p, m_dev)
-        L.check(self.lib.erbf_sched_step(self.handle, ctypes.byref(pr), ctypes.byref(cfg), ctypes.byref(state.c),
+        sc = state.c_hold if hold else state.c
+        L.check(self.lib.erbf_sched_step(self.handle, ctypes.byref(pr), ctypes.byref(cfg), ctypes.byref(sc),
                                          _ptr(self.stats_buf), _ptr(m1), _ptr(m2), _stream(stream)))
 
     def erbf_timing_enable(self, max_calls: int):
@@ -447,7 +450,8 @@ class SchedState:
     """Device arrays of the training-control state of every shape of a
     context (see erbf_sched_state in include/erbf.h)."""
 
-    FLAG_ROWS = ("epoch", "l1_active", "final_phase", "add_request", "refine_request", "b_f", "n_pruned")
+    # the last row's first entry is the hold word (erbf_sched_state.hold)
+    FLAG_ROWS = ("epoch", "l1_active", "final_phase", "add_request", "refine_request", "b_f", "n_pruned", "hold")
 
     def __init__(self, ctx: "Context", cfg):
         dev, n = ctx.device, ctx.n_shapes
@@ -460,4 +464,10 @@ class SchedState:
         self.lr = torch.zeros(n, dtype=torch.float32, device=dev)
         self.l2_ring = torch.zeros(n * cfg.k_l2, dtype=torch.float64, device=dev)
         self.bf_ring = torch.zeros(n * cfg.k_l1, **i32)
-        self.c = L.SchedState(*[_ptr(getattr(self, f)) for f, _ in L.SchedState._fields_])
+        # the hold word (erbf_sched_state.hold, the first entry of its row):
+        # `c` leaves it out (every call acts), `c_hold` passes it (a call
+        # with a request to act on holds the next ones)
+        ptrs = {f: _ptr(getattr(self, f)) for f, _ in L.SchedState._fields_}
+        self.c_hold = L.SchedState(**ptrs)
+        ptrs["hold"] = None
+        self.c = L.SchedState(**ptrs)

@@ -53,7 +53,7 @@ struct Layout {
       off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
-      off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_b_l2, off_b_abs, off_b_id, off_b_pf,
+      off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_sched_held, off_b_l2, off_b_abs, off_b_id, off_b_pf,
       off_b_shape, off_hist, off_cand, off_keep, off_misc, off_init, off_samp_pos, off_samp_start, off_samp_slot,
       off_samp_slots, off_samp_f, off_samp_c, off_samp_pb, off_sel;
   int64_t samp_total = 0, samp_start_total = 0, samp_tiles = 0;
@@ -163,6 +163,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_stat_part = take(sizeof(StatPart) * kStatParts * cfg->n_shapes);
   L.off_stat_ab = take(sizeof(double2) * cfg->n_shapes);
   L.off_prune_flag = take(sizeof(int32_t) * cfg->n_shapes);
+  L.off_sched_held = take(sizeof(int32_t) * cfg->n_shapes);
   const size_t bc = (size_t)std::max(cfg->batch_cap, 1);
   L.off_b_l2 = take(sizeof(double) * bc);
   L.off_b_abs = take(sizeof(float) * bc);
@@ -325,6 +326,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.stat_part = reinterpret_cast<StatPart*>(w + lay.off_stat_part);
   D.stat_ab = reinterpret_cast<double2*>(w + lay.off_stat_ab);
   D.prune_flag = reinterpret_cast<int32_t*>(w + lay.off_prune_flag);
+  D.sched_held = reinterpret_cast<int32_t*>(w + lay.off_sched_held);
   D.b_l2 = reinterpret_cast<double*>(w + lay.off_b_l2);
   D.b_abs = reinterpret_cast<float*>(w + lay.off_b_abs);
   D.b_id = reinterpret_cast<int32_t*>(w + lay.off_b_id);
@@ -639,12 +641,13 @@ namespace {
 // the step counters step_inc are incremented, for the Adam pass of
 // erbf_train_step that combines and applies them
 int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
-                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc);
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc,
+                   const int32_t* hold);
 }  // namespace
 
 int erbf_loss_grad(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
                    erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream) {
-  return loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, nullptr);
+  return loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, nullptr, nullptr);
 }
 
 int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg,
@@ -653,17 +656,18 @@ int erbf_train_step(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cf
   if (!adam || !m1 || !m2 || !step_dev) return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: NULL argument");
   if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f && adam->eps > 0.f))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_train_step: bad Adam hyper-parameters");
-  int rc = loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, step_dev);
+  int rc = loss_grad_impl(ctx, params, cfg, grad_out, stats_dev, f_out, G_out, stream, step_dev, adam->hold_dev);
   if (rc) return rc;
   DeviceGuard guard(ctx->device);
-  AdamArgs a{adam->lr, adam->lr_dev, adam->beta1, adam->beta2, adam->eps};
+  AdamArgs a{adam->lr, adam->lr_dev, adam->beta1, adam->beta2, adam->eps, adam->hold_dev};
   HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, grad_out, m1, m2, step_dev, a, true, stream), "train: adam");
   return ERBF_OK;
 }
 
 namespace {
 int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg* cfg, float* grad_out,
-                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc) {
+                   erbf_stats* stats_dev, float* f_out, float* G_out, hipStream_t stream, int32_t* step_inc,
+                   const int32_t* hold) {
   int rc = check_params(ctx, params);
   if (rc) return rc;
   if (!cfg || !grad_out) return fail(ERBF_ERR_INVALID_ARG, "cfg and grad_out must be non-NULL");
@@ -696,6 +700,7 @@ int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   a.l1_active_dev = cfg->l1_active_dev;
   a.tau_m = cfg->tau_m;
   a.step_inc = step_inc;
+  a.hold = hold;
   HIP_TRY(launch_stats(D, 2, params->p, params->m_dev, grad_out, stats_dev, a, stream, step_inc == nullptr),
           "loss: stats");
   if (G_out)
@@ -782,7 +787,7 @@ int erbf_adam_step(erbf_ctx* ctx, const erbf_params* params, const float* grad, 
   if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_adam_step: bad hyper-parameters");
   DeviceGuard guard(ctx->device);
-  AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps};
+  AdamArgs a{cfg->lr, cfg->lr_dev, cfg->beta1, cfg->beta2, cfg->eps, cfg->hold_dev};
   HIP_TRY(launch_adam(ctx->D, params->p, params->m_dev, const_cast<float*>(grad), m1, m2, step_dev, a, false, stream),
           "adam");
   return ERBF_OK;

@@ -114,6 +114,7 @@ struct Dev {
   uint32_t* tickets;        // [n_shapes + 1] last-block tickets of the statistics, per shape (0 between calls)
   StatPart* stat_part;      // [n_shapes * kStatParts]
   int32_t* prune_flag;      // [n_shapes] eq. 3-27 due after this step (training control)
+  int32_t* sched_held;      // [n_shapes] the control call finds its hold word set (control scratch)
   // mini-batch records, one per batch point (batch order)
   double* b_l2;             // [batch_cap] E^2
   float* b_abs;             // [batch_cap] |E|

@@ -1927,7 +1927,8 @@ __device__ __forceinline__ void stats_final_wave(const Dev& D, const int b, cons
     }
   }
   D.stat_ab[b] = make_double2(alpha, beta);
-  if (a.step_inc) a.step_inc[b] += 1;   // the step's Adam pass follows (erbf_train_step)
+  // the step's Adam pass follows (erbf_train_step); a held step counts nothing
+  if (a.step_inc && !(a.hold && *a.hold != 0)) a.step_inc[b] += 1;
   if (out) {
     const int64_t nb = D.counters[0];
     erbf_stats st;
@@ -2005,16 +2006,17 @@ __global__ __launch_bounds__(256) void k_stats_apply(Dev D, const float* __restr
 // Adam
 // ---------------------------------------------------------------------------
 
-__global__ void k_step_inc(int32_t* step, int n) {
+__global__ void k_step_inc(int32_t* step, int n, const int32_t* hold) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) step[i] += 1;
+  if (i < n && !(hold && *hold != 0)) step[i] += 1;
 }
 
 // Bias-corrected Adam over the packed parameters, at step t = step[b] of
 // each shape (already incremented for this step).  COMBINE: the gradient is
 // the L2 gradient as the backward left it, combined here with the step's loss
 // weights (alpha dL2 + beta sign(w) on w, alpha dL2 elsewhere, eq. 3-21) and
-// written back, so the loss call needs no pass of its own for it.
+// written back, so the loss call needs no pass of its own for it.  While
+// the hold word is non-zero the pass changes nothing.
 template <bool COMBINE>
 __global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, const int32_t* __restrict__ m_dev,
                                               float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
@@ -2022,6 +2024,7 @@ __global__ __launch_bounds__(256) void k_adam(Dev D, float* __restrict__ p, cons
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int C = D.cap_total;
   if (i >= (int64_t)11 * C) return;
+  if (a.hold && *a.hold != 0) return;
   const int j = (int)(i % C);
   const int b = D.kshape[j];
   const ShapeDev S = D.shapes[b];
@@ -2411,7 +2414,7 @@ hipError_t launch_adam(const Dev& D, float* p, const int32_t* m_dev, float* g, f
     // the step counters were incremented by the loss call's statistics
     hipLaunchKernelGGL(k_adam<true>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
   } else {
-    hipLaunchKernelGGL(k_step_inc, dim3(nblk(D.n_shapes, 256)), dim3(256), 0, s, step, D.n_shapes);
+    hipLaunchKernelGGL(k_step_inc, dim3(nblk(D.n_shapes, 256)), dim3(256), 0, s, step, D.n_shapes, a.hold);
     hipLaunchKernelGGL(k_adam<false>, grid, dim3(256), 0, s, D, p, m_dev, g, m1, m2, step, a);
   }
   return hipGetLastError();

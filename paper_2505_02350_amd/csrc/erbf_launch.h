@@ -15,12 +15,14 @@ struct StatsArgs {
   const int32_t* l1_active_dev;   // per-shape flags, or nullptr
   float tau_m;
   int32_t* step_inc;              // per-shape Adam step counters to increment with the statistics, or nullptr
+  const int32_t* hold;            // [1] or nullptr: while non-zero the step counters stay as they are
 };
 
 struct AdamArgs {
   float lr;
   const float* lr_dev;
   float beta1, beta2, eps;
+  const int32_t* hold;   // [1] or nullptr: while non-zero the pass changes nothing
 };
 
 

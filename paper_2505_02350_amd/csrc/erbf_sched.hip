@@ -5,7 +5,9 @@
 // add_activate, the final L2 phase with its cosine learning rate, level
 // requests) and the pruning itself.  Every decision is a deterministic
 // function of the device state, so the control can run inside a captured
-// step.
+// step.  With a hold word, a call that leaves a request the caller will act
+// on sets it, and calls that find it set (and the steps given it) change
+// nothing until the caller clears it.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -17,12 +19,17 @@
 
 namespace erbf {
 
-// b_f = #{ j < m : |w_j| >= tau_d } of each shape.
+// b_f = #{ j < m : |w_j| >= tau_d } of each shape.  Also notes whether the
+// call is held (its hold word set by an earlier call), before this call's
+// decisions may set the word again.
 __global__ __launch_bounds__(256) void k_sched_count(Dev D, const float* __restrict__ p,
                                                      const int32_t* __restrict__ m_dev, float tau_d,
-                                                     int32_t* __restrict__ bf) {
+                                                     int32_t* __restrict__ bf, const int32_t* __restrict__ hold) {
   __shared__ int sh[4];
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int held = hold != nullptr && *hold != 0;
+  if (tid == 0) D.sched_held[b] = held;
+  if (held) return;
   const ShapeDev S = D.shapes[b];
   const int m = min(max(m_dev[b], 0), S.cap);
   int c = 0;
@@ -38,6 +45,11 @@ __global__ __launch_bounds__(64) void k_sched_decide(Dev D, erbf_sched_state st,
                                                      const erbf_stats* __restrict__ stats) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= D.n_shapes) return;
+  if (D.sched_held[b]) {
+    // a held call: the state stays as the requesting call left it
+    D.prune_flag[b] = 0;
+    return;
+  }
   const int e = st.epoch[b] + 1;
   int l1 = st.l1_active[b], fin = st.final_phase[b];
   int add = 0, ref = 0, prune = 0;
@@ -89,22 +101,41 @@ __global__ __launch_bounds__(64) void k_sched_decide(Dev D, erbf_sched_state st,
   D.prune_flag[b] = prune;
 }
 
+// With a hold word: a request the caller will act on -- kernels asked for
+// while the shape has room and a non-empty id_all, or a grid level -- holds
+// the caller's next steps (every such shape stores the same value).
+__device__ __forceinline__ void sched_hold_after(const Dev& D, const erbf_sched_state& st, const erbf_stats* stats,
+                                                 int b, int m_after) {
+  if (!st.hold) return;
+  const bool add = st.add_request[b] && m_after < D.shapes[b].cap && stats[b].n_idall > 0;
+  if (add || st.refine_request[b]) *st.hold = 1;
+}
+
 // eq. 3-27 for the shapes whose flag is set: keep |w| >= tau_d in order,
 // compacting parameters and Adam moments in place.  One block per shape;
 // chunks of 1024 kernels are read completely before any of their kept
 // entries is written, and a kept entry never moves up, so no unread
-// entry is overwritten.
+// entry is overwritten.  Then the hold word, from the live count after
+// pruning.
 __global__ __launch_bounds__(1024) void k_sched_prune(Dev D, float* __restrict__ p, int32_t* __restrict__ m_dev,
                                                       float* __restrict__ m1, float* __restrict__ m2, float tau_d,
-                                                      int32_t* __restrict__ n_pruned) {
+                                                      erbf_sched_state st, const erbf_stats* __restrict__ stats) {
   __shared__ int sh[32];
   __shared__ int written;
   const int b = blockIdx.x, tid = threadIdx.x;
-  if (!D.prune_flag[b]) {
+  int32_t* __restrict__ n_pruned = st.n_pruned;
+  if (D.sched_held[b]) {
     if (tid == 0) n_pruned[b] = 0;
     return;
   }
   const ShapeDev S = D.shapes[b];
+  if (!D.prune_flag[b]) {
+    if (tid == 0) {
+      n_pruned[b] = 0;
+      sched_hold_after(D, st, stats, b, min(max(m_dev[b], 0), S.cap));
+    }
+    return;
+  }
   const int C = D.cap_total;
   const int m = min(max(m_dev[b], 0), S.cap);
   if (tid == 0) written = 0;
@@ -146,6 +177,7 @@ __global__ __launch_bounds__(1024) void k_sched_prune(Dev D, float* __restrict__
   if (tid == 0) {
     m_dev[b] = nm;
     n_pruned[b] = m - nm;
+    sched_hold_after(D, st, stats, b, nm);
   }
 }
 
@@ -163,6 +195,7 @@ __global__ __launch_bounds__(64) void k_sched_init(Dev D, erbf_sched_state st, e
   for (int i = 0; i < a.k_l2; ++i) st.l2_ring[(int64_t)b * a.k_l2 + i] = 0.0;
   for (int i = 0; i < a.k_l1; ++i) st.bf_ring[(int64_t)b * a.k_l1 + i] = 0;
   D.prune_flag[b] = 0;
+  if (b == 0 && st.hold) *st.hold = 0;
 }
 
 static inline unsigned nblk64(int n) { return (unsigned)((n + 63) / 64); }
@@ -175,9 +208,10 @@ hipError_t launch_sched_init(const Dev& D, const erbf_sched_state& st, const erb
 hipError_t launch_sched_step(const Dev& D, const float* p_const, float* p, int32_t* m_dev, float* m1, float* m2,
                              const erbf_sched_state& st, const erbf_sched_cfg& a, const erbf_stats* stats,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_sched_count, dim3(D.n_shapes), dim3(256), 0, s, D, p_const, m_dev, a.tau_d, st.b_f);
+  hipLaunchKernelGGL(k_sched_count, dim3(D.n_shapes), dim3(256), 0, s, D, p_const, m_dev, a.tau_d, st.b_f,
+                     st.hold);
   hipLaunchKernelGGL(k_sched_decide, dim3(nblk64(D.n_shapes)), dim3(64), 0, s, D, st, a, stats);
-  hipLaunchKernelGGL(k_sched_prune, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, m1, m2, a.tau_d, st.n_pruned);
+  hipLaunchKernelGGL(k_sched_prune, dim3(D.n_shapes), dim3(1024), 0, s, D, p, m_dev, m1, m2, a.tau_d, st, stats);
   return hipGetLastError();
 }
 

@@ -163,7 +163,7 @@ class Fitter:
 
     def fit_schedule(self, steps: int, cfg=None, tau1: float = 0.9, tau2: float = 1.1, tau_m: float = 0.02,
                      top_frac: float = 0.01, k_new: int = 256, min_abs_err: float = 0.0, stream=None,
-                     on_step=None, add_every: int = 0, state=None):
+                     on_step=None, add_every: int = 0, state=None, lagged: bool = True):
         """Algorithm 3 on every shape for `steps` full-batch steps.
 
         Each step: loss and gradient with eq. 3-21 gated by the device control
@@ -172,9 +172,13 @@ class Fitter:
         device).  When the control asks for new kernels (eq. add_activate) the
         shape is seeded from the step's residual (Algorithm 2) before the next
         step; when it asks for the next grid level, the level is appended
-        (eq. 3-16).  The host waits once per step, for one copy of the
-        requests, counts and statistics.  Returns the control state and a
-        per-step log of (L2, m, b_f, l1_active, n_added, n_pruned) per shape;
+        (eq. 3-16).  The host reads one copy of the requests, counts and
+        statistics per step.  With ``lagged`` it does so while the next step
+        already runs: the control's hold word makes a step that follows a
+        request change nothing, and after the requests are handled that step
+        is taken again, so the trajectory is the one of waiting for every
+        step (``lagged=False``).  Returns the control state and a per-step
+        log of (L2, m, b_f, l1_active, n_added, n_pruned) per shape;
         ``on_step(i, row)``, when given, is called with each step's log row.
         ``add_every`` > 0 also seeds every shape after each add_every-th step
         (a fixed growth round, next to the control's own requests) until the
@@ -188,41 +192,66 @@ class Fitter:
             self.ctx.erbf_sched_init(cfg, st, stream=stream)
         else:
             st = state
-        G = torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev)
         n = len(self.shapes)
         rows = {f: i for i, f in enumerate(core.SchedState.FLAG_ROWS)}
-        snap_h = torch.empty(tuple(st.flags.shape), dtype=torch.int32, pin_memory=True)
-        stats_h = torch.empty_like(self.ctx.stats_buf, device="cpu").pin_memory()
+        # two slots: a step's G and the copies of its control flags and
+        # statistics go to the slot it was given
+        Gs = [torch.zeros(self.ctx.n_points, dtype=torch.float32, device=self.dev) for _ in range(2)]
+        snaps = [torch.empty(tuple(st.flags.shape), dtype=torch.int32, pin_memory=True) for _ in range(2)]
+        stats_hs = [torch.empty_like(self.ctx.stats_buf, device="cpu").pin_memory() for _ in range(2)]
+        done = [torch.cuda.Event() for _ in range(2)]
         s_obj = stream if stream is not None else torch.cuda.current_stream(self.dev)
         m_host = self.m_dev.cpu().tolist()
         log = []
-        for _ in range(steps):
+
+        def enqueue(k):
             with torch.cuda.stream(s_obj):
                 self.ctx.erbf_train_step(self.p, self.m_dev, self.grad, self.m1, self.m2, self.step_dev,
                                          mode=L.MODE_DYNAMIC, l1_active_dev=st.l1_active, tau1=tau1, tau2=tau2,
-                                         tau_m=tau_m, lr_dev=st.lr, G_out=G, stream=stream)
-                self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, stream=stream)
-                snap_h.copy_(st.flags, non_blocking=True)
-                stats_h.copy_(self.ctx.stats_buf, non_blocking=True)
-            s_obj.synchronize()
-            stats = core.parse_stats(stats_h, n)
+                                         tau_m=tau_m, lr_dev=st.lr, G_out=Gs[k], hold_dev=st.hold if lagged else None,
+                                         stream=stream)
+                self.ctx.erbf_sched_step(self.p, self.m_dev, cfg, st, self.m1, self.m2, hold=lagged, stream=stream)
+                snaps[k].copy_(st.flags, non_blocking=True)
+                stats_hs[k].copy_(self.ctx.stats_buf, non_blocking=True)
+                done[k].record(s_obj)
+
+        def growth_after(i):
+            return add_every > 0 and (i + 1) % add_every == 0
+
+        k = 0
+        if steps > 0:
+            enqueue(k)
+        while len(log) < steps:
+            i = len(log)
+            # the next step goes in before this one is read, unless the host
+            # will change the state in between anyway (a growth round)
+            ahead = lagged and i + 1 < steps and not growth_after(i)
+            if ahead:
+                enqueue(1 - k)
+            done[k].synchronize()
+            stats = core.parse_stats(stats_hs[k], n)
             for b in range(n):
                 if stats[b].flags & L.FLAG_BUCKET_OVERFLOW:
-                    raise RuntimeError(f"tile lists overflowed at step {len(log)} (shape {b}): "
+                    raise RuntimeError(f"tile lists overflowed at step {i} (shape {b}): "
                                        f"{stats[b].n_bucket_pairs} entries needed; build the Fitter with a "
                                        f"larger pair_cap")
-            add, ref, l1, b_f, n_pr, fin = (snap_h[rows[f]].tolist() for f in
+            add, ref, l1, b_f, n_pr, fin = (snaps[k][rows[f]].tolist() for f in
                                             ("add_request", "refine_request", "l1_active", "b_f", "n_pruned",
                                              "final_phase"))
+            # the device's own record of whether it held the following step
+            requested = lagged and int(snaps[k][rows["hold"]][0]) != 0
+            if requested and ahead:
+                # the step enqueued ahead was held: it changed nothing
+                done[1 - k].synchronize()
             # the live counts follow from the pruning counts and the seeding
             m_now = [m_host[b] - n_pr[b] for b in range(n)]
-            grow = add_every > 0 and (len(log) + 1) % add_every == 0
+            grow = growth_after(i)
             row = []
             for b, s in enumerate(self.shapes):
                 n_added = 0
                 room = s.cap - m_now[b]
                 if (add[b] or (grow and not fin[b])) and room > 0 and stats[b].n_idall > 0:
-                    n_added = self.ctx.erbf_seed_from_error(self.p, self.m_dev, b, G, 0.5, stats[b].n_idall,
+                    n_added = self.ctx.erbf_seed_from_error(self.p, self.m_dev, b, Gs[k], 0.5, stats[b].n_idall,
                                                             top_frac=top_frac, k_new=min(k_new, room),
                                                             min_abs_err=min_abs_err, m1=self.m1, m2=self.m2,
                                                             stream=stream)
@@ -233,7 +262,14 @@ class Fitter:
                                 n_added=n_added, n_pruned=int(n_pr[b])))
             log.append(row)
             if on_step is not None:
-                on_step(len(log) - 1, row)
+                on_step(i, row)
+            if requested:
+                with torch.cuda.stream(s_obj):
+                    st.hold.zero_()
+            k = 1 - k
+            if len(log) < steps and (requested or not ahead):
+                # no step in flight that counts: enqueue the next one
+                enqueue(k)
         return st, log
 
     # ---- checkpoint / resume --------------------------------------------------
@@ -273,7 +309,10 @@ class Fitter:
             t.copy_(torch.from_numpy(a))
         if sched is not None:
             for f, _ in L.SchedState._fields_:
-                getattr(sched, f).copy_(torch.from_numpy(z["sched_" + f]))
+                if "sched_" + f in z.files:
+                    getattr(sched, f).copy_(torch.from_numpy(z["sched_" + f]))
+                elif f != "hold":
+                    raise ValueError(f"checkpoint has no control field {f}")
         torch.cuda.synchronize(self.dev)
 
     def init_inscribed(self, b: int = 0, gamma: float = 1e-3, max_centres: int = 0, stream=None):

@@ -175,3 +175,42 @@ def test_checkpoint_resume_continues_bit_for_bit(tmp_path):
     assert [r[0]["L2"] for r in log_full] == [r[0]["L2"] for r in log_a + log_b]
     rows = [json.loads(x) for x in open(tmp_path / "log.jsonl")]
     assert [r["step"] for r in rows] == list(range(25)) and rows[-1]["shapes"][0]["L2"] == log_a[-1][0]["L2"]
+
+
+def test_lagged_fit_matches_waiting_fit_bit_for_bit():
+    """The scheduled fit that enqueues each step before reading the previous
+    one (the control's hold word voids the step after a request, which is
+    then taken again) follows the same trajectory as the fit that waits for
+    every step: two shapes whose requests come at different steps, growth
+    rounds, a level request, pruning; parameters, moments, counters, control
+    state and every log row equal."""
+    torch = _torch()
+    from paper_2505_02350_amd import core
+    from paper_2505_02350_amd.fit import Fitter, ShapeInput
+    probs = [synth.make_custom(57, [16, 24], 40, (1.6, 2.6), kinds=("ellipsoid", "torus"), bands=[None, 0.15],
+                               cap=200),
+             synth.make_custom(61, [16, 24], 48, (1.4, 2.4), kinds=("box", "ellipsoid"), bands=[None, 0.15],
+                               cap=160)]
+    cfg = core.sched_cfg(k_l2=4, tau_l2=1e6, k_l1=6, tau_l1=3.0, tau_d=0.02, T_e=40, M_e=50, lr0=1e-2,
+                         lr_final=1e-3, lr_min=1e-5, refine_epochs=(10,))
+    kw = dict(tau1=float(np.float32(0.9)), tau2=float(np.float32(1.1)), tau_m=1e3, top_frac=0.05, k_new=16,
+              add_every=9)
+    runs = []
+    for lagged in (False, True):
+        print(f"scheduled fit, two shapes, lagged={lagged}", flush=True)
+        f = Fitter([ShapeInput.from_problem(p) for p in probs], cull_k=3.0, all_levels=False)
+        f.refine(0)
+        f.refine(1)
+        st, log = f.fit_schedule(50, cfg, lagged=lagged, **kw)
+        torch.cuda.synchronize()
+        runs.append((f, st, log))
+    (fa, sa, la), (fb, sb, lb) = runs
+    assert la == lb
+    assert sum(r[b]["n_added"] > 0 for r in la for b in range(2)) >= 3
+    assert any(r[b]["n_pruned"] > 0 for r in la for b in range(2))
+    assert fa.next_level == fb.next_level == [2, 2]
+    for name in ("p", "m_dev", "m1", "m2", "step_dev"):
+        assert torch.equal(getattr(fa, name), getattr(fb, name)), name
+    for name in ("flags", "lr", "l2_ring", "bf_ring"):
+        assert torch.equal(getattr(sa, name), getattr(sb, name)), name
+    assert int(sb.hold[0]) == 0
