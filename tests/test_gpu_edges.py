@@ -8,7 +8,8 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_helpers import TAU1, TAU2, GpuProblem, oracle_grads_dict, oracle_levels, record, rel_inf
+from gpu_helpers import (TAU1, TAU2, GpuProblem, oracle_grads_dict, oracle_levels, pair_cap_estimate, record,
+                         rel_inf)
 from test_gpu_parity import _loss_case
 
 pytestmark = pytest.mark.gpu
@@ -186,3 +187,50 @@ def test_bucket_total_past_2_31_is_flagged_and_counted():
     assert st.n_bucket_pairs == m * (n // 8) ** 3 > 2 ** 31
     assert st.flags & L.FLAG_BUCKET_OVERFLOW
     ctx.close()
+
+
+def _host_tile_counts(prob):
+    """Tiles of 8^3 points whose point box each kernel's cull ball reaches
+    (float64, no widening), over every level; all tiles active."""
+    K = O.kernels_from_packed(prob.params, prob.m, prob.cap, prob.cull_k, prob.weight_map, prob.orientation)
+    r2 = K.r2
+    out = np.zeros(len(r2), int)
+    for lv in prob.levels:
+        ax = np.asarray(lv.axis, np.float64)
+        t = np.arange((lv.n + 7) // 8)
+        lo, hi = ax[8 * t], ax[np.minimum(8 * t + 7, lv.n - 1)]
+        for j in range(len(r2)):
+            e = [np.maximum(np.maximum(lo - K.c[j, d], K.c[j, d] - hi), 0.0) for d in range(3)]
+            d2 = e[2][:, None, None] ** 2 + e[1][None, :, None] ** 2 + e[0][None, None, :] ** 2
+            out[j] += int((d2 < r2[j]).sum())
+    return out
+
+
+def test_kept_tile_slots_and_walked_kernels_agree():
+    """The count pass keeps at most hit_cap = min(512, 2 pair_cap / capacity)
+    tile slots per kernel and the emit pass copies them; a kernel with more
+    tiles is walked again.  With the list capacity exactly the step's entry
+    count, kernels of both kinds occur (scales spread over e^1.2 .. e^4); the
+    gradient and the statistics equal bit for bit those of a context where
+    every kernel copies, which the oracle checks."""
+    torch = _torch()
+    prob = synth.make_custom(67, [40], 64, (1.2, 4.0), cap=64)
+    _, g_all, st_all = _loss_case("edge_hit_cap", prob, O.MODE_FIXED, lam=1e-4)
+    E = st_all.n_bucket_pairs
+    hit_cap = min(512, 2 * E // prob.cap)
+    counts = _host_tile_counts(prob)
+    record("edge_hit_cap_mix", entries=E, hit_cap=hit_cap, walked=int((counts > hit_cap).sum()),
+           max_tiles=int(counts.max()))
+    assert 16 <= hit_cap < 512
+    assert (counts > hit_cap + 2).sum() >= 3 and (counts < hit_cap - 2).sum() >= 3
+    # the oracle-checked context (default capacity) keeps every kernel's slots
+    assert min(512, 2 * pair_cap_estimate(prob) // prob.cap) > counts.max() + 2
+    _, t32, _ = oracle_levels(prob)
+    tight = GpuProblem(prob, t32, pair_cap=E)
+    g = tight.ctx.erbf_loss_grad(tight.p, tight.m_dev, mode=O.MODE_FIXED, lam=1e-4, tau1=TAU1, tau2=TAU2)
+    torch.cuda.synchronize()
+    st = tight.ctx.stats()[0]
+    assert st.flags == 0 and st.n_bucket_pairs == E
+    assert (st.L2, st.L1, st.P_fwd, st.P_bwd, st.n_idall) == (st_all.L2, st_all.L1, st_all.P_fwd, st_all.P_bwd,
+                                                               st_all.n_idall)
+    assert torch.equal(g, g_all)
