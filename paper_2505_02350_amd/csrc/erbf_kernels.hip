@@ -1801,26 +1801,6 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(Dev D, const float* __restri
 // the statistics; a grid-wide pass applies the weights to the gradient.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double block_sum_256(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v = wave_sum(v);
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ float block_max_256(float v, float* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v = wave_max_f(v);
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  const float r = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-  __syncthreads();
-  return r;
-}
-
 // MODE 0: forward statistics; 1: backward pair count only; 2: both, plus
 // the sums of eq. 3-21 and L1 over the weights.
 // BATCH: the forward part comes from the mini-batch records (n_pts of them)
@@ -1829,7 +1809,7 @@ template <int MODE, bool BATCH>
 __device__ __forceinline__ void stats_part_body(const Dev& D, const float* __restrict__ p,
                                                 const int32_t* __restrict__ m_dev, const float* __restrict__ grad,
                                                 int n_pts) {
-  __shared__ double shd[4];
+  __shared__ double shd[4][7];
   __shared__ float shf[4];
   const int part = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const ShapeDev S = D.shapes[b];
@@ -1882,17 +1862,35 @@ __device__ __forceinline__ void stats_part_body(const Dev& D, const float* __res
       den += (g2 - g1) * (g2 - g1);
     }
   }
-  StatPart sp;
-  sp.l2 = block_sum_256(l2, shd);
-  sp.nid = block_sum_256(nid, shd);
-  sp.pf = block_sum_256(pf, shd);
-  sp.pb = block_sum_256(pb, shd);
-  sp.l1 = block_sum_256(l1, shd);
-  sp.num = block_sum_256(num, shd);
-  sp.den = block_sum_256(den, shd);
-  sp.mx = block_max_256(mx, shf);
-  sp.pad = 0;
-  if (tid == 0) D.stat_part[b * kStatParts + part] = sp;
+  // wave sums, then the four waves' sums in a fixed order, all behind one
+  // barrier
+  double v[7] = {l2, nid, pf, pb, l1, num, den};
+#pragma unroll
+  for (int i = 0; i < 7; ++i) v[i] = wave_sum(v[i]);
+  mx = wave_max_f(mx);
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) shd[wv][i] = v[i];
+    shf[wv] = mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double r[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r[i] = (shd[0][i] + shd[1][i]) + (shd[2][i] + shd[3][i]);
+    StatPart sp;
+    sp.l2 = r[0];
+    sp.nid = r[1];
+    sp.pf = r[2];
+    sp.pb = r[3];
+    sp.l1 = r[4];
+    sp.num = r[5];
+    sp.den = r[6];
+    sp.mx = fmaxf(fmaxf(shf[0], shf[1]), fmaxf(shf[2], shf[3]));
+    sp.pad = 0;
+    D.stat_part[b * kStatParts + part] = sp;
+  }
 }
 
 template <int MODE, bool BATCH>
