@@ -501,6 +501,8 @@ def main():
                     help="kernel records staged per forward chunk: 64, 128 or 256; default: the library's")
     ap.add_argument("--bwd-waves", type=int, default=-1,
                     help="waves per backward tile workgroup: 2, 4 or 8; default: the library's")
+    ap.add_argument("--tile-order", type=int, default=-1,
+                    help="1: tile kernels take the longest lists first, 0: slot order (default: the library's)")
     ap.add_argument("--init", action="store_true", help="add the inscribed-sphere initialisation timing")
     ap.add_argument("--minibatch", action="store_true", help="add the mini-batch step timing (B_s = 10000)")
     ap.add_argument("--octree", action="store_true", help="add the step on octree layers")
@@ -584,7 +586,7 @@ def main():
     launch = fit.ctx.erbf_get_launch()
     for key, val in (("variant", args.variant), ("slot_chunk", args.slot_chunk),
                      ("bucket_rank", args.bucket_rank), ("fwd_chunk", args.fwd_chunk),
-                     ("bwd_waves", args.bwd_waves)):
+                     ("bwd_waves", args.bwd_waves), ("tile_order", args.tile_order)):
         if val >= 0:
             launch[key] = val
     fit.ctx.erbf_set_launch_dict(launch)

@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define ERBF_ABI_VERSION 6
+#define ERBF_ABI_VERSION 7
 #define ERBF_MAX_LEVELS 8
 #define ERBF_MAX_SHAPES 1024
 
@@ -531,7 +531,12 @@ int erbf_get_variant(const erbf_ctx* ctx, int32_t* variant);
  *                uses 256)
  *   bwd_waves    waves of a backward tile workgroup, each taking its own
  *                groups of 64 kernels of the tile's list: 2, 4 or 8 (default
- *                4; the fused variant always uses 4) */
+ *                4; the fused variant always uses 4)
+ *   tile_order   1 (default): the tile kernels take the active tiles longest
+ *                list first (64 classes of list length, 16 entries wide; a
+ *                one-workgroup pass orders them after every list build, and
+ *                slot_chunk deals runs of that order to the XCDs), so that
+ *                the long tiles do not finish last; 0: in slot order */
 typedef struct {
   int32_t variant;
   int32_t slot_chunk;
@@ -539,6 +544,7 @@ typedef struct {
   int32_t bucket_rank;
   int32_t fwd_chunk;
   int32_t bwd_waves;
+  int32_t tile_order;
 } erbf_launch_cfg;
 
 /* ERBF_ERR_UNSUPPORTED for bucket_rank 1 with a shape capacity above 32768. */
@@ -548,8 +554,9 @@ int erbf_get_launch(const erbf_ctx* ctx, erbf_launch_cfg* cfg);
 /* Tune the context's launch choices for erbf_loss_grad by timing it (one
  * warm-up and `reps` timed calls per candidate, HIP events on `stream`), one
  * choice after the other: the variant (every ERBF_N_VARIANTS entry), then
- * slot_chunk (0, 2, 8, 32), bwd_waves (2, 4, 8) and fwd_chunk (64, 128, 256)
- * (both unless the fused variant won), samp_split (8, 16, 32; only when a
+ * slot_chunk (0, 2, 8, 32), tile_order (0, 1), bwd_waves (2, 4, 8) and
+ * fwd_chunk (64, 128, 256) (both unless the fused variant won), samp_split
+ * (8, 16, 32; only when a
  * surface sample level is registered) and
  * bucket_rank (when the shapes allow the ranked lists), each with the best
  * of the choices before it.  The choice is kept per context, so contexts

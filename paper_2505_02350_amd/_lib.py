@@ -27,7 +27,7 @@ MODE_FIXED, MODE_DYNAMIC, MODE_L2 = 0, 1, 2
 WEIGHT_SIGNED_SQUARE, WEIGHT_LINEAR = 0, 1
 ORIENT_QUATERNION, ORIENT_EULER = 0, 1
 VARIANT_FWD_PERSISTENT, VARIANT_BWD_PERSISTENT, VARIANT_FUSED, N_VARIANTS = 1, 2, 4, 8
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 class ErbfError(RuntimeError):
@@ -100,7 +100,8 @@ STATS_BYTES = ctypes.sizeof(Stats)
 # (name, restype, argtypes) of every exported symbol of include/erbf.h
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("slot_chunk", ctypes.c_int32), ("samp_split", ctypes.c_int32),
-                ("bucket_rank", ctypes.c_int32), ("fwd_chunk", ctypes.c_int32), ("bwd_waves", ctypes.c_int32)]
+                ("bucket_rank", ctypes.c_int32), ("fwd_chunk", ctypes.c_int32), ("bwd_waves", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 _V = ctypes.c_void_p

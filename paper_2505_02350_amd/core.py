@@ -305,9 +305,9 @@ class Context:
         return v.value
 
     def erbf_set_launch(self, variant: int, slot_chunk: int, samp_split: int, bucket_rank: int,
-                        fwd_chunk: int = 256, bwd_waves: int = 4):
+                        fwd_chunk: int = 256, bwd_waves: int = 4, tile_order: int = 1):
         c = L.LaunchCfg(int(variant), int(slot_chunk), int(samp_split), int(bucket_rank), int(fwd_chunk),
-                        int(bwd_waves))
+                        int(bwd_waves), int(tile_order))
         L.check(self.lib.erbf_set_launch(self.handle, ctypes.byref(c)))
 
     def erbf_get_launch(self):

@@ -50,7 +50,7 @@ struct Layout {
   int hit_cap = 0;   // tile slots kept per kernel by the count pass (0: the emit pass walks)
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_tile_cnt,
       off_tile_start64, off_kslot, off_sort_keys[2],
-      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
+      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_tile_order, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_sched_held, off_b_l2, off_b_abs, off_b_id, off_b_pf,
@@ -141,6 +141,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_rhist_ex = take(sizeof(int32_t) * (256 * (size_t)L.radix_nb + 256));
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
+  L.off_tile_order = take(sizeof(int32_t) * ((size_t)L.tiles_total + 1));
   // the count pass keeps each kernel's first hit_cap tile slots, so the emit
   // pass copies them instead of walking the box again; sized to at most
   // twice the list capacity
@@ -308,6 +309,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.rhist_ex = reinterpret_cast<int32_t*>(w + lay.off_rhist_ex);
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
+  D.tile_order = reinterpret_cast<int32_t*>(w + lay.off_tile_order);
   D.hits = reinterpret_cast<int32_t*>(w + lay.off_hits);
   D.hit_cap = lay.hit_cap;
   D.kstart = reinterpret_cast<int64_t*>(w + lay.off_kstart);
@@ -365,6 +367,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.samp_split = 16;
   D.fwd_chunk = 256;
   D.bwd_waves = 4;
+  D.tile_order_on = 1;
   {
     int max_cap = 1;
     for (int b = 0; b < cfg->n_shapes; ++b) max_cap = std::max(max_cap, cfg->shapes[b].m_cap);
@@ -819,17 +822,19 @@ void apply_launch(erbf_ctx* ctx, const erbf_launch_cfg& c) {
   ctx->D.bucket_rank = c.bucket_rank;
   ctx->D.fwd_chunk = c.fwd_chunk;
   ctx->D.bwd_waves = c.bwd_waves;
+  ctx->D.tile_order_on = c.tile_order;
 }
 erbf_launch_cfg current_launch(const erbf_ctx* ctx) {
-  return erbf_launch_cfg{ctx->D.variant,     ctx->D.slot_chunk, ctx->D.samp_split,
-                         ctx->D.bucket_rank, ctx->D.fwd_chunk,  ctx->D.bwd_waves};
+  return erbf_launch_cfg{ctx->D.variant,   ctx->D.slot_chunk, ctx->D.samp_split,   ctx->D.bucket_rank,
+                         ctx->D.fwd_chunk, ctx->D.bwd_waves,  ctx->D.tile_order_on};
 }
 int32_t current_field(const erbf_launch_cfg& c, int field) {
-  const int32_t f[] = {c.variant, c.slot_chunk, c.samp_split, c.bucket_rank, c.fwd_chunk, c.bwd_waves};
+  const int32_t f[] = {c.variant, c.slot_chunk, c.samp_split, c.bucket_rank, c.fwd_chunk, c.bwd_waves, c.tile_order};
   return f[field];
 }
 erbf_launch_cfg with(erbf_launch_cfg c, int field, int32_t v) {
-  int32_t* f[] = {&c.variant, &c.slot_chunk, &c.samp_split, &c.bucket_rank, &c.fwd_chunk, &c.bwd_waves};
+  int32_t* f[] = {&c.variant,   &c.slot_chunk, &c.samp_split, &c.bucket_rank,
+                  &c.fwd_chunk, &c.bwd_waves,  &c.tile_order};
   *f[field] = v;
   return c;
 }
@@ -840,7 +845,8 @@ int erbf_set_launch(erbf_ctx* ctx, const erbf_launch_cfg* cfg) {
       cfg->slot_chunk > 256 || cfg->samp_split < 1 || cfg->samp_split > kSampSplitMax ||
       (cfg->bucket_rank != 0 && cfg->bucket_rank != 1) ||
       (cfg->fwd_chunk != 64 && cfg->fwd_chunk != 128 && cfg->fwd_chunk != 256) ||
-      (cfg->bwd_waves != 2 && cfg->bwd_waves != 4 && cfg->bwd_waves != 8))
+      (cfg->bwd_waves != 2 && cfg->bwd_waves != 4 && cfg->bwd_waves != 8) ||
+      (cfg->tile_order != 0 && cfg->tile_order != 1))
     return fail(ERBF_ERR_INVALID_ARG, "erbf_set_launch: bad arguments");
   if (cfg->bucket_rank && max_shape_cap(ctx) > kRankMaxCap)
     return fail(ERBF_ERR_UNSUPPORTED, "erbf_set_launch: ranked tile lists need shape capacities <= 32768");
@@ -887,7 +893,8 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
     *ms_out = ms / (float)reps;
     return ERBF_OK;
   };
-  erbf_launch_cfg best{0, 0, saved.samp_split, saved.bucket_rank, saved.fwd_chunk, saved.bwd_waves};
+  erbf_launch_cfg best{0, 0, saved.samp_split, saved.bucket_rank, saved.fwd_chunk, saved.bwd_waves,
+                       saved.tile_order_on};
   float best_ms = 0.f;
   bool have = false;
   auto consider = [&](const erbf_launch_cfg& c, float* ms_slot) -> int {
@@ -919,6 +926,7 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
   };
   const Axis axes[] = {
       {1, 3, {2, 8, 32}},     // XCD runs of the grid launches
+      {6, 2, {0, 1}},         // tiles longest list first or in slot order
       {5, 3, {2, 4, 8}},      // backward waves per tile
       {4, 3, {64, 128, 256}}, // forward records staged per chunk
       {2, 3, {8, 16, 32}},    // sample tiles' split
@@ -948,6 +956,7 @@ int erbf_autotune(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg*
     ctx->D.bucket_rank = saved.bucket_rank;
     ctx->D.fwd_chunk = saved.fwd_chunk;
     ctx->D.bwd_waves = saved.bwd_waves;
+    ctx->D.tile_order_on = saved.tile_order_on;
   }
   return status;
 }

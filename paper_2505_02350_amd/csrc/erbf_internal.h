@@ -96,6 +96,7 @@ struct Dev {
   int32_t* tile_keys;       // [pair_cap] tile slot of each tile-major entry (sorted)
   int32_t* tile_e;          // [pair_cap] kernel-major index of each tile-major entry
   int32_t* items;           // [pair_cap] kernel of each tile-major entry: ascending within a tile
+  int32_t* tile_order;      // [tiles_total] active slots, longest list first (launch order of the tile kernels)
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
   int32_t* hits;            // [cap_total * hit_cap] tile slots a kernel hits, in visit order (count pass)
   int64_t* kstart;          // [cap_total + 1] exclusive scan of kcnt
@@ -156,6 +157,7 @@ struct Dev {
   int32_t bucket_rank;      // 1: tile lists by atomic placement and per-tile ranks; 0: by the radix sort
   int32_t fwd_chunk;        // kernel records a forward tile workgroup stages at a time: 64, 128 or 256
   int32_t bwd_waves;        // waves of a backward tile workgroup: 2, 4 or 8
+  int32_t tile_order_on;    // 1: tile kernels take the slots of tile_order (longest list first)
   int32_t rank_words;       // bitmap words per wave of the rank pass (largest shape capacity / 32)
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass

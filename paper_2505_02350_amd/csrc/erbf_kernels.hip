@@ -626,6 +626,37 @@ __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __res
   D.tile_start[s] = (int)lo;
 }
 
+// Launch order of the tile kernels: the active slots by the length of their
+// kernel lists, longest first, in 64 classes of 16 entries (the last class
+// takes every list of 1008 entries or more).  A tile's work grows with its
+// list, so the long tiles start first instead of finishing last.  The order
+// inside a class follows the LDS atomics and is not fixed; no result depends
+// on it (every tile writes only its own outputs).  One workgroup.
+constexpr int kOrderClasses = 64;
+
+__global__ __launch_bounds__(1024) void k_tile_order(Dev D, int n_slots) {
+  __shared__ int start[kOrderClasses];
+  const int t = threadIdx.x;
+  if (t < kOrderClasses) start[t] = 0;
+  __syncthreads();
+  auto cls = [&](int s) {
+    const int len = D.tile_start[s + 1] - D.tile_start[s];
+    return kOrderClasses - 1 - min(len >> 4, kOrderClasses - 1);
+  };
+  for (int s = t; s < n_slots; s += 1024) atomicAdd(&start[cls(s)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int c = 0; c < kOrderClasses; ++c) {
+      const int n = start[c];
+      start[c] = run;
+      run += n;
+    }
+  }
+  __syncthreads();
+  for (int s = t; s < n_slots; s += 1024) D.tile_order[atomicAdd(&start[cls(s)], 1)] = s;
+}
+
 // Tile lists without a sort (rank mode): the emit pass has placed every
 // tile's entries in its range [start, end) in arbitrary order (sort_j[0],
 // sort_vals[0]).  One wave per tile marks the tile's kernels in a bitmap over
@@ -799,6 +830,12 @@ __device__ __forceinline__ int tile_slot(int b, int n, int chunk) {
   const int x = b & 7, k = b >> 3;
   const int slot = ((k / chunk) * 8 + x) * chunk + (k % chunk);
   return slot < n ? slot : -1;
+}
+
+// The slot at launch position pos (-1: none): the pos-th entry of the launch
+// order (the active tiles, longest list first) or, without it, slot pos.
+__device__ __forceinline__ int ordered_slot(const Dev& D, int pos) {
+  return pos < 0 ? -1 : (D.tile_order_on ? D.tile_order[pos] : pos);
 }
 
 __device__ void bwd_stage_from_registers(const Dev& D, const LevelDev& L, int slot, int tx, int ty, int tz,
@@ -982,7 +1019,7 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
 template <bool LOSS, int C>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
   __shared__ __align__(16) char lds[sizeof(FwdLdsT<C>)];
-  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  const int slot = ordered_slot(D, tile_slot(blockIdx.x, n_slots, D.slot_chunk));
   if (slot < 0) return;
   forward_tile<LOSS, false, C>(D, slot, f_out, tau1, tau2, lds);
 }
@@ -995,8 +1032,8 @@ template <bool LOSS, int C>
 __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __restrict__ f_out, float tau1,
                                                             float tau2, int n_slots) {
   __shared__ __align__(16) char lds[sizeof(FwdLdsT<C>)];
-  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    forward_tile<LOSS, false, C>(D, slot, f_out, tau1, tau2, lds);
+  for (int pos = blockIdx.x; pos < n_slots; pos += gridDim.x) {
+    forward_tile<LOSS, false, C>(D, ordered_slot(D, pos), f_out, tau1, tau2, lds);
     __syncthreads();
   }
 }
@@ -1007,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __rest
 // of the two kernels bit for bit).  The LDS of the two bodies overlaps.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step_tiles(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
   __shared__ __align__(16) char lds[kTileLdsBytes];
-  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  const int slot = ordered_slot(D, tile_slot(blockIdx.x, n_slots, D.slot_chunk));
   if (slot < 0) return;
   forward_tile<true, true, kFwdChunk>(D, slot, f_out, tau1, tau2, lds);
 }
@@ -1015,8 +1052,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 __global__ __launch_bounds__(256) void k_step_tiles_persistent(Dev D, float* __restrict__ f_out, float tau1,
                                                                float tau2, int n_slots) {
   __shared__ __align__(16) char lds[kTileLdsBytes];
-  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    forward_tile<true, true, kFwdChunk>(D, slot, f_out, tau1, tau2, lds);
+  for (int pos = blockIdx.x; pos < n_slots; pos += gridDim.x) {
+    forward_tile<true, true, kFwdChunk>(D, ordered_slot(D, pos), f_out, tau1, tau2, lds);
     __syncthreads();
   }
 }
@@ -1616,7 +1653,7 @@ template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_tiles(
     Dev D, const float* __restrict__ Gsrc, int n_slots) {
   __shared__ BwdLdsT<W> B;
-  const int slot = tile_slot(blockIdx.x, n_slots, D.slot_chunk);
+  const int slot = ordered_slot(D, tile_slot(blockIdx.x, n_slots, D.slot_chunk));
   if (slot < 0) return;
   bwd_tile<W>(D, slot, Gsrc, B);
 }
@@ -1625,8 +1662,8 @@ template <int W>
 __global__ __launch_bounds__(64 * W) void k_bwd_tiles_persistent(Dev D, const float* __restrict__ Gsrc,
                                                                   int n_slots) {
   __shared__ BwdLdsT<W> B;
-  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-    bwd_tile<W>(D, slot, Gsrc, B);
+  for (int pos = blockIdx.x; pos < n_slots; pos += gridDim.x) {
+    bwd_tile<W>(D, ordered_slot(D, pos), Gsrc, B);
     __syncthreads();
   }
 }
@@ -2243,6 +2280,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
     const size_t lds = sizeof(uint32_t) * 4 * 2 * (size_t)D.rank_words;
     hipLaunchKernelGGL(k_tile_rank, dim3(nblk(n_slots, 4)), dim3(256), lds, s, D, n_slots);
+    if (D.tile_order_on) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
@@ -2276,6 +2314,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     jin = jout;
   }
   hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.tile_keys, n_slots);
+  if (D.tile_order_on) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
   return hipGetLastError();
 }
 

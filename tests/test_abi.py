@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 def test_abi_version(lib):
     from paper_2505_02350_amd import _lib as L
-    assert lib.erbf_abi_version() == L.ABI_VERSION == 6
+    assert lib.erbf_abi_version() == L.ABI_VERSION == 7
 
 
 def _struct_sizes_from_c():
@@ -52,11 +52,11 @@ def _struct_sizes_from_c():
 #include <stddef.h>
 #include "erbf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(erbf_shape_desc), sizeof(erbf_config),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(erbf_shape_desc), sizeof(erbf_config),
          sizeof(erbf_level), sizeof(erbf_params), sizeof(erbf_loss_cfg), sizeof(erbf_stats),
          sizeof(erbf_adam_cfg), sizeof(erbf_seed_cfg), offsetof(erbf_stats, P_fwd_total),
          sizeof(erbf_launch_cfg), offsetof(erbf_launch_cfg, samp_split), offsetof(erbf_launch_cfg, bwd_waves),
-         sizeof(erbf_sched_state), offsetof(erbf_adam_cfg, hold_dev));
+         sizeof(erbf_sched_state), offsetof(erbf_adam_cfg, hold_dev), offsetof(erbf_launch_cfg, tile_order));
   return 0;
 }
 '''
@@ -81,6 +81,7 @@ def test_struct_layouts_match_binding():
     assert sizes[9] == ctypes.sizeof(L.LaunchCfg) and sizes[10] == L.LaunchCfg.samp_split.offset
     assert sizes[11] == L.LaunchCfg.bwd_waves.offset
     assert sizes[12] == ctypes.sizeof(L.SchedState) and sizes[13] == L.AdamCfg.hold_dev.offset
+    assert sizes[14] == L.LaunchCfg.tile_order.offset
 
 
 def _cfg(L, shapes, pair_cap=1024, cull_k=3.0, wm=0):

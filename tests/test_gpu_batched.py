@@ -44,15 +44,15 @@ def test_batched_equals_plain_bitwise_and_variants():
     lams = torch.tensor([1e-5, 1e-4, 1e-3, 1e-4], device="cuda")
     fb = _fitter(probs)
     outs = {}
-    keys = [(v, c, r, 256, 4) for v in range(8) for c in (0, 8) for r in (1, 0)]
-    keys += [(v, 8, 0, ch, w) for v in (0, 3) for ch in (64, 128, 256) for w in (2, 4, 8)]
-    for v, c, r, ch, w in keys:
+    keys = [(v, c, r, 256, 4, o) for v in range(8) for c in (0, 8) for r in (1, 0) for o in (1, 0)]
+    keys += [(v, 8, 0, ch, w, 1) for v in (0, 3) for ch in (64, 128, 256) for w in (2, 4, 8)]
+    for v, c, r, ch, w, o in keys:
         print(f"batched loss_grad, 4 shapes, launch variant {v}, XCD runs {c}, ranked lists {r}, "
-              f"forward chunk {ch}, backward waves {w}", flush=True)
-        fb.ctx.erbf_set_launch(v, c, 16, r, ch, w)
+              f"forward chunk {ch}, backward waves {w}, longest tiles first {o}", flush=True)
+        fb.ctx.erbf_set_launch(v, c, 16, r, ch, w, o)
         g = fb.ctx.erbf_loss_grad_batched(fb.p, fb.m_dev, lambda_dev=lams, tau1=TAU1, tau2=TAU2)
         torch.cuda.synchronize()
-        outs[(v, c, r, ch, w)] = (g.clone(), fb.ctx.stats())
+        outs[(v, c, r, ch, w, o)] = (g.clone(), fb.ctx.stats())
     for k in keys[1:]:
         assert torch.equal(outs[k][0], outs[keys[0]][0]), k
         assert all(a.P_bwd == b.P_bwd and a.P_fwd == b.P_fwd and a.L2 == b.L2
@@ -122,6 +122,7 @@ def test_autotune_picks_a_variant_and_keeps_results():
     launch = fb.ctx.erbf_get_launch()
     print("autotuned launch:", launch, flush=True)
     assert launch["variant"] == v and launch["fwd_chunk"] in (64, 128, 256) and launch["bwd_waves"] in (2, 4, 8)
+    assert launch["tile_order"] in (0, 1)
     assert torch.equal(fb.p, p0)
     g1 = fb.ctx.erbf_loss_grad(fb.p, fb.m_dev, lam=1e-4, tau1=TAU1, tau2=TAU2)
     torch.cuda.synchronize()
