@@ -1469,11 +1469,22 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W
         T[4] = fmaf(PP.w, e, T[4]);
         pbg += __popcll(__ballot(in));
       };
-      point(B.spx[k0], true);
-      point(B.spx[k0 + 1], false);
-      for (int k = 1; k < kn; ++k) {
-        point(B.spx[k0 + 2 * k], false);
-        point(B.spx[k0 + 2 * k + 1], false);
+      // a row holds one to four point pairs (kn, wave-uniform); the pairs
+      // are unrolled so their LDS reads take fixed offsets from the row
+      const float4* rp = B.spx + k0;
+      point(rp[0], true);
+      point(rp[1], false);
+      if (kn >= 2) {
+        point(rp[2], false);
+        point(rp[3], false);
+      }
+      if (kn >= 3) {
+        point(rp[4], false);
+        point(rp[5], false);
+      }
+      if (kn >= 4) {
+        point(rp[6], false);
+        point(rp[7], false);
       }
       T[0] += s0; T[1] += t1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
       T[5] = fmaf(dy, t1, T[5]); T[6] = fmaf(dz, t1, T[6]);
