@@ -8,6 +8,7 @@
 
 namespace erbf {
 
+constexpr int kOrderClasses = 64;   // list-length classes of the tile launch order
 constexpr int kTile = 8;            // grid points per tile edge (tile = 8^3 points)
 constexpr int kRecF4 = 3;           // float4 per kernel record
 constexpr float kLog2e = 1.4426950408889634f;

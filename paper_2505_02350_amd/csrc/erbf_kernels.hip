@@ -627,34 +627,56 @@ __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __res
 }
 
 // Launch order of the tile kernels: the active slots by the length of their
-// kernel lists, longest first, in 64 classes of 16 entries (the last class
-// takes every list of 1008 entries or more).  A tile's work grows with its
-// list, so the long tiles start first instead of finishing last.  The order
-// inside a class follows the LDS atomics and is not fixed; no result depends
-// on it (every tile writes only its own outputs).  One workgroup.
-constexpr int kOrderClasses = 64;
+// kernel lists, longest first, in kOrderClasses classes of 16 entries (the
+// last class takes every list of 1008 entries or more).  A tile's work grows
+// with its list, so the long tiles start first instead of finishing last.
+// The order inside a class follows the LDS atomics and is not fixed; no
+// result depends on it (every tile writes only its own outputs).  One
+// workgroup; each thread reads the list lengths of up to kOrderRegs slots
+// with all loads in flight and keeps their classes for the placing pass.
+constexpr int kOrderRegs = 16;
 
 __global__ __launch_bounds__(1024) void k_tile_order(Dev D, int n_slots) {
   __shared__ int start[kOrderClasses];
   const int t = threadIdx.x;
   if (t < kOrderClasses) start[t] = 0;
   __syncthreads();
-  auto cls = [&](int s) {
-    const int len = D.tile_start[s + 1] - D.tile_start[s];
-    return kOrderClasses - 1 - min(len >> 4, kOrderClasses - 1);
+  auto classes = [&](int s0, int (&c)[kOrderRegs]) {
+    int lo[kOrderRegs], hi[kOrderRegs];
+#pragma unroll
+    for (int u = 0; u < kOrderRegs; ++u) {
+      const int s = min(s0 + 1024 * u + t, n_slots - 1);
+      lo[u] = D.tile_start[s];
+      hi[u] = D.tile_start[s + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kOrderRegs; ++u)
+      c[u] = s0 + 1024 * u + t < n_slots ? kOrderClasses - 1 - min((hi[u] - lo[u]) >> 4, kOrderClasses - 1) : -1;
   };
-  for (int s = t; s < n_slots; s += 1024) atomicAdd(&start[cls(s)], 1);
+  const bool one_round = n_slots <= 1024 * kOrderRegs;
+  int c[kOrderRegs];
+  for (int s0 = 0; s0 < n_slots; s0 += 1024 * kOrderRegs) {
+    classes(s0, c);
+#pragma unroll
+    for (int u = 0; u < kOrderRegs; ++u)
+      if (c[u] >= 0) atomicAdd(&start[c[u]], 1);
+  }
   __syncthreads();
   if (t == 0) {
     int run = 0;
-    for (int c = 0; c < kOrderClasses; ++c) {
-      const int n = start[c];
-      start[c] = run;
+    for (int k = 0; k < kOrderClasses; ++k) {
+      const int n = start[k];
+      start[k] = run;
       run += n;
     }
   }
   __syncthreads();
-  for (int s = t; s < n_slots; s += 1024) D.tile_order[atomicAdd(&start[cls(s)], 1)] = s;
+  for (int s0 = 0; s0 < n_slots; s0 += 1024 * kOrderRegs) {
+    if (!one_round) classes(s0, c);
+#pragma unroll
+    for (int u = 0; u < kOrderRegs; ++u)
+      if (c[u] >= 0) D.tile_order[atomicAdd(&start[c[u]], 1)] = s0 + 1024 * u + t;
+  }
 }
 
 // Tile lists without a sort (rank mode): the emit pass has placed every
@@ -2291,6 +2313,12 @@ hipError_t launch_scan_any(const int32_t* in, int n, T* blocks, T* out, int64_t*
   return hipGetLastError();
 }
 
+// the launch order of the tile kernels (when switched on), after tile_start
+static void launch_tile_order(const Dev& D, int n_slots, hipStream_t s) {
+  if (!D.tile_order_on || n_slots <= 0) return;
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
+}
+
 hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, int n_slots, hipStream_t s) {
   const int nkb = (int)nblk(D.cap_total, 4);   // count/emit blocks, four kernels each
   // the count pass also forms every kernel's record, which the forward and
@@ -2314,7 +2342,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
     const size_t lds = sizeof(uint32_t) * 4 * 2 * (size_t)D.rank_words;
     hipLaunchKernelGGL(k_tile_rank, dim3(nblk(n_slots, 4)), dim3(256), lds, s, D, n_slots);
-    if (D.tile_order_on) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
+    launch_tile_order(D, n_slots, s);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
@@ -2348,7 +2376,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     jin = jout;
   }
   hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.tile_keys, n_slots);
-  if (D.tile_order_on) hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
+  launch_tile_order(D, n_slots, s);
   return hipGetLastError();
 }
 
