@@ -50,7 +50,7 @@ struct Layout {
   int hit_cap = 0;   // tile slots kept per kernel by the count pass (0: the emit pass walks)
   size_t off_levels, off_shapes, off_kshape, off_slot_tile, off_tile_map, off_tile_start, off_tile_cnt,
       off_tile_start64, off_kslot, off_sort_keys[2],
-      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_tile_order, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
+      off_sort_vals[2], off_kj, off_rhist, off_rhist_ex, off_tile_keys, off_tile_e, off_items, off_kcnt, off_hits, off_tile_order, off_order_hist, off_kstart, off_kblock, off_kblock_ex, off_sort_j[2],
       off_partials,
       off_scan, off_rflags, off_rexcl, off_rec, off_G, off_tstat, off_tile_pbwd,
       off_counters, off_tickets, off_stat_part, off_stat_ab, off_prune_flag, off_sched_held, off_b_l2, off_b_abs, off_b_id, off_b_pf,
@@ -142,6 +142,7 @@ Layout make_layout(const erbf_config* cfg) {
   L.off_items = take(sizeof(int32_t) * cfg->pair_cap);
   L.off_kcnt = take(sizeof(int32_t) * (L.cap_total + 1));
   L.off_tile_order = take(sizeof(int32_t) * ((size_t)L.tiles_total + 1));
+  L.off_order_hist = take(sizeof(int32_t) * kOrderClasses * ((size_t)L.tiles_total / 256 + 2));
   // the count pass keeps each kernel's first hit_cap tile slots, so the emit
   // pass copies them instead of walking the box again; sized to at most
   // twice the list capacity
@@ -310,6 +311,7 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.items = reinterpret_cast<int32_t*>(w + lay.off_items);
   D.kcnt = reinterpret_cast<int32_t*>(w + lay.off_kcnt);
   D.tile_order = reinterpret_cast<int32_t*>(w + lay.off_tile_order);
+  D.order_hist = reinterpret_cast<int32_t*>(w + lay.off_order_hist);
   D.hits = reinterpret_cast<int32_t*>(w + lay.off_hits);
   D.hit_cap = lay.hit_cap;
   D.kstart = reinterpret_cast<int64_t*>(w + lay.off_kstart);

@@ -98,6 +98,7 @@ struct Dev {
   int32_t* tile_e;          // [pair_cap] kernel-major index of each tile-major entry
   int32_t* items;           // [pair_cap] kernel of each tile-major entry: ascending within a tile
   int32_t* tile_order;      // [tiles_total] active slots, longest list first (launch order of the tile kernels)
+  int32_t* order_hist;      // [kOrderClasses * (tiles_total / 256 + 2)] list-length classes of each block of 256 slots
   int32_t* kcnt;            // [cap_total + 1] bucket entries of each kernel
   int32_t* hits;            // [cap_total * hit_cap] tile slots a kernel hits, in visit order (count pass)
   int64_t* kstart;          // [cap_total + 1] exclusive scan of kcnt

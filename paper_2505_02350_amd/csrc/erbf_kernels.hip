@@ -614,69 +614,109 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
 }
 
 // tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots).
+// class of a list of len entries in the launch order (0: longest)
+__device__ __forceinline__ int order_class(int len) {
+  return kOrderClasses - 1 - min(len >> 4, kOrderClasses - 1);
+}
+
+// Tile starts by a lower-bound search over the sorted keys; with the launch
+// order switched on, also the class counts of the block's 256 slots
+// (order_hist row blockIdx.x).
 __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __restrict__ keys, int n_slots) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  if (s > n_slots) return;
-  int64_t lo = 0, hi = bucket_entries(D);
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < s) lo = mid + 1;
-    else hi = mid;
+  __shared__ int st[257];
+  __shared__ int cnt[kOrderClasses];
+  const int t = threadIdx.x, s = blockIdx.x * 256 + t;
+  const int64_t n_e = bucket_entries(D);
+  auto lower = [&](int v) {
+    int64_t lo = 0, hi = n_e;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (keys[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    return (int)lo;
+  };
+  int v = 0;
+  if (s <= n_slots) {
+    v = lower(s);
+    D.tile_start[s] = v;
   }
-  D.tile_start[s] = (int)lo;
+  if (!D.tile_order_on) return;   // uniform over the launch
+  st[t] = v;
+  if (t == 0) {
+    const int s1 = blockIdx.x * 256 + 256;
+    st[256] = s1 <= n_slots ? lower(s1) : 0;
+  }
+  if (t < kOrderClasses) cnt[t] = 0;
+  __syncthreads();
+  if (s < n_slots) atomicAdd(&cnt[order_class(st[t + 1] - st[t])], 1);
+  __syncthreads();
+  if (t < kOrderClasses) D.order_hist[blockIdx.x * kOrderClasses + t] = cnt[t];
 }
 
 // Launch order of the tile kernels: the active slots by the length of their
 // kernel lists, longest first, in kOrderClasses classes of 16 entries (the
 // last class takes every list of 1008 entries or more).  A tile's work grows
 // with its list, so the long tiles start first instead of finishing last.
-// The order inside a class follows the LDS atomics and is not fixed; no
-// result depends on it (every tile writes only its own outputs).  One
-// workgroup; each thread reads the list lengths of up to kOrderRegs slots
-// with all loads in flight and keeps their classes for the placing pass.
-constexpr int kOrderRegs = 16;
-
-__global__ __launch_bounds__(1024) void k_tile_order(Dev D, int n_slots) {
-  __shared__ int start[kOrderClasses];
-  const int t = threadIdx.x;
-  if (t < kOrderClasses) start[t] = 0;
+// Each block of 256 slots has its class counts in order_hist (from
+// k_tile_starts, or k_order_count when the lists are ranked); k_order_place
+// gives the block's slots of class c the places after every slot of a
+// longer class and after the class-c slots of the blocks before it.  The
+// order inside a block's run follows the LDS atomics and is not fixed; no
+// result depends on it (every tile writes only its own outputs).
+__global__ __launch_bounds__(256) void k_order_count(Dev D, int n_slots) {
+  __shared__ int cnt[kOrderClasses];
+  const int t = threadIdx.x, s = blockIdx.x * 256 + t;
+  if (t < kOrderClasses) cnt[t] = 0;
   __syncthreads();
-  auto classes = [&](int s0, int (&c)[kOrderRegs]) {
-    int lo[kOrderRegs], hi[kOrderRegs];
+  if (s < n_slots) atomicAdd(&cnt[order_class(D.tile_start[s + 1] - D.tile_start[s])], 1);
+  __syncthreads();
+  if (t < kOrderClasses) D.order_hist[blockIdx.x * kOrderClasses + t] = cnt[t];
+}
+
+__global__ __launch_bounds__(256) void k_order_place(Dev D, int n_slots, int nb) {
+  constexpr int kRows = 64;   // blocks' counts staged per round
+  __shared__ int hbuf[kRows * kOrderClasses];
+  __shared__ int base[kOrderClasses], pre[kOrderClasses];
+  const int t = threadIdx.x, s = blockIdx.x * 256 + t;
+  const bool have = s < n_slots;
+  const int lo = have ? D.tile_start[s] : 0, hi = have ? D.tile_start[s + 1] : 0;
+  int tot = 0, pr = 0;   // thread t < kOrderClasses: class t over all blocks, and over the blocks before this one
+  for (int b0 = 0; b0 < nb; b0 += kRows) {
+    const int nr = min(kRows, nb - b0);
+    int v[kRows * kOrderClasses / 256];
 #pragma unroll
-    for (int u = 0; u < kOrderRegs; ++u) {
-      const int s = min(s0 + 1024 * u + t, n_slots - 1);
-      lo[u] = D.tile_start[s];
-      hi[u] = D.tile_start[s + 1];
+    for (int i = 0; i < kRows * kOrderClasses / 256; ++i) {
+      const int idx = t + 256 * i;
+      v[i] = idx / kOrderClasses < nr ? D.order_hist[(int64_t)b0 * kOrderClasses + idx] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kOrderRegs; ++u)
-      c[u] = s0 + 1024 * u + t < n_slots ? kOrderClasses - 1 - min((hi[u] - lo[u]) >> 4, kOrderClasses - 1) : -1;
-  };
-  const bool one_round = n_slots <= 1024 * kOrderRegs;
-  int c[kOrderRegs];
-  for (int s0 = 0; s0 < n_slots; s0 += 1024 * kOrderRegs) {
-    classes(s0, c);
-#pragma unroll
-    for (int u = 0; u < kOrderRegs; ++u)
-      if (c[u] >= 0) atomicAdd(&start[c[u]], 1);
+    for (int i = 0; i < kRows * kOrderClasses / 256; ++i) hbuf[t + 256 * i] = v[i];
+    __syncthreads();
+    if (t < kOrderClasses) {
+      for (int r = 0; r < nr; ++r) {
+        const int x = hbuf[r * kOrderClasses + t];
+        tot += x;
+        pr += b0 + r < (int)blockIdx.x ? x : 0;
+      }
+    }
+    __syncthreads();
+  }
+  if (t < kOrderClasses) {
+    base[t] = tot;
+    pre[t] = pr;
   }
   __syncthreads();
   if (t == 0) {
     int run = 0;
-    for (int k = 0; k < kOrderClasses; ++k) {
-      const int n = start[k];
-      start[k] = run;
+    for (int c = 0; c < kOrderClasses; ++c) {
+      const int n = base[c];
+      base[c] = run + pre[c];
       run += n;
     }
   }
   __syncthreads();
-  for (int s0 = 0; s0 < n_slots; s0 += 1024 * kOrderRegs) {
-    if (!one_round) classes(s0, c);
-#pragma unroll
-    for (int u = 0; u < kOrderRegs; ++u)
-      if (c[u] >= 0) D.tile_order[atomicAdd(&start[c[u]], 1)] = s0 + 1024 * u + t;
-  }
+  if (have) D.tile_order[atomicAdd(&base[order_class(hi - lo)], 1)] = s;
 }
 
 // Tile lists without a sort (rank mode): the emit pass has placed every
@@ -2314,9 +2354,12 @@ hipError_t launch_scan_any(const int32_t* in, int n, T* blocks, T* out, int64_t*
 }
 
 // the launch order of the tile kernels (when switched on), after tile_start
-static void launch_tile_order(const Dev& D, int n_slots, hipStream_t s) {
+// and the class counts (counted = false: count them here)
+static void launch_tile_order(const Dev& D, int n_slots, bool counted, hipStream_t s) {
   if (!D.tile_order_on || n_slots <= 0) return;
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, D, n_slots);
+  const int nb = (int)nblk(n_slots, 256);
+  if (!counted) hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, D, n_slots);
+  hipLaunchKernelGGL(k_order_place, dim3(nb), dim3(256), 0, s, D, n_slots, nb);
 }
 
 hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, int n_slots, hipStream_t s) {
@@ -2342,7 +2385,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
     const size_t lds = sizeof(uint32_t) * 4 * 2 * (size_t)D.rank_words;
     hipLaunchKernelGGL(k_tile_rank, dim3(nblk(n_slots, 4)), dim3(256), lds, s, D, n_slots);
-    launch_tile_order(D, n_slots, s);
+    launch_tile_order(D, n_slots, false, s);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_bucket_emit, dim3(nkb), dim3(256), 0, s, D);
@@ -2376,7 +2419,7 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
     jin = jout;
   }
   hipLaunchKernelGGL(k_tile_starts, dim3(nblk(n_slots + 1, 256)), dim3(256), 0, s, D, D.tile_keys, n_slots);
-  launch_tile_order(D, n_slots, s);
+  launch_tile_order(D, n_slots, true, s);
   return hipGetLastError();
 }
 
