@@ -1492,11 +1492,10 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W
     for (int i = 0; i < 10; ++i) T[i] = 0.f;
     uint32_t pbg = 0;
     // Per row the point sums (s0, t1, t2) = sums of (G e, G e x', G e x'^2)
-    // go into the moments about the kernel's centre in y and z (the row's
-    // exact dy, dz) and about the tile's first x in x (U1 = sum g x',
-    // U4 = sum g x'^2, U5 = sum g x' dy, U6 = sum g x' dz); the shift from x'
-    // to dx = x' - co is applied once at the end.  Rows come in ascending
-    // (z, y), so the dz terms of the quadric are formed once per z plane.
+    // are turned into sums of (g, g dx, g dx^2) about the kernel's centre and
+    // folded with the row's dy, dz into the moments.  Rows come in ascending
+    // (z, y), so the dz terms of the quadric are formed once per z plane (the
+    // same values as per row: the results do not change).
     int plane = -1;
     float dz = 0.f, dz2 = 0.f, A02dz = 0.f, A12dz = 0.f, A22dzz = 0.f;
     for (int r = 0; r < R; ++r) {
@@ -1516,10 +1515,9 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W
       const float syz = fmaf(dy, dy, dz2);
       const float bl = fmaf(A01x2, dy, A02dz);
       const float cc = fmaf(dy, fmaf(A11, dy, A12dz), A22dzz);
-      // sums of G e and G e x' over the row (s0, t1); G e x'^2 goes straight
-      // into U4.  The row's first point starts the sums (every row in use
-      // holds at least one pair).
-      float s0, t1;
+      // sums of G e, G e x', G e x'^2 over the row (s0, t1, t2); the row's
+      // first point starts them (every row in use holds at least one pair)
+      float s0, t1, t2;
       auto point = [&](const float4 PP, bool first) {
         const float dx = PP.x - cx;
         const bool in = fmaf(dx, dx, syz) < rad2;
@@ -1528,7 +1526,7 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W
         const float e = fast_exp2(-q);
         s0 = first ? PP.y * e : fmaf(PP.y, e, s0);
         t1 = first ? PP.z * e : fmaf(PP.z, e, t1);
-        T[4] = fmaf(PP.w, e, T[4]);
+        t2 = first ? PP.w * e : fmaf(PP.w, e, t2);
         pbg += __popcll(__ballot(in));
       };
       // a row holds one to four point pairs (kn, wave-uniform); the pairs
@@ -1548,16 +1546,13 @@ __device__ __forceinline__ void bwd_walk(const Dev& D, const int slot, BwdLdsT<W
         point(rp[6], false);
         point(rp[7], false);
       }
-      T[0] += s0; T[1] += t1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
-      T[5] = fmaf(dy, t1, T[5]); T[6] = fmaf(dz, t1, T[6]);
+      // sum g dx and sum g dx^2 about the kernel's centre
+      const float s1 = fmaf(-co, s0, t1);
+      const float s2 = fmaf(co2, s0, fmaf(m2co, t1, t2));
+      T[0] += s0; T[1] += s1; T[2] = fmaf(dy, s0, T[2]); T[3] = fmaf(dz, s0, T[3]);
+      T[4] += s2; T[5] = fmaf(dy, s1, T[5]); T[6] = fmaf(dz, s1, T[6]);
       T[7] = fmaf(dy * dy, s0, T[7]); T[8] = fmaf(dy * dz, s0, T[8]); T[9] = fmaf(dz2, s0, T[9]);
     }
-    // x' -> dx: sum g dx = U1 - co T0, sum g dx^2 = U4 - 2 co U1 + co^2 T0,
-    // sum g dx dy = U5 - co T2, sum g dx dz = U6 - co T3
-    T[4] = fmaf(co2, T[0], fmaf(m2co, T[1], T[4]));
-    T[1] = fmaf(-co, T[0], T[1]);
-    T[5] = fmaf(-co, T[2], T[5]);
-    T[6] = fmaf(-co, T[3], T[6]);
     pb += pbg;
     if (have && e_out >= 0) {
       float2* o = D.partials + 5 * (int64_t)e_out;   // kernel-major: the reduce reads it in order
