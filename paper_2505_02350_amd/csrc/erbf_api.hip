@@ -215,6 +215,7 @@ struct erbf_ctx {
   // optional kernel timing: six events per recorded call (start/stop of the
   // forward, backward-tiles and backward-reduce kernels)
   std::vector<hipEvent_t> tev;
+  std::vector<uint8_t> tshared;   // per call: which intervals start at the previous kernel's stop event
   int t_max = 0, t_used = 0;
   ~erbf_ctx() {
     for (hipEvent_t e : tev) (void)hipEventDestroy(e);
@@ -694,9 +695,11 @@ int loss_grad_impl(erbf_ctx* ctx, const erbf_params* params, const erbf_loss_cfg
   const hipEvent_t* ev = tev_call(ctx);
   const bool fused = (D.variant & kVariantFused) != 0;
   HIP_TRY(launch_forward(D, ctx->slots_used, true, f_out, cfg->tau1, cfg->tau2, ev, stream, fused), "loss: forward");
-  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream, fused),
+  uint8_t shared = 0;
+  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream, fused,
+                          ev && ctx->slots_used > 0 ? ev[1] : nullptr, &shared),
           "loss: backward");
-  if (ev) ctx->t_used += 1;
+  if (ev) ctx->tshared[ctx->t_used++] = shared;
   StatsArgs a{};
   a.mode = cfg->mode;
   a.lambda = cfg->lambda;
@@ -770,13 +773,15 @@ int erbf_vjp(erbf_ctx* ctx, const erbf_params* params, const float* grad_f, floa
       HIP_TRY(launch_mask_copy(D, s.lvl0 + l, L.npts, grad_f, stream), "vjp: mask");
     }
   const hipEvent_t* ev = tev_call(ctx);
-  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream),
+  uint8_t shared = 0;
+  HIP_TRY(launch_backward(D, ctx->slots_used, params->p, D.G, grad_out, ev ? ev + 2 : nullptr, stream, false,
+                          nullptr, &shared),
           "vjp: backward");
   if (ev) {
     // no forward in a VJP: give its pair of events a zero-length interval
     HIP_TRY(hipEventRecord(ev[0], stream), "vjp: event");
     HIP_TRY(hipEventRecord(ev[1], stream), "vjp: event");
-    ctx->t_used += 1;
+    ctx->tshared[ctx->t_used++] = shared;
   }
   if (stats_dev) {
     StatsArgs a{};
@@ -974,6 +979,7 @@ int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls) {
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
     ctx->tev.push_back(e);
   }
+  ctx->tshared.assign((size_t)max_calls, 0);
   ctx->t_max = max_calls;
   ctx->t_used = 0;
   return ERBF_OK;
@@ -986,9 +992,12 @@ int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls) {
   for (int k = 0; k < ctx->t_used; ++k) {
     const hipEvent_t* e = &ctx->tev[kEvPerCall * k];
     HIP_TRY(hipEventSynchronize(e[5]), "timing: sync");
+    const uint8_t sh = ctx->tshared[k];
     for (int i = 0; i < 3; ++i) {
+      // an interval that starts at the previous kernel's stop event
+      const hipEvent_t start = (i == 1 && (sh & 1)) ? e[1] : ((i == 2 && (sh & 2)) ? e[3] : e[2 * i]);
       float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, e[2 * i], e[2 * i + 1]), "timing: elapsed");
+      HIP_TRY(hipEventElapsedTime(&t, start, e[2 * i + 1]), "timing: elapsed");
       acc[i] += t;
     }
   }

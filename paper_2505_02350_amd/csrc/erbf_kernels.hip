@@ -2471,7 +2471,10 @@ hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, fl
 }
 
 hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
-                           const hipEvent_t* ev, hipStream_t s, bool tiles_done) {
+                           const hipEvent_t* ev, hipStream_t s, bool tiles_done, hipEvent_t fwd_stop,
+                           uint8_t* shared) {
+  uint8_t sh = 0;
+  bool tiles_timed = false;   // the tile kernel was launched with ev[1] as its stop
   if (tiles_done) {
     // the grid tiles' moments came with the forward (the fused step kernel):
     // a zero-length interval for the backward-tile events
@@ -2491,22 +2494,41 @@ hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const floa
     static const BwdKernel pers_k[3] = {k_bwd_tiles_persistent<2>, k_bwd_tiles_persistent<4>,
                                         k_bwd_tiles_persistent<8>};
     const int threads = 64 * (wi == 0 ? 2 : (wi == 2 ? 8 : 4));
+    // the tiles follow the forward directly unless sample-level forward
+    // kernels ran in between
+    hipEvent_t e0 = ev ? ev[0] : nullptr;
+    if (ev && fwd_stop && D.n_samp_slots == 0) {
+      e0 = nullptr;
+      sh |= 1;
+    }
     if (D.variant & kVariantBwdPersistent) {
       // the same number of resident waves whatever W
       const int grid = std::min(n_slots, D.persistent_wgs * 256 / threads);
-      launch_timed(pers_k[wi], dim3(grid), dim3(threads), s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, D, G,
-                   n_slots);
+      launch_timed(pers_k[wi], dim3(grid), dim3(threads), s, e0, ev ? ev[1] : nullptr, D, G, n_slots);
     } else {
-      launch_timed(grid_k[wi], dim3(tile_grid(D, n_slots)), dim3(threads), s, ev ? ev[0] : nullptr,
-                   ev ? ev[1] : nullptr, D, G, n_slots);
+      launch_timed(grid_k[wi], dim3(tile_grid(D, n_slots)), dim3(threads), s, e0, ev ? ev[1] : nullptr, D, G,
+                   n_slots);
     }
+    tiles_timed = ev != nullptr;
+  } else if (ev && ev[0]) {
+    // no tile at all: a zero-length interval
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e != hipSuccess) return e;
   }
   if (D.n_samp_slots > 0) {
     hipLaunchKernelGGL(k_sample_bwd, dim3(D.n_samp_slots, D.samp_split), dim3(256), 0, s, D, G);
     hipLaunchKernelGGL(k_sample_bwd_sum, dim3(nblk(D.n_samp_slots, 64)), dim3(64), 0, s, D);
   }
-  launch_timed(k_bwd_reduce, dim3(nblk(D.cap_total, 16)), dim3(256), s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, D, p,
-               grad);
+  // the reduce follows the tiles directly unless sample-level kernels ran
+  // in between
+  hipEvent_t r0 = ev ? ev[2] : nullptr;
+  if (tiles_timed && D.n_samp_slots == 0) {
+    r0 = nullptr;
+    sh |= 2;
+  }
+  launch_timed(k_bwd_reduce, dim3(nblk(D.cap_total, 16)), dim3(256), s, r0, ev ? ev[3] : nullptr, D, p, grad);
+  if (shared) *shared = sh;
   return hipGetLastError();
 }
 

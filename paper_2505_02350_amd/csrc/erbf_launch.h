@@ -37,8 +37,15 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
 // kernel (tiles_done).
 hipError_t launch_forward(const Dev& D, int n_slots, bool loss, float* f_out, float tau1, float tau2,
                           const hipEvent_t* ev, hipStream_t s, bool with_bwd = false);
+// With timing events ev (backward tiles' start/stop, reduce's start/stop):
+// when fwd_stop is the stop event of a forward launched just before, a
+// kernel that directly follows the previous timed kernel takes that
+// kernel's stop event as its start (bit 0 of *shared: the tiles start at
+// fwd_stop; bit 1: the reduce starts at the tiles' stop), so fewer events
+// sit between the kernels.
 hipError_t launch_backward(const Dev& D, int n_slots, const float* p, const float* G, float* grad,
-                           const hipEvent_t* ev, hipStream_t s, bool tiles_done = false);
+                           const hipEvent_t* ev, hipStream_t s, bool tiles_done = false,
+                           hipEvent_t fwd_stop = nullptr, uint8_t* shared = nullptr);
 // mode 2 with apply = false leaves the L2 gradient in grad (the combine then
 // runs in launch_adam with combine = true)
 hipError_t launch_stats(const Dev& D, int mode, const float* p, const int32_t* m_dev, float* grad,
