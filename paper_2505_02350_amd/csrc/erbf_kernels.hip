@@ -795,9 +795,11 @@ __global__ __launch_bounds__(256) void k_tile_rank(Dev D, int n_slots) {
 // A wave walks its kernel list four kernels at a time: lane l of a quad forms
 // the row terms (|dyz|^2 and the y/z parts of the quadric) of kernel k + (l&3)
 // for the quad's row, and each of the four kernels then takes its row terms
-// from the quad lane that formed them (DPP quad broadcast).  The row work is
-// done once per (row, kernel) instead of once per lane, and every value is the
-// same float expression as in a one-kernel-at-a-time walk.
+// from the quad lane that formed them, passed through LDS (DPP quad
+// broadcasts in the fused step kernel, which has no registers to spare for
+// the LDS reads).  The row work is done once per (row, kernel) instead of
+// once per lane, and every value is the same float expression as in a
+// one-kernel-at-a-time walk.
 // ---------------------------------------------------------------------------
 
 constexpr int kFwdChunk = 256;
@@ -824,13 +826,12 @@ __device__ __forceinline__ FwdRowTerms fwd_row_terms(const float4 V0, const floa
   return t;
 }
 
-// one kernel of a group of four at the lane's two points; its row terms come
-// from quad lane I
-template <int I>
-__device__ __forceinline__ void fwd_eval_pair(const float4 U, const FwdRowTerms& t, float px0, float px1,
+// one kernel of a step of four at the lane's two points, with the kernel's
+// row terms RT = (syz, bl, cc) at the lane's row
+__device__ __forceinline__ void fwd_eval_pair(const float4 U, const float4 RT, float px0, float px1,
                                               unsigned long long act_mask0, unsigned long long act_mask1,
                                               float& acc0, float& acc1, uint32_t& pf) {
-  const float syz = quad_bcast<I>(t.syz), bl = quad_bcast<I>(t.bl), cc = quad_bcast<I>(t.cc);
+  const float syz = RT.x, bl = RT.y, cc = RT.z;
   const float dx0 = px0 - U.x, dx1 = px1 - U.x;
   float q0 = fmaf(dx0, fmaf(U.y, dx0, bl), cc);
   float q1 = fmaf(dx1, fmaf(U.y, dx1, bl), cc);
@@ -847,9 +848,15 @@ __device__ __forceinline__ void fwd_eval_pair(const float4 U, const FwdRowTerms&
 template <int C>
 struct FwdLdsT {
   // records of the chunk, plus an inert record (r^2 < 0, a = 0) at index
-  // C that pads each wave's list to a multiple of four
+  // C that pads each wave's list to a multiple of four.  Each wave's list
+  // holds the byte offsets of its records, entry i at slist[i % 4][wave][i / 4]
+  // (the four entries of a step in four arrays, read without unpacking).
   float4 srec[C * 3 + 3];
-  uint32_t slist[4][C + 4];
+  uint16_t slist[4][4][C / 4 + 1];
+  // row terms (syz, bl, cc) of the step's four kernels at each quad's row,
+  // twelve floats a quad: every lane writes its kernel's three, every lane
+  // reads its quad's twelve (three 16-byte reads)
+  float4 sxch[4][16][3];
   int scnt[4][4];
   float sbox[4][6];
   double red_d[4];
@@ -999,27 +1006,52 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
       if ((mybits >> w) & 1u) {
         int off = prefix[w];
         for (int v = 0; v < wv; ++v) off += scnt[w][v];
-        slist[w][off] = (uint32_t)(tid * (int)sizeof(float4) * 3);   // byte offset of the record
+        slist[off & 3][w][off >> 2] = (uint16_t)(tid * (int)sizeof(float4) * 3);   // byte offset of the record
       }
     }
     const int len = __builtin_amdgcn_readfirstlane(scnt[wv][0] + scnt[wv][1] + scnt[wv][2] + scnt[wv][3]);
     const int len4 = (len + 3) & ~3;
     // the wave pads its own list (entries [len, len4), written by no other wave)
-    if (lane < len4 - len) slist[wv][len + lane] = (uint32_t)(C * (int)sizeof(float4) * 3);
+    if (lane < len4 - len) slist[(len + lane) & 3][wv][(len + lane) >> 2] = (uint16_t)(C * (int)sizeof(float4) * 3);
     __syncthreads();
     const char* srec_b = reinterpret_cast<const char*>(srec);
     uint32_t pf = 0;
+    float4* xq = F.sxch[wv][lane >> 2];   // this lane's quad's row terms
+    float* xw = reinterpret_cast<float*>(xq) + 3 * (lane & 3);
     for (int k = 0; k < len4; k += 4) {
-      const float4* own = reinterpret_cast<const float4*>(srec_b + slist[wv][k + (lane & 3)]);
+      const int q = k >> 2;
+      const float4* own = reinterpret_cast<const float4*>(srec_b + slist[lane & 3][wv][q]);
       const FwdRowTerms t = fwd_row_terms(own[1], own[2], py, pz);
-      const float4 U0 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k]);
-      const float4 U1 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 1]);
-      const float4 U2 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 2]);
-      const float4 U3 = *reinterpret_cast<const float4*>(srec_b + slist[wv][k + 3]);
-      fwd_eval_pair<0>(U0, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
-      fwd_eval_pair<1>(U1, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
-      fwd_eval_pair<2>(U2, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
-      fwd_eval_pair<3>(U3, t, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      float4 T0, T1, T2, T3;
+      if (BWD) {
+        // (the fused step kernel, short of registers: DPP quad broadcasts)
+        T0 = make_float4(quad_bcast<0>(t.syz), quad_bcast<0>(t.bl), quad_bcast<0>(t.cc), 0.f);
+        T1 = make_float4(quad_bcast<1>(t.syz), quad_bcast<1>(t.bl), quad_bcast<1>(t.cc), 0.f);
+        T2 = make_float4(quad_bcast<2>(t.syz), quad_bcast<2>(t.bl), quad_bcast<2>(t.cc), 0.f);
+        T3 = make_float4(quad_bcast<3>(t.syz), quad_bcast<3>(t.bl), quad_bcast<3>(t.cc), 0.f);
+      } else {
+        // the quad's four row terms pass through LDS (no VALU work): the LDS
+        // operations of one wave complete in order, so the reads return this
+        // step's writes
+        xw[0] = t.syz;
+        xw[1] = t.bl;
+        xw[2] = t.cc;
+        __builtin_amdgcn_wave_barrier();
+        const float4 X0 = xq[0], X1 = xq[1], X2 = xq[2];
+        T0 = make_float4(X0.x, X0.y, X0.z, 0.f);
+        T1 = make_float4(X0.w, X1.x, X1.y, 0.f);
+        T2 = make_float4(X1.z, X1.w, X2.x, 0.f);
+        T3 = make_float4(X2.y, X2.z, X2.w, 0.f);
+      }
+      const float4 U0 = *reinterpret_cast<const float4*>(srec_b + slist[0][wv][q]);
+      const float4 U1 = *reinterpret_cast<const float4*>(srec_b + slist[1][wv][q]);
+      const float4 U2 = *reinterpret_cast<const float4*>(srec_b + slist[2][wv][q]);
+      const float4 U3 = *reinterpret_cast<const float4*>(srec_b + slist[3][wv][q]);
+      fwd_eval_pair(U0, T0, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair(U1, T1, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair(U2, T2, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      fwd_eval_pair(U3, T3, px0, px1, act_mask0, act_mask1, acc0, acc1, pf);
+      __builtin_amdgcn_wave_barrier();   // the next step's writes come after these reads
     }
     pfw += pf;
     __syncthreads();
@@ -1104,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_forward_persistent(Dev D, float* __rest
 // same tile (the two bodies of k_forward<true> and k_bwd_tiles, with the
 // backward's points staged from the forward's registers; results equal those
 // of the two kernels bit for bit).  The LDS of the two bodies overlaps.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step_tiles(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_step_tiles(Dev D, float* __restrict__ f_out, float tau1, float tau2, int n_slots) {
   __shared__ __align__(16) char lds[kTileLdsBytes];
   const int slot = ordered_slot(D, tile_slot(blockIdx.x, n_slots, D.slot_chunk));
   if (slot < 0) return;
