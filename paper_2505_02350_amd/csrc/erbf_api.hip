@@ -361,6 +361,9 @@ int erbf_ctx_create(int device, const erbf_config* cfg, void* workspace, size_t 
   D.radix_nb = lay.radix_nb;
   D.cap_total = lay.cap_total;
   D.tiles_total = lay.tiles_total;
+  // slots (the filler slot tiles_total included) and kernel ids both fit in
+  // 16 bits: one 32-bit key per entry carries both through the sort
+  D.packed_keys = lay.cap_total <= 65536 && lay.tiles_total <= 65535;
   D.n_shapes = cfg->n_shapes;
   D.cull_k = cfg->cull_k;
   D.weight_map = cfg->weight_map;

@@ -160,6 +160,7 @@ struct Dev {
   int32_t fwd_chunk;        // kernel records a forward tile workgroup stages at a time: 64, 128 or 256
   int32_t bwd_waves;        // waves of a backward tile workgroup: 2, 4 or 8
   int32_t tile_order_on;    // 1: tile kernels take the slots of tile_order (longest list first)
+  int32_t packed_keys;      // 1: the sort's keys carry the kernel id in their low 16 bits (slot << 16 | j)
   int32_t rank_words;       // bitmap words per wave of the rank pass (largest shape capacity / 32)
   int32_t persistent_wgs;   // grid of the persistent variants
   int32_t radix_nb;         // blocks of each radix-sort pass

@@ -338,8 +338,12 @@ __device__ __forceinline__ void bucket_place(const Dev& D, const int j, const in
       D.sort_vals[0][pos] = at < D.pair_cap ? (int)at : -1;
     }
   } else if (at >= 0 && at < D.pair_cap) {
-    D.kslot[at] = slot;
-    D.kj[at] = j;
+    if (D.packed_keys) {
+      D.kslot[at] = (int32_t)(((uint32_t)slot << 16) | (uint32_t)j);
+    } else {
+      D.kslot[at] = slot;
+      D.kj[at] = j;
+    }
   }
 }
 
@@ -406,8 +410,12 @@ __global__ __launch_bounds__(256) void k_bucket_emit(Dev D) {
     const int64_t at = e0 + v;
     if (at >= 0 && at < D.pair_cap) {
       if (!D.bucket_rank) {
-        D.kslot[at] = D.tiles_total;
-        D.kj[at] = j;
+        if (D.packed_keys) {
+          D.kslot[at] = (int32_t)(((uint32_t)D.tiles_total << 16) | (uint32_t)j);
+        } else {
+          D.kslot[at] = D.tiles_total;
+          D.kj[at] = j;
+        }
       }
       float2* o = D.partials + 5 * at;   // no tile writes this entry's moments
 #pragma unroll
@@ -494,13 +502,15 @@ constexpr int kRadixSpan = 4 * kRadixWaveSpan;       // entries per block iterat
 // STAGE: each iteration's entries are first placed in LDS in (digit, wave,
 // rank) order, so that the global stores of one digit's run are contiguous
 // (worth it when neighbouring entries hold different digits, as in the
-// kernel-major input of the first pass).
-template <bool STAGE>
+// kernel-major input of the first pass).  PACKED: the key is slot << 16 | j
+// and no kernel array is read; the last pass (last = 1) writes the slot and
+// the kernel apart.
+template <bool STAGE, bool PACKED>
 __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __restrict__ kin,
                                                        const int32_t* __restrict__ vin,
                                                        const int32_t* __restrict__ jin, int32_t* __restrict__ kout,
                                                        int32_t* __restrict__ vout, int32_t* __restrict__ jout,
-                                                       int shift, int mask, int dbits) {
+                                                       int shift, int mask, int dbits, int last) {
   __shared__ int run[256];
   __shared__ int wcnt[4][256];   // per-wave digit counts, then global starts
   __shared__ int lcnt[4][256];   // starts within this iteration's staged run
@@ -508,7 +518,19 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
   __shared__ int sws[4];
   // staged (key, entry, kernel); an entry's destination is its digit's
   // global start plus its place in the digit's staged run
-  __shared__ int stage_k[STAGE ? kRadixSpan : 1], stage_v[STAGE ? kRadixSpan : 1], stage_j[STAGE ? kRadixSpan : 1];
+  __shared__ int stage_k[STAGE ? kRadixSpan : 1], stage_v[STAGE ? kRadixSpan : 1],
+      stage_j[STAGE && !PACKED ? kRadixSpan : 1];
+  // one sorted entry out: (slot, entry, kernel)
+  auto put = [&](int64_t pos, int k, int v, int j) {
+    if (PACKED) {
+      kout[pos] = last ? (int)((uint32_t)k >> 16) : k;
+      if (last) jout[pos] = k & 0xffff;
+    } else {
+      kout[pos] = k;
+      jout[pos] = j;
+    }
+    vout[pos] = v;
+  };
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
   int64_t lo, hi;
@@ -531,7 +553,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
       ok[i] = idx < hi;
       const int64_t ci = ok[i] ? idx : lo;
       key[i] = kin[ci];
-      kid[i] = jin[ci];
+      kid[i] = PACKED ? 0 : jin[ci];
       val[i] = (int)idx;
     }
     if (vin) {
@@ -586,7 +608,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
           const int q = lcnt[w][d] + rank[i];
           stage_k[q] = key[i];
           stage_v[q] = val[i];
-          stage_j[q] = kid[i];
+          if (!PACKED) stage_j[q] = kid[i];
         }
       }
       __syncthreads();
@@ -594,18 +616,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
       for (int q = t; q < nit; q += 256) {
         const int k = stage_k[q];
         const int pos = run_off[(k >> shift) & mask] + q;
-        kout[pos] = k;
-        vout[pos] = stage_v[q];
-        jout[pos] = stage_j[q];
+        put(pos, k, stage_v[q], PACKED ? 0 : stage_j[q]);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < kRadixPerLane; ++i) {
         if (ok[i]) {
           const int pos = wcnt[w][(key[i] >> shift) & mask] + rank[i];
-          kout[pos] = key[i];
-          vout[pos] = val[i];
-          jout[pos] = kid[i];
+          put(pos, key[i], val[i], kid[i]);
         }
       }
     }
@@ -613,13 +631,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Dev D, const int32_t* __r
   }
 }
 
-// tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots).
 // class of a list of len entries in the launch order (0: longest)
 __device__ __forceinline__ int order_class(int len) {
   return kOrderClasses - 1 - min(len >> 4, kOrderClasses - 1);
 }
 
-// Tile starts by a lower-bound search over the sorted keys; with the launch
+// tile_start[s] = first sorted entry whose slot is >= s (s = 0 .. n_slots),
+// by a lower-bound search over the sorted keys; with the launch
 // order switched on, also the class counts of the block's 256 slots
 // (order_hist row blockIdx.x).
 __global__ __launch_bounds__(256) void k_tile_starts(Dev D, const int32_t* __restrict__ keys, int n_slots) {
@@ -2424,23 +2442,26 @@ hipError_t launch_buckets(const Dev& D, const float* p, const int32_t* m_dev, in
   const int dbits = passes ? (bits + passes - 1) / passes : 0;
   // pass 0 reads the kernel-major entries (kept for the backward reduce);
   // the last pass writes the tile lists
+  // packed keys: the slot sits in the upper 16 bits, the kernel rides along
+  // in the lower 16
+  const bool packed = D.packed_keys != 0;
   const int32_t* kin = D.kslot;
   const int32_t* vin = nullptr;     // identity: entry e holds value e
-  const int32_t* jin = D.kj;
+  const int32_t* jin = packed ? nullptr : D.kj;
   for (int pass = 0; pass < passes; ++pass) {
-    const int shift = pass * dbits, mask = (1 << dbits) - 1;
+    const int shift = (packed ? 16 : 0) + pass * dbits, mask = (1 << dbits) - 1;
     const bool last = pass == passes - 1;
     int32_t* kout = last ? D.tile_keys : D.sort_keys[pass & 1];
     int32_t* vout = last ? D.tile_e : D.sort_vals[pass & 1];
-    int32_t* jout = last ? D.items : D.sort_j[pass & 1];
+    int32_t* jout = last ? D.items : (packed ? nullptr : D.sort_j[pass & 1]);
     hipLaunchKernelGGL(k_radix_hist, dim3(D.radix_nb), dim3(256), 0, s, D, kin, shift, mask);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(1024), 0, s, D);
-    if (pass == 0)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(D.radix_nb), dim3(256), 0, s, D, kin, vin, jin, kout, vout, jout,
-                         shift, mask, dbits);
-    else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(D.radix_nb), dim3(256), 0, s, D, kin, vin, jin, kout, vout,
-                         jout, shift, mask, dbits);
+    using Scatter = void (*)(Dev, const int32_t*, const int32_t*, const int32_t*, int32_t*, int32_t*, int32_t*, int,
+                             int, int, int);
+    const Scatter sc = pass == 0 ? (packed ? k_radix_scatter<true, true> : k_radix_scatter<true, false>)
+                                 : (packed ? k_radix_scatter<false, true> : k_radix_scatter<false, false>);
+    hipLaunchKernelGGL(sc, dim3(D.radix_nb), dim3(256), 0, s, D, kin, vin, jin, kout, vout, jout, shift, mask, dbits,
+                       last ? 1 : 0);
     kin = kout;
     vin = vout;
     jin = jout;
