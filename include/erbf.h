@@ -490,7 +490,10 @@ int erbf_timing_enable(erbf_ctx* ctx, int32_t max_calls);
 
 /* Synchronise on the recorded events; ms[0..2] receive the summed times
  * (milliseconds) of the forward, backward-tile and backward-reduce kernels
- * and *n_calls the number of calls recorded.  Clears the records. */
+ * and *n_calls the number of calls recorded.  Clears the records.  A kernel
+ * launched right after another timed kernel (nothing in between) is timed
+ * from that kernel's stop event, so its interval includes the gap between
+ * the two launches. */
 int erbf_timing_read(erbf_ctx* ctx, double* ms, int32_t* n_calls);
 
 /* ---- launch variants and the autotuner ------------------------------------ */
