@@ -964,6 +964,17 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   const unsigned long long act_mask0 = __ballot(act0), act_mask1 = __ballot(act1);
   int64_t pfw = 0;   // in-ball pairs at this wave's training points (wave-uniform)
 
+  // the first chunk's records, read while the boxes below are formed
+  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
+  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
+  float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0, f2 = f0;
+  if (tid < end - beg && tid < C) {
+    const int j = D.items[beg + tid];
+    f0 = D.rec[3 * j];
+    f1 = D.rec[3 * j + 1];
+    f2 = D.rec[3 * j + 2];
+  }
+
   // bounding box of each wave's training points (its list holds the kernels
   // whose ball meets it; a wave without training points walks nothing)
   {
@@ -986,26 +997,35 @@ __device__ __forceinline__ void forward_tile(const Dev& D, const int slot, float
   __syncthreads();
 
   float acc0 = 0.f, acc1 = 0.f;
-  const int64_t beg = min((int64_t)D.tile_start[slot], D.pair_cap);
-  const int64_t end = min((int64_t)D.tile_start[slot + 1], D.pair_cap);
   if (tid < 3) srec[3 * C + tid] = make_float4(0.f, 0.f, tid == 0 ? -1.f : 0.f, 0.f);
+  // a record into the chunk's LDS (the first chunk's before the loop, so
+  // that its registers are free again)
+  auto stage = [&](const float4 a0, const float4 a1, const float4 a2) {
+    srec[3 * tid] = make_float4(a0.x, a1.x, a0.w, a2.z);
+    srec[3 * tid + 1] = make_float4(a0.y, a0.z, a1.y, a1.z);
+    srec[3 * tid + 2] = make_float4(a1.w, a2.x, a2.y, 0.f);
+  };
+  if (tid < end - beg && tid < C) stage(f0, f1, f2);
 
   for (int64_t c0 = beg; c0 < end; c0 += C) {
     const int cnt = (int)min((int64_t)C, end - c0);
     uint32_t mybits = 0;
     if (tid < cnt) {
-      const int j = D.items[c0 + tid];
-      const float4 a0 = D.rec[3 * j], a1 = D.rec[3 * j + 1], a2 = D.rec[3 * j + 2];
-      srec[3 * tid] = make_float4(a0.x, a1.x, a0.w, a2.z);
-      srec[3 * tid + 1] = make_float4(a0.y, a0.z, a1.y, a1.z);
-      srec[3 * tid + 2] = make_float4(a1.w, a2.x, a2.y, 0.f);
-      const float rr = sqrtf(a0.w) * (1.0f + 1e-5f) + 1e-6f;
+      if (c0 != beg) {
+        const int j = D.items[c0 + tid];
+        stage(D.rec[3 * j], D.rec[3 * j + 1], D.rec[3 * j + 2]);
+      }
+      // the waves whose box the record's padded ball meets (this thread's
+      // own LDS entries: c, r^2)
+      const float4 u = srec[3 * tid], v = srec[3 * tid + 1];
+      const float cx = u.x, cy = v.x, cz = v.y;
+      const float rr = sqrtf(u.z) * (1.0f + 1e-5f) + 1e-6f;
       const float rc2 = rr * rr;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const float ex = fmaxf(fmaxf(sbox[w][0] - a0.x, a0.x - sbox[w][1]), 0.f);
-        const float ey = fmaxf(fmaxf(sbox[w][2] - a0.y, a0.y - sbox[w][3]), 0.f);
-        const float ez = fmaxf(fmaxf(sbox[w][4] - a0.z, a0.z - sbox[w][5]), 0.f);
+        const float ex = fmaxf(fmaxf(sbox[w][0] - cx, cx - sbox[w][1]), 0.f);
+        const float ey = fmaxf(fmaxf(sbox[w][2] - cy, cy - sbox[w][3]), 0.f);
+        const float ez = fmaxf(fmaxf(sbox[w][4] - cz, cz - sbox[w][5]), 0.f);
         if (ex * ex + ey * ey + ez * ez < rc2) mybits |= 1u << w;
       }
     }
