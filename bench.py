@@ -513,7 +513,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the step runs on one GPU (the fit is not sharded across GPUs); --gpus must be 1"}))
         sys.exit(2)
 
     if args.e2e:
