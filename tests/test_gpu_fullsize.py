@@ -5,6 +5,8 @@
   19M points and all kernels (the oracle runs over kernel chunks in worker
   processes);
 * the 128^3 / 2048-ERBF problem with eq. 3-21 active, element by element;
+* every tile of a 128^3 and a 256^3 level (36 864 slots, packed sort keys
+  with the sign bit set), element by element;
 * the 512^3 / 65536-ERBF problem through the autograd path, on sampled
   points (f) and sampled kernels (gradients for a seeded upstream).
 
@@ -105,6 +107,25 @@ def test_mid_full_parity_min_norm_weights():
     prob = synth.make_mid()
     st, ref = _full_step_case("full_mid_dynamic", prob, None, O.MODE_DYNAMIC, True, 10.0)
     assert 0.0 < ref.alpha <= 1.0
+
+
+def test_packed_sort_keys_with_slots_from_2_15():
+    """Every tile of a 128^3 and a 256^3 level: 4096 + 32768 = 36864 tile
+    slots and 512 kernels, so the sort keys carry slot << 16 | kernel in one
+    32-bit word, and the slots of the 256^3 level's top eighth in z (32768
+    and up) set its sign bit.  Element-by-element parity with the oracle, as
+    above, with balls reaching those tiles."""
+    prob = synth.make_custom(108, [128, 256], 512, (3.4, 3.8))
+    slots = sum((lv.n // 8) ** 3 for lv in prob.levels)
+    assert slots == 36864 and prob.cap <= 65536
+    P = np.asarray(prob.params, np.float64).reshape(11, prob.cap)[:, :prob.m]
+    r = prob.cull_k / np.exp(P[4:7].min(axis=0))
+    # slot 4096 + t is at least 32768 from the 256^3 tile row tz = 28 on
+    z_top = prob.levels[1].axis[28 * 8]
+    reach = int((P[3] + r > z_top).sum())
+    _say(f"{reach} kernels reach the tiles of slot 32768 and up")
+    assert reach >= 8
+    _full_step_case("full_packed_keys_high_slots", prob, None, O.MODE_FIXED, False, TAU_M, lam=1e-4)
 
 
 def test_diff_512_autograd_sampled_parity():
